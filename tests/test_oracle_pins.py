@@ -1,0 +1,606 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: identities
+of the equilibrium printed with the fluids command, exact invariants of the
+scheme, closed-form solutions (Poiseuille, diffusion spreading, a reactive
+diffusion slab), the paper's own worked numbers (tests/golden/), Laplace's
+law, and brute-force statistics of the growth rule.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- equilibrium
+
+@pytest.mark.parametrize("k", range(4))
+def test_equilibrium_moments_match_fluids_command(k):
+    """sum f_eq = rho, sum f_eq e = rho u, sum f_eq e e = rho cs^2 I + rho u u
+    with cs^2 = (3/5)(1 - alpha) as printed with the fluids command."""
+    g = golden("fluids_alpha.json")
+    alpha, cs2 = g["alphas"][k], g["cs2"][k]
+    rng = np.random.default_rng(k)
+    for _ in range(20):
+        rho = rng.uniform(0.05, 30.0)
+        ux, uy = rng.uniform(-0.1, 0.1, 2)
+        f = np.array([orc.feq(i, rho, ux, uy, alpha) for i in range(9)])
+        assert abs(f.sum() - rho) <= 1e-14 * rho
+        assert abs((f * EX).sum() - rho * ux) <= 1e-14 * rho
+        assert abs((f * EY).sum() - rho * uy) <= 1e-14 * rho
+        assert abs((f * EX * EX).sum() - (rho * cs2 + rho * ux * ux)) <= 1e-13 * rho
+        assert abs((f * EY * EY).sum() - (rho * cs2 + rho * uy * uy)) <= 1e-13 * rho
+        assert abs((f * EX * EY).sum() - rho * ux * uy) <= 1e-13 * rho
+
+
+def test_equilibrium_alpha_default_is_eq_eq():
+    """alpha = 4/9 reproduces Eq. (eq) with cs^2 = 1/3 (A_i = 1)."""
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    rho, ux, uy = 1.3, 0.03, -0.02
+    for i in range(9):
+        eu = EX[i] * ux + EY[i] * uy
+        ref = w[i] * rho * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy))
+        assert orc.feq(i, rho, ux, uy, 4 / 9) == pytest.approx(ref, rel=1e-15, abs=1e-17)
+
+
+def test_solute_equilibrium_is_linear_and_conserving():
+    """Eq. (ueq) for D2Q4: g_i = C/4 (1 + 2 e.u); the D2Q9 form has the same
+    zeroth and first moments (C and C u)."""
+    C, ux, uy = 0.7, 0.02, -0.01
+    for i in range(1, 5):
+        eu = EX[i] * ux + EY[i] * uy
+        assert orc.geq(4, i, C, ux, uy) == pytest.approx(C / 4 * (1 + 2 * eu), rel=1e-15)
+    for q, idx in ((4, range(1, 5)), (9, range(9))):
+        g = np.array([orc.geq(q, i, C, ux, uy) for i in idx])
+        e = np.array(list(idx))
+        assert g.sum() == pytest.approx(C, rel=1e-15)
+        assert (g * EX[e]).sum() == pytest.approx(C * ux, rel=1e-13)
+        assert (g * EY[e]).sum() == pytest.approx(C * uy, rel=1e-13)
+
+
+# ------------------------------------------------------------ stream + walls
+
+def _frozen(nx, ny):
+    """A lattice whose collision changes nothing (tau so large that
+    (f - f_eq)/tau is below half an ulp of f): a pure streaming operator."""
+    o = Oracle(nx, ny)
+    o.fluids(1, 1e300)
+    return o
+
+
+def test_streaming_moves_e1_by_one_node_in_x():
+    """Velocity numbering: e1 = (1,0), e2 = (0,1), e5 = (1,1)."""
+    o = _frozen(7, 5)
+    f = np.ones((9, 5, 7))
+    f[1, 2, 3] = 2.0
+    f[2, 2, 3] = 3.0
+    f[5, 2, 3] = 4.0
+    o.set_f(f)
+    o.iteration(1)
+    g = o.get_f()
+    assert g[1, 2, 4] == 2.0 and g[2, 3, 3] == 3.0 and g[5, 3, 4] == 4.0
+    assert g.sum() == f.sum() and (g == 1.0).sum() == g.size - 3
+
+
+def test_streaming_is_periodic_permutation():
+    """Without obstacles, after lcm(nx, ny) steps every value returns bitwise."""
+    nx, ny = 6, 4
+    o = _frozen(nx, ny)
+    f0 = np.random.default_rng(1).uniform(0, 1, (9, ny, nx))
+    o.set_f(f0)
+    o.iteration(1)
+    assert not np.array_equal(o.get_f(), f0)
+    o.iteration(math.lcm(nx, ny) - 1)
+    assert np.array_equal(o.get_f(), f0)
+
+
+def test_half_way_bounce_back_reverses_at_wall():
+    """noslip: a population sent towards a solid neighbour comes back to the
+    sender reversed after one step (boundary_style noslip)."""
+    o = _frozen(6, 5)
+    o.obstacle_rect(4, 4, 0, 4)           # solid column x = 4
+    f = np.ones((9, 5, 6))
+    f[:, :, 4] = 0.0
+    f[1, 2, 3] = 2.0                       # moving +x from x = 3 into the wall
+    f[5, 2, 3] = 3.0                       # moving (+1,+1) into (4, 3), solid
+    o.set_f(f)
+    o.iteration(1)
+    g = o.get_f()
+    assert g[3, 2, 3] == 2.0               # back as e3 at the same node
+    assert g[7, 2, 3] == 3.0               # back as e7
+    assert g.sum() == f.sum()
+
+
+def test_streaming_preserves_values_with_obstacles():
+    """With bounce-back the stream operator is still a permutation of the
+    fluid populations: the multiset of values is kept exactly."""
+    nx, ny = 9, 7
+    o = _frozen(nx, ny)
+    o.obstacle_circle(4, 3, 1.5)
+    m = o.get_mask().astype(bool)
+    f0 = np.random.default_rng(2).uniform(0, 1, (9, ny, nx))
+    f0[:, m] = 0.0
+    o.set_f(f0)
+    for _ in range(5):
+        o.iteration(1)
+        assert np.array_equal(np.sort(o.get_f().ravel()), np.sort(f0.ravel()))
+
+
+# ----------------------------------------------------------------- invariants
+
+def test_mass_exact_with_bounce_back_and_forcing():
+    nx, ny = 40, 30
+    o = Oracle(nx, ny)
+    o.fluids(1, 0.7)
+    for xc, yc, r in ((10, 10, 4.5), (30, 20, 6.0), (25, 5, 3.0)):
+        o.obstacle_circle(xc, yc, r)
+    o.aveacceleration(1, 1e-4)
+    rng = np.random.default_rng(3)
+    o.set_fields(0, 1.0 + 0.05 * rng.uniform(-1, 1, nx * ny),
+                 0.02 * rng.uniform(-1, 1, nx * ny), 0.02 * rng.uniform(-1, 1, nx * ny))
+    m0 = o.budgets()["mass0"]
+    o.iteration(400)
+    assert abs(o.budgets()["mass0"] - m0) <= 1e-12 * m0
+
+
+def test_momentum_grows_by_total_force_per_step():
+    """Periodic box, one fluid: the velocity shift adds exactly F per node
+    and step to the post-collision momentum (aveforce along e5 = (v, v))."""
+    nx, ny = 12, 10
+    o = Oracle(nx, ny)
+    o.fluids(1, 0.9)
+    o.aveforce(5, 2e-5)
+    o.aveforce(1, 1e-5)
+    rng = np.random.default_rng(4)
+    o.set_fields(0, 1 + 0.1 * rng.uniform(-1, 1, nx * ny), 0.01 * rng.uniform(-1, 1, nx * ny), 0.0)
+    b0 = o.budgets()
+    o.iteration(50)
+    b1 = o.budgets()
+    n = nx * ny
+    assert b1["mom_x"] - b0["mom_x"] == pytest.approx(50 * n * 3e-5, rel=1e-10)
+    assert b1["mom_y"] - b0["mom_y"] == pytest.approx(50 * n * 2e-5, rel=1e-10)
+
+
+def test_two_component_shan_chen_conserves_total_momentum():
+    """Pair forces are antisymmetric: sum_x (F_A + F_B) = 0 on a periodic box."""
+    nx, ny = 16, 14
+    o = Oracle(nx, ny)
+    o.fluids(2, 1.0, 0.8)
+    o.interforce(1.7)
+    rng = np.random.default_rng(5)
+    o.set_fields(0, rng.uniform(0.1, 1.0, nx * ny))
+    o.set_fields(1, rng.uniform(0.1, 1.0, nx * ny))
+    b0 = o.budgets()
+    o.iteration(30)
+    b1 = o.budgets()
+    assert abs(b1["mom_x"] - b0["mom_x"]) < 1e-12
+    assert abs(b1["mom_y"] - b0["mom_y"]) < 1e-12
+    assert b1["mass0"] == pytest.approx(b0["mass0"], rel=1e-13)
+    assert b1["mass1"] == pytest.approx(b0["mass1"], rel=1e-13)
+
+
+# --------------------------------------------------------------------- forces
+
+def test_shan_chen_force_is_gradient_of_other_component():
+    """For a quadratic density field, sum_i w_i rho(x + e_i) e_i is exactly
+    grad(rho)/3 (odd moments of the D2Q9 weights vanish), so the interforce
+    formula gives F_A = -G rho_A grad(rho_B) / 3 in the interior."""
+    nx, ny = 20, 18
+    G = 0.9
+    o = Oracle(nx, ny)
+    o.fluids(2, 1.0, 1.0)
+    o.interforce(G)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    rho_b = 1.0 + 0.01 * x + 0.02 * y + 0.001 * x * x - 0.0005 * x * y + 0.0007 * y * y
+    rho_a = 0.3 + 0.0 * x
+    o.set_fields(0, rho_a)
+    o.set_fields(1, rho_b)
+    Fx, Fy = o.forces(0)
+    gx = 0.01 + 0.002 * x - 0.0005 * y
+    gy = 0.02 - 0.0005 * x + 0.0014 * y
+    sl = (slice(1, ny - 1), slice(1, nx - 1))
+    np.testing.assert_allclose(Fx[sl], -G * 0.3 * gx[sl] / 3, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(Fy[sl], -G * 0.3 * gy[sl] / 3, rtol=1e-12, atol=1e-16)
+
+
+def test_adhesion_next_to_flat_wall():
+    """Node above a solid row: sum_i w_i s(x + e_i) e_i = (0, -1/6), so the
+    adhesiveforce formula gives F = +G_c rho_c / 6 along +y (away from the
+    wall for G_c > 0)."""
+    nx, ny = 10, 8
+    o = Oracle(nx, ny)
+    o.fluids(2, 1.0, 1.0)
+    o.adhesiveforce(0.3, 0)
+    o.adhesiveforce(-0.3, 1)
+    o.obstacle_rect(0, nx - 1, 0, 0)
+    o.set_fields(0, 0.8)
+    o.set_fields(1, 0.2)
+    for comp, G, rho in ((0, 0.3, 0.8), (1, -0.3, 0.2)):
+        Fx, Fy = o.forces(comp)
+        np.testing.assert_allclose(Fy[1, :], G * rho / 6, rtol=1e-14)
+        np.testing.assert_allclose(Fx[1, :], 0.0, atol=1e-17)
+        np.testing.assert_allclose(Fy[3, :], 0.0, atol=1e-17)
+
+
+# ------------------------------------------------------------------ Poiseuille
+
+def test_poiseuille_application_matches_eq_profile():
+    """The paper's Poiseuille application (golden numbers): g from the printed
+    formula equals the printed 1.11e-4, and after 10000 steps the profile is
+    Eq. (profile) with u_max = 0.07."""
+    g = golden("poiseuille_application.json")
+    Nx, Ny, tau, umax = g["Nx"], g["Ny"], g["tau"], g["u_max"]
+    acc = 4.0 / 3.0 * umax * (2 * tau - 1) / (Ny - 1) ** 2
+    assert acc == pytest.approx(g["g_printed"], rel=2e-3)
+    o = Oracle(Nx + 1, Ny + 1)
+    o.fluids(1, tau)
+    o.obstacle_rect(0, Nx, 0, 0)
+    o.obstacle_rect(0, Nx, Ny, Ny)
+    o.aveacceleration(1, acc)
+    # Initial populations 4 (rest and slow modes) and 1 (fast modes):
+    # rho = 24 at rest, not the rest equilibrium; set them as given.
+    init = np.array([g["pop_rest_slow"]] * 5 + [g["pop_fast"]] * 4)
+    f0 = np.broadcast_to(init[:, None, None], (9, Ny + 1, Nx + 1)).copy()
+    f0[:, 0, :] = 0.0
+    f0[:, Ny, :] = 0.0
+    o.set_f(f0)
+    assert o.budgets()["mass0"] == pytest.approx(24.0 * (Nx + 1) * (Ny - 1))
+    o.iteration(g["steps"])
+    _, ux, _ = o.moments(0)
+    y = np.arange(1, Ny)
+    prof = 3 * acc / (2 * tau - 1) * (((Ny - 1) / 2) ** 2 - (y - Ny / 2) ** 2)
+    assert prof.max() == pytest.approx(umax, rel=2e-3)
+    np.testing.assert_allclose(ux[1:Ny, 7], prof, atol=5e-3 * umax)
+    # u_x is uniform along the periodic x axis
+    assert np.ptp(ux[1:Ny, :], axis=1).max() < 1e-12
+
+
+def test_poiseuille_start_up_series_128x64():
+    """Channel of 128x64 nodes, walls at y = 0.5 and 62.5 (H = 62), g = 1e-6,
+    tau = 1 (nu = 1/6), 5000 steps: compare with the start-up solution of the
+    force-driven channel, u = g/(2 nu) [(H/2)^2 - eta^2]
+    - sum_{n odd} 4 g H^2 / (nu pi^3 n^3) sin(n pi xi / H) exp(-nu n^2 pi^2 t / H^2)."""
+    nx, ny, acc, tau, steps = 128, 64, 1e-6, 1.0, 5000
+    o = Oracle(nx, ny)
+    o.fluids(1, tau)
+    o.obstacle_rect(0, nx - 1, 0, 0)
+    o.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+    o.aveacceleration(1, acc)
+    o.set_fields(0, 1.0)
+    m0 = o.budgets()["mass0"]
+    o.iteration(steps)
+    assert abs(o.budgets()["mass0"] - m0) <= 1e-12 * m0
+    _, ux, _ = o.moments(0)
+    nu = (tau - 0.5) / 3
+    H = ny - 2.0
+    y = np.arange(1, ny - 1, dtype=float)
+    xi = y - 0.5
+    eta = y - (ny - 1) / 2
+    u = acc / (2 * nu) * ((H / 2) ** 2 - eta ** 2)
+    for n in range(1, 200, 2):
+        u -= 4 * acc * H ** 2 / (nu * math.pi ** 3 * n ** 3) * np.sin(n * math.pi * xi / H) \
+            * math.exp(-nu * n * n * math.pi ** 2 * steps / H ** 2)
+    umax = acc * H * H / (8 * nu)
+    assert ux[1:-1, 0].max() == pytest.approx(0.882 * umax, rel=2e-2)
+    np.testing.assert_allclose(ux[1:-1, 0], u, atol=2e-3 * umax)
+
+
+def test_poiseuille_steady_second_difference():
+    """At steady state the bulk profile is exactly quadratic with second
+    difference -g/nu (nu = (tau - 1/2)/3, Matlab script of the Scripts
+    section)."""
+    nx, ny, acc, tau = 4, 18, 1e-5, 0.8
+    o = Oracle(nx, ny)
+    o.fluids(1, tau)
+    o.obstacle_rect(0, nx - 1, 0, 0)
+    o.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+    o.aveacceleration(1, acc)
+    o.set_fields(0, 1.0)
+    o.iteration(8000)
+    _, ux, _ = o.moments(0)
+    u = ux[:, 1]
+    d2 = u[3:ny - 1] - 2 * u[2:ny - 2] + u[1:ny - 3]
+    nu = (tau - 0.5) / 3
+    np.testing.assert_allclose(d2, -acc / nu, rtol=1e-8)
+
+
+# ---------------------------------------------------------- solute transport
+
+def _variance_closed_form(n, tau_s, cs2):
+    lam = 1.0 - 1.0 / tau_s
+    return cs2 * (n * (2 * tau_s - 1) - 2 * lam * (1 - lam ** n) / (1 - lam) ** 2)
+
+
+@pytest.mark.parametrize("q,cs2", [(9, 1.0 / 3.0), (4, 0.5)])
+@pytest.mark.parametrize("tau_s", [0.7, 1.0, 1.6])
+def test_solute_spreading_variance_closed_form(q, cs2, tau_s):
+    """Equilibrium start at rest: Var_x(n) - Var_x(0)
+    = cs^2 [n (2 tau_s - 1) - 2 lam (1 - lam^n) / (1 - lam)^2], lam = 1 - 1/tau_s
+    (moment recursion of the BGK solute scheme; long-time slope 2D with
+    D = cs^2 (tau_s - 1/2), which is the solute command's D for Q = 4)."""
+    nx, ny, nsteps = 160, 3, 60
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.solute(tau_s, q)
+    C = np.zeros((ny, nx))
+    C[:, 80] = 1.0
+    C[:, 81] = 0.5
+    o.set_fields(0, 1.0)
+    o.set_concentration(C)
+    x = np.arange(nx, dtype=float)
+
+    def var():
+        c, _ = o.solute_state()
+        p = c.sum(axis=0)
+        m = p.sum()
+        mu = (p * x).sum() / m
+        return (p * x * x).sum() / m - mu * mu, m, mu
+
+    v0, m0, mu0 = var()
+    o.iteration(nsteps)
+    v1, m1, mu1 = var()
+    assert m1 == pytest.approx(m0, rel=1e-14)
+    assert mu1 == pytest.approx(mu0, abs=1e-12)
+    assert v1 - v0 == pytest.approx(_variance_closed_form(nsteps, tau_s, cs2), rel=1e-11)
+
+
+@pytest.mark.parametrize("q", [9, 4])
+def test_solute_advection_mean_moves_by_u(q):
+    """Uniform solvent velocity u and equilibrium start: the centre of mass
+    moves by exactly u per step (first moment of g_eq is C u)."""
+    nx, ny, nsteps = 120, 4, 40
+    ux, uy = 0.05, 0.0
+    o = Oracle(nx, ny)
+    o.fluids(1, 0.9)
+    o.solute(0.8, q)
+    o.set_fields(0, 1.0, ux, uy)
+    C = np.zeros((ny, nx))
+    C[:, 40:44] = 1.0
+    o.set_concentration(C, ux, uy)
+    x = np.arange(nx, dtype=float)
+    c0, _ = o.solute_state()
+    o.iteration(nsteps)
+    c1, _ = o.solute_state()
+    mu0 = (c0.sum(0) * x).sum() / c0.sum()
+    mu1 = (c1.sum(0) * x).sum() / c1.sum()
+    assert mu1 - mu0 == pytest.approx(nsteps * ux, rel=1e-10)
+
+
+def test_damkohler_numbers_of_surface_growth_application():
+    """D2Q4, tau_s = 1: the measured diffusion coefficient is 1/4 and
+    Da = k_r L / D with L = 200 gives the printed 4, 20, 40, 80."""
+    g = golden("surface_growth_damkohler.json")
+    n = 400
+    v = _variance_closed_form(n, g["tau_s"], 0.5)
+    D_measured = v / (2 * n)
+    o = Oracle(300, 3)
+    o.fluids(1, 1.0)
+    o.solute(g["tau_s"], 4)
+    C = np.zeros((3, 300))
+    C[:, 150] = 1.0
+    o.set_fields(0, 1.0)
+    o.set_concentration(C)
+    o.iteration(100)
+    c, _ = o.solute_state()
+    p = c.sum(0)
+    x = np.arange(300.0)
+    mu = (p * x).sum() / p.sum()
+    var = (p * (x - mu) ** 2).sum() / p.sum()
+    assert var == pytest.approx(_variance_closed_form(100, 1.0, 0.5), rel=1e-11)
+    assert D_measured == pytest.approx(0.25, rel=1e-12)
+    for kr, Da in zip(g["kr"], g["Da"]):
+        assert kr * g["L"] / D_measured == pytest.approx(Da, rel=1e-12)
+
+
+# ------------------------------------------------------------- reactive wall
+
+@pytest.mark.parametrize("g_out", [0.0, 0.013, 0.21, 1.7])
+@pytest.mark.parametrize("kr,Cs", [(0.25, 1.0), (5e-3, 0.5), (0.1, 0.0)])
+def test_reactive_link_reduces_to_d2q4_rule(g_out, kr, Cs):
+    """For Q = 4 the per-link rule is the surface_reaction command's
+    C = (2 g_chi + kr Cs)/(kr + 1/2), g_i = -g_chi + C/2, with deposit
+    kr (C - Cs) when positive (else plain bounce-back)."""
+    for i in range(1, 5):
+        db, gi = orc.reactive_link(4, i, kr, Cs, g_out)
+        C = (2 * g_out + kr * Cs) / (kr + 0.5)
+        if kr * (C - Cs) > 0:
+            assert gi == pytest.approx(-g_out + C / 2, rel=1e-14, abs=1e-17)
+            assert db == pytest.approx(kr * (C - Cs), rel=1e-13, abs=1e-17)
+        else:
+            assert gi == g_out and db == 0.0
+
+
+@pytest.mark.parametrize("q", [9, 4])
+def test_reactive_slab_steady_state_closed_form(q):
+    """1-D slab: Dirichlet C = 1 at x = 0, reactive solid column at x = nx-1
+    (half-way wall at x_w = nx - 1.5), at rest.  The steady state is exactly
+    linear, C = 1 + b x, with the diffusive flux -D b equal to the reaction
+    flux k_r (C(x_w) - C_s): b = -k_r (1 - C_s) / (D + k_r x_w)."""
+    nx, ny, kr, Cs, tau_s = 16, 3, 0.05, 0.2, 1.0
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.solute(tau_s, q)
+    o.solute_opening("xlo", "dirichlet", 1.0)
+    o.solute_opening("xhi", "adiabatic")       # behind the solid column
+    o.obstacle_rect(nx - 1, nx - 1, 0, ny - 1)
+    o.surface_reaction(kr, Cs, 0.0, 1e300, 1)
+    o.set_fields(0, 1.0)
+    C0 = np.full((ny, nx), 0.5)
+    o.set_concentration(C0)
+    o.iteration(20000)
+    C, b = o.solute_state()
+    D = (tau_s - 0.5) / 3 if q == 9 else (tau_s - 0.5) / 2
+    xw = nx - 1.5
+    slope = -kr * (1 - Cs) / (D + kr * xw)
+    x = np.arange(nx - 1, dtype=float)
+    np.testing.assert_allclose(C[:, :nx - 1], np.broadcast_to(1 + slope * x, (ny, nx - 1)),
+                               rtol=1e-10)
+    # deposit per step on the wall equals the diffusive flux through it
+    bud0 = o.budgets()
+    dep0 = b.sum()
+    o.iteration(10)
+    _, b1 = o.solute_state()
+    assert (b1.sum() - dep0) / 10 == pytest.approx(-D * slope * ny, rel=1e-9)
+    bud1 = o.budgets()
+    assert (bud1["inflow"] - bud1["outflow"]) - (bud0["inflow"] - bud0["outflow"]) == \
+        pytest.approx(b1.sum() - dep0, rel=1e-9)
+
+
+def test_solute_budget_closes_with_growth():
+    """sum C + sum b + removed solute + deposits consumed by growth
+    - b0 per grown node = initial + inflow - outflow (FP64, exact up to
+    rounding) in a run where nodes grow; fluid mass + removed is kept."""
+    nx, ny = 40, 24
+    o = Oracle(nx, ny)
+    o.fluids(2, 1.0, 1.0)
+    o.interforce(0.9)
+    o.adhesiveforce(0.3, 0)
+    o.adhesiveforce(-0.3, 1)
+    o.obstacle_circle(20, 12, 4.0)
+    o.obstacle_circle(30, 4, 3.0)
+    o.solute(0.7, 9)
+    o.solute_opening("xlo", "dirichlet", 1.0)
+    o.solute_opening("xhi", "adiabatic")
+    o.surface_reaction(0.2, 0.0, 0.01, 0.05, 7)
+    rng = np.random.default_rng(8)
+    o.set_fields(0, rng.uniform(0.05, 1.0, nx * ny))
+    o.set_fields(1, rng.uniform(0.05, 1.0, nx * ny))
+    o.set_concentration(0.3)
+    b0 = o.budgets()
+    o.iteration(300)
+    b1 = o.budgets()
+    assert b1["grown_nodes"] > 0
+    lhs = (b1["solute"] + b1["deposit"] + b1["removed_solute"] + b1["consumed_deposit"]
+           - 0.01 * b1["grown_nodes"])
+    rhs = b0["solute"] + b0["deposit"] + b1["inflow"] - b1["outflow"]
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    for c in (0, 1):
+        assert b1[f"mass{c}"] + b1[f"removed_mass{c}"] == pytest.approx(b0[f"mass{c}"], rel=1e-12)
+
+
+# --------------------------------------------------------------------- growth
+
+def test_growth_flips_the_hashed_neighbour():
+    """5x5 box, one solid node with b > b_max: exactly one of its direct
+    fluid neighbours (E,N,W,S order) becomes solid -- the one the
+    counter-based hash picks -- b resets to 0, the new solid gets b0 and its
+    fluid and solute mass is tallied as removed."""
+    for seed in range(12):
+        o = Oracle(5, 5)
+        o.fluids(1, 1.0)
+        o.solute(1.0, 9)
+        o.obstacle_rect(2, 2, 2, 2)
+        o.obstacle_rect(2, 2, 3, 3)          # N neighbour solid: 3 candidates
+        o.surface_reaction(0.0, 0.0, 0.25, 1.0, seed)
+        o.set_fields(0, 1.0)
+        o.set_concentration(0.4)
+        b = np.zeros((5, 5))
+        b[2, 2] = 1.5
+        b[3, 2] = 0.25
+        o.set_b(b)
+        o.iteration(1)
+        cands = [(3, 2), (1, 2), (2, 1)]    # (x, y) of E, W, S
+        h = orc.splitmix64(seed ^ (1 * 25 + 2 * 5 + 2))
+        tx, ty = cands[orc.pick(h, 3)]
+        m = o.get_mask()
+        expect = np.zeros((5, 5), np.uint8)
+        expect[2, 2] = expect[3, 2] = 1
+        expect[ty, tx] = 1
+        assert np.array_equal(m, expect)
+        bb = o.get_b()
+        assert bb[2, 2] == 0.0 and bb[ty, tx] == 0.25 and bb[3, 2] == 0.25
+        bud = o.budgets()
+        assert bud["grown_nodes"] == 1
+        assert bud["removed_mass0"] == pytest.approx(1.0, rel=1e-14)
+        assert bud["removed_solute"] == pytest.approx(0.4, rel=1e-14)
+
+
+def test_growth_choice_is_equiprobable():
+    """Chi-square over many hashed picks among m candidates (surface_reaction:
+    every occurrence is equiprobable)."""
+    from scipy.stats import chisquare
+    for m in (2, 3, 4):
+        counts = np.zeros(m)
+        for s in range(60000):
+            counts[orc.pick(orc.splitmix64(0xC0FFEE ^ (7 * 1000003 + s)), m)] += 1
+        assert chisquare(counts).pvalue > 1e-3
+
+
+def test_growth_run_is_deterministic():
+    def run():
+        o = Oracle(24, 20)
+        o.fluids(1, 1.0)
+        o.obstacle_circle(12, 10, 3.0)
+        o.solute(1.0, 9)
+        o.surface_reaction(0.1, 0.5, 0.5, 1.0, 99)
+        o.set_fields(0, 1.0)
+        o.set_concentration(1.5)
+        o.iteration(400)
+        return o.get_mask(), o.get_b(), o.budgets()
+    m1, b1, d1 = run()
+    m2, b2, d2 = run()
+    assert d1["grown_nodes"] > 3
+    assert np.array_equal(m1, m2) and np.array_equal(b1, b2) and d1 == d2
+
+
+# -------------------------------------------------------------------- Laplace
+
+@pytest.mark.slow
+def test_laplace_law_two_component_droplets():
+    """Supercritical two-component Shan-Chen droplets: the pressure jump
+    with p = (rho_A + rho_B + G rho_A rho_B)/3 is proportional to 1/R
+    (linear fit through the measured radii, small intercept)."""
+    n, G = 56, 2.6
+    inv_r, dp = [], []
+    for R in (7.0, 10.0, 14.0):
+        o = Oracle(n, n)
+        o.fluids(2, 1.0, 1.0)
+        o.interforce(G)
+        yy, xx = np.mgrid[0:n, 0:n]
+        inside = (xx - n / 2) ** 2 + (yy - n / 2) ** 2 < R * R
+        o.set_fields(0, np.where(inside, 1.0, 0.05))
+        o.set_fields(1, np.where(inside, 0.05, 1.0))
+        o.iteration(5000)
+        ra, _, _ = o.moments(0)
+        rb, _, _ = o.moments(1)
+        p = (ra + rb + G * ra * rb) / 3
+        area = (ra > rb).sum()
+        inv_r.append(1.0 / math.sqrt(area / math.pi))
+        dp.append(p[n // 2, n // 2] - p[0, 0])
+    slope, icpt = np.polyfit(inv_r, dp, 1)
+    assert slope > 0
+    # finite interface width (a few nodes at R = 7..14) leaves an intercept
+    # of several per cent of the jump
+    assert abs(icpt) <= 0.1 * min(dp)
+    resid = np.array(dp) - (slope * np.array(inv_r) + icpt)
+    assert np.abs(resid).max() <= 0.02 * max(dp)
+
+
+# ----------------------------------------------------------- rasterisation
+
+def test_circle_rasterisation_counts():
+    """obstacle(circle): solid iff dx^2 + dy^2 <= r^2 (integer lattice
+    points in a disc; Gauss circle counts for r^2 = 1, 2, 4, 5, 25)."""
+    for r2, count in ((1, 5), (2, 9), (4, 13), (5, 21), (25, 81)):
+        o = Oracle(31, 31)
+        o.obstacle_circle(15, 15, math.sqrt(r2) if r2 != 25 else 5.0)
+        assert int(o.get_mask().sum()) == count
+    # minimum image across the periodic edge
+    o = Oracle(20, 20)
+    o.obstacle_circle(0, 0, 1.0)
+    m = o.get_mask()
+    assert m[0, 0] and m[0, 19] and m[19, 0] and m[0, 1] and m[1, 0] and m.sum() == 5
