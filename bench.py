@@ -1,0 +1,292 @@
+"""Benchmark of the D2Q9 lattice Boltzmann hot path on one MI355X.
+
+Default workload: one-fluid flow through a seeded porous medium of
+4096 x 4096 nodes (non-overlapping discs, radius 8..24, porosity 0.6,
+periodic, tau = 0.8, acceleration 1e-5 along e1), FP32 shifted storage.
+A step is one fused stream + bounce-back + collide pass over the lattice.
+
+Prints ONE JSON line with MLUPS (all nodes), the HBM roofline of the step
+kernel (algorithmic bytes per launch / measured launch time), the FP64 CPU
+oracle timed on a bounded sample of the same workload, and variants:
+16-bit storage, the two-component Shan-Chen + solute + growth step, and the
+batched ensemble of uneven lattices against running them one at a time.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q9 MLUPS + % of HBM roofline; FP16-store & batched vs plain FP32"
+PEAK_HBM_GBPS = 8000.0
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("lb2d_kernels.hip", "lb2d_common.hpp"):
+        with open(os.path.join(ROOT, "paper_1202_0442_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+source:\s*([0-9a-f]+)", txt)
+    if not m or m.group(2) != source_hash():
+        return None
+    return float(m.group(1))
+
+
+def make_porous_lattice(lb2d, w, storage, stream):
+    L = lb2d.Lattice(0)
+    L.lattice("d2q9", w.nx, w.ny, w.tau)
+    L.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        L.obstacle_circle(xc, yc, r)
+    for r in w.rects:
+        L.obstacle_rect(*r)
+    L.aveacceleration(1, w.accel_x)
+    L.bind(storage, stream=stream)
+    return L
+
+
+def time_steps(torch, stream, fn, steps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def cpu_baseline(target_seconds=15.0):
+    """The FP64 oracle, as it stands, on a 512 x 512 sample of the porous
+    workload (same generator, seed and parameters), one thread."""
+    from oracle import Oracle
+    from paper_1202_0442_amd import inputs
+    w = inputs.porous(n=512, seed=2)
+    o = Oracle(w.nx, w.ny)
+    o.fluids(1, w.tau)
+    for (xc, yc, r) in w.discs:
+        o.obstacle_circle(xc, yc, r)
+    o.aveacceleration(1, w.accel_x)
+    o.set_fields(0, 1.0)
+    o.iteration(2)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < target_seconds:
+        o.iteration(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"porous {w.nx}x{w.ny} (discs r 8..24, porosity 0.6, seed 2), {steps} steps, "
+                      f"{dt:.1f} s, FP64 plain C, 1 thread"}
+
+
+def run_variant_storage(lb2d, torch, w, storage, steps, warmup, stream):
+    L = make_porous_lattice(lb2d, w, storage, stream)
+    L.iteration(warmup)
+    ms = time_steps(torch, stream, L.iteration, steps)
+    n = w.nx * w.ny
+    nfl = L.budgets()["fluid_nodes"]
+    per = ms / steps
+    byt = nfl * 18 * STORE_BYTES[storage] + n
+    out = {"mlups": n * steps / (ms * 1e-3) / 1e6, "ms_per_step": per,
+           "algorithmic_GBps": byt / (per * 1e-3) / 1e9, "steps": steps}
+    L.close()
+    return out
+
+
+def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
+    from paper_1202_0442_amd import inputs
+    w = inputs.sc_solute(n=n)
+    e = w.extra
+    rho_a, rho_b = inputs.sc_initial_fields(w)
+    L = lb2d.Lattice(0)
+    L.lattice("d2q9", w.nx, w.ny, w.tau)
+    L.fluids(w.tau, e["tau2"])
+    L.solute(e["tau_s"], 9)
+    L.solute_opening("xlo", "dirichlet", e["C_in"])
+    L.solute_opening("xhi", "adiabatic", 0.0)
+    L.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        L.obstacle_circle(xc, yc, r)
+    L.surface_reaction(e["kr"], e["Cs"], "growth", e["b0"], e["bmax"], e["rng_seed"])
+    L.set_fields(0, rho_a.ravel())
+    L.set_fields(1, rho_b.ravel())
+    L.interforce(e["G"])
+    L.adhesiveforce(e["Gads"][0], 0)
+    L.adhesiveforce(e["Gads"][1], 1)
+    L.bind("f32", stream=stream)
+    L.iteration(warmup)
+    ms = time_steps(torch, stream, L.iteration, steps)
+    # step-kernel time alone (growth/tally kernel excluded), event-bracketed
+    L.set_timing(True)
+    L.iteration(20)
+    kms, _ = L.kernel_time()
+    L.set_timing(False)
+    b = L.budgets()
+    nn = w.nx * w.ny
+    nfl = b["fluid_nodes"]
+    # per fluid node: 2 comps + solute, 9 loads + 9 stores of 4 bytes; mask 1 byte
+    byt = nfl * 3 * 72 + nn
+    out = {"workload": f"two-component Shan-Chen + D2Q9 solute + growth, {w.nx}x{w.ny}",
+           "mlups": nn * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
+           "step_kernel_ms": kms, "step_kernel_algorithmic_GBps": byt / (kms * 1e-3) / 1e9,
+           "step_kernel_frac_hbm": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+           "grown_nodes": b["grown_nodes"], "steps": steps}
+    L.close()
+    return out
+
+
+def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
+    from paper_1202_0442_amd import inputs
+    ws = inputs.ensemble(count=count)
+    lats = [make_porous_lattice(lb2d, w, storage, stream) for w in ws]
+    ntot = sum(w.nx * w.ny for w in ws)
+    # one at a time, plain kernel, launch per step
+    for L in lats:
+        L.iteration(2)
+
+    def seq(k):
+        for _ in range(k):
+            for L in lats:
+                L.iteration(1)
+    ms_seq = time_steps(torch, stream, seq, seq_steps)
+    B = lb2d.Batch(0)
+    for L in lats:
+        B.add(L)
+    B.finalize(stream=stream)
+    B.iteration(4)
+    ms_b = time_steps(torch, stream, B.iteration, steps)
+    out = {"workload": f"{count} porous lattices, sides log-uniform 256..1536, {ntot} nodes, {storage}",
+           "batched_mlups": ntot * steps / (ms_b * 1e-3) / 1e6,
+           "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6,
+           "tuned": B.config(), "steps": steps, "sequential_steps": seq_steps}
+    out["speedup"] = out["batched_mlups"] / out["sequential_mlups"]
+    B.close()
+    for L in lats:
+        L.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096, help="porous lattice side")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--variants", default="all", help="all | none | comma list of f16,bf16,sc,batch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-readout", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1202_0442_amd import inputs, lb2d
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    stream = torch.cuda.Stream()
+    log("generating porous workload")
+    w = inputs.porous(n=args.n, seed=2)
+    L = make_porous_lattice(lb2d, w, args.storage, stream)
+    n = w.nx * w.ny
+    bud = L.budgets()
+    nfl = int(bud["fluid_nodes"])
+    log(f"lattice {w.nx}x{w.ny}, fluid fraction {nfl / n:.4f}; warmup {args.warmup}")
+    L.iteration(args.warmup)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    ms = time_steps(torch, stream, L.iteration, args.steps)
+    per = ms / args.steps
+    mlups = n * args.steps / (ms * 1e-3) / 1e6
+    log(f"{mlups:.0f} MLUPS, {per * 1e3:.1f} us/step")
+    # one kernel launch per step: launch time = step time (HIP events on the
+    # stream the kernel runs on)
+    bytes_launch = nfl * 18 * STORE_BYTES[args.storage] + n
+    achieved = bytes_launch / (per * 1e-3) / 1e9
+    traffic = measured_traffic(f"k_plain_{args.storage}_porous{args.n}.md")
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": per,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": f"porous {w.nx}x{w.ny}, non-overlapping discs r 8..24, porosity 0.6, "
+                               f"periodic, tau 0.8, accel 1e-5 (e1), {args.storage} shifted storage",
+                   "nx": w.nx, "ny": w.ny, "discs": len(w.discs), "fluid_fraction": nfl / n},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
+                     "kernel": "k_plain", "bytes_per_launch": bytes_launch,
+                     "bytes_rule": "72 B per fluid node (9 loads + 9 stores of 4 B) + 1 B mask per node"},
+        "mflups": round(nfl * args.steps / (ms * 1e-3) / 1e6, 1),
+    }
+    mass_drift = None
+    if not args.no_readout:
+        b1 = L.budgets()
+        mass_drift = (b1["mass0"] - bud["mass0"]) / bud["mass0"]
+        _, ux, _ = L.moments(0)
+        import numpy as np
+        ux = np.where(ux == 0.0, 0.0, ux)
+        nu = (w.tau - 0.5) / 3.0
+        out["permeability"] = {"k_lu2": float(nu * ux.mean() / w.accel_x), "after_steps": L.step_count(),
+                               "rule": "nu <u_x>_all / a_x, nu = (tau - 1/2)/3"}
+        out["mass_drift"] = mass_drift
+    L.close()
+    torch.cuda.empty_cache()
+
+    log("copy ceiling")
+    cb = 1 << 30
+    cms = lb2d.copy_bench(cb, reps=20, stream=stream)
+    out["copy_ceiling_GBps"] = round(2 * cb / (cms * 1e-3) / 1e9, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / out["copy_ceiling_GBps"], 4)
+
+    want = set() if args.variants == "none" else (
+        {"f16", "bf16", "sc", "batch"} if args.variants == "all" else set(args.variants.split(",")))
+    variants = {}
+    for st in ("f16", "bf16"):
+        if st in want:
+            log(f"variant {st}")
+            variants[f"{st}_store"] = run_variant_storage(lb2d, torch, w, st, max(500, args.steps // 5),
+                                                          50, stream)
+            variants[f"{st}_store"]["speedup_vs_f32"] = variants[f"{st}_store"]["mlups"] / mlups
+            torch.cuda.empty_cache()
+    if "sc" in want:
+        log("variant two-component + solute 2048^2")
+        variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, 2000, 20, stream)
+        torch.cuda.empty_cache()
+    if "batch" in want:
+        log("variant batched ensemble")
+        variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 20, stream)
+        torch.cuda.empty_cache()
+    if variants:
+        out["variants"] = variants
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,266 @@
+/*
+ * lb2d.h -- C ABI of the MI355X (gfx950) library for 2-D lattice Boltzmann
+ * simulations with the commands of "Introduction to Perl module lb2d.pm 0.1
+ * for basic Lattice Boltzmann simulations" (D. Sergi, arXiv:1202.0442).
+ *
+ * Conventions (every entry point):
+ *  - Returns an int status: LB2D_OK (0) or one of the negative LB2D_E_*
+ *    codes below; lb2d_last_error() gives a message.  Nothing aborts: where
+ *    the paper says that a wrong command order "interrupts the simulation
+ *    with an error message", the call returns LB2D_E_ORDER and leaves the
+ *    context unchanged.
+ *  - Sizes are NODE COUNTS nx, ny (x fastest).  The paper's
+ *    lattice(d2q9, Nx, Ny, tau) numbers its sites 0..Nx, 0..Ny, i.e. it has
+ *    Nx+1 by Ny+1 nodes; callers that follow the paper pass Nx+1, Ny+1.
+ *  - Host arrays are row-major [ny][nx] (x fastest), owned by the caller,
+ *    read or written only during the call.
+ *  - Device memory is owned by the caller: lb2d_workspace_bytes() says how
+ *    much one lattice needs, lb2d_bind() hands over a device pointer and a
+ *    HIP stream.  The caller keeps that memory alive until lb2d_destroy()
+ *    (or a new bind).  The library allocates no device memory.
+ *  - All device work is enqueued on the bound stream.  lb2d_iteration()
+ *    returns without waiting; read-outs and budgets synchronise the stream.
+ *  - Velocity numbering (D2Q9): e0=(0,0), e1=(1,0), e2=(0,1), e3=(-1,0),
+ *    e4=(0,-1), e5=(1,1), e6=(-1,1), e7=(-1,-1), e8=(1,-1).  A "mode" in
+ *    aveforce/aveacceleration is one of 0..8 (the paper's "e0".."e8").
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LB2D_H
+#define LB2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB2D_OK 0
+#define LB2D_E_INVAL (-1)       /* bad argument value */
+#define LB2D_E_ORDER (-2)       /* command order rule of the paper violated */
+#define LB2D_E_UNSUPPORTED (-3) /* a form of a command this library lacks */
+#define LB2D_E_STATE (-4)       /* not bound yet / already bound / running */
+#define LB2D_E_HIP (-5)         /* a HIP runtime call failed */
+#define LB2D_E_SIZE (-6)        /* workspace too small or size overflow */
+
+/* Storage formats of the populations (arithmetic is FP64 for LB2D_F64 and
+ * FP32 otherwise).  Populations are stored as deviations f_i - w_i rho_ref
+ * (rho_ref = mean initial density); the 16-bit formats also scale each
+ * direction by a power of two (2, 8, 32 for rest, axis, diagonal) and round
+ * to nearest even.  Deposits and budgets are always FP64. */
+#define LB2D_F64 0
+#define LB2D_F32 1
+#define LB2D_F16 2
+#define LB2D_BF16 3
+
+/* Budget vector of lb2d_budgets(), FP64. */
+#define LB2D_NBUDGET 16
+#define LB2D_B_MASS0 0          /* sum of rho_1 over fluid nodes */
+#define LB2D_B_MASS1 1          /* sum of rho_2 over fluid nodes */
+#define LB2D_B_MOMX 2           /* sum over comps and fluid nodes of j_x */
+#define LB2D_B_MOMY 3           /*   (post-collision momentum)          */
+#define LB2D_B_SOLUTE 4         /* sum of C over fluid nodes */
+#define LB2D_B_DEPOSIT 5        /* sum of b over solid nodes */
+#define LB2D_B_REMOVED0 6       /* fluid-1 mass of nodes that turned solid */
+#define LB2D_B_REMOVED1 7       /* fluid-2 mass of nodes that turned solid */
+#define LB2D_B_REMOVED_C 8      /* solute of nodes that turned solid */
+#define LB2D_B_INFLOW 9         /* solute injected by the x openings */
+#define LB2D_B_OUTFLOW 10       /* solute that left through the x openings */
+#define LB2D_B_STEPS 11         /* completed time steps */
+#define LB2D_B_GROWN 12         /* nodes that turned solid by growth */
+#define LB2D_B_FLUID 13         /* current number of fluid nodes */
+#define LB2D_B_CONSUMED 14      /* deposits reset to zero by growth */
+
+typedef struct lb2d_ctx lb2d_ctx;
+typedef struct lb2d_batch lb2d_batch;
+
+/* ------------------------------------------------------------ lifetime */
+
+/* New empty context on HIP device `hip_device`.  *out receives it. */
+int lb2d_create(lb2d_ctx **out, int hip_device);
+/* Frees the context and its graphs (not the caller's device memory). */
+int lb2d_destroy(lb2d_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none; static text for a
+ * NULL ctx). */
+const char *lb2d_last_error(const lb2d_ctx *ctx);
+
+/* ---------------------------------------------- initialization commands */
+
+/* lattice command (Sec. "Commands", lattice): style must be "d2q9"; nx, ny
+ * node counts >= 3; tau > 1/2 the relaxation time.  Must come first; the
+ * box is periodic on both axes unless openings say otherwise. */
+int lb2d_lattice(lb2d_ctx *ctx, const char *style, int nx, int ny, double tau);
+
+/* fluids command: two components with relaxation times tau1, tau2 > 1/2
+ * and density-ratio parameters alpha1, alpha2 in [0,1) (pass NaN for the
+ * default 4/9, which gives the plain equilibrium Eq. (eq)).  The
+ * equilibrium is w_i rho [A_i + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u] with
+ * A_0 = (9/4) alpha, A_i = (9/5)(1 - alpha).  After lattice, before any
+ * force and before bind. */
+int lb2d_fluids(lb2d_ctx *ctx, double tau1, double tau2, double alpha1,
+                double alpha2);
+
+/* solute command: one solute species with relaxation time tau_s > 1/2 on a
+ * D2Q9 lattice (q = 9, g_eq = w_i C (1 + 3 e.u), D = (tau_s - 1/2)/3).
+ * q = 4 (the paper's D2Q4) returns LB2D_E_UNSUPPORTED. */
+int lb2d_solute(lb2d_ctx *ctx, double tau_s, int q);
+
+/* inlet_solute / outlet_solute on an x wall: wall "xlo" or "xhi", style
+ * "dirichlet" (value = imposed C; the unknown populations share the
+ * deficit C - C' in proportion to their weights) or "adiabatic" (zero
+ * normal flux, each unknown copies its x-mirror).  Openings come in pairs
+ * (one per x wall) and make the solute's x axis non-periodic; the fluid
+ * stays periodic.  Needs solute. "flux" returns LB2D_E_UNSUPPORTED. */
+int lb2d_solute_opening(lb2d_ctx *ctx, const char *wall, const char *style,
+                        double value);
+
+/* boundary_style command: "noslip" (half-way bounce-back).  Must precede
+ * every obstacle.  "slip", "mixed", "hybrid" return LB2D_E_UNSUPPORTED. */
+int lb2d_boundary_style(lb2d_ctx *ctx, const char *style);
+
+/* obstacle command, rectangle: nodes x0..x1, y0..y1 (inclusive,
+ * 0 <= x0 <= x1 < nx, 0 <= y0 <= y1 < ny) become solid. */
+int lb2d_obstacle_rect(lb2d_ctx *ctx, int x0, int x1, int y0, int y1);
+/* obstacle command, circle: node (x,y) is solid when dx^2 + dy^2 <= r^2,
+ * dx, dy integer minimum-image distances on the periodic box (compared in
+ * FP64).  0 <= xc < nx, 0 <= yc < ny, r >= 0. */
+int lb2d_obstacle_circle(lb2d_ctx *ctx, int xc, int yc, double r);
+/* obstacle from a host byte map (nonzero = solid), OR-ed into the mask. */
+int lb2d_obstacle_mask(lb2d_ctx *ctx, const uint8_t *host_mask);
+
+/* surface_reaction command: D dC/dn = kr (C - Cs) on solid surfaces, style
+ * "growth"; every solid starts with deposit b0; a solid whose deposit
+ * exceeds bmax turns one of its direct fluid neighbours (E,N,W,S, not on an
+ * open solute column) solid, chosen by a counter-based SplitMix64 hash of
+ * (seed, step, node), and its deposit resets to 0.  Per link i the rate is
+ * k_i = kr w_i / (1/6); the link concentration C_i = (2 g_out + k_i Cs) /
+ * (2 w_i + k_i) and returning population 2 w_i C_i - g_out reduce to the
+ * paper's D2Q4 rule.  Deposits are FP64.  Needs solute; kr >= 0. */
+int lb2d_surface_reaction(lb2d_ctx *ctx, double kr, double Cs,
+                          const char *style, double b0, double bmax,
+                          uint64_t seed);
+
+/* position0 / momentum0: initial density and velocity of component comp
+ * (0 or 1), host arrays of nx*ny doubles (ux, uy may be NULL = 0).  The
+ * populations start at their equilibrium (Fig. "algorithm").  Components
+ * never set start at rho = 1, u = 0.  Before bind. */
+int lb2d_set_fields(lb2d_ctx *ctx, int comp, const double *rho,
+                    const double *ux, const double *uy);
+/* concentration0: initial solute concentration (nx*ny doubles) and the
+ * velocity of its equilibrium (NULL = 0).  Default C = 0.  Needs solute. */
+int lb2d_set_concentration(lb2d_ctx *ctx, const double *C, const double *ux,
+                           const double *uy);
+
+/* -------------------------------------------------- force field commands */
+
+/* aveforce command: adds value * e_mode to the force on component comp
+ * (0 or 1) at every fluid node; repeated calls sum.  After lattice/fluids,
+ * before bind. */
+int lb2d_aveforce(lb2d_ctx *ctx, int mode, double value, int comp);
+/* aveacceleration command: adds value * e_mode to the acceleration of comp;
+ * the force is rho_comp times the summed acceleration. */
+int lb2d_aveacceleration(lb2d_ctx *ctx, int mode, double value, int comp);
+/* interforce command, two-component form F_c = -G rho_c(x) sum_{i=1..8}
+ * w_i rho_cbar(x + e_i) e_i (rho_cbar = 0 on solids); psi0 and rho0 must be
+ * NaN.  The one-component psi form returns LB2D_E_UNSUPPORTED.  Needs
+ * fluids. */
+int lb2d_interforce(lb2d_ctx *ctx, double G, double psi0, double rho0);
+/* adhesiveforce command, two-component form F_c += -G_c rho_c(x)
+ * sum_{i=1..8} w_i s(x + e_i) e_i (s = 1 on solids); psi0, rho0 NaN. */
+int lb2d_adhesiveforce(lb2d_ctx *ctx, double G, double psi0, double rho0,
+                       int comp);
+
+/* ------------------------------------------------------------- memory */
+
+/* Bytes of device memory one lattice needs with the given storage format
+ * (LB2D_F64/F32/F16/BF16), after all commands above. */
+int lb2d_workspace_bytes(lb2d_ctx *ctx, int storage, size_t *bytes);
+/* Binds `bytes` of caller device memory at dev_ptr (256-byte aligned,
+ * on the context's device) and the HIP stream `hip_stream` (NULL = the
+ * null stream) with the storage chosen in the last lb2d_workspace_bytes
+ * call; rasterises obstacles and sets the initial populations on the GPU.
+ * After this, commands return LB2D_E_STATE. */
+int lb2d_bind(lb2d_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* ------------------------------------------------------------ action */
+
+/* iteration command: advances nsteps >= 0 time steps (stream with
+ * bounce-back, moments, forces, collision; then solute stream, reactive and
+ * opening rules, collision, deposit, growth).  Asynchronous on the stream;
+ * launches captured HIP graphs. */
+int lb2d_iteration(lb2d_ctx *ctx, int64_t nsteps);
+
+/* ------------------------------------------------------------ output */
+
+/* output command, fluid part: density and velocity of component comp (or
+ * of the mixture, comp = -1) after the last collision, velocity including
+ * half the force, (j_post - F/2) / rho.  Solid nodes read rho = -11 and
+ * u = 0.  Host arrays of nx*ny doubles. */
+int lb2d_moments(lb2d_ctx *ctx, int comp, double *rho, double *ux,
+                 double *uy);
+/* output command, solute part: C on fluid nodes (0 on solids) and deposit
+ * b on solid nodes (0 on fluid nodes); either pointer may be NULL. */
+int lb2d_solute_state(lb2d_ctx *ctx, double *C, double *b);
+/* Current solid mask (1 = solid), nx*ny bytes. */
+int lb2d_mask(lb2d_ctx *ctx, uint8_t *m);
+/* thermo command: FP64 budgets, out[LB2D_NBUDGET] (see LB2D_B_*). */
+int lb2d_budgets(lb2d_ctx *ctx, double *out);
+
+/* Raw state, decoded to FP64 f_i (comp 0/1) or g_i (comp -1): 9*nx*ny
+ * doubles [9][ny][nx] of the post-collision state (for checkpoints and
+ * one-step comparisons).  set encodes into the storage format. */
+int lb2d_get_populations(lb2d_ctx *ctx, int comp, double *out);
+int lb2d_set_populations(lb2d_ctx *ctx, int comp, const double *in);
+/* Raw deposit array (nx*ny doubles, all nodes) and step counter. */
+int lb2d_get_deposit(lb2d_ctx *ctx, double *b);
+int lb2d_set_deposit(lb2d_ctx *ctx, const double *b);
+int lb2d_set_mask(lb2d_ctx *ctx, const uint8_t *m);
+int lb2d_step_count(lb2d_ctx *ctx, int64_t *t);
+
+/* ------------------------------------------------------- batched lattices */
+
+/* A batch advances many bound one-fluid lattices (no solute, no Shan-Chen;
+ * each with its own size, geometry, tau and forces, one storage format) in
+ * one launch per time step.  Tile shape and the order of tiles are picked
+ * by an autotuner at finalize (results never depend on them). */
+int lb2d_batch_create(lb2d_batch **out, int hip_device);
+int lb2d_batch_destroy(lb2d_batch *b);
+const char *lb2d_batch_last_error(const lb2d_batch *b);
+/* Adds a bound lattice (the batch does not own it). */
+int lb2d_batch_add(lb2d_batch *b, lb2d_ctx *lattice);
+/* Device bytes for the batch's tables (after all adds). */
+int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes);
+/* Binds the tables' memory and the stream, builds the tile tables, runs the
+ * autotuner (timed trial steps that write only the lattices' next-step
+ * buffers, leaving their state unchanged) unless tune_cache_json names a
+ * readable file holding a previous choice for the same lattice set, in which
+ * case that choice is used; the choice is written back to that file when
+ * the path is not NULL.  Stream NULL = null stream. */
+int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes,
+                        void *hip_stream, const char *tune_cache_json);
+/* Advances every lattice by nsteps (asynchronous, graph-launched). */
+int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps);
+/* The tuned launch shape: tile width, tile height, schedule id, blocks per
+ * CU (0 = one block per tile). */
+int lb2d_batch_config(lb2d_batch *b, int *tile_w, int *tile_h, int *schedule,
+                      int *blocks_per_cu);
+
+/* -------------------------------------------------------- measurement */
+
+/* Average device time per call, in milliseconds, of the dominant kernel of
+ * the last lb2d_iteration / lb2d_batch_iteration measured with HIP events
+ * on the bound stream when timing is on (lb2d_set_timing(ctx, 1)); timing
+ * launches the steps one by one instead of through graphs. */
+int lb2d_set_timing(lb2d_ctx *ctx, int on);
+int lb2d_kernel_time(lb2d_ctx *ctx, double *ms_per_launch, int64_t *launches);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16; src and dst
+ * device memory, not overlapping) repeated `reps` times on the stream;
+ * *ms = average milliseconds per copy.  Not a command of the paper: it
+ * measures the practical HBM ceiling the stencil is compared with. */
+int lb2d_copy_bench(void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB2D_H */

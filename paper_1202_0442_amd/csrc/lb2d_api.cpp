@@ -1,0 +1,1181 @@
+// lb2d_api.cpp -- host runtime behind the C ABI of include/lb2d.h.
+//
+// Holds the command state of one lattice (the paper's command API, Sec.
+// "Commands"), checks the ordering rules the paper states, lays the
+// caller-owned workspace out, and drives the gfx950 kernels on the bound
+// stream (HIP graphs for the time loop).
+#include "lb2d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lb2d_common.hpp"
+#include "lb2d_kernels.hpp"
+
+using namespace lb2d;
+
+namespace {
+
+constexpr int kGraphSteps = 32;  // steps per captured graph (even)
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Circle {
+    int xc, yc;
+    double r;
+};
+struct Rect {
+    int x0, x1, y0, y1;
+};
+
+}  // namespace
+
+struct lb2d_ctx {
+    int device = 0;
+    std::string err;
+    // command state
+    bool have_lattice = false, have_fluids = false, have_solute = false;
+    bool have_style = false, have_force = false, bound = false;
+    int nx = 0, ny = 0, ncomp = 1;
+    double tau[2] = {1.0, 1.0}, alpha[2] = {4.0 / 9.0, 4.0 / 9.0};
+    double force[2][2] = {{0, 0}, {0, 0}}, accel[2][2] = {{0, 0}, {0, 0}};
+    bool inter = false;
+    double G = 0.0;
+    bool ads[2] = {false, false};
+    double Gads[2] = {0.0, 0.0};
+    int q = 0;
+    double tau_s = 1.0;
+    int open_style[2] = {0, 0};
+    double open_value[2] = {0.0, 0.0};
+    bool reaction = false;
+    double kr = 0, Cs = 0, b0 = 0, bmax = 0;
+    uint64_t seed = 0;
+    std::vector<Circle> circles;
+    std::vector<Rect> rects;
+    std::vector<std::vector<uint8_t>> host_masks;
+    std::vector<double> rho0[2], ux0[2], uy0[2];
+    std::vector<double> C0, Cux, Cuy;
+    int storage = kF32;
+    bool storage_chosen = false;
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    void *f[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void *g[2] = {nullptr, nullptr};
+    uint8_t *mask = nullptr, *trig = nullptr;
+    double *b = nullptr, *staging = nullptr, *partial = nullptr, *gpartial = nullptr;
+    double *totals = nullptr;
+    unsigned *ticket = nullptr;
+    long long *dstep = nullptr;
+    size_t staging_doubles = 0;
+    double rho_ref[2] = {1.0, 1.0};
+    int64_t t = 0;
+    hipGraphExec_t graph = nullptr;
+    int plain_bx = 256, plain_by = 1;
+    // timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double kernel_ms = 0.0;
+    int64_t kernel_launches = 0;
+
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    size_t n() const { return (size_t)nx * ny; }
+    bool plain() const { return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1]; }
+    bool sc() const { return ncomp == 2 && inter; }
+};
+
+struct lb2d_batch {
+    int device = 0;
+    std::string err;
+    std::vector<lb2d_ctx *> lat;
+    bool final_ = false;
+    int storage = kF32;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    PlainLattice *d_lat = nullptr;
+    Tile *d_tiles = nullptr;
+    size_t max_tiles = 0;
+    int ntiles = 0;
+    int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
+    hipGraphExec_t graph = nullptr;
+    int64_t t = 0;
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+namespace {
+
+#define HIPCHK(ctx, call)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return (ctx)->fail(LB2D_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_nan(double v) { return std::isnan(v); }
+
+// Workspace layout of one lattice.
+struct Layout {
+    size_t f[2][2], g[2], mask, trig, b, staging, partial, gpartial, totals, ticket, dstep, total;
+    size_t staging_doubles;
+};
+
+Layout make_layout(const lb2d_ctx *c, int storage) {
+    Layout L{};
+    const size_t n = c->n();
+    const size_t pop = align_up(9 * n * storage_bytes(storage));
+    size_t off = 0;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 2; ++k) {
+            L.f[p][k] = (k < c->ncomp) ? off : (size_t)-1;
+            if (k < c->ncomp) off += pop;
+        }
+    for (int p = 0; p < 2; ++p) {
+        L.g[p] = c->q ? off : (size_t)-1;
+        if (c->q) off += pop;
+    }
+    L.mask = off;
+    off += align_up(n);
+    L.trig = off;
+    off += align_up(n);
+    L.b = off;
+    if (c->reaction) off += align_up(n * 8);
+    // staging: 3 doubles per node (host transfers, read-outs, budgets,
+    // shape tables)
+    size_t sd = 3 * n;
+    const size_t shapes = 2 * c->circles.size() + c->circles.size() + 2 * c->rects.size() + 16;
+    sd = std::max(sd, shapes + (size_t)c->ny * 8 + 64);
+    L.staging_doubles = sd;
+    L.staging = off;
+    off += align_up(sd * 8);
+    L.partial = off;
+    off += align_up((size_t)full_tiles(c->nx, c->ny) * 4 * 8);
+    L.gpartial = off;
+    off += align_up((size_t)growth_blocks(c->nx, c->ny) * 4 * 8);
+    L.totals = off;
+    off += align_up(16 * 8);
+    L.ticket = off;
+    off += align_up(8);
+    L.dstep = off;
+    off += align_up(8);
+    L.total = off;
+    return L;
+}
+
+FullParams full_params(const lb2d_ctx *c) {
+    FullParams p{};
+    for (int pp = 0; pp < 2; ++pp) {
+        for (int k = 0; k < 2; ++k) p.f[pp][k] = c->f[pp][k];
+        p.g[pp] = c->g[pp];
+    }
+    p.mask = c->mask;
+    p.trig = c->trig;
+    p.b = c->b;
+    p.partial = c->partial;
+    p.gpartial = c->gpartial;
+    p.totals = c->totals;
+    p.ticket = c->ticket;
+    p.dstep = c->dstep;
+    p.nx = c->nx;
+    p.ny = c->ny;
+    p.ncomp = c->ncomp;
+    for (int k = 0; k < 2; ++k) {
+        p.tau[k] = c->tau[k];
+        p.omega[k] = 1.0 / c->tau[k];
+        p.A0[k] = 2.25 * c->alpha[k];
+        p.A1[k] = 1.8 * (1.0 - c->alpha[k]);
+        p.rho_ref[k] = c->rho_ref[k];
+        for (int d = 0; d < 2; ++d) {
+            p.force[k][d] = c->force[k][d];
+            p.accel[k][d] = c->accel[k][d];
+        }
+        p.Gads[k] = c->ads[k] ? c->Gads[k] : 0.0;
+    }
+    p.G = c->inter ? c->G : 0.0;
+    p.has_ads = (c->ads[0] || c->ads[1]) ? 1 : 0;
+    p.tau_s = c->tau_s;
+    p.omega_s = 1.0 / c->tau_s;
+    p.solute_xper = (c->open_style[0] || c->open_style[1]) ? 0 : 1;
+    for (int k = 0; k < 2; ++k) {
+        p.open_style[k] = c->open_style[k];
+        p.open_value[k] = c->open_value[k];
+    }
+    p.kr = c->kr;
+    p.Cs = c->Cs;
+    p.b0 = c->b0;
+    p.bmax = c->bmax;
+    p.seed = c->seed;
+    p.nblk_main = full_tiles(c->nx, c->ny);
+    p.nblk_grow = growth_blocks(c->nx, c->ny);
+    return p;
+}
+
+PlainLattice plain_lattice(const lb2d_ctx *c) {
+    PlainLattice L{};
+    L.f[0] = c->f[0][0];
+    L.f[1] = c->f[1][0];
+    L.mask = c->mask;
+    L.nx = c->nx;
+    L.ny = c->ny;
+    L.tau = c->tau[0];
+    L.omega = 1.0 / c->tau[0];
+    L.Fx = c->force[0][0];
+    L.Fy = c->force[0][1];
+    L.ax = c->accel[0][0];
+    L.ay = c->accel[0][1];
+    L.rho_ref = c->rho_ref[0];
+    return L;
+}
+
+int check_ctx(lb2d_ctx *c) { return c ? LB2D_OK : LB2D_E_INVAL; }
+
+int pre_command(lb2d_ctx *c, bool need_lattice = true) {
+    if (!c) return LB2D_E_INVAL;
+    if (c->bound) return c->fail(LB2D_E_STATE, "commands must come before lb2d_bind");
+    if (need_lattice && !c->have_lattice) return c->fail(LB2D_E_ORDER, "the lattice command must come first");
+    return LB2D_OK;
+}
+
+// One time step on the stream `s` at the current parity.
+hipError_t enqueue_step(lb2d_ctx *c, int parity, hipStream_t s) {
+    if (c->plain()) return launch_plain(c->storage, plain_lattice(c), parity, c->plain_bx, c->plain_by, s);
+    const FullParams p = full_params(c);
+    hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->q != 0, c->reaction, s);
+    if (e != hipSuccess) return e;
+    if (c->q) e = launch_growth(c->storage, p, parity ^ 1, c->reaction, s);
+    return e;
+}
+
+int build_graph(lb2d_ctx *c) {
+    if (c->graph) return LB2D_OK;
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t gr = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(c, k & 1, c->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+    if (e != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));
+    HIPCHK(c, hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0));
+    HIPCHK(c, hipGraphDestroy(gr));
+    return LB2D_OK;
+}
+
+int upload(lb2d_ctx *c, double *dst, const std::vector<double> &src, double fill) {
+    const size_t n = c->n();
+    if (src.empty()) {
+        HIPCHK(c, launch_fill_f64(dst, fill, n, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(dst, src.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    return LB2D_OK;
+}
+
+double mean_of(const std::vector<double> &v) {
+    double s = 0.0;
+    for (double x : v) s += x;
+    return v.empty() ? 1.0 : s / (double)v.size();
+}
+
+}  // namespace
+
+namespace {
+
+struct TuneCand {
+    int w, h, sched, bpc;
+};
+
+// schedule 0: lattice by lattice; 1: largest lattices first; 2: tiles of
+// all lattices interleaved round-robin.
+std::vector<Tile> make_tiles(const lb2d_batch *b, int w, int h, int sched) {
+    std::vector<int> order(b->lat.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    if (sched == 1)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int c) { return b->lat[a]->n() > b->lat[c]->n(); });
+    std::vector<std::vector<Tile>> per(b->lat.size());
+    for (int k : order) {
+        const lb2d_ctx *c = b->lat[k];
+        for (int y0 = 0; y0 < c->ny; y0 += h)
+            for (int x0 = 0; x0 < c->nx; x0 += w) per[k].push_back({k, x0, y0, 0});
+    }
+    std::vector<Tile> out;
+    if (sched == 2) {
+        size_t mx = 0;
+        for (auto &v : per) mx = std::max(mx, v.size());
+        for (size_t i = 0; i < mx; ++i)
+            for (int k : order)
+                if (i < per[k].size()) out.push_back(per[k][i]);
+    } else {
+        for (int k : order) out.insert(out.end(), per[k].begin(), per[k].end());
+    }
+    return out;
+}
+
+int batch_grid(int ntiles, int bpc, int cus) {
+    if (bpc <= 0) return ntiles;
+    return std::min(ntiles, bpc * cus);
+}
+
+std::string batch_key(const lb2d_batch *b) {
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(b->lat.size());
+    mix(b->storage);
+    for (auto *c : b->lat) {
+        mix(c->nx);
+        mix(c->ny);
+    }
+    char buf[32];
+    snprintf(buf, sizeof(buf), "%016llx", h);
+    return buf;
+}
+
+}  // namespace
+
+// ======================================================================
+extern "C" {
+
+int lb2d_create(lb2d_ctx **out, int hip_device) {
+    if (!out) return LB2D_E_INVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (hip_device < 0 || (ndev > 0 && hip_device >= ndev)) return LB2D_E_INVAL;
+    lb2d_ctx *c = new lb2d_ctx();
+    c->device = hip_device;
+    *out = c;
+    return LB2D_OK;
+}
+
+int lb2d_destroy(lb2d_ctx *c) {
+    if (!c) return LB2D_E_INVAL;
+    if (c->graph || c->cap_stream || c->ev0) {
+        (void)hipSetDevice(c->device);
+        if (c->bound) (void)hipStreamSynchronize(c->stream);
+        if (c->graph) (void)hipGraphExecDestroy(c->graph);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        if (c->ev0) (void)hipEventDestroy(c->ev0);
+        if (c->ev1) (void)hipEventDestroy(c->ev1);
+    }
+    delete c;
+    return LB2D_OK;
+}
+
+const char *lb2d_last_error(const lb2d_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int lb2d_lattice(lb2d_ctx *c, const char *style, int nx, int ny, double tau) {
+    int rc = pre_command(c, false);
+    if (rc) return rc;
+    if (c->have_lattice) return c->fail(LB2D_E_ORDER, "lattice given twice");
+    if (!style || std::strcmp(style, "d2q9") != 0)
+        return c->fail(LB2D_E_UNSUPPORTED, "lattice style must be \"d2q9\"");
+    if (nx < 3 || ny < 3) return c->fail(LB2D_E_INVAL, "lattice needs at least 3x3 nodes");
+    if ((double)nx * (double)ny > 4.0e9) return c->fail(LB2D_E_SIZE, "lattice too large");
+    if (!(tau > 0.5)) return c->fail(LB2D_E_INVAL, "tau must exceed 1/2");
+    c->nx = nx;
+    c->ny = ny;
+    c->tau[0] = c->tau[1] = tau;
+    c->have_lattice = true;
+    return LB2D_OK;
+}
+
+int lb2d_fluids(lb2d_ctx *c, double tau1, double tau2, double alpha1, double alpha2) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (c->have_fluids) return c->fail(LB2D_E_ORDER, "fluids given twice");
+    if (c->have_force || !c->rho0[0].empty())
+        return c->fail(LB2D_E_ORDER, "fluids must precede forces and initial fields");
+    if (!(tau1 > 0.5) || !(tau2 > 0.5)) return c->fail(LB2D_E_INVAL, "tau1, tau2 must exceed 1/2");
+    if (is_nan(alpha1)) alpha1 = 4.0 / 9.0;
+    if (is_nan(alpha2)) alpha2 = 4.0 / 9.0;
+    if (!(alpha1 >= 0.0 && alpha1 < 1.0) || !(alpha2 >= 0.0 && alpha2 < 1.0))
+        return c->fail(LB2D_E_INVAL, "alpha must lie in [0, 1)");
+    c->ncomp = 2;
+    c->tau[0] = tau1;
+    c->tau[1] = tau2;
+    c->alpha[0] = alpha1;
+    c->alpha[1] = alpha2;
+    c->have_fluids = true;
+    return LB2D_OK;
+}
+
+int lb2d_solute(lb2d_ctx *c, double tau_s, int q) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (c->have_solute) return c->fail(LB2D_E_ORDER, "solute given twice");
+    if (q == 4) return c->fail(LB2D_E_UNSUPPORTED, "the D2Q4 solute lattice is not implemented on the GPU");
+    if (q != 9) return c->fail(LB2D_E_INVAL, "solute lattice must be 9 (D2Q9)");
+    if (!(tau_s > 0.5)) return c->fail(LB2D_E_INVAL, "tau_s must exceed 1/2");
+    c->q = q;
+    c->tau_s = tau_s;
+    c->have_solute = true;
+    return LB2D_OK;
+}
+
+int lb2d_solute_opening(lb2d_ctx *c, const char *wall, const char *style, double value) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_solute) return c->fail(LB2D_E_ORDER, "solute openings need the solute command first");
+    if (!wall || !style) return c->fail(LB2D_E_INVAL, "null wall or style");
+    int w;
+    if (!std::strcmp(wall, "xlo")) w = 0;
+    else if (!std::strcmp(wall, "xhi")) w = 1;
+    else if (!std::strcmp(wall, "ylo") || !std::strcmp(wall, "yhi"))
+        return c->fail(LB2D_E_UNSUPPORTED, "solute openings on y walls are not implemented");
+    else return c->fail(LB2D_E_INVAL, "wall must be xlo or xhi");
+    int st;
+    if (!std::strcmp(style, "dirichlet")) st = 1;
+    else if (!std::strcmp(style, "adiabatic")) st = 2;
+    else if (!std::strcmp(style, "flux")) return c->fail(LB2D_E_UNSUPPORTED, "flux openings are not implemented");
+    else return c->fail(LB2D_E_INVAL, "style must be dirichlet or adiabatic");
+    if (!std::isfinite(value)) return c->fail(LB2D_E_INVAL, "opening value must be finite");
+    c->open_style[w] = st;
+    c->open_value[w] = value;
+    return LB2D_OK;
+}
+
+int lb2d_boundary_style(lb2d_ctx *c, const char *style) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!style) return c->fail(LB2D_E_INVAL, "null style");
+    if (!std::strcmp(style, "noslip")) {
+        c->have_style = true;
+        return LB2D_OK;
+    }
+    if (!std::strcmp(style, "slip") || !std::strcmp(style, "mixed") || !std::strcmp(style, "hybrid"))
+        return c->fail(LB2D_E_UNSUPPORTED, "boundary style %s is not implemented", style);
+    return c->fail(LB2D_E_INVAL, "unknown boundary style %s", style);
+}
+
+int lb2d_obstacle_rect(lb2d_ctx *c, int x0, int x1, int y0, int y1) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_style) return c->fail(LB2D_E_ORDER, "obstacle must follow boundary_style");
+    if (x0 < 0 || y0 < 0 || x1 >= c->nx || y1 >= c->ny || x0 > x1 || y0 > y1)
+        return c->fail(LB2D_E_INVAL, "rectangle outside the lattice or empty");
+    c->rects.push_back({x0, x1, y0, y1});
+    return LB2D_OK;
+}
+
+int lb2d_obstacle_circle(lb2d_ctx *c, int xc, int yc, double r) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_style) return c->fail(LB2D_E_ORDER, "obstacle must follow boundary_style");
+    if (xc < 0 || yc < 0 || xc >= c->nx || yc >= c->ny || !(r >= 0.0) || !std::isfinite(r))
+        return c->fail(LB2D_E_INVAL, "circle centre outside the lattice or bad radius");
+    c->circles.push_back({xc, yc, r});
+    return LB2D_OK;
+}
+
+int lb2d_obstacle_mask(lb2d_ctx *c, const uint8_t *host_mask) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_style) return c->fail(LB2D_E_ORDER, "obstacle must follow boundary_style");
+    if (!host_mask) return c->fail(LB2D_E_INVAL, "null mask");
+    c->host_masks.emplace_back(host_mask, host_mask + c->n());
+    return LB2D_OK;
+}
+
+int lb2d_surface_reaction(lb2d_ctx *c, double kr, double Cs, const char *style, double b0, double bmax,
+                          uint64_t seed) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_solute) return c->fail(LB2D_E_ORDER, "surface_reaction needs the solute command first");
+    if (!style || std::strcmp(style, "growth") != 0) return c->fail(LB2D_E_INVAL, "style must be \"growth\"");
+    if (!(kr >= 0.0) || !std::isfinite(Cs) || !std::isfinite(b0) || std::isnan(bmax))
+        return c->fail(LB2D_E_INVAL, "bad reaction parameters");
+    c->reaction = true;
+    c->kr = kr;
+    c->Cs = Cs;
+    c->b0 = b0;
+    c->bmax = bmax;
+    c->seed = seed;
+    return LB2D_OK;
+}
+
+int lb2d_set_fields(lb2d_ctx *c, int comp, const double *rho, const double *ux, const double *uy) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+    if (!rho) return c->fail(LB2D_E_INVAL, "null density");
+    const size_t n = c->n();
+    for (size_t k = 0; k < n; ++k)
+        if (!(rho[k] > 0.0) || !std::isfinite(rho[k])) return c->fail(LB2D_E_INVAL, "density must be positive");
+    c->rho0[comp].assign(rho, rho + n);
+    if (ux) c->ux0[comp].assign(ux, ux + n); else c->ux0[comp].clear();
+    if (uy) c->uy0[comp].assign(uy, uy + n); else c->uy0[comp].clear();
+    return LB2D_OK;
+}
+
+int lb2d_set_concentration(lb2d_ctx *c, const double *C, const double *ux, const double *uy) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_solute) return c->fail(LB2D_E_ORDER, "concentration0 needs the solute command first");
+    if (!C) return c->fail(LB2D_E_INVAL, "null concentration");
+    const size_t n = c->n();
+    c->C0.assign(C, C + n);
+    if (ux) c->Cux.assign(ux, ux + n); else c->Cux.clear();
+    if (uy) c->Cuy.assign(uy, uy + n); else c->Cuy.clear();
+    return LB2D_OK;
+}
+
+static int add_force(lb2d_ctx *c, int mode, double value, int comp, bool accel) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (mode < 0 || mode > 8) return c->fail(LB2D_E_INVAL, "mode must be 0..8");
+    if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+    if (!std::isfinite(value)) return c->fail(LB2D_E_INVAL, "value must be finite");
+    static const int EXh[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int EYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    double(*dst)[2] = accel ? c->accel : c->force;
+    dst[comp][0] += value * EXh[mode];
+    dst[comp][1] += value * EYh[mode];
+    c->have_force = true;
+    return LB2D_OK;
+}
+
+int lb2d_aveforce(lb2d_ctx *c, int mode, double value, int comp) { return add_force(c, mode, value, comp, false); }
+int lb2d_aveacceleration(lb2d_ctx *c, int mode, double value, int comp) {
+    return add_force(c, mode, value, comp, true);
+}
+
+int lb2d_interforce(lb2d_ctx *c, double G, double psi0, double rho0) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!is_nan(psi0) || !is_nan(rho0) || c->ncomp != 2)
+        return c->fail(LB2D_E_UNSUPPORTED, "only the two-component interforce (psi0, rho0 omitted) is implemented");
+    if (!std::isfinite(G)) return c->fail(LB2D_E_INVAL, "G must be finite");
+    c->inter = true;
+    c->G = G;
+    c->have_force = true;
+    return LB2D_OK;
+}
+
+int lb2d_adhesiveforce(lb2d_ctx *c, double G, double psi0, double rho0, int comp) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!is_nan(psi0) || !is_nan(rho0) || c->ncomp != 2)
+        return c->fail(LB2D_E_UNSUPPORTED,
+                       "only the two-component adhesiveforce (psi0, rho0 omitted) is implemented");
+    if (comp < 0 || comp > 1) return c->fail(LB2D_E_INVAL, "component must be 0 or 1");
+    if (!std::isfinite(G)) return c->fail(LB2D_E_INVAL, "G must be finite");
+    c->ads[comp] = true;
+    c->Gads[comp] = G;
+    c->have_force = true;
+    return LB2D_OK;
+}
+
+int lb2d_workspace_bytes(lb2d_ctx *c, int storage, size_t *bytes) {
+    if (!c || !bytes) return LB2D_E_INVAL;
+    if (!c->have_lattice) return c->fail(LB2D_E_ORDER, "the lattice command must come first");
+    if (storage < kF64 || storage > kBF16) return c->fail(LB2D_E_INVAL, "unknown storage format");
+    if (!c->plain() && (storage == kF16 || storage == kBF16))
+        return c->fail(LB2D_E_UNSUPPORTED, "16-bit storage is implemented for the one-fluid step only");
+    if (c->bound && storage != c->storage) return c->fail(LB2D_E_STATE, "already bound");
+    *bytes = make_layout(c, storage).total;
+    if (!c->bound) {
+        c->storage = storage;
+        c->storage_chosen = true;
+    }
+    return LB2D_OK;
+}
+
+int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
+    if (!c) return LB2D_E_INVAL;
+    if (c->bound) return c->fail(LB2D_E_STATE, "already bound");
+    if (!c->have_lattice) return c->fail(LB2D_E_ORDER, "the lattice command must come first");
+    if (!c->storage_chosen) return c->fail(LB2D_E_ORDER, "call lb2d_workspace_bytes before lb2d_bind");
+    if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0)
+        return c->fail(LB2D_E_INVAL, "workspace must be a 256-byte aligned device pointer");
+    if ((c->open_style[0] != 0) != (c->open_style[1] != 0))
+        return c->fail(LB2D_E_INVAL, "solute openings come in pairs (xlo and xhi)");
+    const Layout L = make_layout(c, c->storage);
+    if (bytes < L.total) return c->fail(LB2D_E_SIZE, "workspace of %zu bytes, %zu needed", bytes, L.total);
+    HIPCHK(c, hipSetDevice(c->device));
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != c->device) {
+        (void)hipGetLastError();
+        return c->fail(LB2D_E_INVAL, "workspace is not device memory of device %d", c->device);
+    }
+    c->ws = (char *)dev_ptr;
+    c->ws_bytes = bytes;
+    c->stream = (hipStream_t)hip_stream;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < c->ncomp; ++k) c->f[p][k] = c->ws + L.f[p][k];
+    for (int p = 0; p < 2; ++p) c->g[p] = c->q ? (void *)(c->ws + L.g[p]) : nullptr;
+    c->mask = (uint8_t *)(c->ws + L.mask);
+    c->trig = (uint8_t *)(c->ws + L.trig);
+    c->b = c->reaction ? (double *)(c->ws + L.b) : nullptr;
+    c->staging = (double *)(c->ws + L.staging);
+    c->staging_doubles = L.staging_doubles;
+    c->partial = (double *)(c->ws + L.partial);
+    c->gpartial = (double *)(c->ws + L.gpartial);
+    c->totals = (double *)(c->ws + L.totals);
+    c->ticket = (unsigned *)(c->ws + L.ticket);
+    c->dstep = (long long *)(c->ws + L.dstep);
+    const size_t n = c->n();
+    hipStream_t s = c->stream;
+
+    // a1: obstacles -> mask
+    HIPCHK(c, launch_fill_u8(c->mask, 0, n, s));
+    HIPCHK(c, launch_fill_u8(c->trig, 0, n, s));
+    for (const auto &hm : c->host_masks) {
+        HIPCHK(c, hipMemcpyAsync(c->staging, hm.data(), n, hipMemcpyHostToDevice, s));
+        HIPCHK(c, launch_or_mask(c->mask, (const uint8_t *)c->staging, n, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (!c->circles.empty()) {
+        std::vector<int> cxy(2 * c->circles.size());
+        std::vector<double> cr(c->circles.size());
+        for (size_t k = 0; k < c->circles.size(); ++k) {
+            cxy[2 * k] = c->circles[k].xc;
+            cxy[2 * k + 1] = c->circles[k].yc;
+            cr[k] = c->circles[k].r;
+        }
+        double *dr = c->staging;
+        int *dxy = (int *)(c->staging + cr.size());
+        HIPCHK(c, hipMemcpyAsync(dr, cr.data(), cr.size() * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(dxy, cxy.data(), cxy.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(c, launch_raster_circles(c->mask, c->nx, c->ny, dxy, dr, (int)c->circles.size(), s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (!c->rects.empty()) {
+        std::vector<int> rr(4 * c->rects.size());
+        for (size_t k = 0; k < c->rects.size(); ++k) {
+            rr[4 * k] = c->rects[k].x0;
+            rr[4 * k + 1] = c->rects[k].x1;
+            rr[4 * k + 2] = c->rects[k].y0;
+            rr[4 * k + 3] = c->rects[k].y1;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->staging, rr.data(), rr.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(c, launch_raster_rects(c->mask, c->nx, (const int *)c->staging, (int)c->rects.size(), s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    // a2: populations at equilibrium of the initial fields
+    for (int k = 0; k < c->ncomp; ++k) {
+        const double rr = c->rho0[k].empty() ? 1.0 : mean_of(c->rho0[k]);
+        c->rho_ref[k] = (double)(float)rr;
+        int e;
+        if ((e = upload(c, c->staging, c->rho0[k], 1.0))) return e;
+        if ((e = upload(c, c->staging + n, c->ux0[k], 0.0))) return e;
+        if ((e = upload(c, c->staging + 2 * n, c->uy0[k], 0.0))) return e;
+        HIPCHK(c, launch_init_fluid(c->storage, c->f[0][k], c->staging, c->staging + n, c->staging + 2 * n, n,
+                                    2.25 * c->alpha[k], 1.8 * (1.0 - c->alpha[k]), c->rho_ref[k], s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (c->q) {
+        int e;
+        if ((e = upload(c, c->staging, c->C0, 0.0))) return e;
+        if ((e = upload(c, c->staging + n, c->Cux, 0.0))) return e;
+        if ((e = upload(c, c->staging + 2 * n, c->Cuy, 0.0))) return e;
+        HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
+    HIPCHK(c, launch_fill_f64(c->totals, 0.0, 16, s));
+    HIPCHK(c, launch_fill_u8((uint8_t *)c->ticket, 0, 8, s));
+    HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->t = 0;
+    c->bound = true;
+    return LB2D_OK;
+}
+
+int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
+    if (!c) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "bind the lattice before iteration");
+    if (nsteps < 0) return c->fail(LB2D_E_INVAL, "nsteps must be >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    int64_t left = nsteps;
+    if (c->timing) {
+        // one launch at a time, the dominant (step) kernel bracketed by events
+        for (; left > 0; --left) {
+            const int parity = (int)(c->t & 1);
+            HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+            if (c->plain()) {
+                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->plain_bx, c->plain_by, c->stream));
+                HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+            } else {
+                const FullParams p = full_params(c);
+                HIPCHK(c, launch_full(c->storage, p, parity, c->sc(), c->q != 0, c->reaction, c->stream));
+                HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+                if (c->q) HIPCHK(c, launch_growth(c->storage, p, parity ^ 1, c->reaction, c->stream));
+            }
+            HIPCHK(c, hipEventSynchronize(c->ev1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            c->kernel_ms += ms;
+            c->kernel_launches += 1;
+            c->t += 1;
+        }
+        return LB2D_OK;
+    }
+    if ((c->t & 1) && left > 0) {
+        HIPCHK(c, enqueue_step(c, 1, c->stream));
+        c->t += 1;
+        --left;
+    }
+    if (left >= kGraphSteps) {
+        int rc = build_graph(c);
+        if (rc) return rc;
+        while (left >= kGraphSteps) {
+            HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+            c->t += kGraphSteps;
+            left -= kGraphSteps;
+        }
+    }
+    for (; left > 0; --left) {
+        HIPCHK(c, enqueue_step(c, (int)(c->t & 1), c->stream));
+        c->t += 1;
+    }
+    return LB2D_OK;
+}
+
+int lb2d_moments(lb2d_ctx *c, int comp, double *rho, double *ux, double *uy) {
+    if (!c || !rho || !ux || !uy) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    if (comp < -1 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = c->n();
+    const FullParams p = full_params(c);
+    HIPCHK(c, launch_moments(c->storage, p, (int)(c->t & 1), comp, c->staging, c->staging + n,
+                             c->staging + 2 * n, c->stream));
+    HIPCHK(c, hipMemcpyAsync(rho, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ux, c->staging + n, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(uy, c->staging + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_solute_state(lb2d_ctx *c, double *C, double *b) {
+    if (!c) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    if (!c->q) return c->fail(LB2D_E_ORDER, "no solute in this lattice");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = c->n();
+    const FullParams p = full_params(c);
+    HIPCHK(c, launch_solute_state(c->storage, p, (int)(c->t & 1), c->reaction ? 1 : 0, c->staging,
+                                  c->staging + n, c->stream));
+    if (C) HIPCHK(c, hipMemcpyAsync(C, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (b) HIPCHK(c, hipMemcpyAsync(b, c->staging + n, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_mask(lb2d_ctx *c, uint8_t *m) {
+    if (!c || !m) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(m, c->mask, c->n(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_budgets(lb2d_ctx *c, double *out) {
+    if (!c || !out) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    HIPCHK(c, hipSetDevice(c->device));
+    const FullParams p = full_params(c);
+    double *part = c->staging;
+    double *out8 = c->staging + (size_t)c->ny * 8;
+    HIPCHK(c, launch_budgets(c->storage, p, (int)(c->t & 1), c->q ? 1 : 0, c->reaction ? 1 : 0, part, out8,
+                             c->stream));
+    double v8[8], tot[16];
+    HIPCHK(c, hipMemcpyAsync(v8, out8, sizeof(v8), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(tot, c->totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < LB2D_NBUDGET; ++k) out[k] = 0.0;
+    out[LB2D_B_MASS0] = v8[0];
+    out[LB2D_B_MASS1] = v8[1];
+    out[LB2D_B_MOMX] = v8[2];
+    out[LB2D_B_MOMY] = v8[3];
+    out[LB2D_B_SOLUTE] = v8[4];
+    out[LB2D_B_DEPOSIT] = v8[5];
+    out[LB2D_B_FLUID] = v8[6];
+    out[LB2D_B_REMOVED0] = tot[6];
+    out[LB2D_B_REMOVED1] = tot[7];
+    out[LB2D_B_REMOVED_C] = tot[8];
+    out[LB2D_B_INFLOW] = tot[9];
+    out[LB2D_B_OUTFLOW] = tot[10];
+    out[LB2D_B_GROWN] = tot[12];
+    out[LB2D_B_CONSUMED] = tot[14];
+    out[LB2D_B_STEPS] = (double)c->t;
+    return LB2D_OK;
+}
+
+static int pop_target(lb2d_ctx *c, int comp, void **buf, double *ref) {
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    const int parity = (int)(c->t & 1);
+    if (comp == -1) {
+        if (!c->q) return c->fail(LB2D_E_INVAL, "no solute in this lattice");
+        *buf = c->g[parity];
+        *ref = 0.0;
+    } else {
+        if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+        *buf = c->f[parity][comp];
+        *ref = c->rho_ref[comp];
+    }
+    return LB2D_OK;
+}
+
+static const double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
+    if (!c || !out) return LB2D_E_INVAL;
+    void *buf;
+    double ref;
+    int rc = pop_target(c, comp, &buf, &ref);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = c->n();
+    for (int i = 0; i < 9; ++i) {
+        HIPCHK(c, launch_decode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LB2D_OK;
+}
+
+int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
+    if (!c || !in) return LB2D_E_INVAL;
+    void *buf;
+    double ref;
+    int rc = pop_target(c, comp, &buf, &ref);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = c->n();
+    for (int i = 0; i < 9; ++i) {
+        HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LB2D_OK;
+}
+
+int lb2d_get_deposit(lb2d_ctx *c, double *b) {
+    if (!c || !b) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    if (!c->reaction) return c->fail(LB2D_E_ORDER, "no surface reaction in this lattice");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(b, c->b, c->n() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_set_deposit(lb2d_ctx *c, const double *b) {
+    if (!c || !b) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    if (!c->reaction) return c->fail(LB2D_E_ORDER, "no surface reaction in this lattice");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->b, b, c->n() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_set_mask(lb2d_ctx *c, const uint8_t *m) {
+    if (!c || !m) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->mask, m, c->n(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fill_u8(c->trig, 0, c->n(), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_step_count(lb2d_ctx *c, int64_t *t) {
+    if (!c || !t) return LB2D_E_INVAL;
+    *t = c->t;
+    return LB2D_OK;
+}
+
+int lb2d_set_timing(lb2d_ctx *c, int on) {
+    if (!c) return LB2D_E_INVAL;
+    if (on && !c->ev0) {
+        HIPCHK(c, hipSetDevice(c->device));
+        HIPCHK(c, hipEventCreate(&c->ev0));
+        HIPCHK(c, hipEventCreate(&c->ev1));
+    }
+    c->timing = on != 0;
+    c->kernel_ms = 0.0;
+    c->kernel_launches = 0;
+    return LB2D_OK;
+}
+
+int lb2d_kernel_time(lb2d_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return LB2D_E_INVAL;
+    *launches = c->kernel_launches;
+    *ms = c->kernel_launches ? c->kernel_ms / (double)c->kernel_launches : 0.0;
+    return LB2D_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+int lb2d_batch_create(lb2d_batch **out, int hip_device) {
+    if (!out || hip_device < 0) return LB2D_E_INVAL;
+    lb2d_batch *b = new lb2d_batch();
+    b->device = hip_device;
+    *out = b;
+    return LB2D_OK;
+}
+
+int lb2d_batch_destroy(lb2d_batch *b) {
+    if (!b) return LB2D_E_INVAL;
+    if (b->graph || b->cap_stream) {
+        (void)hipSetDevice(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    }
+    delete b;
+    return LB2D_OK;
+}
+
+const char *lb2d_batch_last_error(const lb2d_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int lb2d_batch_add(lb2d_batch *b, lb2d_ctx *c) {
+    if (!b || !c) return LB2D_E_INVAL;
+    if (b->final_) return b->fail(LB2D_E_STATE, "batch already finalized");
+    if (!c->bound) return b->fail(LB2D_E_STATE, "lattices must be bound before lb2d_batch_add");
+    if (!c->plain()) return b->fail(LB2D_E_UNSUPPORTED, "batches hold one-fluid lattices without solute");
+    if (c->device != b->device) return b->fail(LB2D_E_INVAL, "lattice on another device");
+    if (!b->lat.empty()) {
+        if (c->storage != b->storage) return b->fail(LB2D_E_INVAL, "all lattices need the same storage format");
+        if ((c->t & 1) != (b->lat[0]->t & 1)) return b->fail(LB2D_E_STATE, "lattices at different step parity");
+    }
+    for (auto *o : b->lat)
+        if (o == c) return b->fail(LB2D_E_INVAL, "lattice added twice");
+    b->storage = c->storage;
+    b->lat.push_back(c);
+    return LB2D_OK;
+}
+
+static size_t tiles_for(const lb2d_batch *b, int w, int h) {
+    size_t n = 0;
+    for (auto *c : b->lat) n += (size_t)((c->nx + w - 1) / w) * ((c->ny + h - 1) / h);
+    return n;
+}
+
+int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
+    if (!b || !bytes) return LB2D_E_INVAL;
+    if (b->lat.empty()) return b->fail(LB2D_E_STATE, "empty batch");
+    const size_t tiles = tiles_for(b, 32, 4);  // smallest tile the tuner tries
+    *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile));
+    return LB2D_OK;
+}
+
+
+static int batch_upload_tiles(lb2d_batch *b, int w, int h, int sched) {
+    std::vector<Tile> t = make_tiles(b, w, h, sched);
+    if (t.size() > b->max_tiles) return b->fail(LB2D_E_SIZE, "tile table too large");
+    HIPCHK(b, hipMemcpyAsync(b->d_tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    b->ntiles = (int)t.size();
+    return LB2D_OK;
+}
+
+int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_stream, const char *cache) {
+    if (!b) return LB2D_E_INVAL;
+    if (b->final_) return b->fail(LB2D_E_STATE, "batch already finalized");
+    size_t need = 0;
+    int rc = lb2d_batch_workspace_bytes(b, &need);
+    if (rc) return rc;
+    if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0) return b->fail(LB2D_E_INVAL, "bad workspace pointer");
+    if (bytes < need) return b->fail(LB2D_E_SIZE, "workspace of %zu bytes, %zu needed", bytes, need);
+    HIPCHK(b, hipSetDevice(b->device));
+    b->ws = (char *)dev_ptr;
+    b->ws_bytes = bytes;
+    b->stream = (hipStream_t)hip_stream;
+    b->d_lat = (PlainLattice *)b->ws;
+    b->d_tiles = (Tile *)(b->ws + align_up(b->lat.size() * sizeof(PlainLattice)));
+    b->max_tiles = tiles_for(b, 32, 4);
+    std::vector<PlainLattice> L;
+    for (auto *c : b->lat) L.push_back(plain_lattice(c));
+    HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    int cus = 256;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    const std::string key = batch_key(b);
+    bool have = false;
+    if (cache) {
+        FILE *fh = std::fopen(cache, "r");
+        if (fh) {
+            char k[64] = {0};
+            int w, h, s, p;
+            if (std::fscanf(fh, "{\"key\": \"%63[0-9a-f]\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
+                                "\"blocks_per_cu\": %d}",
+                            k, &w, &h, &s, &p) == 5 &&
+                key == k && w > 0 && h > 0 && w * h <= 1024 && w * h >= 64 && s >= 0 && s <= 2 && p >= 0) {
+                b->tile_w = w;
+                b->tile_h = h;
+                b->schedule = s;
+                b->bpc = p;
+                have = true;
+            }
+            std::fclose(fh);
+        }
+    }
+    if (!have) {
+        // timed trial steps: each writes the lattices' next buffers from the
+        // current ones without advancing, so the state is unchanged
+        const TuneCand cands[] = {{64, 4, 0, 0},  {128, 2, 0, 0}, {256, 1, 0, 0}, {64, 8, 0, 0},
+                                  {128, 4, 0, 0}, {32, 8, 0, 0},  {64, 4, 1, 8},  {128, 2, 1, 8},
+                                  {256, 1, 1, 8}, {64, 4, 2, 8},  {128, 2, 2, 8}, {64, 4, 1, 16},
+                                  {128, 2, 1, 16}, {256, 1, 0, 16}};
+        hipEvent_t e0, e1;
+        HIPCHK(b, hipEventCreate(&e0));
+        HIPCHK(b, hipEventCreate(&e1));
+        const int parity = (int)(b->lat[0]->t & 1);
+        float best = 1e30f;
+        TuneCand bc = cands[0];
+        for (const auto &cd : cands) {
+            if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
+            const int grid = batch_grid(b->ntiles, cd.bpc, cus);
+            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, cd.w, cd.h, grid, b->stream));
+            HIPCHK(b, hipEventRecord(e0, b->stream));
+            for (int r = 0; r < 3; ++r)
+                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, cd.w, cd.h, grid,
+                                       b->stream));
+            HIPCHK(b, hipEventRecord(e1, b->stream));
+            HIPCHK(b, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bc = cd;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->tile_w = bc.w;
+        b->tile_h = bc.h;
+        b->schedule = bc.sched;
+        b->bpc = bc.bpc;
+    }
+    if ((rc = batch_upload_tiles(b, b->tile_w, b->tile_h, b->schedule))) return rc;
+    b->grid = batch_grid(b->ntiles, b->bpc, cus);
+    if (cache) {
+        FILE *fh = std::fopen(cache, "w");
+        if (fh) {
+            std::fprintf(fh,
+                         "{\"key\": \"%s\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
+                         "\"blocks_per_cu\": %d}\n",
+                         key.c_str(), b->tile_w, b->tile_h, b->schedule, b->bpc);
+            std::fclose(fh);
+        }
+    }
+    b->t = b->lat[0]->t;
+    b->final_ = true;
+    return LB2D_OK;
+}
+
+static hipError_t batch_step(lb2d_batch *b, int parity, hipStream_t s) {
+    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->tile_w, b->tile_h, b->grid, s);
+}
+
+int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
+    if (!b) return LB2D_E_INVAL;
+    if (!b->final_) return b->fail(LB2D_E_STATE, "finalize the batch first");
+    if (nsteps < 0) return b->fail(LB2D_E_INVAL, "nsteps must be >= 0");
+    for (auto *c : b->lat)
+        if (c->t != b->t) return b->fail(LB2D_E_STATE, "a lattice of the batch was advanced on its own");
+    HIPCHK(b, hipSetDevice(b->device));
+    int64_t left = nsteps;
+    if ((b->t & 1) && left > 0) {
+        HIPCHK(b, batch_step(b, 1, b->stream));
+        b->t += 1;
+        --left;
+    }
+    if (left >= kGraphSteps && !b->graph) {
+        if (!b->cap_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = batch_step(b, k & 1, b->cap_stream);
+        hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess) return b->fail(LB2D_E_HIP, "batch graph capture failed");
+        HIPCHK(b, hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0));
+        HIPCHK(b, hipGraphDestroy(gr));
+    }
+    while (left >= kGraphSteps) {
+        HIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+        b->t += kGraphSteps;
+        left -= kGraphSteps;
+    }
+    for (; left > 0; --left) {
+        HIPCHK(b, batch_step(b, (int)(b->t & 1), b->stream));
+        b->t += 1;
+    }
+    for (auto *c : b->lat) c->t = b->t;
+    return LB2D_OK;
+}
+
+int lb2d_batch_config(lb2d_batch *b, int *w, int *h, int *s, int *p) {
+    if (!b || !w || !h || !s || !p) return LB2D_E_INVAL;
+    if (!b->final_) return b->fail(LB2D_E_STATE, "not finalized");
+    *w = b->tile_w;
+    *h = b->tile_h;
+    *s = b->schedule;
+    *p = b->bpc;
+    return LB2D_OK;
+}
+
+// Measures a plain device-to-device copy of `bytes` (read + write) on the
+// stream and returns the average milliseconds per copy over `reps` (not a
+// paper command: the practical bandwidth ceiling next to the stencil).
+int lb2d_copy_bench(void *src, void *dst, size_t bytes, int reps, void *hip_stream, double *ms) {
+    if (!src || !dst || !ms || reps < 1 || bytes == 0 || bytes % 16) return LB2D_E_INVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB2D_E_HIP;
+    if (launch_copy(src, dst, bytes, s) != hipSuccess) return LB2D_E_HIP;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(src, dst, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return e == hipSuccess ? LB2D_OK : LB2D_E_HIP;
+}
+
+}  // extern "C"

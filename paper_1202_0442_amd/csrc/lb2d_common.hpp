@@ -1,0 +1,66 @@
+// lb2d_common.hpp -- parameter blocks shared by the host runtime and the
+// gfx950 kernels of the D2Q9 lattice Boltzmann library.  Plain structs only.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace lb2d {
+
+// Storage formats (same values as LB2D_F64 ... in include/lb2d.h).
+enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+// One single-fluid lattice for the plain fused step (and for one entry of
+// the batched step).  Populations live in two buffers (two-lattice pull
+// scheme); f[p] holds [9][ny][nx] deviations f_i - w_i rho_ref.
+struct PlainLattice {
+    void *f[2];
+    const uint8_t *mask;  // 1 = solid, [ny][nx]
+    int nx, ny;
+    double omega;         // 1 / tau
+    double tau;
+    double Fx, Fy;        // aveforce (summed vector)
+    double ax, ay;        // aveacceleration (summed vector)
+    double rho_ref;       // shift of the stored populations
+};
+
+// Tile of the batched step: lattice index and lower-left node.
+struct Tile {
+    int lattice;
+    int x0, y0;
+    int pad;
+};
+
+// Everything the general fused step needs: up to two fluid components with
+// Shan-Chen cohesion / adhesion and an optional D2Q9 solute with openings,
+// a reactive surface, FP64 deposits and growth triggers.
+struct FullParams {
+    void *f[2][2];        // [parity][component] fluid populations
+    void *g[2];           // [parity] solute populations (deviation from 0)
+    uint8_t *mask;        // 1 = solid
+    uint8_t *trig;        // growth trigger: 0 or 1..4 = direction to grow
+    double *b;            // deposits, FP64, [ny][nx]
+    double *partial;      // per-block tallies of the step kernel [nblk][4]
+    double *gpartial;     // per-block tallies of the growth kernel [nblk][4]
+    double *totals;       // running FP64 tallies (LB2D_B_* indices)
+    unsigned *ticket;     // last-block counter of the growth kernel
+    long long *dstep;     // completed steps (device copy)
+    int nx, ny;
+    int ncomp;
+    double tau[2], omega[2];
+    double A0[2], A1[2];  // equilibrium coefficients A_0, A_{1..8}
+    double rho_ref[2];
+    double force[2][2], accel[2][2];
+    double G;             // interforce (two components)
+    double Gads[2];       // adhesiveforce per component (0 = off)
+    int has_ads;
+    double tau_s, omega_s;
+    int solute_xper;      // 1: solute periodic in x
+    int open_style[2];    // xlo, xhi: 1 dirichlet, 2 adiabatic
+    double open_value[2];
+    double kr, Cs, b0, bmax;
+    unsigned long long seed;
+    int nblk_main;        // blocks of the step kernel
+    int nblk_grow;        // blocks of the growth kernel
+};
+
+}  // namespace lb2d

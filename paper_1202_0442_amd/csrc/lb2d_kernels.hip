@@ -1,0 +1,1086 @@
+// lb2d_kernels.hip -- gfx950 kernels of the D2Q9 lattice Boltzmann library.
+//
+// Method: "Introduction to Perl module lb2d.pm 0.1 for basic Lattice
+// Boltzmann simulations" (D. Sergi, arXiv:1202.0442), Sec. "Model and
+// algorithm" (Eq. (lb), Eq. (eq), Fig. "algorithm") and the commands
+// fluids, solute, boundary_style (noslip), obstacle, surface_reaction,
+// inlet_solute/outlet_solute, aveforce, aveacceleration, interforce,
+// adhesiveforce, thermo and output.
+//
+// Design (bandwidth-bound stencil, no matrix cores):
+//  * populations are SoA planes [9][ny][nx] (x fastest) in two buffers; a
+//    step pulls f_i from x - e_i in buffer p and writes buffer p^1, so every
+//    load and store of a wavefront is a contiguous row segment;
+//  * half-way bounce-back is a per-lane address select: when x - e_i is
+//    solid the lane reads its own opposite population instead;
+//  * one fused pass per step does stream, moments, forces, equilibrium and
+//    BGK relaxation (and, in the general kernel, the solute step, reactive
+//    links and deposit gathering); solid nodes are skipped entirely;
+//  * Shan-Chen cohesion needs the post-stream densities of the 8
+//    neighbours: the general kernel computes a (TX+2) x (TY+2) density tile
+//    in LDS, pulling the halo nodes' populations again (they come from L2),
+//    and maps tiles to XCDs in contiguous bands so neighbouring tiles share
+//    an L2;
+//  * deposits are gathered by the solid node's own thread (no atomics);
+//    growth is decided there and applied by a separate gather kernel;
+//  * every FP64 tally is a fixed-order block reduction followed by a
+//    fixed-order sum of the block partials, so results are bitwise
+//    reproducible.
+#include <hip/hip_runtime.h>
+
+#include "lb2d_common.hpp"
+#include "lb2d_kernels.hpp"
+
+namespace lb2d {
+namespace {
+
+// ----------------------------------------------------------------- lattice
+
+__host__ __device__ constexpr int ex(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 5 + 2) % 4) + 5);
+}
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp");
+// x-mirror (ex -> -ex): 1<->3, 5<->6, 7<->8.
+__host__ __device__ constexpr int mirx(int i) {
+    return i == 1 ? 3 : i == 3 ? 1 : i == 5 ? 6 : i == 6 ? 5 : i == 7 ? 8 : i == 8 ? 7 : i;
+}
+// Eq. (eq) weights.
+template <typename R>
+__host__ __device__ constexpr R wgt(int i) {
+    return i == 0 ? R(4.0 / 9.0) : (i <= 4 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+}
+
+// ----------------------------------------------------------------- storage
+
+struct bf16s {
+    uint16_t u;
+};
+
+template <typename S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using R = double;
+    __device__ static double dec(double v, int) { return v; }
+    __device__ static double enc(double v, int) { return v; }
+};
+template <>
+struct Codec<float> {
+    using R = float;
+    __device__ static float dec(float v, int) { return v; }
+    __device__ static float enc(float v, int) { return v; }
+};
+// 16-bit formats: deviation times 2 (rest), 8 (axis), 32 (diagonal), which
+// brings all nine to a similar magnitude, then rounded to nearest even.
+__host__ __device__ constexpr float scale16(int i) { return i == 0 ? 2.0f : (i <= 4 ? 8.0f : 32.0f); }
+__host__ __device__ constexpr float iscale16(int i) { return i == 0 ? 0.5f : (i <= 4 ? 0.125f : 0.03125f); }
+template <>
+struct Codec<_Float16> {
+    using R = float;
+    __device__ static float dec(_Float16 v, int i) { return (float)v * iscale16(i); }
+    __device__ static _Float16 enc(float d, int i) { return (_Float16)(d * scale16(i)); }
+};
+template <>
+struct Codec<bf16s> {
+    using R = float;
+    __device__ static float dec(bf16s v, int i) {
+        return __uint_as_float((uint32_t)v.u << 16) * iscale16(i);
+    }
+    __device__ static bf16s enc(float d, int i) {
+        // round to nearest even on the upper 16 bits (NaN stays NaN)
+        uint32_t u = __float_as_uint(d * scale16(i));
+        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16s{(uint16_t)((u >> 16) | 0x40u)};
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return bf16s{(uint16_t)(u >> 16)};
+    }
+};
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+// Deterministic block sum of K doubles per thread into out[0..K) (valid in
+// thread 0).  `sh` must hold blockDim.x * blockDim.y * K doubles... to keep
+// LDS small the reduction goes through wavefront shuffles first.
+template <int K>
+__device__ void block_sum(double (&v)[K], double *sh, double *out) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthr = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wid = tid >> 6, nw = (nthr + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double a = v[k];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        v[k] = a;
+    }
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sh[wid * K + k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < K; ++k) {
+            double a = 0.0;
+            for (int w = 0; w < nw; ++w) a += sh[w * K + k];
+            out[k] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------- plain fused step
+
+// One node of the single-fluid step: pull with half-way bounce-back,
+// moments, velocity-shift forcing, BGK relaxation to Eq. (eq), store.
+// Populations are deviations d_i = f_i - w_i rho_ref, so
+// rho = rho_ref + sum d_i and j = sum d_i e_i; the equilibrium deviation is
+// w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)].
+template <typename S>
+__device__ __forceinline__ void plain_node(const PlainLattice &L, int parity, int x, int y) {
+    using C = Codec<S>;
+    using R = typename C::R;
+    const int nx = L.nx, ny = L.ny;
+    const size_t plane = (size_t)nx * ny;
+    const size_t s = (size_t)y * nx + x;
+    const uint8_t *__restrict__ m = L.mask;
+    if (m[s]) return;
+    const S *__restrict__ fin = (const S *)L.f[parity];
+    S *__restrict__ fout = (S *)L.f[parity ^ 1];
+
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const size_t rm = (size_t)((y == 0) ? ny - 1 : y - 1) * nx;
+    const size_t r0 = (size_t)y * nx;
+    const size_t rp = (size_t)((y == ny - 1) ? 0 : y + 1) * nx;
+    // source node x - e_i of each direction
+    const size_t src[9] = {s,       r0 + xm, rm + x,  r0 + xp, rp + x,
+                           rm + xm, rm + xp, rp + xp, rp + xm};
+    R d[9];
+    d[0] = C::dec(fin[s], 0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const bool wall = m[src[i]] != 0;
+        const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
+        d[i] = C::dec(fin[a], i);
+    }
+    R drho = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        drho += d[i];
+        if (ex(i)) jx += ex(i) > 0 ? d[i] : -d[i];
+        if (ey(i)) jy += ey(i) > 0 ? d[i] : -d[i];
+    }
+    const R rho = R(L.rho_ref) + drho;
+    const R tau = R(L.tau), omega = R(L.omega);
+    const R Fx = R(L.Fx) + rho * R(L.ax);
+    const R Fy = R(L.Fy) + rho * R(L.ay);
+    const R inv = R(1) / rho;
+    const R ux = (jx + tau * Fx) * inv;
+    const R uy = (jy + tau * Fy) * inv;
+    const R usq = R(1.5) * (ux * ux + uy * uy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
+        const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
+        fout[(size_t)i * plane + s] = C::enc(d[i] + omega * (deq - d[i]), i);
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(1024) k_plain(PlainLattice L, int parity) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= L.nx || y >= L.ny) return;
+    plain_node<S>(L, parity, x, y);
+}
+
+// Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
+// independent lattices; `persistent` grids stride over the table.
+template <typename S>
+__global__ void __launch_bounds__(1024) k_batch(const PlainLattice *__restrict__ lat,
+                                               const Tile *__restrict__ tiles, int ntiles,
+                                               int parity) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const PlainLattice L = lat[tl.lattice];
+        const int x = tl.x0 + threadIdx.x;
+        const int y = tl.y0 + threadIdx.y;
+        if (x < L.nx && y < L.ny) plain_node<S>(L, parity, x, y);
+    }
+}
+
+// --------------------------------------------------------- general step
+
+constexpr int kTX = 64;   // tile width = one wavefront
+constexpr int kTY = 8;    // tile height
+
+template <typename S>
+__device__ __forceinline__ typename Codec<S>::R ldpop(const S *__restrict__ f, size_t a, int i) {
+    return Codec<S>::dec(f[a], i);
+}
+
+// Reactive half-way link (surface_reaction command, generalised per link):
+// k_i = kr w_i / (1/6); C_i = (2 g_out + k_i Cs) / (2 w_i + k_i);
+// returning population 2 w_i C_i - g_out; deposit g_out - g_in if positive,
+// otherwise plain bounce-back.
+template <typename R>
+__device__ __forceinline__ R reactive_link(int i, R kr, R Cs, R g_out, R &g_in) {
+    const R w = wgt<R>(i);
+    const R k = kr * w * R(6);
+    const R Ci = (R(2) * g_out + k * Cs) / (R(2) * w + k);
+    R gi = R(2) * w * Ci - g_out;
+    R db = g_out - gi;
+    if (!(db > R(0))) {
+        gi = g_out;
+        db = R(0);
+    }
+    g_in = gi;
+    return db;
+}
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Maps the linear block id to a tile so that each XCD (blocks are dealt
+// round-robin over 8 XCDs) works on one contiguous band of tile rows.
+__device__ __forceinline__ int xcd_band(int b, int nblk) {
+    const int per = nblk / 8, rem = nblk % 8;
+    const int xcd = b % 8, k = b / 8;
+    // the first `rem` XCDs take one extra tile
+    const int start = xcd * per + (xcd < rem ? xcd : rem);
+    const int len = per + (xcd < rem ? 1 : 0);
+    return (k < len) ? start + k : -1;
+}
+
+template <typename S, int NC, bool SC, bool SOL, bool REACT>
+__global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
+    using C = Codec<S>;
+    using R = typename C::R;
+    __shared__ uint8_t smask[kTY + 4][kTX + 4];
+    __shared__ R srho[SC ? NC : 1][kTY + 2][kTX + 2];
+    __shared__ double sred[(kTX * kTY / 64) * 4];
+
+    const int nx = p.nx, ny = p.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int tiles_x = (nx + kTX - 1) / kTX;
+    const int nblk = gridDim.x;
+    int tile = xcd_band(blockIdx.x, nblk);
+    if (tile < 0) tile = blockIdx.x;  // (never: launch uses nblk tiles)
+    const int tx0 = (tile % tiles_x) * kTX, ty0 = (tile / tiles_x) * kTY;
+    const int tid = threadIdx.x;
+    const int lx = tid % kTX, ly = tid / kTX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool valid = (x < nx) && (y < ny);
+
+    // mask tile with a two-node halo (periodic wrap)
+    for (int k = tid; k < (kTX + 4) * (kTY + 4); k += kTX * kTY) {
+        const int hx = k % (kTX + 4), hy = k / (kTX + 4);
+        const int gx = wrapi(tx0 + hx - 2, nx), gy = wrapi(ty0 + hy - 2, ny);
+        smask[hy][hx] = p.mask[(size_t)gy * nx + gx];
+    }
+    __syncthreads();
+
+    const bool solid = !valid || smask[ly + 2][lx + 2];
+    const size_t s = valid ? (size_t)y * nx + x : 0;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x >= nx - 1) ? 0 : x + 1;
+    const size_t rm = (size_t)((y == 0) ? ny - 1 : y - 1) * nx;
+    const size_t r0 = (size_t)y * nx;
+    const size_t rp = (size_t)((y >= ny - 1) ? 0 : y + 1) * nx;
+    const size_t src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+
+    // 1. pull both components at the own node
+    R d[NC][9];
+    R drho[NC], jx[NC], jy[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        drho[c] = jx[c] = jy[c] = R(0);
+        if (!solid) {
+            const S *__restrict__ fin = (const S *)p.f[parity][c];
+            d[c][0] = ldpop(fin, s, 0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
+                const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
+                d[c][i] = ldpop(fin, a, i);
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                drho[c] += d[c][i];
+                if (ex(i)) jx[c] += ex(i) > 0 ? d[c][i] : -d[c][i];
+                if (ey(i)) jy[c] += ey(i) > 0 ? d[c][i] : -d[c][i];
+            }
+        }
+    }
+
+    // 2. density tile for the cohesion stencil: own nodes from registers,
+    // halo (and wrapped ragged-edge) nodes pulled again.
+    if constexpr (SC) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : R(p.rho_ref[c]) + drho[c];
+        for (int k = tid; k < (kTX + 2) * (kTY + 2); k += kTX * kTY) {
+            const int hx = k % (kTX + 2), hy = k / (kTX + 2);
+            const bool inner = hx >= 1 && hx <= kTX && hy >= 1 && hy <= kTY;
+            if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
+            const int gx = wrapi(tx0 + hx - 1, nx), gy = wrapi(ty0 + hy - 1, ny);
+            const bool hsolid = smask[hy + 1][hx + 1] != 0;
+            R rr[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) rr[c] = R(0);
+            if (!hsolid) {
+                const size_t hs = (size_t)gy * nx + gx;
+                const int gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx == nx - 1) ? 0 : gx + 1;
+                const size_t hrm = (size_t)((gy == 0) ? ny - 1 : gy - 1) * nx;
+                const size_t hr0 = (size_t)gy * nx;
+                const size_t hrp = (size_t)((gy == ny - 1) ? 0 : gy + 1) * nx;
+                const size_t hsrc[9] = {hs,         hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
+                                        hrm + gxm, hrm + gxp, hrp + gxp, hrp + gxm};
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const S *__restrict__ fin = (const S *)p.f[parity][c];
+                    R acc = ldpop(fin, hs, 0);
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        const bool wall = smask[hy + 1 - ey(i)][hx + 1 - ex(i)] != 0;
+                        const size_t a = wall ? (size_t)opp(i) * plane + hs : (size_t)i * plane + hsrc[i];
+                        acc += ldpop(fin, a, i);
+                    }
+                    rr[c] = R(p.rho_ref[c]) + acc;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = rr[c];
+        }
+        __syncthreads();
+    }
+
+    double tal[4] = {0.0, 0.0, 0.0, 0.0};  // inflow, outflow, consumed deposit
+    if (valid && !solid) {
+        // 3. forces
+        R rho[NC], Fx[NC], Fy[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            rho[c] = R(p.rho_ref[c]) + drho[c];
+            Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
+            Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
+        }
+        if constexpr (SC && NC == 2) {
+            R sx[2] = {R(0), R(0)}, sy[2] = {R(0), R(0)};
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const R rb = srho[1 - c][ly + 1 + ey(i)][lx + 1 + ex(i)];
+                    if (ex(i)) sx[c] += wgt<R>(i) * (ex(i) > 0 ? rb : -rb);
+                    if (ey(i)) sy[c] += wgt<R>(i) * (ey(i) > 0 ? rb : -rb);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                Fx[c] += -R(p.G) * rho[c] * sx[c];
+                Fy[c] += -R(p.G) * rho[c] * sy[c];
+            }
+        }
+        if (p.has_ads) {
+            R ax = R(0), ay = R(0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
+                if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
+                if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
+                Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
+            }
+        }
+        // 4. common velocity u' and per-component equilibrium velocities
+        R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const R om = R(p.omega[c]);
+            nux += jx[c] * om;
+            nuy += jy[c] * om;
+            den += rho[c] * om;
+            sjx += jx[c] + R(0.5) * Fx[c];
+            sjy += jy[c] + R(0.5) * Fy[c];
+            srh += rho[c];
+        }
+        const R upx = nux / den, upy = nuy / den;
+        // 5. collide and store
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+            const R tau = R(p.tau[c]), om = R(p.omega[c]);
+            const R ux = upx + tau * Fx[c] / rho[c];
+            const R uy = upy + tau * Fy[c] / rho[c];
+            const R usq = R(1.5) * (ux * ux + uy * uy);
+            const R rr = R(p.rho_ref[c]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
+                const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
+                const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
+                fout[(size_t)i * plane + s] = C::enc(d[c][i] + om * (deq - d[c][i]), i);
+            }
+        }
+        // 6. solute: pull, walls / reactive links / openings, collide
+        if constexpr (SOL) {
+            const R usx = sjx / srh, usy = sjy / srh;
+            const S *__restrict__ gin = (const S *)p.g[parity];
+            S *__restrict__ gout = (S *)p.g[parity ^ 1];
+            R g[9];
+            bool unk[9];
+            bool any_unk = false;
+            const R kr = R(p.kr), Cs = R(p.Cs);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                unk[i] = false;
+                const int sxr = x - ex(i);
+                if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
+                    unk[i] = true;
+                    any_unk = true;
+                    g[i] = R(0);
+                    continue;
+                }
+                const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
+                if (wall) {
+                    const R g_out = ldpop(gin, (size_t)opp(i) * plane + s, opp(i));
+                    R gi = g_out;
+                    if constexpr (REACT) reactive_link<R>(i, kr, Cs, g_out, gi);
+                    g[i] = gi;
+                } else {
+                    g[i] = ldpop(gin, (size_t)i * plane + src[i], i);
+                }
+            }
+            if (any_unk) {
+                const int side = (x == 0) ? 0 : 1;
+                if (p.open_style[side] == 1) {
+                    R known = R(0), wu = R(0);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        if (unk[i]) wu += wgt<R>(i);
+                        else known += g[i];
+                    }
+                    const R deficit = R(p.open_value[side]) - known;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        if (unk[i]) {
+                            g[i] = wgt<R>(i) / wu * deficit;
+                            tal[0] += (double)g[i];
+                        }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        if (unk[i]) {
+                            g[i] = g[mirx(i)];
+                            tal[0] += (double)g[i];
+                        }
+                }
+            }
+            if (!p.solute_xper && (x == 0 || x == nx - 1)) {
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const int dx = x + ex(i);
+                    if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)i * plane + s, i);
+                }
+            }
+            R Cc = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Cc += g[i];
+            const R oms = R(p.omega_s);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R eu = R(ex(i)) * usx + R(ey(i)) * usy;
+                const R geq = wgt<R>(i) * Cc * (R(1) + R(3) * eu);
+                gout[(size_t)i * plane + s] = C::enc(g[i] + oms * (geq - g[i]), i);
+            }
+        }
+    } else if (valid && REACT) {
+        // 7. solid node: gather the deposit of its reactive links, then
+        // decide growth from the post-deposit value.
+        bool fluid8 = false, fluid4 = false;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int fxg = x + ex(i);
+            if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+            if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
+                fluid8 = true;
+                if (i <= 4) fluid4 = true;
+            }
+        }
+        if (fluid8) {
+            const S *__restrict__ gin = (const S *)p.g[parity];
+            const R kr = R(p.kr), Cs = R(p.Cs);
+            double dep = 0.0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int fxg = x + ex(i);
+                if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+                if (smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) continue;
+                const size_t fl = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(fxg, nx);
+                const R g_out = ldpop(gin, (size_t)opp(i) * plane + fl, opp(i));
+                R gi;
+                dep += (double)reactive_link<R>(i, kr, Cs, g_out, gi);
+            }
+            double bn = p.b[s] + dep;
+            if (fluid4) {
+                // candidates: E, N, W, S that are fluid, inside the solute
+                // domain and not on an open solute column
+                int cand[4];
+                int m = 0;
+#pragma unroll
+                for (int i = 1; i <= 4; ++i) {
+                    const int cx = x + ex(i);
+                    if (!p.solute_xper && (cx <= 0 || cx >= nx - 1)) continue;
+                    if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) cand[m++] = i;
+                }
+                uint8_t code = 0;
+                if (bn > p.bmax && m > 0) {
+                    const unsigned long long t = (unsigned long long)(*p.dstep) + 1ull;
+                    const unsigned long long h =
+                        splitmix64(p.seed ^ (t * (unsigned long long)plane + (unsigned long long)s));
+                    const int k = (int)(((h >> 32) * (unsigned long long)m) >> 32);
+                    code = (uint8_t)cand[k];
+                    tal[2] += bn;
+                    bn = 0.0;
+                }
+                p.trig[s] = code;
+            }
+            p.b[s] = bn;
+        }
+    }
+
+    if constexpr (SOL) {
+        double out[4];
+        block_sum<4>(tal, sred, out);
+        if (tid == 0) {
+            double *dst = p.partial + (size_t)blockIdx.x * 4;
+            dst[0] = out[0];
+            dst[1] = out[1];
+            dst[2] = out[2];
+            dst[3] = 0.0;
+        }
+    }
+}
+
+// Growth: a fluid node turns solid when a direct neighbour's trigger points
+// at it; its populations' mass is tallied as removed, it gets deposit b0.
+// The last block to finish sums every block's tallies in a fixed order into
+// the running totals and advances the device step counter.
+template <typename S, int NC, bool REACT>
+__global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
+    using C = Codec<S>;
+    __shared__ double sred[4 * 4];
+    __shared__ bool last;
+    const int nx = p.nx, ny = p.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int x = blockIdx.x * 256 + threadIdx.x;  // one row segment
+    const int y = blockIdx.y;
+    double tal[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (REACT) {
+        if (x < nx && !p.mask[(size_t)y * nx + x]) {
+            const size_t s = (size_t)y * nx + x;
+            bool grow = false;
+#pragma unroll
+            for (int k = 1; k <= 4; ++k) {
+                const int sx = x + ex(k);
+                if (!p.solute_xper && (sx < 0 || sx >= nx)) continue;
+                const size_t sn = (size_t)wrapi(y + ey(k), ny) * nx + wrapi(sx, nx);
+                if (p.trig[sn] == (uint8_t)opp(k)) grow = true;
+            }
+            if (grow) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const S *__restrict__ f = (const S *)p.f[parity_new][c];
+                    double r = 0.0;
+                    for (int i = 0; i < 9; ++i)
+                        r += wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + s], i);
+                    tal[c] = r;
+                }
+                const S *__restrict__ g = (const S *)p.g[parity_new];
+                double cc = 0.0;
+                for (int i = 0; i < 9; ++i) cc += (double)C::dec(g[(size_t)i * plane + s], i);
+                tal[2] = cc;
+                tal[3] = 1.0;
+                p.mask[s] = 1;
+                p.b[s] = p.b0;
+            }
+        }
+    }
+    const int blin = blockIdx.x + blockIdx.y * gridDim.x;
+    double out[4];
+    block_sum<4>(tal, sred, out);
+    if (threadIdx.x == 0) {
+        double *dst = p.gpartial + (size_t)blin * 4;
+        for (int k = 0; k < 4; ++k) dst[k] = out[k];
+        __threadfence();
+        const unsigned done = atomicAdd(p.ticket, 1u);
+        last = (done == (unsigned)(gridDim.x * gridDim.y) - 1u);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // fixed-order sums over all block partials
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < p.nblk_main; k += 256) {
+        const volatile double *q = p.partial + (size_t)k * 4;
+        acc[0] += q[0];
+        acc[1] += q[1];
+        acc[2] += q[2];
+    }
+    for (int k = threadIdx.x; k < p.nblk_grow; k += 256) {
+        const volatile double *q = p.gpartial + (size_t)k * 4;
+        acc[3] += q[0];
+        acc[4] += q[1];
+        acc[5] += q[2];
+        acc[6] += q[3];
+    }
+    __shared__ double sred8[4 * 8];
+    double tot[8];
+    block_sum<8>(acc, sred8, tot);
+    if (threadIdx.x == 0) {
+        // LB2D_B_* indices
+        p.totals[9] += tot[0];   // inflow
+        p.totals[10] += tot[1];  // outflow
+        p.totals[14] += tot[2];  // consumed deposit
+        p.totals[6] += tot[3];   // removed mass 0
+        p.totals[7] += tot[4];   // removed mass 1
+        p.totals[8] += tot[5];   // removed solute
+        p.totals[12] += tot[6];  // grown nodes
+        p.totals[11] += 1.0;     // steps
+        *p.dstep += 1;
+        *p.ticket = 0u;
+    }
+}
+
+// ---------------------------------------------------------- set-up kernels
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+__global__ void k_fill_f64(double *p, double v, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+__global__ void k_or_mask(uint8_t *mask, const uint8_t *src, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        if (src[k]) mask[k] = 1;
+}
+
+// obstacle(circle): one block per circle sweeps its bounding box; a node is
+// solid when its squared minimum-image distance (integers, exact in FP64)
+// is at most r^2.  Stores are idempotent, so overlapping circles are fine.
+__global__ void k_raster_circles(uint8_t *mask, int nx, int ny, const int *cxy, const double *cr) {
+    const int xc = cxy[2 * blockIdx.x], yc = cxy[2 * blockIdx.x + 1];
+    const double r = cr[blockIdx.x];
+    const double r2 = r * r;
+    // half-width of the bounding box (a radius beyond the box sweeps it all)
+    const int h = (r < (double)(nx + ny)) ? (int)r + 1 : nx + ny;
+    const int wx = (2 * h + 1 < nx) ? 2 * h + 1 : nx;
+    const int wy = (2 * h + 1 < ny) ? 2 * h + 1 : ny;
+    const int x0 = (2 * h + 1 < nx) ? xc - h : 0;
+    const int y0 = (2 * h + 1 < ny) ? yc - h : 0;
+    for (int k = threadIdx.x; k < wx * wy; k += blockDim.x) {
+        const int gx = wrapi(x0 + k % wx, nx), gy = wrapi(y0 + k / wx, ny);
+        long long dx = wrapi(gx - xc, nx), dy = wrapi(gy - yc, ny);
+        if (nx - dx < dx) dx = nx - dx;
+        if (ny - dy < dy) dy = ny - dy;
+        const double d2 = (double)(dx * dx + dy * dy);
+        if (d2 <= r2) mask[(size_t)gy * nx + gx] = 1;
+    }
+}
+
+__global__ void k_raster_rects(uint8_t *mask, int nx, const int *rects) {
+    const int x0 = rects[4 * blockIdx.x], x1 = rects[4 * blockIdx.x + 1];
+    const int y0 = rects[4 * blockIdx.x + 2], y1 = rects[4 * blockIdx.x + 3];
+    const int w = x1 - x0 + 1, h = y1 - y0 + 1;
+    for (long long k = threadIdx.x; k < (long long)w * h; k += blockDim.x)
+        mask[(size_t)(y0 + k / w) * nx + (x0 + k % w)] = 1;
+}
+
+// Populations at the equilibrium of (rho, u) from FP64 staging arrays
+// (computed in FP64, then shifted and encoded).
+template <typename S>
+__global__ void k_init_fluid(S *f, const double *rho, const double *ux, const double *uy, size_t n,
+                             double A0, double A1, double rho_ref) {
+    using C = Codec<S>;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const double r = rho[k], u = ux[k], v = uy[k];
+        const double usq = 1.5 * (u * u + v * v);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double eu = ex(i) * u + ey(i) * v;
+            const double A = (i == 0) ? A0 : A1;
+            const double fe = wgt<double>(i) * r * (A + 3.0 * eu + 4.5 * eu * eu - usq);
+            f[(size_t)i * n + k] = C::enc((typename C::R)(fe - wgt<double>(i) * rho_ref), i);
+        }
+    }
+}
+
+template <typename S>
+__global__ void k_init_solute(S *g, const double *Cc, const double *ux, const double *uy, size_t n) {
+    using C = Codec<S>;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const double c = Cc[k], u = ux[k], v = uy[k];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double eu = ex(i) * u + ey(i) * v;
+            g[(size_t)i * n + k] = C::enc((typename C::R)(wgt<double>(i) * c * (1.0 + 3.0 * eu)), i);
+        }
+    }
+}
+
+__global__ void k_init_b(double *b, const uint8_t *mask, double b0, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        b[k] = mask[k] ? b0 : 0.0;
+}
+
+// Raw state <-> FP64 (one plane at a time); `shift` = w_i rho_ref.
+template <typename S>
+__global__ void k_decode_plane(const S *f, double *out, size_t n, int i, double shift) {
+    using C = Codec<S>;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        out[k] = shift + (double)C::dec(f[(size_t)i * n + k], i);
+}
+template <typename S>
+__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift) {
+    using C = Codec<S>;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        f[(size_t)i * n + k] = C::enc((typename C::R)(in[k] - shift), i);
+}
+
+// ---------------------------------------------------------------- read-out
+
+template <typename S>
+__device__ double node_rho(const S *f, size_t plane, int nx, int ny, int x, int y, double rho_ref) {
+    using C = Codec<S>;
+    const size_t s = (size_t)y * nx + x;
+    double r = rho_ref;
+    for (int i = 0; i < 9; ++i) r += (double)C::dec(f[(size_t)i * plane + s], i);
+    return r;
+}
+
+// Density and velocity (j_post - F/2)/rho of component `comp` (or the
+// mixture for comp < 0), in FP64 from the stored state; -11 at solids.
+template <typename S>
+__global__ void k_moments(FullParams p, int parity, int comp, double *orho, double *oux, double *ouy) {
+    using C = Codec<S>;
+    const int nx = p.nx, ny = p.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= nx) return;
+    const size_t s = (size_t)y * nx + x;
+    if (p.mask[s]) {
+        orho[s] = -11.0;
+        oux[s] = ouy[s] = 0.0;
+        return;
+    }
+    double rho[2] = {0, 0}, jx[2] = {0, 0}, jy[2] = {0, 0};
+    for (int c = 0; c < p.ncomp; ++c) {
+        const S *f = (const S *)p.f[parity][c];
+        double r = p.rho_ref[c], mx = 0, my = 0;
+        for (int i = 0; i < 9; ++i) {
+            const double v = (double)C::dec(f[(size_t)i * plane + s], i);
+            r += v;
+            mx += ex(i) * v;
+            my += ey(i) * v;
+        }
+        rho[c] = r;
+        jx[c] = mx;
+        jy[c] = my;
+    }
+    double R = 0, MX = 0, MY = 0;
+    for (int c = 0; c < p.ncomp; ++c) {
+        if (comp >= 0 && c != comp) continue;
+        double Fx = p.force[c][0] + rho[c] * p.accel[c][0];
+        double Fy = p.force[c][1] + rho[c] * p.accel[c][1];
+        if (p.ncomp == 2 && p.G != 0.0) {
+            double sx = 0, sy = 0;
+            const S *fo = (const S *)p.f[parity][1 - c];
+            for (int i = 1; i < 9; ++i) {
+                const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
+                if (p.mask[(size_t)gy * nx + gx]) continue;
+                const double rb = node_rho<S>(fo, plane, nx, ny, gx, gy, p.rho_ref[1 - c]);
+                sx += wgt<double>(i) * rb * ex(i);
+                sy += wgt<double>(i) * rb * ey(i);
+            }
+            Fx += -p.G * rho[c] * sx;
+            Fy += -p.G * rho[c] * sy;
+        }
+        if (p.has_ads) {
+            double sx = 0, sy = 0;
+            for (int i = 1; i < 9; ++i) {
+                const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
+                const double sv = p.mask[(size_t)gy * nx + gx] ? 1.0 : 0.0;
+                sx += wgt<double>(i) * sv * ex(i);
+                sy += wgt<double>(i) * sv * ey(i);
+            }
+            Fx += -p.Gads[c] * rho[c] * sx;
+            Fy += -p.Gads[c] * rho[c] * sy;
+        }
+        R += rho[c];
+        MX += jx[c] - 0.5 * Fx;
+        MY += jy[c] - 0.5 * Fy;
+    }
+    orho[s] = R;
+    oux[s] = MX / R;
+    ouy[s] = MY / R;
+}
+
+template <typename S>
+__global__ void k_solute_state(FullParams p, int parity, int reaction, double *oc, double *ob) {
+    using C = Codec<S>;
+    const size_t n = (size_t)p.nx * p.ny;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        double c = 0.0;
+        const bool sol = p.mask[k] != 0;
+        if (!sol) {
+            const S *g = (const S *)p.g[parity];
+            for (int i = 0; i < 9; ++i) c += (double)C::dec(g[(size_t)i * n + k], i);
+        }
+        oc[k] = c;
+        ob[k] = (sol && reaction) ? p.b[k] : 0.0;
+    }
+}
+
+// Budgets: per-block FP64 partials over rows, then one block sums them.
+template <typename S>
+__global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity, int has_solute,
+                                                        int reaction, double *part) {
+    using C = Codec<S>;
+    __shared__ double sred[4 * 8];
+    const int nx = p.nx;
+    const size_t plane = (size_t)nx * p.ny;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // m0 m1 jx jy C b nfluid -
+    const int y = blockIdx.x;
+    for (int x = threadIdx.x; x < nx; x += 256) {
+        const size_t s = (size_t)y * nx + x;
+        if (p.mask[s]) {
+            if (reaction) v[5] += p.b[s];
+            continue;
+        }
+        v[6] += 1.0;
+        for (int c = 0; c < p.ncomp; ++c) {
+            const S *f = (const S *)p.f[parity][c];
+            for (int i = 0; i < 9; ++i) {
+                const double fv = wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + s], i);
+                v[c] += fv;
+                v[2] += ex(i) * fv;
+                v[3] += ey(i) * fv;
+            }
+        }
+        if (has_solute) {
+            const S *g = (const S *)p.g[parity];
+            for (int i = 0; i < 9; ++i) v[4] += (double)C::dec(g[(size_t)i * plane + s], i);
+        }
+    }
+    double out[8];
+    block_sum<8>(v, sred, out);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) part[(size_t)blockIdx.x * 8 + k] = out[k];
+}
+
+__global__ void __launch_bounds__(256) k_budget_final(const double *part, int nblk, double *out8) {
+    __shared__ double sred[4 * 8];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < nblk; k += 256)
+        for (int j = 0; j < 8; ++j) v[j] += part[(size_t)k * 8 + j];
+    double out[8];
+    block_sum<8>(v, sred, out);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 8; ++j) out8[j] = out[j];
+}
+
+// Plain copy kernel (read + write n floats) used to measure the practical
+// HBM ceiling next to the stencil.
+__global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n4) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n4; k += (size_t)gridDim.x * blockDim.x)
+        b[k] = a[k];
+}
+
+inline int grid1d(size_t n, int bs = 256) {
+    size_t g = (n + bs - 1) / bs;
+    if (g > 65536) g = 65536;
+    return (int)(g ? g : 1);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers
+
+#define LB2D_DISPATCH(st, CALL)                       \
+    switch (st) {                                     \
+        case kF64: { using S = double; CALL; break; } \
+        case kF32: { using S = float; CALL; break; }  \
+        case kF16: { using S = _Float16; CALL; break; } \
+        default: { using S = bf16s; CALL; break; }    \
+    }
+
+size_t storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
+
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, int bx, int by, hipStream_t stream) {
+    dim3 blk(bx, by), grd((L.nx + bx - 1) / bx, (L.ny + by - 1) / by);
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_plain<S>, grd, blk, 0, stream, L, parity));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int bx,
+                        int by, int grid, hipStream_t stream) {
+    dim3 blk(bx, by);
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_batch<S>, dim3(grid), blk, 0, stream, lat, tiles, ntiles, parity));
+    return hipGetLastError();
+}
+
+int full_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
+int growth_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
+
+template <typename S>
+static void full_dispatch(const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t st) {
+    const int nblk = full_tiles(p.nx, p.ny);
+    const dim3 g(nblk), b(kTX * kTY);
+    if (p.ncomp == 2) {
+        if (sc) {
+            if (sol) {
+                if (react) hipLaunchKernelGGL((k_full<S, 2, true, true, true>), g, b, 0, st, p, parity);
+                else hipLaunchKernelGGL((k_full<S, 2, true, true, false>), g, b, 0, st, p, parity);
+            } else {
+                hipLaunchKernelGGL((k_full<S, 2, true, false, false>), g, b, 0, st, p, parity);
+            }
+        } else {
+            if (sol) {
+                if (react) hipLaunchKernelGGL((k_full<S, 2, false, true, true>), g, b, 0, st, p, parity);
+                else hipLaunchKernelGGL((k_full<S, 2, false, true, false>), g, b, 0, st, p, parity);
+            } else {
+                hipLaunchKernelGGL((k_full<S, 2, false, false, false>), g, b, 0, st, p, parity);
+            }
+        }
+    } else {
+        if (sol) {
+            if (react) hipLaunchKernelGGL((k_full<S, 1, false, true, true>), g, b, 0, st, p, parity);
+            else hipLaunchKernelGGL((k_full<S, 1, false, true, false>), g, b, 0, st, p, parity);
+        } else {
+            hipLaunchKernelGGL((k_full<S, 1, false, false, false>), g, b, 0, st, p, parity);
+        }
+    }
+}
+
+hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react,
+                       hipStream_t stream) {
+    if (st == kF64) full_dispatch<double>(p, parity, sc, sol, react, stream);
+    else full_dispatch<float>(p, parity, sc, sol, react, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t stream) {
+    const dim3 g((p.nx + 255) / 256, p.ny), b(256);
+    if (st == kF64) {
+        if (p.ncomp == 2) {
+            if (react) hipLaunchKernelGGL((k_growth<double, 2, true>), g, b, 0, stream, p, parity_new);
+            else hipLaunchKernelGGL((k_growth<double, 2, false>), g, b, 0, stream, p, parity_new);
+        } else {
+            if (react) hipLaunchKernelGGL((k_growth<double, 1, true>), g, b, 0, stream, p, parity_new);
+            else hipLaunchKernelGGL((k_growth<double, 1, false>), g, b, 0, stream, p, parity_new);
+        }
+    } else {
+        if (p.ncomp == 2) {
+            if (react) hipLaunchKernelGGL((k_growth<float, 2, true>), g, b, 0, stream, p, parity_new);
+            else hipLaunchKernelGGL((k_growth<float, 2, false>), g, b, 0, stream, p, parity_new);
+        } else {
+            if (react) hipLaunchKernelGGL((k_growth<float, 1, true>), g, b, 0, stream, p, parity_new);
+            else hipLaunchKernelGGL((k_growth<float, 1, false>), g, b, 0, stream, p, parity_new);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid1d(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid1d(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_or_mask(uint8_t *mask, const uint8_t *src, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_or_mask, dim3(grid1d(n)), dim3(256), 0, s, mask, src, n);
+    return hipGetLastError();
+}
+hipError_t launch_raster_circles(uint8_t *mask, int nx, int ny, const int *cxy, const double *cr, int count,
+                                 hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_raster_circles, dim3(count), dim3(256), 0, s, mask, nx, ny, cxy, cr);
+    return hipGetLastError();
+}
+hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_raster_rects, dim3(count), dim3(256), 0, s, mask, nx, rects);
+    return hipGetLastError();
+}
+hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
+                             double A0, double A1, double rho_ref, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_init_fluid<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, rho, ux, uy, n,
+                                         A0, A1, rho_ref));
+    return hipGetLastError();
+}
+hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
+                              hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_init_solute<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux, uy, n));
+    return hipGetLastError();
+}
+hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_b, dim3(grid1d(n)), dim3(256), 0, s, b, mask, b0, n);
+    return hipGetLastError();
+}
+hipError_t launch_decode_plane(int st, const void *f, double *out, size_t n, int i, double shift, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, out, n, i,
+                                         shift));
+    return hipGetLastError();
+}
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_encode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, in, n, i,
+                                         shift));
+    return hipGetLastError();
+}
+hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
+                          hipStream_t s) {
+    const dim3 g((p.nx + 255) / 256, p.ny), b(256);
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_moments<S>, g, b, 0, s, p, parity, comp, rho, ux, uy));
+    return hipGetLastError();
+}
+hipError_t launch_solute_state(int st, const FullParams &p, int parity, int reaction, double *C, double *b,
+                               hipStream_t s) {
+    const size_t n = (size_t)p.nx * p.ny;
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_solute_state<S>, dim3(grid1d(n)), dim3(256), 0, s, p, parity, reaction, C,
+                                         b));
+    return hipGetLastError();
+}
+hipError_t launch_budgets(int st, const FullParams &p, int parity, int has_solute, int reaction, double *part,
+                          double *out8, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_budget_partial<S>, dim3(p.ny), dim3(256), 0, s, p, parity, has_solute,
+                                         reaction, part));
+    hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(256), 0, s, part, p.ny, out8);
+    return hipGetLastError();
+}
+hipError_t launch_copy(const void *a, void *b, size_t bytes, hipStream_t s) {
+    const size_t n4 = bytes / 16;
+    hipLaunchKernelGGL(k_copy, dim3(grid1d(n4, 256) < 8192 ? grid1d(n4, 256) : 8192), dim3(256), 0, s,
+                       (const float4 *)a, (float4 *)b, n4);
+    return hipGetLastError();
+}
+
+}  // namespace lb2d

@@ -1,0 +1,40 @@
+// lb2d_kernels.hpp -- host-side launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lb2d_common.hpp"
+
+namespace lb2d {
+
+size_t storage_bytes(int st);
+int full_tiles(int nx, int ny);
+int growth_blocks(int nx, int ny);
+
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, int bx, int by, hipStream_t s);
+hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int bx, int by,
+                        int grid, hipStream_t s);
+hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t s);
+hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+hipError_t launch_or_mask(uint8_t *mask, const uint8_t *src, size_t n, hipStream_t s);
+hipError_t launch_raster_circles(uint8_t *mask, int nx, int ny, const int *cxy, const double *cr, int count,
+                                 hipStream_t s);
+hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int count, hipStream_t s);
+hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
+                             double A0, double A1, double rho_ref, hipStream_t s);
+hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
+                              hipStream_t s);
+hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s);
+hipError_t launch_decode_plane(int st, const void *f, double *out, size_t n, int i, double shift, hipStream_t s);
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s);
+hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
+                          hipStream_t s);
+hipError_t launch_solute_state(int st, const FullParams &p, int parity, int reaction, double *C, double *b,
+                               hipStream_t s);
+hipError_t launch_budgets(int st, const FullParams &p, int parity, int has_solute, int reaction, double *part,
+                          double *out8, hipStream_t s);
+hipError_t launch_copy(const void *a, void *b, size_t bytes, hipStream_t s);
+
+}  // namespace lb2d

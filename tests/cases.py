@@ -1,0 +1,135 @@
+"""Builds the same seeded case on the HIP library and on the oracle.
+
+A case is a plain dict of commands (lattice size, fluids, forces, obstacles,
+initial fields, solute, reaction).  ``build_oracle`` and ``build_gpu`` apply
+it to each side; both take their inputs from the same arrays, and no value
+ever flows from the GPU side into the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import Oracle
+
+
+def poiseuille_case(nx=128, ny=64, accel=1e-6, tau=1.0):
+    return dict(nx=nx, ny=ny, tau=tau, accel=[(1, accel, 0)],
+                rects=[(0, nx - 1, 0, 0), (0, nx - 1, ny - 1, ny - 1)])
+
+
+def porous_case(nx, ny, seed, tau=0.8, accel=1e-5, nd=None, rmin=2.0, rmax=6.0, noise=0.02):
+    rng = np.random.default_rng(seed)
+    nd = nd if nd is not None else max(1, nx * ny // 300)
+    circles = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), float(rng.uniform(rmin, rmax)))
+               for _ in range(nd)]
+    n = nx * ny
+    rho = 1.0 + noise * rng.uniform(-1, 1, n)
+    ux = noise * 0.5 * rng.uniform(-1, 1, n)
+    uy = noise * 0.5 * rng.uniform(-1, 1, n)
+    return dict(nx=nx, ny=ny, tau=tau, accel=[(1, accel, 0)], circles=circles,
+                fields={0: (rho, ux, uy)})
+
+
+def sc_solute_case(nx, ny, seed, react=True, kr=0.01, bmax=0.2, G=0.9, gads=(0.3, -0.3),
+                   openings=True, tau_s=0.7, nd=None, C0=0.05, b0=0.0):
+    rng = np.random.default_rng(seed)
+    nd = nd if nd is not None else max(2, nx * ny // 500)
+    circles = []
+    for _ in range(nd):
+        r = float(rng.uniform(2.0, 5.0))
+        xc = int(rng.integers(int(r) + 3, nx - int(r) - 3))
+        circles.append((xc, int(rng.integers(0, ny)), r))
+    n = nx * ny
+    blob = rng.uniform(0, 1, n) < 0.3
+    rho_a = np.where(blob, 1.0, 0.05) * (1 + 0.01 * rng.uniform(-1, 1, n))
+    rho_b = np.where(blob, 0.05, 1.0) * (1 + 0.01 * rng.uniform(-1, 1, n))
+    case = dict(nx=nx, ny=ny, tau=1.0, fluids=(1.0, 1.0), G=G, gads=gads, circles=circles,
+                fields={0: (rho_a, None, None), 1: (rho_b, None, None)},
+                solute=tau_s, C=np.full(n, C0), accel=[(1, 1e-5, 0)])
+    if openings:
+        case["openings"] = [("xlo", "dirichlet", 1.0), ("xhi", "adiabatic", 0.0)]
+    if react:
+        case["reaction"] = (kr, 0.0, b0, bmax, 4242 + seed)
+    return case
+
+
+def build_oracle(case):
+    o = Oracle(case["nx"], case["ny"])
+    if "fluids" in case:
+        o.fluids(2, *case["fluids"])
+    else:
+        o.fluids(1, case["tau"])
+    for mode, v, comp in case.get("force", []):
+        o.aveforce(mode, v, comp)
+    for mode, v, comp in case.get("accel", []):
+        o.aveacceleration(mode, v, comp)
+    if case.get("G") is not None:
+        o.interforce(case["G"])
+    if case.get("gads") is not None:
+        o.adhesiveforce(case["gads"][0], 0)
+        o.adhesiveforce(case["gads"][1], 1)
+    for r in case.get("rects", []):
+        o.obstacle_rect(*r)
+    for c in case.get("circles", []):
+        o.obstacle_circle(*c)
+    if case.get("mask") is not None:
+        o.set_mask(np.maximum(o.get_mask(), case["mask"]))
+    for comp, (rho, ux, uy) in case.get("fields", {}).items():
+        o.set_fields(comp, rho, 0.0 if ux is None else ux, 0.0 if uy is None else uy)
+    if "fluids" in case:
+        for comp in (0, 1):
+            if comp not in case.get("fields", {}):
+                o.set_fields(comp, 1.0)
+    elif 0 not in case.get("fields", {}):
+        o.set_fields(0, 1.0)
+    if case.get("solute") is not None:
+        o.solute(case["solute"], 9)
+        for wall, style, val in case.get("openings", []):
+            o.solute_opening(wall, style, val)
+        if case.get("reaction") is not None:
+            o.surface_reaction(*case["reaction"])
+        o.set_concentration(case.get("C", 0.0))
+    return o
+
+
+def build_gpu(case, storage="f32", bind=True, stream=None):
+    from paper_1202_0442_amd import lb2d
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", case["nx"], case["ny"], case["tau"])
+    if "fluids" in case:
+        g.fluids(*case["fluids"])
+    if case.get("solute") is not None:
+        g.solute(case["solute"], 9)
+        for wall, style, val in case.get("openings", []):
+            g.solute_opening(wall, style, val)
+    g.boundary_style("noslip")
+    for r in case.get("rects", []):
+        g.obstacle_rect(*r)
+    for c in case.get("circles", []):
+        g.obstacle_circle(*c)
+    if case.get("mask") is not None:
+        g.obstacle_mask(case["mask"])
+    if case.get("reaction") is not None:
+        kr, Cs, b0, bmax, seed = case["reaction"]
+        g.surface_reaction(kr, Cs, "growth", b0, bmax, seed)
+    for comp, (rho, ux, uy) in case.get("fields", {}).items():
+        g.set_fields(comp, rho, ux, uy)
+    if case.get("solute") is not None:
+        g.set_concentration(case.get("C", np.zeros(case["nx"] * case["ny"])))
+    for mode, v, comp in case.get("force", []):
+        g.aveforce(mode, v, comp)
+    for mode, v, comp in case.get("accel", []):
+        g.aveacceleration(mode, v, comp)
+    if case.get("G") is not None:
+        g.interforce(case["G"])
+    if case.get("gads") is not None:
+        g.adhesiveforce(case["gads"][0], 0)
+        g.adhesiveforce(case["gads"][1], 1)
+    if bind:
+        g.bind(storage, stream=stream)
+    return g
+
+
+def rel_err(a, b, scale=None):
+    scale = np.abs(b).max() if scale is None else scale
+    return float(np.abs(a - b).max() / max(scale, 1e-300))
