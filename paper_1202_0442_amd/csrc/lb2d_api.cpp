@@ -73,6 +73,7 @@ struct lb2d_ctx {
     void *f[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void *g[2] = {nullptr, nullptr};
     uint8_t *mask = nullptr, *trig = nullptr;
+    uint16_t *links = nullptr;
     double *b = nullptr, *staging = nullptr, *partial = nullptr, *gpartial = nullptr;
     double *totals = nullptr;
     unsigned *ticket = nullptr;
@@ -142,7 +143,7 @@ bool is_nan(double v) { return std::isnan(v); }
 
 // Workspace layout of one lattice.
 struct Layout {
-    size_t f[2][2], g[2], mask, trig, b, staging, partial, gpartial, totals, ticket, dstep, total;
+    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, ticket, dstep, total;
     size_t staging_doubles;
 };
 
@@ -164,6 +165,8 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     off += align_up(n);
     L.trig = off;
     off += align_up(n);
+    L.links = off;
+    off += align_up(2 * n);
     L.b = off;
     if (c->reaction) off += align_up(n * 8);
     // staging: 3 doubles per node (host transfers, read-outs, budgets,
@@ -240,7 +243,7 @@ PlainLattice plain_lattice(const lb2d_ctx *c) {
     PlainLattice L{};
     L.f[0] = c->f[0][0];
     L.f[1] = c->f[1][0];
-    L.mask = c->mask;
+    L.links = c->links;
     L.nx = c->nx;
     L.ny = c->ny;
     L.tau = c->tau[0];
@@ -638,6 +641,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     for (int p = 0; p < 2; ++p) c->g[p] = c->q ? (void *)(c->ws + L.g[p]) : nullptr;
     c->mask = (uint8_t *)(c->ws + L.mask);
     c->trig = (uint8_t *)(c->ws + L.trig);
+    c->links = (uint16_t *)(c->ws + L.links);
     c->b = c->reaction ? (double *)(c->ws + L.b) : nullptr;
     c->staging = (double *)(c->ws + L.staging);
     c->staging_doubles = L.staging_doubles;
@@ -705,6 +709,8 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
+    HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, s));
+    if (c->plain()) HIPCHK(c, launch_ghost_fill(c->storage, c->f[0][0], c->links, c->nx, c->ny, s));
     HIPCHK(c, launch_fill_f64(c->totals, 0.0, 16, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->ticket, 0, 8, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
@@ -863,7 +869,7 @@ int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = c->n();
     for (int i = 0; i < 9; ++i) {
-        HIPCHK(c, launch_decode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, i, kW[i] * ref, c->stream));
         HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -881,6 +887,10 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
     for (int i = 0; i < 9; ++i) {
         HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (comp >= 0 && c->plain()) {
+        HIPCHK(c, launch_ghost_fill(c->storage, buf, c->links, c->nx, c->ny, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return LB2D_OK;
@@ -912,6 +922,9 @@ int lb2d_set_mask(lb2d_ctx *c, const uint8_t *m) {
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipMemcpyAsync(c->mask, m, c->n(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_fill_u8(c->trig, 0, c->n(), c->stream));
+    HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, c->stream));
+    if (c->plain())
+        HIPCHK(c, launch_ghost_fill(c->storage, c->f[c->t & 1][0], c->links, c->nx, c->ny, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LB2D_OK;
 }
@@ -989,10 +1002,20 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
+// Tile shapes the autotuner may choose (width x height threads); a tile
+// table large enough for every one of them is reserved.
+static const int kTileShapes[][2] = {{64, 4}, {128, 2}, {256, 1}, {64, 8}, {128, 4}, {32, 8}, {64, 2}, {64, 1}};
+
+static size_t max_tiles_for(const lb2d_batch *b) {
+    size_t m = 0;
+    for (const auto &t : kTileShapes) m = std::max(m, tiles_for(b, t[0], t[1]));
+    return m;
+}
+
 int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
     if (!b || !bytes) return LB2D_E_INVAL;
     if (b->lat.empty()) return b->fail(LB2D_E_STATE, "empty batch");
-    const size_t tiles = tiles_for(b, 32, 4);  // smallest tile the tuner tries
+    const size_t tiles = max_tiles_for(b);
     *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile));
     return LB2D_OK;
 }
@@ -1021,7 +1044,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     b->stream = (hipStream_t)hip_stream;
     b->d_lat = (PlainLattice *)b->ws;
     b->d_tiles = (Tile *)(b->ws + align_up(b->lat.size() * sizeof(PlainLattice)));
-    b->max_tiles = tiles_for(b, 32, 4);
+    b->max_tiles = max_tiles_for(b);
     std::vector<PlainLattice> L;
     for (auto *c : b->lat) L.push_back(plain_lattice(c));
     HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
@@ -1042,7 +1065,9 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             if (std::fscanf(fh, "{\"key\": \"%63[0-9a-f]\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
                                 "\"blocks_per_cu\": %d}",
                             k, &w, &h, &s, &p) == 5 &&
-                key == k && w > 0 && h > 0 && w * h <= 1024 && w * h >= 64 && s >= 0 && s <= 2 && p >= 0) {
+                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 &&
+                std::any_of(std::begin(kTileShapes), std::end(kTileShapes),
+                            [&](const int *t) { return t[0] == w && t[1] == h; })) {
                 b->tile_w = w;
                 b->tile_h = h;
                 b->schedule = s;

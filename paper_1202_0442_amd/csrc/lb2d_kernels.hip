@@ -137,39 +137,41 @@ __device__ void block_sum(double (&v)[K], double *sh, double *out) {
 
 // ------------------------------------------------------- plain fused step
 
-// One node of the single-fluid step: pull with half-way bounce-back,
-// moments, velocity-shift forcing, BGK relaxation to Eq. (eq), store.
-// Populations are deviations d_i = f_i - w_i rho_ref, so
-// rho = rho_ref + sum d_i and j = sum d_i e_i; the equilibrium deviation is
-// w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)].
+// One node of the single-fluid step: pull, moments, velocity-shift forcing,
+// BGK relaxation to Eq. (eq), store.  Populations are deviations
+// d_i = f_i - w_i rho_ref, so rho = rho_ref + sum d_i and j = sum d_i e_i;
+// the equilibrium deviation is w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)].
+//
+// Half-way bounce-back (boundary_style noslip) without any mask test in the
+// pull: when node + e_i is solid the node also stores its post-collision
+// f_i into that solid node's slot of direction opp(i).  The only node that
+// ever pulls that slot is this node itself (it pulls f_opp(i) from
+// node - e_opp(i) = node + e_i), so the next step's plain pull returns
+// f_opp(i) = f_i^post -- the bounce-back -- and all nine loads of a node are
+// independent and issued together.  Each (solid node, direction) slot has
+// exactly one writer and one reader.
 template <typename S>
 __device__ __forceinline__ void plain_node(const PlainLattice &L, int parity, int x, int y) {
     using C = Codec<S>;
     using R = typename C::R;
-    const int nx = L.nx, ny = L.ny;
+    const unsigned nx = (unsigned)L.nx, ny = (unsigned)L.ny;
+    const unsigned s = (unsigned)y * nx + (unsigned)x;
+    const unsigned lk = L.links[s];
+    if (lk & 1u) return;
     const size_t plane = (size_t)nx * ny;
-    const size_t s = (size_t)y * nx + x;
-    const uint8_t *__restrict__ m = L.mask;
-    if (m[s]) return;
     const S *__restrict__ fin = (const S *)L.f[parity];
     S *__restrict__ fout = (S *)L.f[parity ^ 1];
 
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
-    const size_t rm = (size_t)((y == 0) ? ny - 1 : y - 1) * nx;
-    const size_t r0 = (size_t)y * nx;
-    const size_t rp = (size_t)((y == ny - 1) ? 0 : y + 1) * nx;
-    // source node x - e_i of each direction
-    const size_t src[9] = {s,       r0 + xm, rm + x,  r0 + xp, rp + x,
-                           rm + xm, rm + xp, rp + xp, rp + xm};
+    const unsigned xm = (x == 0) ? nx - 1 : (unsigned)x - 1;
+    const unsigned xp = ((unsigned)x == nx - 1) ? 0 : (unsigned)x + 1;
+    const unsigned rm = ((y == 0) ? ny - 1 : (unsigned)y - 1) * nx;
+    const unsigned r0 = (unsigned)y * nx;
+    const unsigned rp = (((unsigned)y == ny - 1) ? 0 : (unsigned)y + 1) * nx;
+    // node - e_i for each direction (so node + e_i = src[opp(i)])
+    const unsigned src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
     R d[9];
-    d[0] = C::dec(fin[s], 0);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const bool wall = m[src[i]] != 0;
-        const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
-        d[i] = C::dec(fin[a], i);
-    }
+    for (int i = 0; i < 9; ++i) d[i] = C::dec(fin[(size_t)i * plane + src[i]], i);
     R drho = 0, jx = 0, jy = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -189,7 +191,9 @@ __device__ __forceinline__ void plain_node(const PlainLattice &L, int parity, in
     for (int i = 0; i < 9; ++i) {
         const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
         const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
-        fout[(size_t)i * plane + s] = C::enc(d[i] + omega * (deq - d[i]), i);
+        const S v = C::enc(d[i] + omega * (deq - d[i]), i);
+        fout[(size_t)i * plane + s] = v;
+        if (i > 0 && (lk & (1u << i))) fout[(size_t)opp(i) * plane + src[opp(i)]] = v;
     }
 }
 
@@ -667,6 +671,38 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     }
 }
 
+// ------------------------------------------------- plain-step geometry
+
+// Link word of every node: bit 0 = node solid, bit i = node + e_i solid.
+__global__ void k_links(const uint8_t *__restrict__ mask, uint16_t *__restrict__ links, int nx, int ny) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= nx) return;
+    unsigned v = mask[(size_t)y * nx + x] ? 1u : 0u;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
+        if (mask[(size_t)gy * nx + gx]) v |= 1u << i;
+    }
+    links[(size_t)y * nx + x] = (uint16_t)v;
+}
+
+// Fills the ghost slots of buffer f from the fluid nodes' own populations
+// (the state a bounce-back would return), e.g. after initialisation.
+template <typename S>
+__global__ void k_ghost_fill(S *f, const uint16_t *__restrict__ links, int nx, int ny) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny, s = (size_t)y * nx + x;
+    const unsigned lk = links[s];
+    if (lk & 1u) return;
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        if (lk & (1u << i)) {
+            const size_t nb = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(x + ex(i), nx);
+            f[(size_t)opp(i) * plane + nb] = f[(size_t)i * plane + s];
+        }
+}
+
 // ---------------------------------------------------------- set-up kernels
 
 __global__ void k_fill_u8(uint8_t *p, uint8_t v, size_t n) {
@@ -754,10 +790,10 @@ __global__ void k_init_b(double *b, const uint8_t *mask, double b0, size_t n) {
 
 // Raw state <-> FP64 (one plane at a time); `shift` = w_i rho_ref.
 template <typename S>
-__global__ void k_decode_plane(const S *f, double *out, size_t n, int i, double shift) {
+__global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, double shift) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        out[k] = shift + (double)C::dec(f[(size_t)i * n + k], i);
+        out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * n + k], i);
 }
 template <typename S>
 __global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift) {
@@ -911,8 +947,16 @@ __global__ void __launch_bounds__(256) k_budget_final(const double *part, int nb
 // Plain copy kernel (read + write n floats) used to measure the practical
 // HBM ceiling next to the stencil.
 __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n4) {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n4; k += (size_t)gridDim.x * blockDim.x)
-        b[k] = a[k];
+    // each block copies 4 consecutive chunks of 256 float4: four loads in
+    // flight per thread before the stores
+    const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + 256 * k < n4) v[k] = a[base + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + 256 * k < n4) b[base + 256 * k] = v[k];
 }
 
 inline int grid1d(size_t n, int bs = 256) {
@@ -1046,9 +1090,19 @@ hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hi
     hipLaunchKernelGGL(k_init_b, dim3(grid1d(n)), dim3(256), 0, s, b, mask, b0, n);
     return hipGetLastError();
 }
-hipError_t launch_decode_plane(int st, const void *f, double *out, size_t n, int i, double shift, hipStream_t s) {
-    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, out, n, i,
-                                         shift));
+hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
+                               double shift, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, mask,
+                                         out, n, i, shift));
+    return hipGetLastError();
+}
+hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s) {
+    hipLaunchKernelGGL(k_links, dim3((nx + 255) / 256, ny), dim3(256), 0, s, mask, links, nx, ny);
+    return hipGetLastError();
+}
+hipError_t launch_ghost_fill(int st, void *f, const uint16_t *links, int nx, int ny, hipStream_t s) {
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_ghost_fill<S>, dim3((nx + 255) / 256, ny), dim3(256), 0, s, (S *)f, links,
+                                         nx, ny));
     return hipGetLastError();
 }
 hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s) {
@@ -1078,8 +1132,8 @@ hipError_t launch_budgets(int st, const FullParams &p, int parity, int has_solut
 }
 hipError_t launch_copy(const void *a, void *b, size_t bytes, hipStream_t s) {
     const size_t n4 = bytes / 16;
-    hipLaunchKernelGGL(k_copy, dim3(grid1d(n4, 256) < 8192 ? grid1d(n4, 256) : 8192), dim3(256), 0, s,
-                       (const float4 *)a, (float4 *)b, n4);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n4 + 1023) / 1024)), dim3(256), 0, s, (const float4 *)a,
+                       (float4 *)b, n4);
     return hipGetLastError();
 }
 

@@ -1,0 +1,137 @@
+"""Parity at the benchmark's full sizes and launch configuration.
+
+The oracle cannot run a 4096^2 lattice, but after k steps a node depends
+only on the initial state within k nodes (2k with the Shan-Chen stencil).
+So the oracle recomputes sampled patches from the *initial* state, each on
+its own window of (patch + 2k + margin) nodes -- obstacles of that window
+rasterised by the oracle from the same disc list -- and the interior
+patch is compared with the GPU run, which goes through the same graph
+launches the benchmark times.  No value from the GPU side enters the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1202_0442_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _window_oracle(w, x0, y0, W, tau, accel):
+    """Oracle lattice for the global window [x0, x0+W) x [y0, y0+W)
+    (periodic wrap of the global box), with the discs that touch it."""
+    o = Oracle(W, W)
+    o.fluids(1, tau)
+    o.aveacceleration(1, accel)
+    nx, ny = w.nx, w.ny
+    for (xc, yc, r) in w.discs:
+        dx = (xc - x0) % nx
+        dy = (yc - y0) % ny
+        if dx > nx / 2:
+            dx -= nx
+        if dy > ny / 2:
+            dy -= ny
+        if -r - 1 <= dx <= W + r and -r - 1 <= dy <= W + r:
+            o.obstacle_circle(int(dx), int(dy), r)
+    o.set_fields(0, 1.0)
+    return o
+
+
+@pytest.mark.parametrize("storage,tol_u", [("f32", 1e-5), ("f16", 5e-2)])
+def test_porous_4096_sampled_patches(storage, tol_u):
+    from paper_1202_0442_amd import lb2d
+    import torch
+    w = inputs.porous(n=4096, seed=2)
+    stream = torch.cuda.Stream()
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", w.nx, w.ny, w.tau)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        g.obstacle_circle(xc, yc, r)
+    g.aveacceleration(1, w.accel_x)
+    g.bind(storage, stream=stream)
+    k = 96                         # three graph launches of 32 steps
+    g.iteration(k)
+    rho, ux, uy = g.moments(0)
+    gm = g.mask()
+    rng = np.random.default_rng(77)
+    P, ring = 8, k + 2
+    W = P + 2 * ring
+    worst = 0.0
+    for _ in range(10):
+        px, py = int(rng.integers(0, w.nx)), int(rng.integers(0, w.ny))
+        x0, y0 = (px - ring) % w.nx, (py - ring) % w.ny
+        o = _window_oracle(w, x0, y0, W, w.tau, w.accel_x)
+        ys = (np.arange(ring, ring + P) + y0) % w.ny
+        xs = (np.arange(ring, ring + P) + x0) % w.nx
+        om = o.get_mask()[ring:ring + P, ring:ring + P]
+        assert np.array_equal(gm[np.ix_(ys, xs)], om)
+        o.iteration(k)
+        orr, ox, oy = o.moments(0)
+        sl = (slice(ring, ring + P), slice(ring, ring + P))
+        gu = np.stack([ux[np.ix_(ys, xs)], uy[np.ix_(ys, xs)]])
+        ou = np.stack([ox[sl], oy[sl]])
+        scale = max(np.abs(ox).max(), 1e-12)
+        worst = max(worst, float(np.abs(gu - ou).max() / scale))
+        fl = om == 0
+        if fl.any():
+            assert np.abs(rho[np.ix_(ys, xs)][fl] - orr[sl][fl]).max() <= 10 * tol_u
+    print(f"{storage}: worst patch rel u err {worst:.3e}")
+    assert worst <= tol_u
+
+
+def test_porous_4096_mass_conserved_fp32():
+    """A property at full size: the fluid mass is conserved by the FP32 run
+    to FP32 rounding of the stored deviations."""
+    from paper_1202_0442_amd import lb2d
+    import torch
+    w = inputs.porous(n=4096, seed=2)
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", w.nx, w.ny, w.tau)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        g.obstacle_circle(xc, yc, r)
+    g.aveacceleration(1, w.accel_x)
+    g.bind("f32", stream=torch.cuda.Stream())
+    b0 = g.budgets()
+    g.iteration(2000)
+    b1 = g.budgets()
+    assert abs(b1["mass0"] - b0["mass0"]) / b0["mass0"] < 1e-6
+    # momentum grows by at most the total force per step (walls take some)
+    assert 0 < b1["mom_x"] <= 2000 * w.accel_x * b0["mass0"] * (1 + 1e-6)
+
+
+def test_sc_solute_2048_properties():
+    """Two-component + solute at its full 2048^2 size: component masses and
+    the solute budget close; no growth yet in the first steps."""
+    from paper_1202_0442_amd import lb2d
+    import torch
+    w = inputs.sc_solute(n=2048)
+    e = w.extra
+    rho_a, rho_b = inputs.sc_initial_fields(w)
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", w.nx, w.ny, w.tau)
+    g.fluids(w.tau, e["tau2"])
+    g.solute(e["tau_s"], 9)
+    g.solute_opening("xlo", "dirichlet", e["C_in"])
+    g.solute_opening("xhi", "adiabatic", 0.0)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        g.obstacle_circle(xc, yc, r)
+    g.surface_reaction(e["kr"], e["Cs"], "growth", e["b0"], e["bmax"], e["rng_seed"])
+    g.set_fields(0, rho_a.ravel())
+    g.set_fields(1, rho_b.ravel())
+    g.interforce(e["G"])
+    g.adhesiveforce(e["Gads"][0], 0)
+    g.adhesiveforce(e["Gads"][1], 1)
+    g.bind("f32", stream=torch.cuda.Stream())
+    b0 = g.budgets()
+    g.iteration(640)
+    b1 = g.budgets()
+    for c in (0, 1):
+        assert abs(b1[f"mass{c}"] - b0[f"mass{c}"]) / b0[f"mass{c}"] < 1e-5
+    assert b1["inflow"] > 0
+    lhs = b1["solute"] + b1["deposit"] + b1["removed_solute"] + b1["consumed_deposit"]
+    rhs = b0["solute"] + b0["deposit"] + b1["inflow"] - b1["outflow"]
+    assert lhs == pytest.approx(rhs, rel=1e-5)
+    assert b1["grown_nodes"] == 0
