@@ -242,6 +242,11 @@ def main():
                      "bytes_rule": "72 B per fluid node (9 loads + 9 stores of 4 B) + 1 B mask per node"},
         "mflups": round(nfl * args.steps / (ms * 1e-3) / 1e6, 1),
     }
+    if traffic is not None:
+        # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        # scaled by a copy kernel of known size) at this launch's duration
+        out["roofline"]["traffic_GBps"] = round(traffic / (per * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(traffic / (per * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)
     mass_drift = None
     if not args.no_readout:
         b1 = L.budgets()

@@ -710,7 +710,6 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     }
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
     HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, s));
-    if (c->plain()) HIPCHK(c, launch_ghost_fill(c->storage, c->f[0][0], c->links, c->nx, c->ny, s));
     HIPCHK(c, launch_fill_f64(c->totals, 0.0, 16, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->ticket, 0, 8, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
@@ -889,10 +888,6 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
         HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    if (comp >= 0 && c->plain()) {
-        HIPCHK(c, launch_ghost_fill(c->storage, buf, c->links, c->nx, c->ny, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
     return LB2D_OK;
 }
 
@@ -923,8 +918,6 @@ int lb2d_set_mask(lb2d_ctx *c, const uint8_t *m) {
     HIPCHK(c, hipMemcpyAsync(c->mask, m, c->n(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_fill_u8(c->trig, 0, c->n(), c->stream));
     HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, c->stream));
-    if (c->plain())
-        HIPCHK(c, launch_ghost_fill(c->storage, c->f[c->t & 1][0], c->links, c->nx, c->ny, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LB2D_OK;
 }

@@ -11,9 +11,8 @@ enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 // One single-fluid lattice for the plain fused step (and for one entry of
 // the batched step).  Populations live in two buffers (two-lattice pull
-// scheme); f[p] holds [9][ny][nx] deviations f_i - w_i rho_ref.  Solid
-// nodes hold "ghost" values: the populations their fluid neighbours sent
-// towards them, already reversed, so that a plain pull bounces back.
+// scheme); f[p] holds [9][ny][nx] deviations f_i - w_i rho_ref (zero, and
+// never read, at solid nodes).
 struct PlainLattice {
     void *f[2];
     const uint16_t *links; // bit 0: node solid; bit i (1..8): node + e_i solid

@@ -59,9 +59,9 @@ __host__ __device__ constexpr R wgt(int i) {
 
 // ----------------------------------------------------------------- storage
 
-struct bf16s {
-    uint16_t u;
-};
+// bfloat16 bits (a distinct scalar type, so it can be read through any
+// address space)
+enum class bf16s : uint16_t {};
 
 template <typename S>
 struct Codec;
@@ -92,14 +92,14 @@ template <>
 struct Codec<bf16s> {
     using R = float;
     __device__ static float dec(bf16s v, int i) {
-        return __uint_as_float((uint32_t)v.u << 16) * iscale16(i);
+        return __uint_as_float((uint32_t)(uint16_t)v << 16) * iscale16(i);
     }
     __device__ static bf16s enc(float d, int i) {
         // round to nearest even on the upper 16 bits (NaN stays NaN)
         uint32_t u = __float_as_uint(d * scale16(i));
-        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16s{(uint16_t)((u >> 16) | 0x40u)};
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16s)(uint16_t)((u >> 16) | 0x40u);
         u += 0x7fffu + ((u >> 16) & 1u);
-        return bf16s{(uint16_t)(u >> 16)};
+        return (bf16s)(uint16_t)(u >> 16);
     }
 };
 
@@ -137,41 +137,120 @@ __device__ void block_sum(double (&v)[K], double *sh, double *out) {
 
 // ------------------------------------------------------- plain fused step
 
-// One node of the single-fluid step: pull, moments, velocity-shift forcing,
-// BGK relaxation to Eq. (eq), store.  Populations are deviations
-// d_i = f_i - w_i rho_ref, so rho = rho_ref + sum d_i and j = sum d_i e_i;
-// the equilibrium deviation is w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)].
+// One node of the single-fluid step: pull with half-way bounce-back,
+// moments, velocity-shift forcing, BGK relaxation to Eq. (eq), store.
+// Populations are deviations d_i = f_i - w_i rho_ref, so
+// rho = rho_ref + sum d_i and j = sum d_i e_i; the equilibrium deviation is
+// w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)].
 //
-// Half-way bounce-back (boundary_style noslip) without any mask test in the
-// pull: when node + e_i is solid the node also stores its post-collision
-// f_i into that solid node's slot of direction opp(i).  The only node that
-// ever pulls that slot is this node itself (it pulls f_opp(i) from
-// node - e_opp(i) = node + e_i), so the next step's plain pull returns
-// f_opp(i) = f_i^post -- the bounce-back -- and all nine loads of a node are
-// independent and issued together.  Each (solid node, direction) slot has
-// exactly one writer and one reader.
+// Memory behaviour:
+//  * one 16-bit link word per node says which of the 8 neighbours are
+//    solid, so the nine population addresses (own opposite population when
+//    the source is solid: noslip bounce-back) are known after one load and
+//    the nine loads are issued together;
+//  * a wavefront with at least one fluid lane stores all its lanes (solid
+//    lanes store zeros, which nothing ever reads), so every store writes
+//    whole 128-byte lines -- partial lines along obstacle edges would make
+//    HBM read-modify-write them; wavefronts that are entirely solid do no
+//    memory work at all.
+// Pointers known to address global memory (so the compiler emits global_*
+// rather than flat_* instructions for pointers read from device tables).
+#define LB2D_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ LB2D_GLOBAL T *gbl(T *p) {
+    return (LB2D_GLOBAL T *)p;
+}
+
+// Wavefront-uniform copy of one step's lattice parameters (scalar registers).
 template <typename S>
-__device__ __forceinline__ void plain_node(const PlainLattice &L, int parity, int x, int y) {
+struct PlainArgs {
+    const S *fin;
+    S *fout;
+    const uint16_t *links;
+    unsigned nx, ny;
+    double omega, tau, Fx, Fy, ax, ay, rho_ref;
+};
+
+__device__ __forceinline__ unsigned ufl(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long ufl64(unsigned long long v) {
+    return ((unsigned long long)ufl((unsigned)(v >> 32)) << 32) | ufl((unsigned)v);
+}
+__device__ __forceinline__ double ufld(double v) { return __longlong_as_double((long long)ufl64((unsigned long long)__double_as_longlong(v))); }
+template <typename T>
+__device__ __forceinline__ T *uflp(T *p) { return (T *)ufl64((unsigned long long)p); }
+
+// Parameters of lattice L at the given parity; `uniform` forces them into
+// scalar registers when L was read from memory.
+template <typename S>
+__device__ __forceinline__ PlainArgs<S> plain_args(const PlainLattice &L, int parity) {
+    PlainArgs<S> a;
+    a.fin = (const S *)(parity ? L.f[1] : L.f[0]);
+    a.fout = (S *)(parity ? L.f[0] : L.f[1]);
+    a.links = L.links;
+    a.nx = (unsigned)L.nx;
+    a.ny = (unsigned)L.ny;
+    a.omega = L.omega;
+    a.tau = L.tau;
+    a.Fx = L.Fx;
+    a.Fy = L.Fy;
+    a.ax = L.ax;
+    a.ay = L.ay;
+    a.rho_ref = L.rho_ref;
+    return a;
+}
+
+template <typename S>
+__device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
+    a.fin = uflp(a.fin);
+    a.fout = uflp(a.fout);
+    a.links = uflp(a.links);
+    a.nx = ufl(a.nx);
+    a.ny = ufl(a.ny);
+    a.omega = ufld(a.omega);
+    a.tau = ufld(a.tau);
+    a.Fx = ufld(a.Fx);
+    a.Fy = ufld(a.Fy);
+    a.ax = ufld(a.ax);
+    a.ay = ufld(a.ay);
+    a.rho_ref = ufld(a.rho_ref);
+    return a;
+}
+
+template <typename S>
+__device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside) {
     using C = Codec<S>;
     using R = typename C::R;
-    const unsigned nx = (unsigned)L.nx, ny = (unsigned)L.ny;
-    const unsigned s = (unsigned)y * nx + (unsigned)x;
-    const unsigned lk = L.links[s];
-    if (lk & 1u) return;
+    const unsigned nx = L.nx, ny = L.ny;
+    const unsigned s = inside ? (unsigned)y * nx + (unsigned)x : 0u;
+    const unsigned lk = inside ? (unsigned)gbl(L.links)[s] : 1u;
+    const bool fluid = (lk & 1u) == 0u;
+    if (!__any(fluid)) return;
+    if (!inside) return;
     const size_t plane = (size_t)nx * ny;
-    const S *__restrict__ fin = (const S *)L.f[parity];
-    S *__restrict__ fout = (S *)L.f[parity ^ 1];
+    const LB2D_GLOBAL S *__restrict__ fin = gbl(L.fin);
+    LB2D_GLOBAL S *__restrict__ fout = gbl(L.fout);
 
-    const unsigned xm = (x == 0) ? nx - 1 : (unsigned)x - 1;
-    const unsigned xp = ((unsigned)x == nx - 1) ? 0 : (unsigned)x + 1;
-    const unsigned rm = ((y == 0) ? ny - 1 : (unsigned)y - 1) * nx;
-    const unsigned r0 = (unsigned)y * nx;
-    const unsigned rp = (((unsigned)y == ny - 1) ? 0 : (unsigned)y + 1) * nx;
-    // node - e_i for each direction (so node + e_i = src[opp(i)])
-    const unsigned src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
     R d[9];
+    if (fluid) {
+        const unsigned xm = (x == 0) ? nx - 1 : (unsigned)x - 1;
+        const unsigned xp = ((unsigned)x == nx - 1) ? 0 : (unsigned)x + 1;
+        const unsigned rm = ((y == 0) ? ny - 1 : (unsigned)y - 1) * nx;
+        const unsigned r0 = (unsigned)y * nx;
+        const unsigned rp = (((unsigned)y == ny - 1) ? 0 : (unsigned)y + 1) * nx;
+        // node - e_i for each direction
+        const unsigned src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+        d[0] = C::dec(fin[s], 0);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = C::dec(fin[(size_t)i * plane + src[i]], i);
+        for (int i = 1; i < 9; ++i) {
+            // node - e_i is node + e_opp(i): solid -> bounce-back
+            const bool wall = (lk >> opp(i)) & 1u;
+            const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
+            d[i] = C::dec(fin[a], i);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = R(0);
+    }
     R drho = 0, jx = 0, jy = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -191,9 +270,8 @@ __device__ __forceinline__ void plain_node(const PlainLattice &L, int parity, in
     for (int i = 0; i < 9; ++i) {
         const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
         const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
-        const S v = C::enc(d[i] + omega * (deq - d[i]), i);
-        fout[(size_t)i * plane + s] = v;
-        if (i > 0 && (lk & (1u << i))) fout[(size_t)opp(i) * plane + src[opp(i)]] = v;
+        const R v = fluid ? d[i] + omega * (deq - d[i]) : R(0);
+        fout[(size_t)i * plane + s] = C::enc(v, i);
     }
 }
 
@@ -201,8 +279,7 @@ template <typename S>
 __global__ void __launch_bounds__(1024) k_plain(PlainLattice L, int parity) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= L.nx || y >= L.ny) return;
-    plain_node<S>(L, parity, x, y);
+    plain_node<S>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny);
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
@@ -212,11 +289,12 @@ __global__ void __launch_bounds__(1024) k_batch(const PlainLattice *__restrict__
                                                const Tile *__restrict__ tiles, int ntiles,
                                                int parity) {
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = tiles[t];
-        const PlainLattice L = lat[tl.lattice];
-        const int x = tl.x0 + threadIdx.x;
-        const int y = tl.y0 + threadIdx.y;
-        if (x < L.nx && y < L.ny) plain_node<S>(L, parity, x, y);
+        const int li = (int)ufl((unsigned)tiles[t].lattice);
+        const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
+        const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
+        const int x = x0 + threadIdx.x;
+        const int y = y0 + threadIdx.y;
+        plain_node<S>(a, x, y, x < (int)a.nx && y < (int)a.ny);
     }
 }
 
@@ -296,6 +374,9 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
     __syncthreads();
 
     const bool solid = !valid || smask[ly + 2][lx + 2];
+    // wavefronts with a fluid lane store whole lines (solid lanes write
+    // zeros that nothing reads); all-solid wavefronts store nothing
+    const bool wave_fluid = __any(!solid);
     const size_t s = valid ? (size_t)y * nx + x : 0;
     const int xm = (x == 0) ? nx - 1 : x - 1;
     const int xp = (x >= nx - 1) ? 0 : x + 1;
@@ -513,7 +594,20 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
                 gout[(size_t)i * plane + s] = C::enc(g[i] + oms * (geq - g[i]), i);
             }
         }
-    } else if (valid && REACT) {
+    } else if (valid && wave_fluid) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fout[(size_t)i * plane + s] = C::enc(R(0), i);
+        }
+        if constexpr (SOL) {
+            S *__restrict__ gout = (S *)p.g[parity ^ 1];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) gout[(size_t)i * plane + s] = C::enc(R(0), i);
+        }
+    }
+    if (valid && solid && REACT) {
         // 7. solid node: gather the deposit of its reactive links, then
         // decide growth from the post-deposit value.
         bool fluid8 = false, fluid4 = false;
@@ -684,23 +778,6 @@ __global__ void k_links(const uint8_t *__restrict__ mask, uint16_t *__restrict__
         if (mask[(size_t)gy * nx + gx]) v |= 1u << i;
     }
     links[(size_t)y * nx + x] = (uint16_t)v;
-}
-
-// Fills the ghost slots of buffer f from the fluid nodes' own populations
-// (the state a bounce-back would return), e.g. after initialisation.
-template <typename S>
-__global__ void k_ghost_fill(S *f, const uint16_t *__restrict__ links, int nx, int ny) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= nx) return;
-    const size_t plane = (size_t)nx * ny, s = (size_t)y * nx + x;
-    const unsigned lk = links[s];
-    if (lk & 1u) return;
-#pragma unroll
-    for (int i = 1; i < 9; ++i)
-        if (lk & (1u << i)) {
-            const size_t nb = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(x + ex(i), nx);
-            f[(size_t)opp(i) * plane + nb] = f[(size_t)i * plane + s];
-        }
 }
 
 // ---------------------------------------------------------- set-up kernels
@@ -1098,11 +1175,6 @@ hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, doubl
 }
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s) {
     hipLaunchKernelGGL(k_links, dim3((nx + 255) / 256, ny), dim3(256), 0, s, mask, links, nx, ny);
-    return hipGetLastError();
-}
-hipError_t launch_ghost_fill(int st, void *f, const uint16_t *links, int nx, int ny, hipStream_t s) {
-    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_ghost_fill<S>, dim3((nx + 255) / 256, ny), dim3(256), 0, s, (S *)f, links,
-                                         nx, ny));
     return hipGetLastError();
 }
 hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s) {

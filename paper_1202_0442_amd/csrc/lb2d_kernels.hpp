@@ -30,7 +30,6 @@ hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hi
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
                                double shift, hipStream_t s);
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s);
-hipError_t launch_ghost_fill(int st, void *f, const uint16_t *links, int nx, int ny, hipStream_t s);
 hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s);
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
                           hipStream_t s);

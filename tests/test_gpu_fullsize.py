@@ -19,12 +19,14 @@ pytestmark = pytest.mark.gpu
 
 def _window_oracle(w, x0, y0, W, tau, accel):
     """Oracle lattice for the global window [x0, x0+W) x [y0, y0+W)
-    (periodic wrap of the global box), with the discs that touch it."""
+    (periodic wrap of the global box), with the discs that touch it.  The
+    window is itself periodic, so results are exact only away from its
+    edges (see the ring below)."""
     o = Oracle(W, W)
     o.fluids(1, tau)
     o.aveacceleration(1, accel)
     nx, ny = w.nx, w.ny
-    for (xc, yc, r) in w.discs:
+    for (xc, yc, r) in w.discs:  # every disc that reaches into the window
         dx = (xc - x0) % nx
         dy = (yc - y0) % ny
         if dx > nx / 2:
@@ -37,7 +39,7 @@ def _window_oracle(w, x0, y0, W, tau, accel):
     return o
 
 
-@pytest.mark.parametrize("storage,tol_u", [("f32", 1e-5), ("f16", 5e-2)])
+@pytest.mark.parametrize("storage,tol_u", [("f64", 1e-11), ("f32", 1e-5), ("f16", 5e-2)])
 def test_porous_4096_sampled_patches(storage, tol_u):
     from paper_1202_0442_amd import lb2d
     import torch
@@ -55,9 +57,13 @@ def test_porous_4096_sampled_patches(storage, tol_u):
     rho, ux, uy = g.moments(0)
     gm = g.mask()
     rng = np.random.default_rng(77)
-    P, ring = 8, k + 2
+    # discs centred just outside the oracle's periodic window wrap onto its
+    # far side, so spurious solids lie up to 2 r_max + 1 nodes inside every
+    # window edge; the ring keeps them out of the patch's light cone
+    P, ring = 8, k + 2 * 24 + 2
     W = P + 2 * ring
     worst = 0.0
+    info = []
     for _ in range(10):
         px, py = int(rng.integers(0, w.nx)), int(rng.integers(0, w.ny))
         x0, y0 = (px - ring) % w.nx, (py - ring) % w.ny
@@ -72,12 +78,17 @@ def test_porous_4096_sampled_patches(storage, tol_u):
         gu = np.stack([ux[np.ix_(ys, xs)], uy[np.ix_(ys, xs)]])
         ou = np.stack([ox[sl], oy[sl]])
         scale = max(np.abs(ox).max(), 1e-12)
-        worst = max(worst, float(np.abs(gu - ou).max() / scale))
+        err = float(np.abs(gu - ou).max() / scale)
+        if err > worst:
+            k_ = np.unravel_index(np.argmax(np.abs(gu - ou)), gu.shape)
+            info.append(f"patch ({px},{py}) err {err:.3e} at {k_}: gpu {gu[k_]:.9e} oracle {ou[k_]:.9e} "
+                        f"max|u| {scale:.3e} solid in patch {int(om.sum())}")
+        worst = max(worst, err)
         fl = om == 0
         if fl.any():
             assert np.abs(rho[np.ix_(ys, xs)][fl] - orr[sl][fl]).max() <= 10 * tol_u
     print(f"{storage}: worst patch rel u err {worst:.3e}")
-    assert worst <= tol_u
+    assert worst <= tol_u, "\n".join(info)
 
 
 def test_porous_4096_mass_conserved_fp32():
