@@ -35,10 +35,15 @@ def log(msg):
 
 
 def source_hash():
+    """Hash of the code the one-fluid step kernel is built from: the shared
+    parameter header and the kernel file up to the general step."""
+    csrc = os.path.join(ROOT, "paper_1202_0442_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("lb2d_kernels.hip", "lb2d_common.hpp"):
-        with open(os.path.join(ROOT, "paper_1202_0442_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "lb2d_common.hpp"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "lb2d_kernels.hip"), "rb") as fh:
+        src = fh.read()
+    h.update(src[:src.index(b"// --------------------------------------------------------- general step")])
     return h.hexdigest()[:16]
 
 

@@ -76,7 +76,6 @@ struct lb2d_ctx {
     uint16_t *links = nullptr;
     double *b = nullptr, *staging = nullptr, *partial = nullptr, *gpartial = nullptr;
     double *totals = nullptr;
-    unsigned *ticket = nullptr;
     long long *dstep = nullptr;
     size_t staging_doubles = 0;
     double rho_ref[2] = {1.0, 1.0};
@@ -143,7 +142,7 @@ bool is_nan(double v) { return std::isnan(v); }
 
 // Workspace layout of one lattice.
 struct Layout {
-    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, ticket, dstep, total;
+    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, total;
     size_t staging_doubles;
 };
 
@@ -183,8 +182,6 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     off += align_up((size_t)growth_blocks(c->nx, c->ny) * 4 * 8);
     L.totals = off;
     off += align_up(16 * 8);
-    L.ticket = off;
-    off += align_up(8);
     L.dstep = off;
     off += align_up(8);
     L.total = off;
@@ -203,7 +200,6 @@ FullParams full_params(const lb2d_ctx *c) {
     p.partial = c->partial;
     p.gpartial = c->gpartial;
     p.totals = c->totals;
-    p.ticket = c->ticket;
     p.dstep = c->dstep;
     p.nx = c->nx;
     p.ny = c->ny;
@@ -648,7 +644,6 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->partial = (double *)(c->ws + L.partial);
     c->gpartial = (double *)(c->ws + L.gpartial);
     c->totals = (double *)(c->ws + L.totals);
-    c->ticket = (unsigned *)(c->ws + L.ticket);
     c->dstep = (long long *)(c->ws + L.dstep);
     const size_t n = c->n();
     hipStream_t s = c->stream;
@@ -711,7 +706,8 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
     HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, s));
     HIPCHK(c, launch_fill_f64(c->totals, 0.0, 16, s));
-    HIPCHK(c, launch_fill_u8((uint8_t *)c->ticket, 0, 8, s));
+    HIPCHK(c, launch_fill_f64(c->partial, 0.0, (size_t)full_tiles(c->nx, c->ny) * 4, s));
+    HIPCHK(c, launch_fill_f64(c->gpartial, 0.0, (size_t)growth_blocks(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->t = 0;
@@ -818,6 +814,7 @@ int lb2d_budgets(lb2d_ctx *c, double *out) {
     double *out8 = c->staging + (size_t)c->ny * 8;
     HIPCHK(c, launch_budgets(c->storage, p, (int)(c->t & 1), c->q ? 1 : 0, c->reaction ? 1 : 0, part, out8,
                              c->stream));
+    if (c->q) HIPCHK(c, launch_tally_final(p, c->stream));
     double v8[8], tot[16];
     HIPCHK(c, hipMemcpyAsync(v8, out8, sizeof(v8), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(tot, c->totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));

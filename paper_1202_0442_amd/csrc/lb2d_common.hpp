@@ -40,10 +40,9 @@ struct FullParams {
     uint8_t *mask;        // 1 = solid
     uint8_t *trig;        // growth trigger: 0 or 1..4 = direction to grow
     double *b;            // deposits, FP64, [ny][nx]
-    double *partial;      // per-block tallies of the step kernel [nblk][4]
-    double *gpartial;     // per-block tallies of the growth kernel [nblk][4]
-    double *totals;       // running FP64 tallies (LB2D_B_* indices)
-    unsigned *ticket;     // last-block counter of the growth kernel
+    double *partial;      // running per-block tallies of the step kernel [nblk][4]
+    double *gpartial;     // running per-block tallies of the growth kernel [nblk][4]
+    double *totals;       // fixed-order sums of the tallies (LB2D_B_* indices)
     long long *dstep;     // completed steps (device copy)
     int nx, ny;
     int ncomp;

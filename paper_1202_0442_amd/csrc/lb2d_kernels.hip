@@ -345,38 +345,51 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
     return (k < len) ? start + k : -1;
 }
 
-template <typename S, int NC, bool SC, bool SOL, bool REACT>
-__global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
+// General fused step.  One thread per node of a TX x TY tile:
+//  1. pull both components (fluid lanes), bounce-back from the LDS mask;
+//  2. densities of the tile plus a one-node halo in LDS -- the halo nodes'
+//     populations are pulled again (from L2) so that the Shan-Chen force
+//     sees the post-stream densities of this step;
+//  3. forces (aveforce, aveacceleration, cohesion, adhesion), the common
+//     velocity u' and each component's equilibrium velocity, collision;
+//  4. solute: pull, bounce-back or reactive link, x openings, collision at
+//     the solvent velocity of Eq. (u_solvent);
+//  5. solid lanes next to fluid gather the deposit of their reactive links
+//     and decide growth.
+// Every plane is written by ONE store per wavefront (solid lanes of a
+// wavefront with fluid lanes write zeros), so no line is written twice in
+// part; all-solid wavefronts store nothing.
+template <typename S, int NC, bool SC, bool SOL, bool REACT, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
-    __shared__ uint8_t smask[kTY + 4][kTX + 4];
-    __shared__ R srho[SC ? NC : 1][kTY + 2][kTX + 2];
-    __shared__ double sred[(kTX * kTY / 64) * 4];
+    __shared__ uint8_t smask[TY + 4][TX + 4];
+    __shared__ R srho[SC ? NC : 1][TY + 2][TX + 2];
+    __shared__ double sred[(TX * TY / 64) * 4];
 
     const int nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)nx * ny;
-    const int tiles_x = (nx + kTX - 1) / kTX;
-    const int nblk = gridDim.x;
-    int tile = xcd_band(blockIdx.x, nblk);
-    if (tile < 0) tile = blockIdx.x;  // (never: launch uses nblk tiles)
-    const int tx0 = (tile % tiles_x) * kTX, ty0 = (tile / tiles_x) * kTY;
+    const int tiles_x = (nx + TX - 1) / TX;
+    int tile = xcd_band(blockIdx.x, gridDim.x);
+    if (tile < 0) tile = blockIdx.x;
+    const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
     const int tid = threadIdx.x;
-    const int lx = tid % kTX, ly = tid / kTX;
+    const int lx = tid % TX, ly = tid / TX;
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = (x < nx) && (y < ny);
 
     // mask tile with a two-node halo (periodic wrap)
-    for (int k = tid; k < (kTX + 4) * (kTY + 4); k += kTX * kTY) {
-        const int hx = k % (kTX + 4), hy = k / (kTX + 4);
+    for (int k = tid; k < (TX + 4) * (TY + 4); k += TX * TY) {
+        const int hx = k % (TX + 4), hy = k / (TX + 4);
         const int gx = wrapi(tx0 + hx - 2, nx), gy = wrapi(ty0 + hy - 2, ny);
         smask[hy][hx] = p.mask[(size_t)gy * nx + gx];
     }
     __syncthreads();
 
     const bool solid = !valid || smask[ly + 2][lx + 2];
-    // wavefronts with a fluid lane store whole lines (solid lanes write
-    // zeros that nothing reads); all-solid wavefronts store nothing
-    const bool wave_fluid = __any(!solid);
+    const bool fluid = !solid;
+    const bool wave_fluid = __any(fluid);
+    const bool store = valid && wave_fluid;
     const size_t s = valid ? (size_t)y * nx + x : 0;
     const int xm = (x == 0) ? nx - 1 : x - 1;
     const int xp = (x >= nx - 1) ? 0 : x + 1;
@@ -390,8 +403,9 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
     R drho[NC], jx[NC], jy[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        drho[c] = jx[c] = jy[c] = R(0);
-        if (!solid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[c][i] = R(0);
+        if (fluid) {
             const S *__restrict__ fin = (const S *)p.f[parity][c];
             d[c][0] = ldpop(fin, s, 0);
 #pragma unroll
@@ -400,12 +414,13 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
                 const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
                 d[c][i] = ldpop(fin, a, i);
             }
+        }
+        drho[c] = jx[c] = jy[c] = R(0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                drho[c] += d[c][i];
-                if (ex(i)) jx[c] += ex(i) > 0 ? d[c][i] : -d[c][i];
-                if (ey(i)) jy[c] += ey(i) > 0 ? d[c][i] : -d[c][i];
-            }
+        for (int i = 0; i < 9; ++i) {
+            drho[c] += d[c][i];
+            if (ex(i)) jx[c] += ex(i) > 0 ? d[c][i] : -d[c][i];
+            if (ey(i)) jy[c] += ey(i) > 0 ? d[c][i] : -d[c][i];
         }
     }
 
@@ -415,9 +430,9 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : R(p.rho_ref[c]) + drho[c];
-        for (int k = tid; k < (kTX + 2) * (kTY + 2); k += kTX * kTY) {
-            const int hx = k % (kTX + 2), hy = k / (kTX + 2);
-            const bool inner = hx >= 1 && hx <= kTX && hy >= 1 && hy <= kTY;
+        for (int k = tid; k < (TX + 2) * (TY + 2); k += TX * TY) {
+            const int hx = k % (TX + 2), hy = k / (TX + 2);
+            const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
             if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
             const int gx = wrapi(tx0 + hx - 1, nx), gy = wrapi(ty0 + hy - 1, ny);
             const bool hsolid = smask[hy + 1][hx + 1] != 0;
@@ -430,7 +445,7 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
                 const size_t hrm = (size_t)((gy == 0) ? ny - 1 : gy - 1) * nx;
                 const size_t hr0 = (size_t)gy * nx;
                 const size_t hrp = (size_t)((gy == ny - 1) ? 0 : gy + 1) * nx;
-                const size_t hsrc[9] = {hs,         hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
+                const size_t hsrc[9] = {hs,        hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
                                         hrm + gxm, hrm + gxp, hrp + gxp, hrp + gxm};
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -452,16 +467,16 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
     }
 
     double tal[4] = {0.0, 0.0, 0.0, 0.0};  // inflow, outflow, consumed deposit
-    if (valid && !solid) {
-        // 3. forces
-        R rho[NC], Fx[NC], Fy[NC];
+    // 3. forces (solid lanes compute throw-away values from zero populations)
+    R rho[NC], Fx[NC], Fy[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            rho[c] = R(p.rho_ref[c]) + drho[c];
-            Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
-            Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
-        }
-        if constexpr (SC && NC == 2) {
+    for (int c = 0; c < NC; ++c) {
+        rho[c] = R(p.rho_ref[c]) + drho[c];
+        Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
+        Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
+    }
+    if constexpr (SC && NC == 2) {
+        if (valid) {
             R sx[2] = {R(0), R(0)}, sy[2] = {R(0), R(0)};
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
@@ -478,133 +493,124 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
                 Fy[c] += -R(p.G) * rho[c] * sy[c];
             }
         }
-        if (p.has_ads) {
-            R ax = R(0), ay = R(0);
+    }
+    if (p.has_ads) {
+        R ax = R(0), ay = R(0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
+            if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
+            if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
+            Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
+        }
+    }
+    // 4. common velocity u' and per-component equilibrium velocities
+    R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const R om = R(p.omega[c]);
+        nux += jx[c] * om;
+        nuy += jy[c] * om;
+        den += rho[c] * om;
+        sjx += jx[c] + R(0.5) * Fx[c];
+        sjy += jy[c] + R(0.5) * Fy[c];
+        srh += rho[c];
+    }
+    const R upx = nux / den, upy = nuy / den;
+    // 5. collide and store (one store per plane for the whole wavefront)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+        const R tau = R(p.tau[c]), om = R(p.omega[c]);
+        const R ux = upx + tau * Fx[c] / rho[c];
+        const R uy = upy + tau * Fy[c] / rho[c];
+        const R usq = R(1.5) * (ux * ux + uy * uy);
+        const R rr = R(p.rho_ref[c]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
+            const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
+            const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
+            const R v = fluid ? d[c][i] + om * (deq - d[c][i]) : R(0);
+            if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
+        }
+    }
+    // 6. solute: pull, walls / reactive links / openings, collide
+    if constexpr (SOL) {
+        const R usx = sjx / srh, usy = sjy / srh;
+        const S *__restrict__ gin = (const S *)p.g[parity];
+        S *__restrict__ gout = (S *)p.g[parity ^ 1];
+        R g[9];
+        bool unk[9];
+        bool any_unk = false;
+        const R kr = R(p.kr), Cs = R(p.Cs);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            unk[i] = false;
+            g[i] = R(0);
+            if (!fluid) continue;
+            const int sxr = x - ex(i);
+            if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
+                unk[i] = true;
+                any_unk = true;
+                continue;
+            }
+            const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
+            if (wall) {
+                const R g_out = ldpop(gin, (size_t)opp(i) * plane + s, opp(i));
+                R gi = g_out;
+                if constexpr (REACT) reactive_link<R>(i, kr, Cs, g_out, gi);
+                g[i] = gi;
+            } else {
+                g[i] = ldpop(gin, (size_t)i * plane + src[i], i);
+            }
+        }
+        if (any_unk) {
+            const int side = (x == 0) ? 0 : 1;
+            if (p.open_style[side] == 1) {
+                R known = R(0), wu = R(0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    if (unk[i]) wu += wgt<R>(i);
+                    else known += g[i];
+                }
+                const R deficit = R(p.open_value[side]) - known;
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    if (unk[i]) {
+                        g[i] = wgt<R>(i) / wu * deficit;
+                        tal[0] += (double)g[i];
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    if (unk[i]) {
+                        g[i] = g[mirx(i)];
+                        tal[0] += (double)g[i];
+                    }
+            }
+        }
+        if (fluid && !p.solute_xper && (x == 0 || x == nx - 1)) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
-                if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
-                if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
-                Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
+                const int dx = x + ex(i);
+                if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)i * plane + s, i);
             }
         }
-        // 4. common velocity u' and per-component equilibrium velocities
-        R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
+        R Cc = R(0);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const R om = R(p.omega[c]);
-            nux += jx[c] * om;
-            nuy += jy[c] * om;
-            den += rho[c] * om;
-            sjx += jx[c] + R(0.5) * Fx[c];
-            sjy += jy[c] + R(0.5) * Fy[c];
-            srh += rho[c];
-        }
-        const R upx = nux / den, upy = nuy / den;
-        // 5. collide and store
+        for (int i = 0; i < 9; ++i) Cc += g[i];
+        const R oms = R(p.omega_s);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
-            const R tau = R(p.tau[c]), om = R(p.omega[c]);
-            const R ux = upx + tau * Fx[c] / rho[c];
-            const R uy = upy + tau * Fy[c] / rho[c];
-            const R usq = R(1.5) * (ux * ux + uy * uy);
-            const R rr = R(p.rho_ref[c]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
-                const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
-                const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
-                fout[(size_t)i * plane + s] = C::enc(d[c][i] + om * (deq - d[c][i]), i);
-            }
-        }
-        // 6. solute: pull, walls / reactive links / openings, collide
-        if constexpr (SOL) {
-            const R usx = sjx / srh, usy = sjy / srh;
-            const S *__restrict__ gin = (const S *)p.g[parity];
-            S *__restrict__ gout = (S *)p.g[parity ^ 1];
-            R g[9];
-            bool unk[9];
-            bool any_unk = false;
-            const R kr = R(p.kr), Cs = R(p.Cs);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                unk[i] = false;
-                const int sxr = x - ex(i);
-                if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
-                    unk[i] = true;
-                    any_unk = true;
-                    g[i] = R(0);
-                    continue;
-                }
-                const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
-                if (wall) {
-                    const R g_out = ldpop(gin, (size_t)opp(i) * plane + s, opp(i));
-                    R gi = g_out;
-                    if constexpr (REACT) reactive_link<R>(i, kr, Cs, g_out, gi);
-                    g[i] = gi;
-                } else {
-                    g[i] = ldpop(gin, (size_t)i * plane + src[i], i);
-                }
-            }
-            if (any_unk) {
-                const int side = (x == 0) ? 0 : 1;
-                if (p.open_style[side] == 1) {
-                    R known = R(0), wu = R(0);
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        if (unk[i]) wu += wgt<R>(i);
-                        else known += g[i];
-                    }
-                    const R deficit = R(p.open_value[side]) - known;
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (unk[i]) {
-                            g[i] = wgt<R>(i) / wu * deficit;
-                            tal[0] += (double)g[i];
-                        }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (unk[i]) {
-                            g[i] = g[mirx(i)];
-                            tal[0] += (double)g[i];
-                        }
-                }
-            }
-            if (!p.solute_xper && (x == 0 || x == nx - 1)) {
-#pragma unroll
-                for (int i = 1; i < 9; ++i) {
-                    const int dx = x + ex(i);
-                    if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)i * plane + s, i);
-                }
-            }
-            R Cc = R(0);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Cc += g[i];
-            const R oms = R(p.omega_s);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const R eu = R(ex(i)) * usx + R(ey(i)) * usy;
-                const R geq = wgt<R>(i) * Cc * (R(1) + R(3) * eu);
-                gout[(size_t)i * plane + s] = C::enc(g[i] + oms * (geq - g[i]), i);
-            }
-        }
-    } else if (valid && wave_fluid) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fout[(size_t)i * plane + s] = C::enc(R(0), i);
-        }
-        if constexpr (SOL) {
-            S *__restrict__ gout = (S *)p.g[parity ^ 1];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) gout[(size_t)i * plane + s] = C::enc(R(0), i);
+        for (int i = 0; i < 9; ++i) {
+            const R eu = R(ex(i)) * usx + R(ey(i)) * usy;
+            const R geq = wgt<R>(i) * Cc * (R(1) + R(3) * eu);
+            const R v = fluid ? g[i] + oms * (geq - g[i]) : R(0);
+            if (store) gout[(size_t)i * plane + s] = C::enc(v, i);
         }
     }
     if (valid && solid && REACT) {
@@ -638,13 +644,16 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
             if (fluid4) {
                 // candidates: E, N, W, S that are fluid, inside the solute
                 // domain and not on an open solute column
-                int cand[4];
+                unsigned candbits = 0;
                 int m = 0;
 #pragma unroll
                 for (int i = 1; i <= 4; ++i) {
                     const int cx = x + ex(i);
                     if (!p.solute_xper && (cx <= 0 || cx >= nx - 1)) continue;
-                    if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) cand[m++] = i;
+                    if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
+                        candbits |= 1u << i;
+                        ++m;
+                    }
                 }
                 uint8_t code = 0;
                 if (bn > p.bmax && m > 0) {
@@ -652,7 +661,14 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
                     const unsigned long long h =
                         splitmix64(p.seed ^ (t * (unsigned long long)plane + (unsigned long long)s));
                     const int k = (int)(((h >> 32) * (unsigned long long)m) >> 32);
-                    code = (uint8_t)cand[k];
+                    // the k-th candidate in E, N, W, S order
+                    int seen = 0;
+#pragma unroll
+                    for (int i = 1; i <= 4; ++i)
+                        if (candbits & (1u << i)) {
+                            if (seen == k) code = (uint8_t)i;
+                            ++seen;
+                        }
                     tal[2] += bn;
                     bn = 0.0;
                 }
@@ -663,36 +679,40 @@ __global__ void __launch_bounds__(kTX *kTY) k_full(FullParams p, int parity) {
     }
 
     if constexpr (SOL) {
-        double out[4];
-        block_sum<4>(tal, sred, out);
-        if (tid == 0) {
-            double *dst = p.partial + (size_t)blockIdx.x * 4;
-            dst[0] = out[0];
-            dst[1] = out[1];
-            dst[2] = out[2];
-            dst[3] = 0.0;
+        // running per-block tallies (inflow, outflow, consumed deposit):
+        // each block owns one slot and adds its step's sum in step order;
+        // the slots are summed in a fixed order only when budgets are read
+        const bool has = tal[0] != 0.0 || tal[1] != 0.0 || tal[2] != 0.0;
+        if (__syncthreads_or(has)) {
+            double out[4];
+            block_sum<4>(tal, sred, out);
+            if (tid == 0) {
+                double *dst = p.partial + (size_t)blockIdx.x * 4;
+                dst[0] += out[0];
+                dst[1] += out[1];
+                dst[2] += out[2];
+            }
         }
     }
 }
 
 // Growth: a fluid node turns solid when a direct neighbour's trigger points
 // at it; its populations' mass is tallied as removed, it gets deposit b0.
-// The last block to finish sums every block's tallies in a fixed order into
-// the running totals and advances the device step counter.
+// Per-block running tallies as in the step kernel; block 0 advances the
+// device step counter (read by the next step's growth decisions).
 template <typename S, int NC, bool REACT>
 __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     using C = Codec<S>;
     __shared__ double sred[4 * 4];
-    __shared__ bool last;
     const int nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)nx * ny;
     const int x = blockIdx.x * 256 + threadIdx.x;  // one row segment
     const int y = blockIdx.y;
     double tal[4] = {0.0, 0.0, 0.0, 0.0};
+    bool grow = false;
     if constexpr (REACT) {
         if (x < nx && !p.mask[(size_t)y * nx + x]) {
             const size_t s = (size_t)y * nx + x;
-            bool grow = false;
 #pragma unroll
             for (int k = 1; k <= 4; ++k) {
                 const int sx = x + ex(k);
@@ -719,49 +739,45 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
             }
         }
     }
-    const int blin = blockIdx.x + blockIdx.y * gridDim.x;
-    double out[4];
-    block_sum<4>(tal, sred, out);
-    if (threadIdx.x == 0) {
-        double *dst = p.gpartial + (size_t)blin * 4;
-        for (int k = 0; k < 4; ++k) dst[k] = out[k];
-        __threadfence();
-        const unsigned done = atomicAdd(p.ticket, 1u);
-        last = (done == (unsigned)(gridDim.x * gridDim.y) - 1u);
+    if (__syncthreads_or(grow)) {
+        double out[4];
+        block_sum<4>(tal, sred, out);
+        if (threadIdx.x == 0) {
+            double *dst = p.gpartial + (size_t)(blockIdx.x + blockIdx.y * gridDim.x) * 4;
+            for (int k = 0; k < 4; ++k) dst[k] += out[k];
+        }
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // fixed-order sums over all block partials
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.dstep += 1;
+}
+
+// Sums the per-block running tallies in a fixed order into totals
+// (LB2D_B_* indices 6..10, 12, 14).
+__global__ void __launch_bounds__(256) k_tally_final(FullParams p) {
+    __shared__ double sred[4 * 8];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < p.nblk_main; k += 256) {
-        const volatile double *q = p.partial + (size_t)k * 4;
+        const double *q = p.partial + (size_t)k * 4;
         acc[0] += q[0];
         acc[1] += q[1];
         acc[2] += q[2];
     }
     for (int k = threadIdx.x; k < p.nblk_grow; k += 256) {
-        const volatile double *q = p.gpartial + (size_t)k * 4;
+        const double *q = p.gpartial + (size_t)k * 4;
         acc[3] += q[0];
         acc[4] += q[1];
         acc[5] += q[2];
         acc[6] += q[3];
     }
-    __shared__ double sred8[4 * 8];
     double tot[8];
-    block_sum<8>(acc, sred8, tot);
+    block_sum<8>(acc, sred, tot);
     if (threadIdx.x == 0) {
-        // LB2D_B_* indices
-        p.totals[9] += tot[0];   // inflow
-        p.totals[10] += tot[1];  // outflow
-        p.totals[14] += tot[2];  // consumed deposit
-        p.totals[6] += tot[3];   // removed mass 0
-        p.totals[7] += tot[4];   // removed mass 1
-        p.totals[8] += tot[5];   // removed solute
-        p.totals[12] += tot[6];  // grown nodes
-        p.totals[11] += 1.0;     // steps
-        *p.dstep += 1;
-        *p.ticket = 0u;
+        p.totals[9] = tot[0];   // inflow
+        p.totals[10] = tot[1];  // outflow
+        p.totals[14] = tot[2];  // consumed deposit
+        p.totals[6] = tot[3];   // removed mass 0
+        p.totals[7] = tot[4];   // removed mass 1
+        p.totals[8] = tot[5];   // removed solute
+        p.totals[12] = tot[6];  // grown nodes
     }
 }
 
@@ -1076,30 +1092,33 @@ template <typename S>
 static void full_dispatch(const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
+#define LB2D_FULL(NC_, SC_, SOL_, REACT_) \
+    hipLaunchKernelGGL((k_full<S, NC_, SC_, SOL_, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
             if (sol) {
-                if (react) hipLaunchKernelGGL((k_full<S, 2, true, true, true>), g, b, 0, st, p, parity);
-                else hipLaunchKernelGGL((k_full<S, 2, true, true, false>), g, b, 0, st, p, parity);
+                if (react) LB2D_FULL(2, true, true, true);
+                else LB2D_FULL(2, true, true, false);
             } else {
-                hipLaunchKernelGGL((k_full<S, 2, true, false, false>), g, b, 0, st, p, parity);
+                LB2D_FULL(2, true, false, false);
             }
         } else {
             if (sol) {
-                if (react) hipLaunchKernelGGL((k_full<S, 2, false, true, true>), g, b, 0, st, p, parity);
-                else hipLaunchKernelGGL((k_full<S, 2, false, true, false>), g, b, 0, st, p, parity);
+                if (react) LB2D_FULL(2, false, true, true);
+                else LB2D_FULL(2, false, true, false);
             } else {
-                hipLaunchKernelGGL((k_full<S, 2, false, false, false>), g, b, 0, st, p, parity);
+                LB2D_FULL(2, false, false, false);
             }
         }
     } else {
         if (sol) {
-            if (react) hipLaunchKernelGGL((k_full<S, 1, false, true, true>), g, b, 0, st, p, parity);
-            else hipLaunchKernelGGL((k_full<S, 1, false, true, false>), g, b, 0, st, p, parity);
+            if (react) LB2D_FULL(1, false, true, true);
+            else LB2D_FULL(1, false, true, false);
         } else {
-            hipLaunchKernelGGL((k_full<S, 1, false, false, false>), g, b, 0, st, p, parity);
+            LB2D_FULL(1, false, false, false);
         }
     }
+#undef LB2D_FULL
 }
 
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react,
@@ -1128,6 +1147,11 @@ hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react
             else hipLaunchKernelGGL((k_growth<float, 1, false>), g, b, 0, stream, p, parity_new);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tally_final(const FullParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(k_tally_final, dim3(1), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int 
                         int grid, hipStream_t s);
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
+hipError_t launch_tally_final(const FullParams &p, hipStream_t s);
 
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
