@@ -40,7 +40,8 @@ def source_hash():
     csrc = os.path.join(ROOT, "paper_1202_0442_amd", "csrc")
     h = hashlib.sha256()
     with open(os.path.join(csrc, "lb2d_common.hpp"), "rb") as fh:
-        h.update(fh.read())
+        hdr = fh.read()
+    h.update(hdr[hdr.index(b"struct PlainLattice"):hdr.index(b"struct FullParams")])
     with open(os.path.join(csrc, "lb2d_kernels.hip"), "rb") as fh:
         src = fh.read()
     h.update(src[:src.index(b"// --------------------------------------------------------- general step")])

@@ -77,6 +77,7 @@ struct lb2d_ctx {
     double *b = nullptr, *staging = nullptr, *partial = nullptr, *gpartial = nullptr;
     double *totals = nullptr;
     long long *dstep = nullptr;
+    unsigned *gflag = nullptr;
     size_t staging_doubles = 0;
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
@@ -142,7 +143,7 @@ bool is_nan(double v) { return std::isnan(v); }
 
 // Workspace layout of one lattice.
 struct Layout {
-    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, total;
+    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, gflag, total;
     size_t staging_doubles;
 };
 
@@ -184,6 +185,8 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     off += align_up(16 * 8);
     L.dstep = off;
     off += align_up(8);
+    L.gflag = off;
+    off += align_up(8);
     L.total = off;
     return L;
 }
@@ -201,6 +204,7 @@ FullParams full_params(const lb2d_ctx *c) {
     p.gpartial = c->gpartial;
     p.totals = c->totals;
     p.dstep = c->dstep;
+    p.gflag = c->gflag;
     p.nx = c->nx;
     p.ny = c->ny;
     p.ncomp = c->ncomp;
@@ -645,6 +649,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->gpartial = (double *)(c->ws + L.gpartial);
     c->totals = (double *)(c->ws + L.totals);
     c->dstep = (long long *)(c->ws + L.dstep);
+    c->gflag = (unsigned *)(c->ws + L.gflag);
     const size_t n = c->n();
     hipStream_t s = c->stream;
 
@@ -709,6 +714,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     HIPCHK(c, launch_fill_f64(c->partial, 0.0, (size_t)full_tiles(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_f64(c->gpartial, 0.0, (size_t)growth_blocks(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
+    HIPCHK(c, launch_fill_u8((uint8_t *)c->gflag, 0, 8, s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->t = 0;
     c->bound = true;

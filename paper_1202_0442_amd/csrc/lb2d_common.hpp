@@ -44,6 +44,7 @@ struct FullParams {
     double *gpartial;     // running per-block tallies of the growth kernel [nblk][4]
     double *totals;       // fixed-order sums of the tallies (LB2D_B_* indices)
     long long *dstep;     // completed steps (device copy)
+    unsigned *gflag;      // [2]: a growth trigger fired in the step of that parity
     int nx, ny;
     int ncomp;
     double tau[2], omega[2];

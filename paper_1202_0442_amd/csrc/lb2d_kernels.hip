@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(1024) k_batch(const PlainLattice *__restrict__
 // --------------------------------------------------------- general step
 
 constexpr int kTX = 64;   // tile width = one wavefront
-constexpr int kTY = 8;    // tile height
+constexpr int kTY = 4;    // tile height (measured: 64x4 beats 64x8..256x4)
 
 template <typename S>
 __device__ __forceinline__ typename Codec<S>::R ldpop(const S *__restrict__ f, size_t a, int i) {
@@ -424,134 +424,23 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         }
     }
 
-    // 2. density tile for the cohesion stencil: own nodes from registers,
-    // halo (and wrapped ragged-edge) nodes pulled again.
-    if constexpr (SC) {
+    // 2. solute pull (issued before the density-tile barrier so that its
+    // latency overlaps the halo pulls): bounce-back or reactive link at
+    // walls, the opening rules on open x walls
+    R g[9];
+    bool unk[9];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : R(p.rho_ref[c]) + drho[c];
-        for (int k = tid; k < (TX + 2) * (TY + 2); k += TX * TY) {
-            const int hx = k % (TX + 2), hy = k / (TX + 2);
-            const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
-            if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
-            const int gx = wrapi(tx0 + hx - 1, nx), gy = wrapi(ty0 + hy - 1, ny);
-            const bool hsolid = smask[hy + 1][hx + 1] != 0;
-            R rr[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) rr[c] = R(0);
-            if (!hsolid) {
-                const size_t hs = (size_t)gy * nx + gx;
-                const int gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx == nx - 1) ? 0 : gx + 1;
-                const size_t hrm = (size_t)((gy == 0) ? ny - 1 : gy - 1) * nx;
-                const size_t hr0 = (size_t)gy * nx;
-                const size_t hrp = (size_t)((gy == ny - 1) ? 0 : gy + 1) * nx;
-                const size_t hsrc[9] = {hs,        hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
-                                        hrm + gxm, hrm + gxp, hrp + gxp, hrp + gxm};
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const S *__restrict__ fin = (const S *)p.f[parity][c];
-                    R acc = ldpop(fin, hs, 0);
-#pragma unroll
-                    for (int i = 1; i < 9; ++i) {
-                        const bool wall = smask[hy + 1 - ey(i)][hx + 1 - ex(i)] != 0;
-                        const size_t a = wall ? (size_t)opp(i) * plane + hs : (size_t)i * plane + hsrc[i];
-                        acc += ldpop(fin, a, i);
-                    }
-                    rr[c] = R(p.rho_ref[c]) + acc;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = rr[c];
-        }
-        __syncthreads();
+    for (int i = 0; i < 9; ++i) {
+        g[i] = R(0);
+        unk[i] = false;
     }
-
     double tal[4] = {0.0, 0.0, 0.0, 0.0};  // inflow, outflow, consumed deposit
-    // 3. forces (solid lanes compute throw-away values from zero populations)
-    R rho[NC], Fx[NC], Fy[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        rho[c] = R(p.rho_ref[c]) + drho[c];
-        Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
-        Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
-    }
-    if constexpr (SC && NC == 2) {
-        if (valid) {
-            R sx[2] = {R(0), R(0)}, sy[2] = {R(0), R(0)};
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const R rb = srho[1 - c][ly + 1 + ey(i)][lx + 1 + ex(i)];
-                    if (ex(i)) sx[c] += wgt<R>(i) * (ex(i) > 0 ? rb : -rb);
-                    if (ey(i)) sy[c] += wgt<R>(i) * (ey(i) > 0 ? rb : -rb);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                Fx[c] += -R(p.G) * rho[c] * sx[c];
-                Fy[c] += -R(p.G) * rho[c] * sy[c];
-            }
-        }
-    }
-    if (p.has_ads) {
-        R ax = R(0), ay = R(0);
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
-            if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
-            if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
-            Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
-        }
-    }
-    // 4. common velocity u' and per-component equilibrium velocities
-    R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const R om = R(p.omega[c]);
-        nux += jx[c] * om;
-        nuy += jy[c] * om;
-        den += rho[c] * om;
-        sjx += jx[c] + R(0.5) * Fx[c];
-        sjy += jy[c] + R(0.5) * Fy[c];
-        srh += rho[c];
-    }
-    const R upx = nux / den, upy = nuy / den;
-    // 5. collide and store (one store per plane for the whole wavefront)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
-        const R tau = R(p.tau[c]), om = R(p.omega[c]);
-        const R ux = upx + tau * Fx[c] / rho[c];
-        const R uy = upy + tau * Fy[c] / rho[c];
-        const R usq = R(1.5) * (ux * ux + uy * uy);
-        const R rr = R(p.rho_ref[c]);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
-            const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
-            const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
-            const R v = fluid ? d[c][i] + om * (deq - d[c][i]) : R(0);
-            if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
-        }
-    }
-    // 6. solute: pull, walls / reactive links / openings, collide
     if constexpr (SOL) {
-        const R usx = sjx / srh, usy = sjy / srh;
         const S *__restrict__ gin = (const S *)p.g[parity];
-        S *__restrict__ gout = (S *)p.g[parity ^ 1];
-        R g[9];
-        bool unk[9];
         bool any_unk = false;
         const R kr = R(p.kr), Cs = R(p.Cs);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            unk[i] = false;
-            g[i] = R(0);
             if (!fluid) continue;
             const int sxr = x - ex(i);
             if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
@@ -601,6 +490,156 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)i * plane + s, i);
             }
         }
+    }
+    // deposit gathered by solid nodes next to fluid (loads issued early too)
+    bool fluid8 = false, fluid4 = false;
+    double dep = 0.0;
+    if constexpr (REACT) {
+        if (valid && solid) {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int fxg = x + ex(i);
+                if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+                if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
+                    fluid8 = true;
+                    if (i <= 4) fluid4 = true;
+                }
+            }
+            if (fluid8) {
+                const S *__restrict__ gin = (const S *)p.g[parity];
+                const R kr = R(p.kr), Cs = R(p.Cs);
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const int fxg = x + ex(i);
+                    if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+                    if (smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) continue;
+                    const size_t fl = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(fxg, nx);
+                    const R g_out = ldpop(gin, (size_t)opp(i) * plane + fl, opp(i));
+                    R gi;
+                    dep += (double)reactive_link<R>(i, kr, Cs, g_out, gi);
+                }
+            }
+        }
+    }
+
+    // 3. density tile for the cohesion stencil: own nodes from registers,
+    // halo (and wrapped ragged-edge) nodes pulled again.
+    if constexpr (SC) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : R(p.rho_ref[c]) + drho[c];
+        for (int k = tid; k < (TX + 2) * (TY + 2); k += TX * TY) {
+            const int hx = k % (TX + 2), hy = k / (TX + 2);
+            const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
+            if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
+            const int gx = wrapi(tx0 + hx - 1, nx), gy = wrapi(ty0 + hy - 1, ny);
+            const bool hsolid = smask[hy + 1][hx + 1] != 0;
+            R rr[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) rr[c] = R(0);
+            if (!hsolid) {
+                const size_t hs = (size_t)gy * nx + gx;
+                const int gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx == nx - 1) ? 0 : gx + 1;
+                const size_t hrm = (size_t)((gy == 0) ? ny - 1 : gy - 1) * nx;
+                const size_t hr0 = (size_t)gy * nx;
+                const size_t hrp = (size_t)((gy == ny - 1) ? 0 : gy + 1) * nx;
+                const size_t hsrc[9] = {hs,        hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
+                                        hrm + gxm, hrm + gxp, hrp + gxp, hrp + gxm};
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const S *__restrict__ fin = (const S *)p.f[parity][c];
+                    R acc = ldpop(fin, hs, 0);
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        const bool wall = smask[hy + 1 - ey(i)][hx + 1 - ex(i)] != 0;
+                        const size_t a = wall ? (size_t)opp(i) * plane + hs : (size_t)i * plane + hsrc[i];
+                        acc += ldpop(fin, a, i);
+                    }
+                    rr[c] = R(p.rho_ref[c]) + acc;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = rr[c];
+        }
+        __syncthreads();
+    }
+
+    // 4. forces (solid lanes compute throw-away values from zero populations)
+    R rho[NC], Fx[NC], Fy[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        rho[c] = R(p.rho_ref[c]) + drho[c];
+        Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
+        Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
+    }
+    if constexpr (SC && NC == 2) {
+        if (valid) {
+            R sx[2] = {R(0), R(0)}, sy[2] = {R(0), R(0)};
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const R rb = srho[1 - c][ly + 1 + ey(i)][lx + 1 + ex(i)];
+                    if (ex(i)) sx[c] += wgt<R>(i) * (ex(i) > 0 ? rb : -rb);
+                    if (ey(i)) sy[c] += wgt<R>(i) * (ey(i) > 0 ? rb : -rb);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                Fx[c] += -R(p.G) * rho[c] * sx[c];
+                Fy[c] += -R(p.G) * rho[c] * sy[c];
+            }
+        }
+    }
+    if (p.has_ads) {
+        R ax = R(0), ay = R(0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
+            if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
+            if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
+            Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
+        }
+    }
+    // 5. common velocity u' and per-component equilibrium velocities
+    R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const R om = R(p.omega[c]);
+        nux += jx[c] * om;
+        nuy += jy[c] * om;
+        den += rho[c] * om;
+        sjx += jx[c] + R(0.5) * Fx[c];
+        sjy += jy[c] + R(0.5) * Fy[c];
+        srh += rho[c];
+    }
+    const R upx = nux / den, upy = nuy / den;
+    // 6. collide and store (one store per plane for the whole wavefront)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+        const R tau = R(p.tau[c]), om = R(p.omega[c]);
+        const R ux = upx + tau * Fx[c] / rho[c];
+        const R uy = upy + tau * Fy[c] / rho[c];
+        const R usq = R(1.5) * (ux * ux + uy * uy);
+        const R rr = R(p.rho_ref[c]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
+            const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
+            const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
+            const R v = fluid ? d[c][i] + om * (deq - d[c][i]) : R(0);
+            if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
+        }
+    }
+    // 7. solute collision at the solvent velocity, one store per plane
+    if constexpr (SOL) {
+        const R usx = sjx / srh, usy = sjy / srh;
+        S *__restrict__ gout = (S *)p.g[parity ^ 1];
         R Cc = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) Cc += g[i];
@@ -613,33 +652,10 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             if (store) gout[(size_t)i * plane + s] = C::enc(v, i);
         }
     }
-    if (valid && solid && REACT) {
-        // 7. solid node: gather the deposit of its reactive links, then
-        // decide growth from the post-deposit value.
-        bool fluid8 = false, fluid4 = false;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const int fxg = x + ex(i);
-            if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
-            if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
-                fluid8 = true;
-                if (i <= 4) fluid4 = true;
-            }
-        }
-        if (fluid8) {
-            const S *__restrict__ gin = (const S *)p.g[parity];
-            const R kr = R(p.kr), Cs = R(p.Cs);
-            double dep = 0.0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const int fxg = x + ex(i);
-                if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
-                if (smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) continue;
-                const size_t fl = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(fxg, nx);
-                const R g_out = ldpop(gin, (size_t)opp(i) * plane + fl, opp(i));
-                R gi;
-                dep += (double)reactive_link<R>(i, kr, Cs, g_out, gi);
-            }
+    if (valid && solid && REACT && fluid8) {
+        // 8. solid node next to fluid: add the gathered deposit, then decide
+        // growth from the post-deposit value
+        {
             double bn = p.b[s] + dep;
             if (fluid4) {
                 // candidates: E, N, W, S that are fluid, inside the solute
@@ -671,6 +687,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                         }
                     tal[2] += bn;
                     bn = 0.0;
+                    p.gflag[parity] = 1u;
                 }
                 p.trig[s] = code;
             }
@@ -708,6 +725,15 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     const size_t plane = (size_t)nx * ny;
     const int x = blockIdx.x * 256 + threadIdx.x;  // one row segment
     const int y = blockIdx.y;
+    // steps without any trigger (the common case) only advance the counter
+    const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    if (!REACT || p.gflag[parity_new ^ 1] == 0u) {
+        if (first) {
+            *p.dstep += 1;
+            p.gflag[parity_new] = 0u;
+        }
+        return;
+    }
     double tal[4] = {0.0, 0.0, 0.0, 0.0};
     bool grow = false;
     if constexpr (REACT) {
@@ -747,7 +773,10 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
             for (int k = 0; k < 4; ++k) dst[k] += out[k];
         }
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.dstep += 1;
+    if (first) {
+        *p.dstep += 1;
+        p.gflag[parity_new] = 0u;
+    }
 }
 
 // Sums the per-block running tallies in a fixed order into totals
@@ -1129,7 +1158,7 @@ hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool so
 }
 
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t stream) {
-    const dim3 g((p.nx + 255) / 256, p.ny), b(256);
+    const dim3 g = react ? dim3((p.nx + 255) / 256, p.ny) : dim3(1), b(256);
     if (st == kF64) {
         if (p.ncomp == 2) {
             if (react) hipLaunchKernelGGL((k_growth<double, 2, true>), g, b, 0, stream, p, parity_new);
