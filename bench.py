@@ -206,6 +206,9 @@ def main():
     ap.add_argument("--variants", default="all", help="all | none | comma list of f16,bf16,sc,batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
+    ap.add_argument("--sc-steps", type=int, default=2000, help="steps of the two-component variant")
+    ap.add_argument("--no-main", action="store_true",
+                    help="profiling aid: run only the selected variants (no headline line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -215,6 +218,14 @@ def main():
     from paper_1202_0442_amd import inputs, lb2d
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     stream = torch.cuda.Stream()
+    if args.no_main:
+        want = set(args.variants.split(",")) if args.variants not in ("all", "none") else set()
+        res = {}
+        if "sc" in want:
+            res["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 10, stream)
+        print(json.dumps(res), flush=True)
+        lb2d.copy_bench(1 << 30, reps=3, stream=stream)
+        return
     log("generating porous workload")
     w = inputs.porous(n=args.n, seed=2)
     L = make_porous_lattice(lb2d, w, args.storage, stream)
@@ -285,7 +296,7 @@ def main():
             torch.cuda.empty_cache()
     if "sc" in want:
         log("variant two-component + solute 2048^2")
-        variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, 2000, 20, stream)
+        variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 20, stream)
         torch.cuda.empty_cache()
     if "batch" in want:
         log("variant batched ensemble")

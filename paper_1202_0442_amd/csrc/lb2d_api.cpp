@@ -82,7 +82,11 @@ struct lb2d_ctx {
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
     hipGraphExec_t graph = nullptr;
-    int plain_bx = 256, plain_by = 1;
+    // population plane geometry: brick layout (padded) for one-fluid
+    // lattices, row-major for the others
+    int brick = 0;
+    unsigned pnx = 0;
+    size_t pplane = 0;
     // timing
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -147,10 +151,30 @@ struct Layout {
     size_t staging_doubles;
 };
 
+// Padded plane geometry of the populations for the given storage.
+void plane_geometry(const lb2d_ctx *c, int storage, int *brick, unsigned *pnx, size_t *pplane) {
+    if (c->plain()) {
+        const unsigned bh = (unsigned)brick_h_for((int)storage_bytes(storage));
+        const unsigned px = (unsigned)((c->nx + kBrickW - 1) / kBrickW * kBrickW);
+        const unsigned py = (unsigned)((c->ny + bh - 1) / bh * bh);
+        *brick = 1;
+        *pnx = px;
+        *pplane = (size_t)px * py;
+    } else {
+        *brick = 0;
+        *pnx = (unsigned)c->nx;
+        *pplane = c->n();
+    }
+}
+
 Layout make_layout(const lb2d_ctx *c, int storage) {
     Layout L{};
     const size_t n = c->n();
-    const size_t pop = align_up(9 * n * storage_bytes(storage));
+    int brick;
+    unsigned pnx;
+    size_t pplane;
+    plane_geometry(c, storage, &brick, &pnx, &pplane);
+    const size_t pop = align_up(9 * pplane * storage_bytes(storage));
     size_t off = 0;
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < 2; ++k) {
@@ -236,6 +260,9 @@ FullParams full_params(const lb2d_ctx *c) {
     p.seed = c->seed;
     p.nblk_main = full_tiles(c->nx, c->ny);
     p.nblk_grow = growth_blocks(c->nx, c->ny);
+    p.brick = c->brick;
+    p.pnx = c->pnx;
+    p.pplane = c->pplane;
     return p;
 }
 
@@ -246,6 +273,8 @@ PlainLattice plain_lattice(const lb2d_ctx *c) {
     L.links = c->links;
     L.nx = c->nx;
     L.ny = c->ny;
+    L.pnx = c->pnx;
+    L.plane = c->pplane;
     L.tau = c->tau[0];
     L.omega = 1.0 / c->tau[0];
     L.Fx = c->force[0][0];
@@ -267,7 +296,7 @@ int pre_command(lb2d_ctx *c, bool need_lattice = true) {
 
 // One time step on the stream `s` at the current parity.
 hipError_t enqueue_step(lb2d_ctx *c, int parity, hipStream_t s) {
-    if (c->plain()) return launch_plain(c->storage, plain_lattice(c), parity, c->plain_bx, c->plain_by, s);
+    if (c->plain()) return launch_plain(c->storage, plain_lattice(c), parity, s);
     const FullParams p = full_params(c);
     hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->q != 0, c->reaction, s);
     if (e != hipSuccess) return e;
@@ -636,6 +665,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->ws = (char *)dev_ptr;
     c->ws_bytes = bytes;
     c->stream = (hipStream_t)hip_stream;
+    plane_geometry(c, c->storage, &c->brick, &c->pnx, &c->pplane);
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < c->ncomp; ++k) c->f[p][k] = c->ws + L.f[p][k];
     for (int p = 0; p < 2; ++p) c->g[p] = c->q ? (void *)(c->ws + L.g[p]) : nullptr;
@@ -697,7 +727,8 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         if ((e = upload(c, c->staging + n, c->ux0[k], 0.0))) return e;
         if ((e = upload(c, c->staging + 2 * n, c->uy0[k], 0.0))) return e;
         HIPCHK(c, launch_init_fluid(c->storage, c->f[0][k], c->staging, c->staging + n, c->staging + 2 * n, n,
-                                    2.25 * c->alpha[k], 1.8 * (1.0 - c->alpha[k]), c->rho_ref[k], s));
+                                    2.25 * c->alpha[k], 1.8 * (1.0 - c->alpha[k]), c->rho_ref[k],
+                                    (unsigned)c->nx, c->brick, c->pnx, c->pplane, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->q) {
@@ -733,7 +764,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
             const int parity = (int)(c->t & 1);
             HIPCHK(c, hipEventRecord(c->ev0, c->stream));
             if (c->plain()) {
-                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->plain_bx, c->plain_by, c->stream));
+                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
             } else {
                 const FullParams p = full_params(c);
@@ -871,7 +902,8 @@ int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = c->n();
     for (int i = 0; i < 9; ++i) {
-        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, i, kW[i] * ref, (unsigned)c->nx,
+                                      comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
         HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -888,7 +920,8 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
     const size_t n = c->n();
     for (int i = 0; i < 9; ++i) {
         HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, c->stream));
+        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, (unsigned)c->nx,
+                                      comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return LB2D_OK;
@@ -998,14 +1031,11 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
-// Tile shapes the autotuner may choose (width x height threads); a tile
-// table large enough for every one of them is reserved.
-static const int kTileShapes[][2] = {{64, 4}, {128, 2}, {256, 1}, {64, 8}, {128, 4}, {32, 8}, {64, 2}, {64, 1}};
-
+// The tile of one block is fixed by the brick layout of the storage format.
 static size_t max_tiles_for(const lb2d_batch *b) {
-    size_t m = 0;
-    for (const auto &t : kTileShapes) m = std::max(m, tiles_for(b, t[0], t[1]));
-    return m;
+    int tw, th;
+    plain_tile(b->storage, &tw, &th);
+    return tiles_for(b, tw, th);
 }
 
 int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
@@ -1041,6 +1071,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     b->d_lat = (PlainLattice *)b->ws;
     b->d_tiles = (Tile *)(b->ws + align_up(b->lat.size() * sizeof(PlainLattice)));
     b->max_tiles = max_tiles_for(b);
+    plain_tile(b->storage, &b->tile_w, &b->tile_h);
     std::vector<PlainLattice> L;
     for (auto *c : b->lat) L.push_back(plain_lattice(c));
     HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
@@ -1061,9 +1092,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             if (std::fscanf(fh, "{\"key\": \"%63[0-9a-f]\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
                                 "\"blocks_per_cu\": %d}",
                             k, &w, &h, &s, &p) == 5 &&
-                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 &&
-                std::any_of(std::begin(kTileShapes), std::end(kTileShapes),
-                            [&](const int *t) { return t[0] == w && t[1] == h; })) {
+                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 && w == b->tile_w && h == b->tile_h) {
                 b->tile_w = w;
                 b->tile_h = h;
                 b->schedule = s;
@@ -1076,10 +1105,12 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     if (!have) {
         // timed trial steps: each writes the lattices' next buffers from the
         // current ones without advancing, so the state is unchanged
-        const TuneCand cands[] = {{64, 4, 0, 0},  {128, 2, 0, 0}, {256, 1, 0, 0}, {64, 8, 0, 0},
-                                  {128, 4, 0, 0}, {32, 8, 0, 0},  {64, 4, 1, 8},  {128, 2, 1, 8},
-                                  {256, 1, 1, 8}, {64, 4, 2, 8},  {128, 2, 2, 8}, {64, 4, 1, 16},
-                                  {128, 2, 1, 16}, {256, 1, 0, 16}};
+        // schedules (lattice by lattice, largest first, interleaved) x grid
+        // (one block per tile, or persistent blocks per CU)
+        const int tw = b->tile_w, th = b->tile_h;
+        const TuneCand cands[] = {{tw, th, 0, 0},  {tw, th, 1, 0},  {tw, th, 2, 0},  {tw, th, 0, 8},
+                                  {tw, th, 1, 8},  {tw, th, 2, 8},  {tw, th, 0, 16}, {tw, th, 1, 16},
+                                  {tw, th, 2, 16}, {tw, th, 1, 32}};
         hipEvent_t e0, e1;
         HIPCHK(b, hipEventCreate(&e0));
         HIPCHK(b, hipEventCreate(&e1));
@@ -1089,11 +1120,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, cd.w, cd.h, grid, b->stream));
+            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, cd.w, cd.h, grid,
-                                       b->stream));
+                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1128,7 +1158,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 }
 
 static hipError_t batch_step(lb2d_batch *b, int parity, hipStream_t s) {
-    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->tile_w, b->tile_h, b->grid, s);
+    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, s);
 }
 
 int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {

@@ -9,14 +9,26 @@ namespace lb2d {
 // Storage formats (same values as LB2D_F64 ... in include/lb2d.h).
 enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
+// Brick layout of the one-fluid populations: each plane is cut into bricks
+// of BW x BH nodes stored contiguously (8x4 for 4- and 8-byte values, 8x8
+// for 2-byte values, i.e. one or two 128-byte lines per brick), bricks in
+// row-major order over the plane padded to whole bricks.  A line then
+// covers a compact 2-D patch, so lines that lie entirely inside obstacles
+// are never read or written.
+constexpr int kBrickW = 8;
+inline constexpr int brick_h_for(int value_bytes) { return value_bytes == 2 ? 8 : 4; }
+
 // One single-fluid lattice for the plain fused step (and for one entry of
 // the batched step).  Populations live in two buffers (two-lattice pull
-// scheme); f[p] holds [9][ny][nx] deviations f_i - w_i rho_ref (zero, and
-// never read, at solid nodes).
+// scheme); f[p] holds 9 brick-layout planes of deviations f_i - w_i rho_ref
+// (zero, and never read, at solid nodes).
 struct PlainLattice {
     void *f[2];
     const uint16_t *links; // bit 0: node solid; bit i (1..8): node + e_i solid
+                           // (row-major [ny][nx])
     int nx, ny;
+    unsigned pnx;          // nx padded to whole bricks
+    size_t plane;          // elements per population plane (padded)
     double omega;         // 1 / tau
     double tau;
     double Fx, Fy;        // aveforce (summed vector)
@@ -45,6 +57,9 @@ struct FullParams {
     double *totals;       // fixed-order sums of the tallies (LB2D_B_* indices)
     long long *dstep;     // completed steps (device copy)
     unsigned *gflag;      // [2]: a growth trigger fired in the step of that parity
+    int brick;            // populations in brick layout (one-fluid lattices)
+    unsigned pnx;         // padded nx of the brick layout
+    size_t pplane;        // elements per population plane
     int nx, ny;
     int ncomp;
     double tau[2], omega[2];

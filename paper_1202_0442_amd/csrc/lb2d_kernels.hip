@@ -108,6 +108,19 @@ __device__ __forceinline__ int wrapi(int a, int n) {
     return a < 0 ? a + n : a;
 }
 
+// Element index of node (x, y) in a brick-layout plane of padded width pnx.
+template <typename S>
+__host__ __device__ __forceinline__ size_t brick_index(unsigned x, unsigned y, unsigned pnx) {
+    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
+    return ((size_t)(y / H) * (pnx / W) + (x / W)) * (W * H) + (y % H) * W + (x % W);
+}
+
+// Element index of node (x, y) in a population plane of either layout.
+template <typename S>
+__device__ __forceinline__ size_t pop_index(int brick, unsigned x, unsigned y, unsigned nx, unsigned pnx) {
+    return brick ? brick_index<S>(x, y, pnx) : (size_t)y * nx + x;
+}
+
 // Deterministic block sum of K doubles per thread into out[0..K) (valid in
 // thread 0).  `sh` must hold blockDim.x * blockDim.y * K doubles... to keep
 // LDS small the reduction goes through wavefront shuffles first.
@@ -167,7 +180,8 @@ struct PlainArgs {
     const S *fin;
     S *fout;
     const uint16_t *links;
-    unsigned nx, ny;
+    unsigned nx, ny, pnx;
+    size_t plane;
     double omega, tau, Fx, Fy, ax, ay, rho_ref;
 };
 
@@ -189,6 +203,8 @@ __device__ __forceinline__ PlainArgs<S> plain_args(const PlainLattice &L, int pa
     a.links = L.links;
     a.nx = (unsigned)L.nx;
     a.ny = (unsigned)L.ny;
+    a.pnx = L.pnx;
+    a.plane = L.plane;
     a.omega = L.omega;
     a.tau = L.tau;
     a.Fx = L.Fx;
@@ -206,6 +222,8 @@ __device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
     a.links = uflp(a.links);
     a.nx = ufl(a.nx);
     a.ny = ufl(a.ny);
+    a.pnx = ufl(a.pnx);
+    a.plane = (size_t)ufl64((unsigned long long)a.plane);
     a.omega = ufld(a.omega);
     a.tau = ufld(a.tau);
     a.Fx = ufld(a.Fx);
@@ -220,25 +238,37 @@ template <typename S>
 __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside) {
     using C = Codec<S>;
     using R = typename C::R;
-    const unsigned nx = L.nx, ny = L.ny;
-    const unsigned s = inside ? (unsigned)y * nx + (unsigned)x : 0u;
-    const unsigned lk = inside ? (unsigned)gbl(L.links)[s] : 1u;
+    constexpr unsigned kGroup = kBrickW * brick_h_for(sizeof(S));  // lanes per brick
+    const unsigned nx = L.nx, ny = L.ny, pnx = L.pnx;
+    const unsigned s_row = inside ? (unsigned)y * nx + (unsigned)x : 0u;
+    const unsigned lk = inside ? (unsigned)gbl(L.links)[s_row] : 1u;
     const bool fluid = (lk & 1u) == 0u;
-    if (!__any(fluid)) return;
+    const unsigned long long bal = __ballot(fluid);
+    if (bal == 0ull) return;
     if (!inside) return;
-    const size_t plane = (size_t)nx * ny;
+    // a brick (one or two whole lines) is written iff it holds a fluid node
+    const unsigned lane = __lane_id();
+    const unsigned long long gmask =
+        (kGroup >= 64) ? ~0ull : (((1ull << kGroup) - 1ull) << ((lane / kGroup) * kGroup));
+    const bool store = (bal & gmask) != 0ull;
+    const size_t plane = L.plane;
     const LB2D_GLOBAL S *__restrict__ fin = gbl(L.fin);
     LB2D_GLOBAL S *__restrict__ fout = gbl(L.fout);
+    const size_t s = brick_index<S>((unsigned)x, (unsigned)y, pnx);
 
     R d[9];
     if (fluid) {
-        const unsigned xm = (x == 0) ? nx - 1 : (unsigned)x - 1;
-        const unsigned xp = ((unsigned)x == nx - 1) ? 0 : (unsigned)x + 1;
-        const unsigned rm = ((y == 0) ? ny - 1 : (unsigned)y - 1) * nx;
-        const unsigned r0 = (unsigned)y * nx;
-        const unsigned rp = (((unsigned)y == ny - 1) ? 0 : (unsigned)y + 1) * nx;
+        const unsigned xx = (unsigned)x, yy = (unsigned)y;
+        const unsigned xm = (xx == 0) ? nx - 1 : xx - 1;
+        const unsigned xp = (xx == nx - 1) ? 0 : xx + 1;
+        const unsigned ym = (yy == 0) ? ny - 1 : yy - 1;
+        const unsigned yp = (yy == ny - 1) ? 0 : yy + 1;
         // node - e_i for each direction
-        const unsigned src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+        const size_t src[9] = {s,
+                               brick_index<S>(xm, yy, pnx), brick_index<S>(xx, ym, pnx),
+                               brick_index<S>(xp, yy, pnx), brick_index<S>(xx, yp, pnx),
+                               brick_index<S>(xm, ym, pnx), brick_index<S>(xp, ym, pnx),
+                               brick_index<S>(xp, yp, pnx), brick_index<S>(xm, yp, pnx)};
         d[0] = C::dec(fin[s], 0);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -271,29 +301,45 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
         const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
         const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
         const R v = fluid ? d[i] + omega * (deq - d[i]) : R(0);
-        fout[(size_t)i * plane + s] = C::enc(v, i);
+        if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
     }
 }
 
+// Thread t of a 256-thread block -> node of a brick-aligned tile of
+// (256 / (BW*BH)) bricks side by side: 32 (or 64) consecutive lanes cover
+// one brick, so each store of a wavefront writes whole bricks.
 template <typename S>
-__global__ void __launch_bounds__(1024) k_plain(PlainLattice L, int parity) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+__device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
+    constexpr int W = kBrickW, H = brick_h_for(sizeof(S));
+    const int b = t / (W * H), k = t % (W * H);
+    lx = b * W + k % W;
+    ly = k / W;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity) {
+    constexpr int TW = 256 / (kBrickW * brick_h_for(sizeof(S))) * kBrickW, TH = brick_h_for(sizeof(S));
+    int lx, ly;
+    brick_thread<S>(threadIdx.x, lx, ly);
+    const int x = blockIdx.x * TW + lx;
+    const int y = blockIdx.y * TH + ly;
     plain_node<S>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny);
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
 // independent lattices; `persistent` grids stride over the table.
 template <typename S>
-__global__ void __launch_bounds__(1024) k_batch(const PlainLattice *__restrict__ lat,
-                                               const Tile *__restrict__ tiles, int ntiles,
-                                               int parity) {
+__global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
+                                              const Tile *__restrict__ tiles, int ntiles,
+                                              int parity) {
+    int lx, ly;
+    brick_thread<S>(threadIdx.x, lx, ly);
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int li = (int)ufl((unsigned)tiles[t].lattice);
         const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
-        const int x = x0 + threadIdx.x;
-        const int y = y0 + threadIdx.y;
+        const int x = x0 + lx;
+        const int y = y0 + ly;
         plain_node<S>(a, x, y, x < (int)a.nx && y < (int)a.ny);
     }
 }
@@ -877,9 +923,11 @@ __global__ void k_raster_rects(uint8_t *mask, int nx, const int *rects) {
 // (computed in FP64, then shifted and encoded).
 template <typename S>
 __global__ void k_init_fluid(S *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref) {
+                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t dst = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
         const double r = rho[k], u = ux[k], v = uy[k];
         const double usq = 1.5 * (u * u + v * v);
 #pragma unroll
@@ -887,7 +935,7 @@ __global__ void k_init_fluid(S *f, const double *rho, const double *ux, const do
             const double eu = ex(i) * u + ey(i) * v;
             const double A = (i == 0) ? A0 : A1;
             const double fe = wgt<double>(i) * r * (A + 3.0 * eu + 4.5 * eu * eu - usq);
-            f[(size_t)i * n + k] = C::enc((typename C::R)(fe - wgt<double>(i) * rho_ref), i);
+            f[(size_t)i * pplane + dst] = C::enc((typename C::R)(fe - wgt<double>(i) * rho_ref), i);
         }
     }
 }
@@ -910,26 +958,34 @@ __global__ void k_init_b(double *b, const uint8_t *mask, double b0, size_t n) {
         b[k] = mask[k] ? b0 : 0.0;
 }
 
-// Raw state <-> FP64 (one plane at a time); `shift` = w_i rho_ref.
+// Raw state <-> FP64 row-major staging (one plane at a time);
+// `shift` = w_i rho_ref.
 template <typename S>
-__global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, double shift) {
+__global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, double shift,
+                               unsigned nx, int brick, unsigned pnx, size_t pplane) {
     using C = Codec<S>;
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * n + k], i);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t a = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
+        out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * pplane + a], i);
+    }
 }
 template <typename S>
-__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift) {
+__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift, unsigned nx, int brick,
+                               unsigned pnx, size_t pplane) {
     using C = Codec<S>;
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        f[(size_t)i * n + k] = C::enc((typename C::R)(in[k] - shift), i);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t a = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
+        f[(size_t)i * pplane + a] = C::enc((typename C::R)(in[k] - shift), i);
+    }
 }
 
 // ---------------------------------------------------------------- read-out
 
 template <typename S>
-__device__ double node_rho(const S *f, size_t plane, int nx, int ny, int x, int y, double rho_ref) {
+__device__ double node_rho(const FullParams &p, const S *f, int x, int y, double rho_ref) {
     using C = Codec<S>;
-    const size_t s = (size_t)y * nx + x;
+    const size_t plane = p.pplane;
+    const size_t s = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)p.nx, p.pnx);
     double r = rho_ref;
     for (int i = 0; i < 9; ++i) r += (double)C::dec(f[(size_t)i * plane + s], i);
     return r;
@@ -941,10 +997,11 @@ template <typename S>
 __global__ void k_moments(FullParams p, int parity, int comp, double *orho, double *oux, double *ouy) {
     using C = Codec<S>;
     const int nx = p.nx, ny = p.ny;
-    const size_t plane = (size_t)nx * ny;
+    const size_t plane = p.pplane;
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
     const size_t s = (size_t)y * nx + x;
+    const size_t ps = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)nx, p.pnx);
     if (p.mask[s]) {
         orho[s] = -11.0;
         oux[s] = ouy[s] = 0.0;
@@ -955,7 +1012,7 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
         const S *f = (const S *)p.f[parity][c];
         double r = p.rho_ref[c], mx = 0, my = 0;
         for (int i = 0; i < 9; ++i) {
-            const double v = (double)C::dec(f[(size_t)i * plane + s], i);
+            const double v = (double)C::dec(f[(size_t)i * plane + ps], i);
             r += v;
             mx += ex(i) * v;
             my += ey(i) * v;
@@ -975,7 +1032,7 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
             for (int i = 1; i < 9; ++i) {
                 const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
                 if (p.mask[(size_t)gy * nx + gx]) continue;
-                const double rb = node_rho<S>(fo, plane, nx, ny, gx, gy, p.rho_ref[1 - c]);
+                const double rb = node_rho<S>(p, fo, gx, gy, p.rho_ref[1 - c]);
                 sx += wgt<double>(i) * rb * ex(i);
                 sy += wgt<double>(i) * rb * ey(i);
             }
@@ -1025,7 +1082,7 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
     using C = Codec<S>;
     __shared__ double sred[4 * 8];
     const int nx = p.nx;
-    const size_t plane = (size_t)nx * p.ny;
+    const size_t plane = p.pplane;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // m0 m1 jx jy C b nfluid -
     const int y = blockIdx.x;
     for (int x = threadIdx.x; x < nx; x += 256) {
@@ -1035,10 +1092,11 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
             continue;
         }
         v[6] += 1.0;
+        const size_t ps = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)nx, p.pnx);
         for (int c = 0; c < p.ncomp; ++c) {
             const S *f = (const S *)p.f[parity][c];
             for (int i = 0; i < 9; ++i) {
-                const double fv = wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + s], i);
+                const double fv = wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
                 v[c] += fv;
                 v[2] += ex(i) * fv;
                 v[3] += ey(i) * fv;
@@ -1101,15 +1159,23 @@ inline int grid1d(size_t n, int bs = 256) {
 
 size_t storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
 
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, int bx, int by, hipStream_t stream) {
-    dim3 blk(bx, by), grd((L.nx + bx - 1) / bx, (L.ny + by - 1) / by);
+void plain_tile(int st, int *tw, int *th) {
+    const int h = brick_h_for((int)storage_bytes(st));
+    *tw = 256 / (kBrickW * h) * kBrickW;
+    *th = h;
+}
+
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t stream) {
+    int tw, th;
+    plain_tile(st, &tw, &th);
+    const dim3 blk(256), grd((L.nx + tw - 1) / tw, (L.ny + th - 1) / th);
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_plain<S>, grd, blk, 0, stream, L, parity));
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int bx,
-                        int by, int grid, hipStream_t stream) {
-    dim3 blk(bx, by);
+hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                        hipStream_t stream) {
+    dim3 blk(256);
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_batch<S>, dim3(grid), blk, 0, stream, lat, tiles, ntiles, parity));
     return hipGetLastError();
 }
@@ -1206,9 +1272,10 @@ hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int coun
     return hipGetLastError();
 }
 hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref, hipStream_t s) {
+                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_init_fluid<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, rho, ux, uy, n,
-                                         A0, A1, rho_ref));
+                                         A0, A1, rho_ref, nx, brick, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
@@ -1221,18 +1288,19 @@ hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hi
     return hipGetLastError();
 }
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
-                               double shift, hipStream_t s) {
+                               double shift, unsigned nx, int brick, unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, mask,
-                                         out, n, i, shift));
+                                         out, n, i, shift, nx, brick, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s) {
     hipLaunchKernelGGL(k_links, dim3((nx + 255) / 256, ny), dim3(256), 0, s, mask, links, nx, ny);
     return hipGetLastError();
 }
-hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s) {
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
+                               int brick, unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_encode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, in, n, i,
-                                         shift));
+                                         shift, nx, brick, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,

@@ -10,9 +10,11 @@ size_t storage_bytes(int st);
 int full_tiles(int nx, int ny);
 int growth_blocks(int nx, int ny);
 
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, int bx, int by, hipStream_t s);
-hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int bx, int by,
-                        int grid, hipStream_t s);
+// Tile (in nodes) covered by one 256-thread block of the one-fluid step.
+void plain_tile(int st, int *tw, int *th);
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t s);
+hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                        hipStream_t s);
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
 hipError_t launch_tally_final(const FullParams &p, hipStream_t s);
@@ -24,14 +26,16 @@ hipError_t launch_raster_circles(uint8_t *mask, int nx, int ny, const int *cxy, 
                                  hipStream_t s);
 hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int count, hipStream_t s);
 hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref, hipStream_t s);
+                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             size_t pplane, hipStream_t s);
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
                               hipStream_t s);
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s);
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
-                               double shift, hipStream_t s);
+                               double shift, unsigned nx, int brick, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s);
-hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, hipStream_t s);
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
+                               int brick, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
                           hipStream_t s);
 hipError_t launch_solute_state(int st, const FullParams &p, int parity, int reaction, double *C, double *b,
