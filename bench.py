@@ -89,7 +89,9 @@ def cpu_baseline(target_seconds=15.0):
     """The FP64 oracle, as it stands, on a 512 x 512 sample of the porous
     workload (same generator, seed and parameters), one thread."""
     from oracle import Oracle
+    from oracle.oracle import set_threads
     from paper_1202_0442_amd import inputs
+    set_threads(1)
     w = inputs.porous(n=512, seed=2)
     o = Oracle(w.nx, w.ny)
     o.fluids(1, w.tau)
@@ -196,6 +198,59 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
     return out
 
 
+def run_precision(lb2d, torch, stream, ref_path, n=2048, steps=10000):
+    """Precision sweep: the channel and porous workloads at n x n, stored as
+    FP32, FP16 and BF16 deviations (FP32 arithmetic), against the FP64
+    oracle after `steps` steps: max and L2 errors of rho and u, MLUPS and
+    algorithmic GB/s."""
+    import numpy as np
+    from paper_1202_0442_amd import inputs
+    if ref_path and os.path.exists(ref_path):
+        ref = dict(np.load(ref_path))
+        assert int(ref["n"]) == n and int(ref["steps"]) == steps, "reference of another size"
+    else:
+        from oracle import reference_fields as rf
+        log("computing the oracle reference (slow)")
+        cr, cu, cv = rf.channel(n, steps)
+        pr, pu, pv, pm = rf.porous(n, steps)
+        ref = dict(channel_rho=cr, channel_ux=cu, channel_uy=cv, porous_rho=pr, porous_ux=pu,
+                   porous_uy=pv, porous_mask=pm)
+    res = {}
+    for wl in ("channel", "porous"):
+        if wl == "channel":
+            w = inputs.poiseuille(nx=n, ny=n, accel=1e-6, tau=1.0)
+            rr = np.broadcast_to(ref["channel_rho"][:, None], (n, n))
+            ru = np.broadcast_to(ref["channel_ux"][:, None], (n, n))
+            rv = np.broadcast_to(ref["channel_uy"][:, None], (n, n))
+        else:
+            w = inputs.porous(n=n, seed=4)
+            rr, ru, rv = ref["porous_rho"], ref["porous_ux"], ref["porous_uy"]
+        fl = rr != -11.0
+        for st in ("f32", "f16", "bf16"):
+            L = make_porous_lattice(lb2d, w, st, stream)
+            nfl = L.budgets()["fluid_nodes"]
+            ms = time_steps(torch, stream, L.iteration, steps)
+            g_r, g_u, g_v = L.moments(0)
+            assert np.array_equal(g_r == -11.0, ~fl)
+            du = np.hypot(g_u - ru, g_v - rv)[fl]
+            um = np.hypot(ru, rv)[fl]
+            drho = np.abs(g_r - rr)[fl]
+            per = ms / steps
+            res[f"{wl}_{st}"] = {
+                "u_max_rel": float(du.max() / um.max()),
+                "u_l2_rel": float(np.sqrt((du ** 2).sum() / (um ** 2).sum())),
+                "rho_max_abs": float(drho.max()),
+                "rho_l2_abs": float(np.sqrt((drho ** 2).mean())),
+                "mlups": n * n / (per * 1e-3) / 1e6,
+                "algorithmic_GBps": (nfl * 18 * STORE_BYTES[st] + n * n) / (per * 1e-3) / 1e9,
+            }
+            log(f"precision {wl} {st}: {res[f'{wl}_{st}']}")
+            L.close()
+            torch.cuda.empty_cache()
+    return {"precision_sweep": res, "n": n, "steps": steps,
+            "reference": "FP64 oracle (channel: 4-wide strip, uniform in x; porous: full lattice)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +264,10 @@ def main():
     ap.add_argument("--sc-steps", type=int, default=2000, help="steps of the two-component variant")
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: run only the selected variants (no headline line)")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the precision sweep instead (prints its own JSON line)")
+    ap.add_argument("--precision-ref", default="refdata/precision_2048.npz",
+                    help="npz written by `python -m oracle.reference_fields` (else computed here)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -218,6 +277,9 @@ def main():
     from paper_1202_0442_amd import inputs, lb2d
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     stream = torch.cuda.Stream()
+    if args.precision:
+        print(json.dumps(run_precision(lb2d, torch, stream, os.path.join(ROOT, args.precision_ref))), flush=True)
+        return
     if args.no_main:
         want = set(args.variants.split(",")) if args.variants not in ("all", "none") else set()
         res = {}
@@ -259,6 +321,12 @@ def main():
                      "bytes_rule": "72 B per fluid node (9 loads + 9 stores of 4 B) + 1 B mask per node"},
         "mflups": round(nfl * args.steps / (ms * 1e-3) / 1e6, 1),
     }
+    # dense accounting (every node, solids included, moves 18 values + mask):
+    # the bandwidth a kernel without obstacle skipping would need for the
+    # same MLUPS; the kernel itself moves only fluid-bearing lines
+    dense = n * (18 * STORE_BYTES[args.storage] + 1) / (per * 1e-3) / 1e9
+    out["roofline"]["dense_equiv_GBps"] = round(dense, 1)
+    out["roofline"]["dense_equiv_frac"] = round(dense / PEAK_HBM_GBPS, 4)
     if traffic is not None:
         # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
         # scaled by a copy kernel of known size) at this launch's duration

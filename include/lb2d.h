@@ -100,9 +100,12 @@ int lb2d_lattice(lb2d_ctx *ctx, const char *style, int nx, int ny, double tau);
 int lb2d_fluids(lb2d_ctx *ctx, double tau1, double tau2, double alpha1,
                 double alpha2);
 
-/* solute command: one solute species with relaxation time tau_s > 1/2 on a
- * D2Q9 lattice (q = 9, g_eq = w_i C (1 + 3 e.u), D = (tau_s - 1/2)/3).
- * q = 4 (the paper's D2Q4) returns LB2D_E_UNSUPPORTED. */
+/* solute command: one solute species with relaxation time tau_s > 1/2,
+ * advected by the solvent velocity of Eq. (u_solvent), on
+ *   q = 9: D2Q9, g_eq = w_i C (1 + 3 e.u), D = (tau_s - 1/2)/3, or
+ *   q = 4: the paper's D2Q4 (directions e1..e4), g_eq = C/4 (1 + 2 e.u),
+ *          D = (tau_s - 1/2)/2.
+ * Other q: LB2D_E_INVAL.  Needs the general (FP64/FP32) step. */
 int lb2d_solute(lb2d_ctx *ctx, double tau_s, int q);
 
 /* inlet_solute / outlet_solute on an x wall: wall "xlo" or "xhi", style
@@ -133,9 +136,10 @@ int lb2d_obstacle_mask(lb2d_ctx *ctx, const uint8_t *host_mask);
  * exceeds bmax turns one of its direct fluid neighbours (E,N,W,S, not on an
  * open solute column) solid, chosen by a counter-based SplitMix64 hash of
  * (seed, step, node), and its deposit resets to 0.  Per link i the rate is
- * k_i = kr w_i / (1/6); the link concentration C_i = (2 g_out + k_i Cs) /
- * (2 w_i + k_i) and returning population 2 w_i C_i - g_out reduce to the
- * paper's D2Q4 rule.  Deposits are FP64.  Needs solute; kr >= 0. */
+ * k_i = kr w_i / W (W = 1/6 on D2Q9, 1/4 on D2Q4); the link concentration
+ * C_i = (2 g_out + k_i Cs) / (2 w_i + k_i) and returning population
+ * 2 w_i C_i - g_out are, on D2Q4, the paper's rule of App. C.  Deposits
+ * are FP64.  Needs solute; kr >= 0. */
 int lb2d_surface_reaction(lb2d_ctx *ctx, double kr, double Cs,
                           const char *style, double b0, double bmax,
                           uint64_t seed);
@@ -208,7 +212,9 @@ int lb2d_budgets(lb2d_ctx *ctx, double *out);
 
 /* Raw state, decoded to FP64 f_i (comp 0/1) or g_i (comp -1): 9*nx*ny
  * doubles [9][ny][nx] of the post-collision state (for checkpoints and
- * one-step comparisons).  set encodes into the storage format. */
+ * one-step comparisons).  set encodes into the storage format.  With a
+ * D2Q4 solute, planes 0 and 5..8 of g read as 0 and must be 0 on set
+ * (LB2D_E_INVAL otherwise). */
 int lb2d_get_populations(lb2d_ctx *ctx, int comp, double *out);
 int lb2d_set_populations(lb2d_ctx *ctx, int comp, const double *in);
 /* Raw deposit array (nx*ny doubles, all nodes) and step counter. */

@@ -41,6 +41,20 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads used by the row loops (1 without OpenMP). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------- lattice */
 
@@ -240,15 +254,26 @@ int orc_surface_reaction(orc *o, double kr, double Cs, double b0, double bmax,
 /* obstacle(circle, xc, yc, r): a node is solid when its squared distance to
  * the centre, measured with the minimum image on the periodic box, is at
  * most r^2. */
+static void circle_node(orc *o, int x, int y, int xc, int yc, double r) {
+    long dx = wrap(x - xc, o->nx), dy = wrap(y - yc, o->ny);
+    if (o->nx - dx < dx) dx = o->nx - dx;
+    if (o->ny - dy < dy) dy = o->ny - dy;
+    double d2 = (double)(dx * dx + dy * dy);
+    if (d2 <= r * r) o->mask[idx(o, x, y)] = 1;
+}
+
 int orc_obstacle_circle(orc *o, int xc, int yc, double r) {
-    for (int y = 0; y < o->ny; ++y)
-        for (int x = 0; x < o->nx; ++x) {
-            long dx = wrap(x - xc, o->nx), dy = wrap(y - yc, o->ny);
-            if (o->nx - dx < dx) dx = o->nx - dx;
-            if (o->ny - dy < dy) dy = o->ny - dy;
-            double d2 = (double)(dx * dx + dy * dy);
-            if (d2 <= r * r) o->mask[idx(o, x, y)] = 1;
-        }
+    /* only nodes within the bounding box can be inside; a circle that spans
+     * half the box or more is tested against every node */
+    int h = (r < (double)(o->nx + o->ny)) ? (int)r + 1 : o->nx + o->ny;
+    if (2 * h + 1 >= o->nx || 2 * h + 1 >= o->ny) {
+        for (int y = 0; y < o->ny; ++y)
+            for (int x = 0; x < o->nx; ++x) circle_node(o, x, y, xc, yc, r);
+        return 0;
+    }
+    for (int dy = -h; dy <= h; ++dy)
+        for (int dx = -h; dx <= h; ++dx)
+            circle_node(o, wrap(xc + dx, o->nx), wrap(yc + dy, o->ny), xc, yc, r);
     return 0;
 }
 
@@ -385,6 +410,7 @@ static long fluid_src(const orc *o, int x, int y, int i) {
  * with rho_cbar = 0 on solid neighbours and s = 1 on solids. */
 static void compute_forces(orc *o) {
     for (int c = 0; c < o->ncomp; ++c)
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < o->ny; ++y)
             for (int x = 0; x < o->nx; ++x) {
                 long s = idx(o, x, y);
@@ -426,6 +452,7 @@ static void compute_forces(orc *o) {
 /* Densities and momenta of the populations in arrays f[c]. */
 static void compute_moments(orc *o, double *const *f) {
     for (int c = 0; c < o->ncomp; ++c)
+#pragma omp parallel for schedule(static)
         for (long s = 0; s < o->n; ++s) {
             double r = 0.0, mx = 0.0, my = 0.0;
             if (!o->mask[s])
@@ -475,6 +502,7 @@ static void one_step(orc *o) {
      * x - e_i; if that node is solid, the population that x itself sent
      * towards the wall comes back reversed (noslip, half-way bounce-back). */
     for (int c = 0; c < o->ncomp; ++c)
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long s = idx(o, x, y);
@@ -502,6 +530,7 @@ static void one_step(orc *o) {
      * u_s = sum_c (j_c + F_c/2) / sum_c rho_c, is kept for the solute. */
     double *usx = (double *)calloc(n, sizeof(double));
     double *usy = (double *)calloc(n, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (long s = 0; s < n; ++s) {
         if (o->mask[s]) {
             for (int c = 0; c < o->ncomp; ++c)
@@ -545,6 +574,11 @@ static void one_step(orc *o) {
      * open x walls.  o->g still holds the post-collision values of the
      * previous step. */
     const int q = o->q;
+    /* opening fluxes are summed per row, then over rows in order, so the
+     * result does not depend on how rows are shared among threads */
+    double *in_row = (double *)calloc(ny, sizeof(double));
+    double *out_row = (double *)calloc(ny, sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             long s = idx(o, x, y);
@@ -592,7 +626,7 @@ static void one_step(orc *o) {
                         if (unknown[i]) {
                             double gi = solute_w(q, i) / wu * deficit;
                             o->gtmp[i * n + s] = gi;
-                            o->inflow += gi;
+                            in_row[y] += gi;
                         }
                 } else {
                     /* adiabatic: zero normal flux; each unknown takes the
@@ -601,7 +635,7 @@ static void one_step(orc *o) {
                         if (unknown[i]) {
                             double gi = o->gtmp[mirror_x(i) * n + s];
                             o->gtmp[i * n + s] = gi;
-                            o->inflow += gi;
+                            in_row[y] += gi;
                         }
                 }
             }
@@ -611,14 +645,21 @@ static void one_step(orc *o) {
                 if (!solute_has(q, i)) continue;
                 int dx = x + EX9[i];
                 if ((dx < 0 || dx >= nx) && !solute_x_periodic(o))
-                    o->outflow += o->g[i * n + s];
+                    out_row[y] += o->g[i * n + s];
             }
         }
+    for (int y = 0; y < ny; ++y) {
+        o->inflow += in_row[y];
+        o->outflow += out_row[y];
+    }
+    free(in_row);
+    free(out_row);
 
     /* 7. Deposit (surface_reaction command): each solid node collects the
      * flux of every reactive link that ends on it, recomputed from the
      * population that entered the wall, i.e. the value the fluid side used. */
     if (o->reaction) {
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long sd = idx(o, x, y);
@@ -641,6 +682,7 @@ static void one_step(orc *o) {
     }
 
     /* 8. Solute collision towards g_eq(C, u_s). */
+#pragma omp parallel for schedule(static)
     for (long s = 0; s < n; ++s) {
         if (o->mask[s]) {
             for (int i = 0; i < 9; ++i) o->g[i * n + s] = 0.0;

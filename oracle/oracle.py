@@ -31,9 +31,10 @@ WALL = {"xlo": 0, "xhi": 1}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction;
+    OpenMP over rows -- results do not depend on the thread count)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-shared",
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-shared",
                "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
@@ -91,6 +92,7 @@ def _load():
         "orc_reactive_link": (D, [I, I, D, D, D, DP]),
         "orc_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64]),
         "orc_pick": (I, [ctypes.c_uint64, I]),
+        "orc_set_threads": (I, [I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -136,6 +138,12 @@ def splitmix64(x):
 
 def pick(h, m):
     return _load().orc_pick(h, m)
+
+
+def set_threads(n=0):
+    """Sets the oracle's OpenMP thread count (n <= 0 keeps it); returns the
+    count in use."""
+    return _load().orc_set_threads(int(n))
 
 
 class Oracle:

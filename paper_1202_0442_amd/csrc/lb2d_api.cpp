@@ -182,8 +182,9 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
             if (k < c->ncomp) off += pop;
         }
     for (int p = 0; p < 2; ++p) {
+        // solute: q planes of n (row-major, no bricks)
         L.g[p] = c->q ? off : (size_t)-1;
-        if (c->q) off += pop;
+        if (c->q) off += align_up((size_t)c->q * n * storage_bytes(storage));
     }
     L.mask = off;
     off += align_up(n);
@@ -255,6 +256,16 @@ FullParams full_params(const lb2d_ctx *c) {
     }
     p.kr = c->kr;
     p.Cs = c->Cs;
+    // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
+    // links of a flat wall add up to kr) and the denominator of the link
+    // concentration; D2Q4 has no diagonal links
+    p.sq = c->q;
+    const double wa = c->q == 4 ? 0.25 : 1.0 / 9.0, wd = 1.0 / 36.0;
+    const double iW = c->q == 4 ? 4.0 : 6.0;
+    p.klink[0] = c->kr * wa * iW;
+    p.klink[1] = c->kr * wd * iW;
+    p.klink_inv[0] = 1.0 / (2.0 * wa + p.klink[0]);
+    p.klink_inv[1] = 1.0 / (2.0 * wd + p.klink[1]);
     p.b0 = c->b0;
     p.bmax = c->bmax;
     p.seed = c->seed;
@@ -298,7 +309,7 @@ int pre_command(lb2d_ctx *c, bool need_lattice = true) {
 hipError_t enqueue_step(lb2d_ctx *c, int parity, hipStream_t s) {
     if (c->plain()) return launch_plain(c->storage, plain_lattice(c), parity, s);
     const FullParams p = full_params(c);
-    hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->q != 0, c->reaction, s);
+    hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->reaction, s);
     if (e != hipSuccess) return e;
     if (c->q) e = launch_growth(c->storage, p, parity ^ 1, c->reaction, s);
     return e;
@@ -467,8 +478,7 @@ int lb2d_solute(lb2d_ctx *c, double tau_s, int q) {
     int rc = pre_command(c);
     if (rc) return rc;
     if (c->have_solute) return c->fail(LB2D_E_ORDER, "solute given twice");
-    if (q == 4) return c->fail(LB2D_E_UNSUPPORTED, "the D2Q4 solute lattice is not implemented on the GPU");
-    if (q != 9) return c->fail(LB2D_E_INVAL, "solute lattice must be 9 (D2Q9)");
+    if (q != 9 && q != 4) return c->fail(LB2D_E_INVAL, "solute lattice must be 9 (D2Q9) or 4 (D2Q4)");
     if (!(tau_s > 0.5)) return c->fail(LB2D_E_INVAL, "tau_s must exceed 1/2");
     c->q = q;
     c->tau_s = tau_s;
@@ -736,7 +746,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         if ((e = upload(c, c->staging, c->C0, 0.0))) return e;
         if ((e = upload(c, c->staging + n, c->Cux, 0.0))) return e;
         if ((e = upload(c, c->staging + 2 * n, c->Cuy, 0.0))) return e;
-        HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, s));
+        HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, c->q, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
@@ -768,7 +778,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
             } else {
                 const FullParams p = full_params(c);
-                HIPCHK(c, launch_full(c->storage, p, parity, c->sc(), c->q != 0, c->reaction, c->stream));
+                HIPCHK(c, launch_full(c->storage, p, parity, c->sc(), c->reaction, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
                 if (c->q) HIPCHK(c, launch_growth(c->storage, p, parity ^ 1, c->reaction, c->stream));
             }
@@ -890,6 +900,9 @@ static int pop_target(lb2d_ctx *c, int comp, void **buf, double *ref) {
     return LB2D_OK;
 }
 
+// Storage plane of solute direction i (-1: absent from D2Q4).
+static int solute_plane(int q, int i) { return q == 9 ? i : ((i >= 1 && i <= 4) ? i - 1 : -1); }
+
 static const double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
@@ -902,7 +915,12 @@ int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = c->n();
     for (int i = 0; i < 9; ++i) {
-        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, i, kW[i] * ref, (unsigned)c->nx,
+        const int pl = comp >= 0 ? i : solute_plane(c->q, i);
+        if (pl < 0) {  // direction absent from the D2Q4 solute lattice
+            std::memset(out + (size_t)i * n, 0, n * 8);
+            continue;
+        }
+        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
                                       comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
         HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -918,9 +936,17 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
     if (rc) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = c->n();
+    if (comp < 0)
+        for (int i = 0; i < 9; ++i)
+            if (solute_plane(c->q, i) < 0)
+                for (size_t k = 0; k < n; ++k)
+                    if (in[(size_t)i * n + k] != 0.0)
+                        return c->fail(LB2D_E_INVAL, "the D2Q4 solute lattice has no population %d", i);
     for (int i = 0; i < 9; ++i) {
+        const int pl = comp >= 0 ? i : solute_plane(c->q, i);
+        if (pl < 0) continue;
         HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, i, kW[i] * ref, (unsigned)c->nx,
+        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
                                       comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }

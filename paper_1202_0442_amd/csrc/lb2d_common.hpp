@@ -48,7 +48,7 @@ struct Tile {
 // a reactive surface, FP64 deposits and growth triggers.
 struct FullParams {
     void *f[2][2];        // [parity][component] fluid populations
-    void *g[2];           // [parity] solute populations (deviation from 0)
+    void *g[2];           // [parity] solute populations, sq planes of nx*ny
     uint8_t *mask;        // 1 = solid
     uint8_t *trig;        // growth trigger: 0 or 1..4 = direction to grow
     double *b;            // deposits, FP64, [ny][nx]
@@ -69,11 +69,15 @@ struct FullParams {
     double G;             // interforce (two components)
     double Gads[2];       // adhesiveforce per component (0 = off)
     int has_ads;
+    int sq;               // solute lattice: 9 (D2Q9, plane i = direction i) or
+                          // 4 (D2Q4, plane i-1 = direction i = 1..4); 0 = none
     double tau_s, omega_s;
     int solute_xper;      // 1: solute periodic in x
     int open_style[2];    // xlo, xhi: 1 dirichlet, 2 adiabatic
     double open_value[2];
     double kr, Cs, b0, bmax;
+    double klink[2];      // per-link reaction rate k_i: axial, diagonal links
+    double klink_inv[2];  // 1 / (2 w_i + k_i): axial, diagonal links
     unsigned long long seed;
     int nblk_main;        // blocks of the step kernel
     int nblk_grow;        // blocks of the growth kernel

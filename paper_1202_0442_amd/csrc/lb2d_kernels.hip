@@ -57,6 +57,32 @@ __host__ __device__ constexpr R wgt(int i) {
     return i == 0 ? R(4.0 / 9.0) : (i <= 4 ? R(1.0 / 9.0) : R(1.0 / 36.0));
 }
 
+// Solute lattices (solute command): D2Q9 with the weights above and
+// c_s^2 = 1/3, or the paper's D2Q4 (directions 1..4, weight 1/4 each,
+// c_s^2 = 1/2).  SQ = 0 means no solute.
+template <int SQ>
+__host__ __device__ constexpr bool shas(int i) {
+    return SQ == 9 ? true : (SQ == 4 ? (i >= 1 && i <= 4) : false);
+}
+template <int SQ, typename R>
+__host__ __device__ constexpr R swgt(int i) {
+    return SQ == 9 ? wgt<R>(i) : R(0.25);
+}
+// 1 / c_s^2 of the solute lattice
+template <int SQ, typename R>
+__host__ __device__ constexpr R sics2() {
+    return SQ == 9 ? R(3) : R(2);
+}
+// storage plane of solute direction i
+template <int SQ>
+__host__ __device__ constexpr int spl(int i) {
+    return SQ == 9 ? i : i - 1;
+}
+
+// Reciprocal: the hardware's (1 ulp) in FP32, exact division in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
 // ----------------------------------------------------------------- storage
 
 // bfloat16 bits (a distinct scalar type, so it can be read through any
@@ -249,7 +275,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     // a brick (one or two whole lines) is written iff it holds a fluid node
     const unsigned lane = __lane_id();
     const unsigned long long gmask =
-        (kGroup >= 64) ? ~0ull : (((1ull << kGroup) - 1ull) << ((lane / kGroup) * kGroup));
+        (kGroup >= 64) ? ~0ull : (((1ull << (kGroup & 63)) - 1ull) << ((lane / kGroup) * kGroup));
     const bool store = (bal & gmask) != 0ull;
     const size_t plane = L.plane;
     const LB2D_GLOBAL S *__restrict__ fin = gbl(L.fin);
@@ -292,7 +318,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     const R tau = R(L.tau), omega = R(L.omega);
     const R Fx = R(L.Fx) + rho * R(L.ax);
     const R Fy = R(L.Fy) + rho * R(L.ay);
-    const R inv = R(1) / rho;
+    const R inv = rcp(rho);
     const R ux = (jx + tau * Fx) * inv;
     const R uy = (jy + tau * Fy) * inv;
     const R usq = R(1.5) * (ux * ux + uy * uy);
@@ -354,15 +380,18 @@ __device__ __forceinline__ typename Codec<S>::R ldpop(const S *__restrict__ f, s
     return Codec<S>::dec(f[a], i);
 }
 
-// Reactive half-way link (surface_reaction command, generalised per link):
-// k_i = kr w_i / (1/6); C_i = (2 g_out + k_i Cs) / (2 w_i + k_i);
+// Reactive half-way link (surface_reaction command, App. C, applied per
+// link): k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4, so the links of
+// a flat wall add up to kr); C_i = (2 g_out + k_i Cs) / (2 w_i + k_i);
 // returning population 2 w_i C_i - g_out; deposit g_out - g_in if positive,
-// otherwise plain bounce-back.
-template <typename R>
-__device__ __forceinline__ R reactive_link(int i, R kr, R Cs, R g_out, R &g_in) {
-    const R w = wgt<R>(i);
-    const R k = kr * w * R(6);
-    const R Ci = (R(2) * g_out + k * Cs) / (R(2) * w + k);
+// otherwise plain bounce-back.  For D2Q4 this is the rule as printed.
+// k_i and 1/(2 w_i + k_i) depend only on whether the link is axial or
+// diagonal; the host passes both pairs.
+template <int SQ, typename R>
+__device__ __forceinline__ R reactive_link(int i, const FullParams &p, R Cs, R g_out, R &g_in) {
+    const R w = swgt<SQ, R>(i);
+    const R k = R(i <= 4 ? p.klink[0] : p.klink[1]);
+    const R Ci = (R(2) * g_out + k * Cs) * R(i <= 4 ? p.klink_inv[0] : p.klink_inv[1]);
     R gi = R(2) * w * Ci - g_out;
     R db = g_out - gi;
     if (!(db > R(0))) {
@@ -405,10 +434,11 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
 // Every plane is written by ONE store per wavefront (solid lanes of a
 // wavefront with fluid lanes write zeros), so no line is written twice in
 // part; all-solid wavefronts store nothing.
-template <typename S, int NC, bool SC, bool SOL, bool REACT, int TX, int TY>
+template <typename S, int NC, bool SC, int SQ, bool REACT, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
+    constexpr bool SOL = SQ != 0;
     __shared__ uint8_t smask[TY + 4][TX + 4];
     __shared__ R srho[SC ? NC : 1][TY + 2][TX + 2];
     __shared__ double sred[(TX * TY / 64) * 4];
@@ -484,10 +514,10 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     if constexpr (SOL) {
         const S *__restrict__ gin = (const S *)p.g[parity];
         bool any_unk = false;
-        const R kr = R(p.kr), Cs = R(p.Cs);
+        const R Cs = R(p.Cs);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            if (!fluid) continue;
+            if (!shas<SQ>(i) || !fluid) continue;
             const int sxr = x - ex(i);
             if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
                 unk[i] = true;
@@ -496,12 +526,12 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             }
             const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
             if (wall) {
-                const R g_out = ldpop(gin, (size_t)opp(i) * plane + s, opp(i));
+                const R g_out = ldpop(gin, (size_t)spl<SQ>(opp(i)) * plane + s, opp(i));
                 R gi = g_out;
-                if constexpr (REACT) reactive_link<R>(i, kr, Cs, g_out, gi);
+                if constexpr (REACT) reactive_link<SQ, R>(i, p, Cs, g_out, gi);
                 g[i] = gi;
             } else {
-                g[i] = ldpop(gin, (size_t)i * plane + src[i], i);
+                g[i] = ldpop(gin, (size_t)spl<SQ>(i) * plane + src[i], i);
             }
         }
         if (any_unk) {
@@ -510,14 +540,15 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 R known = R(0), wu = R(0);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    if (unk[i]) wu += wgt<R>(i);
+                    if (!shas<SQ>(i)) continue;
+                    if (unk[i]) wu += swgt<SQ, R>(i);
                     else known += g[i];
                 }
-                const R deficit = R(p.open_value[side]) - known;
+                const R deficit = (R(p.open_value[side]) - known) * rcp(wu);
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     if (unk[i]) {
-                        g[i] = wgt<R>(i) / wu * deficit;
+                        g[i] = swgt<SQ, R>(i) * deficit;
                         tal[0] += (double)g[i];
                     }
             } else {
@@ -532,8 +563,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         if (fluid && !p.solute_xper && (x == 0 || x == nx - 1)) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
+                if (!shas<SQ>(i)) continue;
                 const int dx = x + ex(i);
-                if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)i * plane + s, i);
+                if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)spl<SQ>(i) * plane + s, i);
             }
         }
     }
@@ -553,16 +585,17 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             }
             if (fluid8) {
                 const S *__restrict__ gin = (const S *)p.g[parity];
-                const R kr = R(p.kr), Cs = R(p.Cs);
+                const R Cs = R(p.Cs);
 #pragma unroll
                 for (int i = 1; i < 9; ++i) {
+                    if (!shas<SQ>(i)) continue;
                     const int fxg = x + ex(i);
                     if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
                     if (smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) continue;
                     const size_t fl = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(fxg, nx);
-                    const R g_out = ldpop(gin, (size_t)opp(i) * plane + fl, opp(i));
+                    const R g_out = ldpop(gin, (size_t)spl<SQ>(opp(i)) * plane + fl, opp(i));
                     R gi;
-                    dep += (double)reactive_link<R>(i, kr, Cs, g_out, gi);
+                    dep += (double)reactive_link<SQ, R>(i, p, Cs, g_out, gi);
                 }
             }
         }
@@ -663,14 +696,16 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         sjy += jy[c] + R(0.5) * Fy[c];
         srh += rho[c];
     }
-    const R upx = nux / den, upy = nuy / den;
+    const R iden = rcp(den);
+    const R upx = nux * iden, upy = nuy * iden;
     // 6. collide and store (one store per plane for the whole wavefront)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
         const R tau = R(p.tau[c]), om = R(p.omega[c]);
-        const R ux = upx + tau * Fx[c] / rho[c];
-        const R uy = upy + tau * Fy[c] / rho[c];
+        const R irho = rcp(rho[c]);
+        const R ux = upx + tau * Fx[c] * irho;
+        const R uy = upy + tau * Fy[c] * irho;
         const R usq = R(1.5) * (ux * ux + uy * uy);
         const R rr = R(p.rho_ref[c]);
 #pragma unroll
@@ -684,18 +719,21 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     }
     // 7. solute collision at the solvent velocity, one store per plane
     if constexpr (SOL) {
-        const R usx = sjx / srh, usy = sjy / srh;
+        const R isrh = rcp(srh);
+        const R usx = sjx * isrh, usy = sjy * isrh;
         S *__restrict__ gout = (S *)p.g[parity ^ 1];
         R Cc = R(0);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Cc += g[i];
+        for (int i = 0; i < 9; ++i)
+            if (shas<SQ>(i)) Cc += g[i];
         const R oms = R(p.omega_s);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
+            if (!shas<SQ>(i)) continue;
             const R eu = R(ex(i)) * usx + R(ey(i)) * usy;
-            const R geq = wgt<R>(i) * Cc * (R(1) + R(3) * eu);
+            const R geq = swgt<SQ, R>(i) * Cc * (R(1) + sics2<SQ, R>() * eu);
             const R v = fluid ? g[i] + oms * (geq - g[i]) : R(0);
-            if (store) gout[(size_t)i * plane + s] = C::enc(v, i);
+            if (store) gout[(size_t)spl<SQ>(i) * plane + s] = C::enc(v, i);
         }
     }
     if (valid && solid && REACT && fluid8) {
@@ -803,7 +841,7 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
                 }
                 const S *__restrict__ g = (const S *)p.g[parity_new];
                 double cc = 0.0;
-                for (int i = 0; i < 9; ++i) cc += (double)C::dec(g[(size_t)i * plane + s], i);
+                for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + s], k);
                 tal[2] = cc;
                 tal[3] = 1.0;
                 p.mask[s] = 1;
@@ -940,15 +978,17 @@ __global__ void k_init_fluid(S *f, const double *rho, const double *ux, const do
     }
 }
 
-template <typename S>
+template <typename S, int SQ>
 __global__ void k_init_solute(S *g, const double *Cc, const double *ux, const double *uy, size_t n) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
         const double c = Cc[k], u = ux[k], v = uy[k];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
+            if (!shas<SQ>(i)) continue;
             const double eu = ex(i) * u + ey(i) * v;
-            g[(size_t)i * n + k] = C::enc((typename C::R)(wgt<double>(i) * c * (1.0 + 3.0 * eu)), i);
+            const double ge = swgt<SQ, double>(i) * c * (1.0 + sics2<SQ, double>() * eu);
+            g[(size_t)spl<SQ>(i) * n + k] = C::enc((typename C::R)ge, i);
         }
     }
 }
@@ -1068,7 +1108,7 @@ __global__ void k_solute_state(FullParams p, int parity, int reaction, double *o
         const bool sol = p.mask[k] != 0;
         if (!sol) {
             const S *g = (const S *)p.g[parity];
-            for (int i = 0; i < 9; ++i) c += (double)C::dec(g[(size_t)i * n + k], i);
+            for (int j = 0; j < p.sq; ++j) c += (double)C::dec(g[(size_t)j * n + k], j);
         }
         oc[k] = c;
         ob[k] = (sol && reaction) ? p.b[k] : 0.0;
@@ -1104,7 +1144,7 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
         }
         if (has_solute) {
             const S *g = (const S *)p.g[parity];
-            for (int i = 0; i < 9; ++i) v[4] += (double)C::dec(g[(size_t)i * plane + s], i);
+            for (int j = 0; j < p.sq; ++j) v[4] += (double)C::dec(g[(size_t)j * (size_t)p.nx * p.ny + s], j);
         }
     }
     double out[8];
@@ -1183,43 +1223,38 @@ hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int 
 int full_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 int growth_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
 
-template <typename S>
-static void full_dispatch(const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t st) {
+template <typename S, int SQ>
+static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
-#define LB2D_FULL(NC_, SC_, SOL_, REACT_) \
-    hipLaunchKernelGGL((k_full<S, NC_, SC_, SOL_, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
+#define LB2D_FULL(NC_, SC_, REACT_) \
+    hipLaunchKernelGGL((k_full<S, NC_, SC_, SQ, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
-            if (sol) {
-                if (react) LB2D_FULL(2, true, true, true);
-                else LB2D_FULL(2, true, true, false);
-            } else {
-                LB2D_FULL(2, true, false, false);
-            }
+            if (react) LB2D_FULL(2, true, true);
+            else LB2D_FULL(2, true, false);
         } else {
-            if (sol) {
-                if (react) LB2D_FULL(2, false, true, true);
-                else LB2D_FULL(2, false, true, false);
-            } else {
-                LB2D_FULL(2, false, false, false);
-            }
+            if (react) LB2D_FULL(2, false, true);
+            else LB2D_FULL(2, false, false);
         }
     } else {
-        if (sol) {
-            if (react) LB2D_FULL(1, false, true, true);
-            else LB2D_FULL(1, false, true, false);
-        } else {
-            LB2D_FULL(1, false, false, false);
-        }
+        if (react) LB2D_FULL(1, false, true);
+        else LB2D_FULL(1, false, false);
     }
 #undef LB2D_FULL
 }
 
-hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react,
-                       hipStream_t stream) {
-    if (st == kF64) full_dispatch<double>(p, parity, sc, sol, react, stream);
-    else full_dispatch<float>(p, parity, sc, sol, react, stream);
+// The reaction needs a solute; the solute lattice is p.sq (0, 9 or 4).
+template <typename S>
+static void full_dispatch(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
+    if (p.sq == 9) full_dispatch_sq<S, 9>(p, parity, sc, react, st);
+    else if (p.sq == 4) full_dispatch_sq<S, 4>(p, parity, sc, react, st);
+    else full_dispatch_sq<S, 0>(p, parity, sc, false, st);
+}
+
+hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t stream) {
+    if (st == kF64) full_dispatch<double>(p, parity, sc, react, stream);
+    else full_dispatch<float>(p, parity, sc, react, stream);
     return hipGetLastError();
 }
 
@@ -1279,8 +1314,14 @@ hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *u
     return hipGetLastError();
 }
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
-                              hipStream_t s) {
-    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_init_solute<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux, uy, n));
+                              int sq, hipStream_t s) {
+    if (sq == 4) {
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 4>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
+                                             uy, n));
+    } else {
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 9>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
+                                             uy, n));
+    }
     return hipGetLastError();
 }
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s) {

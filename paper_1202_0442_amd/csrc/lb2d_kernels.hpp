@@ -15,7 +15,8 @@ void plain_tile(int st, int *tw, int *th);
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t s);
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
                         hipStream_t s);
-hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool sol, bool react, hipStream_t s);
+// General step; the solute lattice (none, D2Q9, D2Q4) is p.sq.
+hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
 hipError_t launch_tally_final(const FullParams &p, hipStream_t s);
 
@@ -28,8 +29,10 @@ hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int coun
 hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
                              double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
                              size_t pplane, hipStream_t s);
+// Solute populations at equilibrium on a D2Q9 (sq = 9) or D2Q4 (sq = 4)
+// lattice, sq planes of n.
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
-                              hipStream_t s);
+                              int sq, hipStream_t s);
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s);
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
                                double shift, unsigned nx, int brick, unsigned pnx, size_t pplane, hipStream_t s);

@@ -31,7 +31,7 @@ def porous_case(nx, ny, seed, tau=0.8, accel=1e-5, nd=None, rmin=2.0, rmax=6.0, 
 
 
 def sc_solute_case(nx, ny, seed, react=True, kr=0.01, bmax=0.2, G=0.9, gads=(0.3, -0.3),
-                   openings=True, tau_s=0.7, nd=None, C0=0.05, b0=0.0):
+                   openings=True, tau_s=0.7, nd=None, C0=0.05, b0=0.0, q=9):
     rng = np.random.default_rng(seed)
     nd = nd if nd is not None else max(2, nx * ny // 500)
     circles = []
@@ -45,12 +45,25 @@ def sc_solute_case(nx, ny, seed, react=True, kr=0.01, bmax=0.2, G=0.9, gads=(0.3
     rho_b = np.where(blob, 0.05, 1.0) * (1 + 0.01 * rng.uniform(-1, 1, n))
     case = dict(nx=nx, ny=ny, tau=1.0, fluids=(1.0, 1.0), G=G, gads=gads, circles=circles,
                 fields={0: (rho_a, None, None), 1: (rho_b, None, None)},
-                solute=tau_s, C=np.full(n, C0), accel=[(1, 1e-5, 0)])
+                solute=tau_s, q=q, C=np.full(n, C0), accel=[(1, 1e-5, 0)])
     if openings:
         case["openings"] = [("xlo", "dirichlet", 1.0), ("xhi", "adiabatic", 0.0)]
     if react:
         case["reaction"] = (kr, 0.0, b0, bmax, 4242 + seed)
     return case
+
+
+def surface_growth_case(kr, n=200, side=11, f0=24.0, C0=1.5, Cs=0.5, b0=0.5, bmax=1.0, tau=1.0,
+                        tau_s=1.0, q=4, seed=2012):
+    """The paper's surface-growth example (section Surface growth and its
+    script): an n x n periodic box, one fluid at rest of density f0, a
+    side x side solid seed square in the centre, D2Q4 solute C0, reaction
+    kr / Cs / b0 / bmax.  The fluid starts at its equilibrium (rho = f0)."""
+    h = side // 2
+    c = n // 2
+    return dict(nx=n, ny=n, tau=tau, rects=[(c - h, c + h, c - h, c + h)],
+                fields={0: (np.full(n * n, f0), None, None)}, solute=tau_s, q=q,
+                C=np.full(n * n, C0), reaction=(kr, Cs, b0, bmax, seed))
 
 
 def build_oracle(case):
@@ -83,7 +96,7 @@ def build_oracle(case):
     elif 0 not in case.get("fields", {}):
         o.set_fields(0, 1.0)
     if case.get("solute") is not None:
-        o.solute(case["solute"], 9)
+        o.solute(case["solute"], case.get("q", 9))
         for wall, style, val in case.get("openings", []):
             o.solute_opening(wall, style, val)
         if case.get("reaction") is not None:
@@ -99,7 +112,7 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
     if "fluids" in case:
         g.fluids(*case["fluids"])
     if case.get("solute") is not None:
-        g.solute(case["solute"], 9)
+        g.solute(case["solute"], case.get("q", 9))
         for wall, style, val in case.get("openings", []):
             g.solute_opening(wall, style, val)
     g.boundary_style("noslip")

@@ -77,7 +77,7 @@ def test_unsupported_forms():
     L = lb2d.Lattice()
     L.lattice("d2q9", 10, 10, 1.0)
     cases = [lambda: L.boundary_style("slip"), lambda: L.boundary_style("mixed"),
-             lambda: L.solute(1.0, 4), lambda: L.interforce(-120, 4, 200),
+             lambda: L.interforce(-120, 4, 200),
              lambda: L.adhesiveforce(-200, 0, 4, 200)]
     for call in cases:
         with pytest.raises(lb2d.LB2DError) as e:
@@ -104,7 +104,7 @@ def test_bad_arguments():
                  lambda: L.obstacle_circle(10, 0, 1.0), lambda: L.obstacle_circle(1, 1, -1.0),
                  lambda: L.aveforce(9, 1.0), lambda: L.aveforce(1, 1.0, 1),
                  lambda: L.set_fields(0, -np.ones(80)), lambda: L.set_fields(1, np.ones(80)),
-                 lambda: L.fluids(0.4, 1.0)):
+                 lambda: L.fluids(0.4, 1.0), lambda: L.solute(1.0, 5), lambda: L.solute(0.5, 4)):
         with pytest.raises(lb2d.LB2DError) as e:
             call()
         assert e.value.code == lb2d.E_INVAL

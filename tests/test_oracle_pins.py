@@ -604,3 +604,33 @@ def test_circle_rasterisation_counts():
     o.obstacle_circle(0, 0, 1.0)
     m = o.get_mask()
     assert m[0, 0] and m[0, 19] and m[19, 0] and m[0, 1] and m[1, 0] and m.sum() == 5
+
+
+def test_results_do_not_depend_on_thread_count():
+    """Row loops run in parallel; every reduction is ordered, so 1 and many
+    threads give bitwise the same state and budgets."""
+    def run(threads):
+        orc.set_threads(threads)
+        o = Oracle(40, 30)
+        o.fluids(2, 1.0, 0.8)
+        o.interforce(1.2)
+        o.adhesiveforce(0.2, 0)
+        o.obstacle_circle(20, 15, 4.0)
+        o.solute(0.8, 9)
+        o.solute_opening("xlo", "dirichlet", 1.0)
+        o.solute_opening("xhi", "adiabatic")
+        o.surface_reaction(0.05, 0.0, 0.0, 0.02, 3)
+        rng = np.random.default_rng(9)
+        o.set_fields(0, rng.uniform(0.1, 1.0, 1200))
+        o.set_fields(1, rng.uniform(0.1, 1.0, 1200))
+        o.set_concentration(0.1)
+        o.iteration(120)
+        return o.get_f(0), o.get_g(), o.get_mask(), o.budgets()
+    n0 = orc.set_threads(0)
+    try:
+        a, b = run(1), run(max(2, n0))
+    finally:
+        orc.set_threads(n0)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert a[3] == b[3]
