@@ -82,9 +82,7 @@ struct lb2d_ctx {
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
     hipGraphExec_t graph = nullptr;
-    // population plane geometry: brick layout (padded) for one-fluid
-    // lattices, row-major for the others
-    int brick = 0;
+    // population plane geometry: brick layout, padded to whole bricks
     unsigned pnx = 0;
     size_t pplane = 0;
     // timing
@@ -152,28 +150,20 @@ struct Layout {
 };
 
 // Padded plane geometry of the populations for the given storage.
-void plane_geometry(const lb2d_ctx *c, int storage, int *brick, unsigned *pnx, size_t *pplane) {
-    if (c->plain()) {
-        const unsigned bh = (unsigned)brick_h_for((int)storage_bytes(storage));
-        const unsigned px = (unsigned)((c->nx + kBrickW - 1) / kBrickW * kBrickW);
-        const unsigned py = (unsigned)((c->ny + bh - 1) / bh * bh);
-        *brick = 1;
-        *pnx = px;
-        *pplane = (size_t)px * py;
-    } else {
-        *brick = 0;
-        *pnx = (unsigned)c->nx;
-        *pplane = c->n();
-    }
+void plane_geometry(const lb2d_ctx *c, int storage, unsigned *pnx, size_t *pplane) {
+    const unsigned bh = (unsigned)brick_h_for((int)storage_bytes(storage));
+    const unsigned px = (unsigned)((c->nx + kBrickW - 1) / kBrickW * kBrickW);
+    const unsigned py = (unsigned)((c->ny + bh - 1) / bh * bh);
+    *pnx = px;
+    *pplane = (size_t)px * py;
 }
 
 Layout make_layout(const lb2d_ctx *c, int storage) {
     Layout L{};
     const size_t n = c->n();
-    int brick;
     unsigned pnx;
     size_t pplane;
-    plane_geometry(c, storage, &brick, &pnx, &pplane);
+    plane_geometry(c, storage, &pnx, &pplane);
     const size_t pop = align_up(9 * pplane * storage_bytes(storage));
     size_t off = 0;
     for (int p = 0; p < 2; ++p)
@@ -182,16 +172,18 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
             if (k < c->ncomp) off += pop;
         }
     for (int p = 0; p < 2; ++p) {
-        // solute: q planes of n (row-major, no bricks)
+        // solute: q brick-layout planes
         L.g[p] = c->q ? off : (size_t)-1;
-        if (c->q) off += align_up((size_t)c->q * n * storage_bytes(storage));
+        if (c->q) off += align_up((size_t)c->q * pplane * storage_bytes(storage));
     }
     L.mask = off;
     off += align_up(n);
     L.trig = off;
     off += align_up(n);
+    // 16-bit link words; the region is padded to whole 32-bit words (the
+    // growth kernel updates them with 32-bit atomic ORs)
     L.links = off;
-    off += align_up(2 * n);
+    off += align_up(2 * n + 2);
     L.b = off;
     if (c->reaction) off += align_up(n * 8);
     // staging: 3 doubles per node (host transfers, read-outs, budgets,
@@ -203,7 +195,7 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     L.staging = off;
     off += align_up(sd * 8);
     L.partial = off;
-    off += align_up((size_t)full_tiles(c->nx, c->ny) * 4 * 8);
+    off += align_up((size_t)full_slots(c->nx, c->ny) * 4 * 8);
     L.gpartial = off;
     off += align_up((size_t)growth_blocks(c->nx, c->ny) * 4 * 8);
     L.totals = off;
@@ -223,6 +215,7 @@ FullParams full_params(const lb2d_ctx *c) {
         p.g[pp] = c->g[pp];
     }
     p.mask = c->mask;
+    p.links = c->links;
     p.trig = c->trig;
     p.b = c->b;
     p.partial = c->partial;
@@ -233,45 +226,63 @@ FullParams full_params(const lb2d_ctx *c) {
     p.nx = c->nx;
     p.ny = c->ny;
     p.ncomp = c->ncomp;
+    StepCoef<double> &k8 = p.cd;
     for (int k = 0; k < 2; ++k) {
-        p.tau[k] = c->tau[k];
-        p.omega[k] = 1.0 / c->tau[k];
-        p.A0[k] = 2.25 * c->alpha[k];
-        p.A1[k] = 1.8 * (1.0 - c->alpha[k]);
-        p.rho_ref[k] = c->rho_ref[k];
+        k8.tau[k] = c->tau[k];
+        k8.omega[k] = 1.0 / c->tau[k];
+        k8.A0[k] = 2.25 * c->alpha[k];
+        k8.A1[k] = 1.8 * (1.0 - c->alpha[k]);
+        k8.rho_ref[k] = c->rho_ref[k];
         for (int d = 0; d < 2; ++d) {
-            p.force[k][d] = c->force[k][d];
-            p.accel[k][d] = c->accel[k][d];
+            k8.force[k][d] = c->force[k][d];
+            k8.accel[k][d] = c->accel[k][d];
         }
-        p.Gads[k] = c->ads[k] ? c->Gads[k] : 0.0;
+        k8.Gads[k] = c->ads[k] ? c->Gads[k] : 0.0;
     }
-    p.G = c->inter ? c->G : 0.0;
+    k8.G = c->inter ? c->G : 0.0;
     p.has_ads = (c->ads[0] || c->ads[1]) ? 1 : 0;
-    p.tau_s = c->tau_s;
-    p.omega_s = 1.0 / c->tau_s;
+    k8.omega_s = c->q ? 1.0 / c->tau_s : 0.0;
     p.solute_xper = (c->open_style[0] || c->open_style[1]) ? 0 : 1;
     for (int k = 0; k < 2; ++k) {
         p.open_style[k] = c->open_style[k];
-        p.open_value[k] = c->open_value[k];
+        k8.open_value[k] = c->open_value[k];
     }
-    p.kr = c->kr;
-    p.Cs = c->Cs;
+    k8.Cs = c->Cs;
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
     // links of a flat wall add up to kr) and the denominator of the link
     // concentration; D2Q4 has no diagonal links
     p.sq = c->q;
     const double wa = c->q == 4 ? 0.25 : 1.0 / 9.0, wd = 1.0 / 36.0;
     const double iW = c->q == 4 ? 4.0 : 6.0;
-    p.klink[0] = c->kr * wa * iW;
-    p.klink[1] = c->kr * wd * iW;
-    p.klink_inv[0] = 1.0 / (2.0 * wa + p.klink[0]);
-    p.klink_inv[1] = 1.0 / (2.0 * wd + p.klink[1]);
+    k8.klink[0] = c->kr * wa * iW;
+    k8.klink[1] = c->kr * wd * iW;
+    k8.klink_inv[0] = 1.0 / (2.0 * wa + k8.klink[0]);
+    k8.klink_inv[1] = 1.0 / (2.0 * wd + k8.klink[1]);
+    // FP32 copy (each value rounded once)
+    StepCoef<float> &k4 = p.cf;
+    for (int k = 0; k < 2; ++k) {
+        k4.tau[k] = (float)k8.tau[k];
+        k4.omega[k] = (float)k8.omega[k];
+        k4.A0[k] = (float)k8.A0[k];
+        k4.A1[k] = (float)k8.A1[k];
+        k4.rho_ref[k] = (float)k8.rho_ref[k];
+        for (int d = 0; d < 2; ++d) {
+            k4.force[k][d] = (float)k8.force[k][d];
+            k4.accel[k][d] = (float)k8.accel[k][d];
+        }
+        k4.Gads[k] = (float)k8.Gads[k];
+        k4.open_value[k] = (float)k8.open_value[k];
+        k4.klink[k] = (float)k8.klink[k];
+        k4.klink_inv[k] = (float)k8.klink_inv[k];
+    }
+    k4.G = (float)k8.G;
+    k4.omega_s = (float)k8.omega_s;
+    k4.Cs = (float)k8.Cs;
     p.b0 = c->b0;
     p.bmax = c->bmax;
     p.seed = c->seed;
-    p.nblk_main = full_tiles(c->nx, c->ny);
+    p.nblk_main = full_slots(c->nx, c->ny);
     p.nblk_grow = growth_blocks(c->nx, c->ny);
-    p.brick = c->brick;
     p.pnx = c->pnx;
     p.pplane = c->pplane;
     return p;
@@ -675,7 +686,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->ws = (char *)dev_ptr;
     c->ws_bytes = bytes;
     c->stream = (hipStream_t)hip_stream;
-    plane_geometry(c, c->storage, &c->brick, &c->pnx, &c->pplane);
+    plane_geometry(c, c->storage, &c->pnx, &c->pplane);
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < c->ncomp; ++k) c->f[p][k] = c->ws + L.f[p][k];
     for (int p = 0; p < 2; ++p) c->g[p] = c->q ? (void *)(c->ws + L.g[p]) : nullptr;
@@ -738,7 +749,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         if ((e = upload(c, c->staging + 2 * n, c->uy0[k], 0.0))) return e;
         HIPCHK(c, launch_init_fluid(c->storage, c->f[0][k], c->staging, c->staging + n, c->staging + 2 * n, n,
                                     2.25 * c->alpha[k], 1.8 * (1.0 - c->alpha[k]), c->rho_ref[k],
-                                    (unsigned)c->nx, c->brick, c->pnx, c->pplane, s));
+                                    (unsigned)c->nx, c->pnx, c->pplane, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->q) {
@@ -746,13 +757,14 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         if ((e = upload(c, c->staging, c->C0, 0.0))) return e;
         if ((e = upload(c, c->staging + n, c->Cux, 0.0))) return e;
         if ((e = upload(c, c->staging + 2 * n, c->Cuy, 0.0))) return e;
-        HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, c->q, s));
+        HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, c->q,
+                                     (unsigned)c->nx, c->pnx, c->pplane, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));
     HIPCHK(c, launch_links(c->mask, c->links, c->nx, c->ny, s));
     HIPCHK(c, launch_fill_f64(c->totals, 0.0, 16, s));
-    HIPCHK(c, launch_fill_f64(c->partial, 0.0, (size_t)full_tiles(c->nx, c->ny) * 4, s));
+    HIPCHK(c, launch_fill_f64(c->partial, 0.0, (size_t)full_slots(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_f64(c->gpartial, 0.0, (size_t)growth_blocks(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->gflag, 0, 8, s));
@@ -921,7 +933,7 @@ int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
             continue;
         }
         HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
-                                      comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
+                                      c->pnx, c->pplane, c->stream));
         HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -947,7 +959,7 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
         if (pl < 0) continue;
         HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
-                                      comp >= 0 ? c->brick : 0, c->pnx, comp >= 0 ? c->pplane : n, c->stream));
+                                      c->pnx, c->pplane, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return LB2D_OK;

@@ -9,7 +9,8 @@ namespace lb2d {
 // Storage formats (same values as LB2D_F64 ... in include/lb2d.h).
 enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
-// Brick layout of the one-fluid populations: each plane is cut into bricks
+// Brick layout of every population plane (fluid components and solute):
+// each plane is cut into bricks
 // of BW x BH nodes stored contiguously (8x4 for 4- and 8-byte values, 8x8
 // for 2-byte values, i.e. one or two 128-byte lines per brick), bricks in
 // row-major order over the plane padded to whole bricks.  A line then
@@ -43,44 +44,53 @@ struct Tile {
     int pad;
 };
 
+// Physical coefficients of the general step in its arithmetic type (the
+// host fills an FP64 and an FP32 copy, so no kernel converts them).
+template <typename R>
+struct StepCoef {
+    R tau[2], omega[2];
+    R A0[2], A1[2];        // equilibrium coefficients A_0, A_{1..8}
+    R rho_ref[2];          // shift of the stored populations
+    R force[2][2], accel[2][2];
+    R G;                   // interforce (two components)
+    R Gads[2];             // adhesiveforce per component (0 = off)
+    R omega_s;             // 1 / tau_s
+    R open_value[2];       // xlo, xhi opening values
+    R Cs;                  // saturation concentration
+    R klink[2];            // per-link reaction rate k_i: axial, diagonal links
+    R klink_inv[2];        // 1 / (2 w_i + k_i): axial, diagonal links
+};
+
 // Everything the general fused step needs: up to two fluid components with
-// Shan-Chen cohesion / adhesion and an optional D2Q9 solute with openings,
-// a reactive surface, FP64 deposits and growth triggers.
+// Shan-Chen cohesion / adhesion and an optional solute (D2Q9 or D2Q4) with
+// openings, a reactive surface, FP64 deposits and growth triggers.
 struct FullParams {
     void *f[2][2];        // [parity][component] fluid populations
-    void *g[2];           // [parity] solute populations, sq planes of nx*ny
+    void *g[2];           // [parity] solute populations, sq planes
     uint8_t *mask;        // 1 = solid
+    uint16_t *links;      // bit 0: node solid; bit i: node + e_i solid
     uint8_t *trig;        // growth trigger: 0 or 1..4 = direction to grow
     double *b;            // deposits, FP64, [ny][nx]
-    double *partial;      // running per-block tallies of the step kernel [nblk][4]
+    double *partial;      // running per-wavefront tallies of the step kernel [slots][4]
     double *gpartial;     // running per-block tallies of the growth kernel [nblk][4]
     double *totals;       // fixed-order sums of the tallies (LB2D_B_* indices)
     long long *dstep;     // completed steps (device copy)
     unsigned *gflag;      // [2]: a growth trigger fired in the step of that parity
-    int brick;            // populations in brick layout (one-fluid lattices)
     unsigned pnx;         // padded nx of the brick layout
     size_t pplane;        // elements per population plane
     int nx, ny;
     int ncomp;
-    double tau[2], omega[2];
-    double A0[2], A1[2];  // equilibrium coefficients A_0, A_{1..8}
-    double rho_ref[2];
-    double force[2][2], accel[2][2];
-    double G;             // interforce (two components)
-    double Gads[2];       // adhesiveforce per component (0 = off)
     int has_ads;
     int sq;               // solute lattice: 9 (D2Q9, plane i = direction i) or
                           // 4 (D2Q4, plane i-1 = direction i = 1..4); 0 = none
-    double tau_s, omega_s;
     int solute_xper;      // 1: solute periodic in x
     int open_style[2];    // xlo, xhi: 1 dirichlet, 2 adiabatic
-    double open_value[2];
-    double kr, Cs, b0, bmax;
-    double klink[2];      // per-link reaction rate k_i: axial, diagonal links
-    double klink_inv[2];  // 1 / (2 w_i + k_i): axial, diagonal links
+    double b0, bmax;
     unsigned long long seed;
-    int nblk_main;        // blocks of the step kernel
-    int nblk_grow;        // blocks of the growth kernel
+    int nblk_main;        // tally slots of the step kernel (one per wavefront)
+    int nblk_grow;        // blocks (tally slots) of the growth kernel
+    StepCoef<double> cd;  // FP64 coefficients
+    StepCoef<float> cf;   // the same rounded to FP32
 };
 
 }  // namespace lb2d

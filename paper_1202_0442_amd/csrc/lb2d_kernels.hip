@@ -141,11 +141,6 @@ __host__ __device__ __forceinline__ size_t brick_index(unsigned x, unsigned y, u
     return ((size_t)(y / H) * (pnx / W) + (x / W)) * (W * H) + (y % H) * W + (x % W);
 }
 
-// Element index of node (x, y) in a population plane of either layout.
-template <typename S>
-__device__ __forceinline__ size_t pop_index(int brick, unsigned x, unsigned y, unsigned nx, unsigned pnx) {
-    return brick ? brick_index<S>(x, y, pnx) : (size_t)y * nx + x;
-}
 
 // Deterministic block sum of K doubles per thread into out[0..K) (valid in
 // thread 0).  `sh` must hold blockDim.x * blockDim.y * K doubles... to keep
@@ -372,8 +367,9 @@ __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ 
 
 // --------------------------------------------------------- general step
 
-constexpr int kTX = 64;   // tile width = one wavefront
-constexpr int kTY = 4;    // tile height (measured: 64x4 beats 64x8..256x4)
+constexpr int kTX = 32;   // tile width (nodes, whole 8-node bricks)
+constexpr int kTY = 8;    // tile height (nodes, whole 4-node bricks); measured:
+                          // 32x8 and 16x16 beat 64x4, 32x4, 64x8, 128x4, 128x8
 
 template <typename S>
 __device__ __forceinline__ typename Codec<S>::R ldpop(const S *__restrict__ f, size_t a, int i) {
@@ -388,10 +384,10 @@ __device__ __forceinline__ typename Codec<S>::R ldpop(const S *__restrict__ f, s
 // k_i and 1/(2 w_i + k_i) depend only on whether the link is axial or
 // diagonal; the host passes both pairs.
 template <int SQ, typename R>
-__device__ __forceinline__ R reactive_link(int i, const FullParams &p, R Cs, R g_out, R &g_in) {
+__device__ __forceinline__ R reactive_link(int i, const StepCoef<R> &q, R g_out, R &g_in) {
     const R w = swgt<SQ, R>(i);
-    const R k = R(i <= 4 ? p.klink[0] : p.klink[1]);
-    const R Ci = (R(2) * g_out + k * Cs) * R(i <= 4 ? p.klink_inv[0] : p.klink_inv[1]);
+    const R k = i <= 4 ? q.klink[0] : q.klink[1];
+    const R Ci = (R(2) * g_out + k * q.Cs) * (i <= 4 ? q.klink_inv[0] : q.klink_inv[1]);
     R gi = R(2) * w * Ci - g_out;
     R db = g_out - gi;
     if (!(db > R(0))) {
@@ -420,59 +416,113 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
     return (k < len) ? start + k : -1;
 }
 
-// General fused step.  One thread per node of a TX x TY tile:
-//  1. pull both components (fluid lanes), bounce-back from the LDS mask;
-//  2. densities of the tile plus a one-node halo in LDS -- the halo nodes'
+// Node of a TX x TY tile handled by thread t: 32 consecutive threads cover
+// one 8x4 brick, the tile's bricks in row-major order, so a wavefront's
+// loads and stores of one plane touch two whole 128-byte brick lines (FP32)
+// or four (FP64).
+template <int TX>
+__device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
+    constexpr int BW = kBrickW, BH = 4, BPR = TX / BW;
+    const int b = t / (BW * BH), k = t % (BW * BH);
+    lx = (b % BPR) * BW + k % BW;
+    ly = (b / BPR) * BH + k / BW;
+}
+
+// Sum of three doubles over a wavefront (fixed butterfly order).
+__device__ __forceinline__ void wave_sum3(double (&v)[4]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = v[k];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        v[k] = a;
+    }
+}
+
+// General fused step on the brick layout.  One thread per node of a
+// TX x TY tile:
+//  1. one 16-bit link word per node (bit 0: solid; bit i: node + e_i
+//     solid) gives every bounce-back, adhesion and surface decision;
+//  2. pull both components (fluid lanes); solute pull with bounce-back or
+//     reactive link at walls and the opening rules on open x walls;
+//     solid lanes next to fluid gather the deposit of their reactive links;
+//  3. densities of the tile plus a one-node halo in LDS -- the halo nodes'
 //     populations are pulled again (from L2) so that the Shan-Chen force
 //     sees the post-stream densities of this step;
-//  3. forces (aveforce, aveacceleration, cohesion, adhesion), the common
+//  4. forces (aveforce, aveacceleration, cohesion, adhesion), the common
 //     velocity u' and each component's equilibrium velocity, collision;
-//  4. solute: pull, bounce-back or reactive link, x openings, collision at
-//     the solvent velocity of Eq. (u_solvent);
-//  5. solid lanes next to fluid gather the deposit of their reactive links
-//     and decide growth.
-// Every plane is written by ONE store per wavefront (solid lanes of a
-// wavefront with fluid lanes write zeros), so no line is written twice in
-// part; all-solid wavefronts store nothing.
-template <typename S, int NC, bool SC, int SQ, bool REACT, int TX, int TY>
+//  5. solute collision at the solvent velocity of Eq. (u_solvent);
+//  6. deposits and growth decisions of solid lanes next to fluid.
+// A brick is stored iff it holds a fluid node (solid lanes store zeros),
+// so every store writes whole lines and all-solid bricks move no data.
+// Population addresses are byte offsets of type O from the array base:
+// 32-bit when the arrays are below 4 GiB (a uniform base plus a 32-bit
+// lane offset, no 64-bit lane arithmetic), 64-bit otherwise.
+// Tallies (inflow, outflow, consumed deposit) go to one running slot per
+// wavefront, summed in a fixed order only when budgets are read.
+// Byte offset of node (x, y) in a brick-layout plane, computed in O.
+template <typename S, typename O>
+__device__ __forceinline__ O brick_off(unsigned x, unsigned y, unsigned pnx) {
+    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
+    return (((O)(y / H) * (O)(pnx / W) + (O)(x / W)) * (O)(W * H) + (O)((y % H) * W + (x % W))) * (O)sizeof(S);
+}
+template <typename S, typename O>
+__device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, O off, int i) {
+    return Codec<S>::dec(*(const S *)((const char *)base + off), i);
+}
+template <typename S, typename O>
+__device__ __forceinline__ void stb(S *__restrict__ base, O off, S v) {
+    *(S *)((char *)base + off) = v;
+}
+template <typename R>
+__device__ __forceinline__ const StepCoef<R> &coef(const FullParams &p);
+template <>
+__device__ __forceinline__ const StepCoef<double> &coef<double>(const FullParams &p) { return p.cd; }
+template <>
+__device__ __forceinline__ const StepCoef<float> &coef<float>(const FullParams &p) { return p.cf; }
+
+template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
     constexpr bool SOL = SQ != 0;
-    __shared__ uint8_t smask[TY + 4][TX + 4];
-    __shared__ R srho[SC ? NC : 1][TY + 2][TX + 2];
-    __shared__ double sred[(TX * TY / 64) * 4];
+    constexpr O SB = (O)sizeof(S);
+    static_assert(brick_h_for(sizeof(S)) == 4, "general step: 8x4 bricks");
+    static_assert(TX % kBrickW == 0 && TY % 4 == 0, "tile of whole bricks");
+    __shared__ R srho[SC ? NC : 1][SC ? TY + 2 : 1][SC ? TX + 2 : 1];
+    const StepCoef<R> &q = coef<R>(p);
 
     const int nx = p.nx, ny = p.ny;
-    const size_t plane = (size_t)nx * ny;
+    const unsigned pnx = p.pnx;
+    const O pl = (O)p.pplane * SB;  // bytes per plane
+    const uint16_t *__restrict__ links = p.links;
     const int tiles_x = (nx + TX - 1) / TX;
     int tile = xcd_band(blockIdx.x, gridDim.x);
     if (tile < 0) tile = blockIdx.x;
     const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
     const int tid = threadIdx.x;
-    const int lx = tid % TX, ly = tid / TX;
+    int lx, ly;
+    tile_thread<TX>(tid, lx, ly);
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = (x < nx) && (y < ny);
-
-    // mask tile with a two-node halo (periodic wrap)
-    for (int k = tid; k < (TX + 4) * (TY + 4); k += TX * TY) {
-        const int hx = k % (TX + 4), hy = k / (TX + 4);
-        const int gx = wrapi(tx0 + hx - 2, nx), gy = wrapi(ty0 + hy - 2, ny);
-        smask[hy][hx] = p.mask[(size_t)gy * nx + gx];
-    }
-    __syncthreads();
-
-    const bool solid = !valid || smask[ly + 2][lx + 2];
+    const size_t srow = valid ? (size_t)y * nx + x : 0;
+    const unsigned lk = valid ? (unsigned)links[srow] : 1u;
+    const bool solid = (lk & 1u) != 0u;
     const bool fluid = !solid;
-    const bool wave_fluid = __any(fluid);
-    const bool store = valid && wave_fluid;
-    const size_t s = valid ? (size_t)y * nx + x : 0;
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x >= nx - 1) ? 0 : x + 1;
-    const size_t rm = (size_t)((y == 0) ? ny - 1 : y - 1) * nx;
-    const size_t r0 = (size_t)y * nx;
-    const size_t rp = (size_t)((y >= ny - 1) ? 0 : y + 1) * nx;
-    const size_t src[9] = {s, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+    // a brick (32 lanes) is stored iff it holds a fluid node
+    const unsigned long long bal = __ballot(fluid);
+    const unsigned lane = __lane_id();
+    const bool store = valid && ((bal >> (lane & 32u)) & 0xffffffffull) != 0ull;
+
+    // byte offsets of the node and of node - e_i (periodic) in a plane
+    const unsigned ux_ = valid ? (unsigned)x : 0u, uy_ = valid ? (unsigned)y : 0u;
+    const unsigned xm = (ux_ == 0) ? nx - 1 : ux_ - 1, xp = (ux_ + 1 >= (unsigned)nx) ? 0 : ux_ + 1;
+    const unsigned ym = (uy_ == 0) ? ny - 1 : uy_ - 1, yp = (uy_ + 1 >= (unsigned)ny) ? 0 : uy_ + 1;
+    const O s = brick_off<S, O>(ux_, uy_, pnx);
+    const O src[9] = {s,
+                      brick_off<S, O>(xm, uy_, pnx), brick_off<S, O>(ux_, ym, pnx),
+                      brick_off<S, O>(xp, uy_, pnx), brick_off<S, O>(ux_, yp, pnx),
+                      brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
+                      brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
 
     // 1. pull both components at the own node
     R d[NC][9];
@@ -483,12 +533,12 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         for (int i = 0; i < 9; ++i) d[c][i] = R(0);
         if (fluid) {
             const S *__restrict__ fin = (const S *)p.f[parity][c];
-            d[c][0] = ldpop(fin, s, 0);
+            d[c][0] = ldb(fin, s, 0);
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
-                const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
-                d[c][i] = ldpop(fin, a, i);
+                const bool wall = (lk >> opp(i)) & 1u;
+                const O a = wall ? (O)opp(i) * pl + s : (O)i * pl + src[i];
+                d[c][i] = ldb(fin, a, i);
             }
         }
         drho[c] = jx[c] = jy[c] = R(0);
@@ -514,24 +564,26 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     if constexpr (SOL) {
         const S *__restrict__ gin = (const S *)p.g[parity];
         bool any_unk = false;
-        const R Cs = R(p.Cs);
+        // lanes on an open x wall (only in the first and last tile columns)
+        const bool edge = !p.solute_xper && (x == 0 || x == nx - 1);
+        if (fluid) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            if (!shas<SQ>(i) || !fluid) continue;
-            const int sxr = x - ex(i);
-            if (!p.solute_xper && (sxr < 0 || sxr >= nx)) {
-                unk[i] = true;
-                any_unk = true;
-                continue;
-            }
-            const bool wall = smask[ly + 2 - ey(i)][lx + 2 - ex(i)] != 0;
-            if (wall) {
-                const R g_out = ldpop(gin, (size_t)spl<SQ>(opp(i)) * plane + s, opp(i));
-                R gi = g_out;
-                if constexpr (REACT) reactive_link<SQ, R>(i, p, Cs, g_out, gi);
-                g[i] = gi;
-            } else {
-                g[i] = ldpop(gin, (size_t)spl<SQ>(i) * plane + src[i], i);
+            for (int i = 0; i < 9; ++i) {
+                if (!shas<SQ>(i)) continue;
+                const int sxr = x - ex(i);
+                const bool open = edge && (sxr < 0 || sxr >= nx);
+                unk[i] = open;
+                any_unk |= open;
+                // half-way wall: own population of the opposite direction
+                const bool wall = (lk >> opp(i)) & 1u;
+                const O a = wall ? (O)spl<SQ>(opp(i)) * pl + s : (O)spl<SQ>(i) * pl + src[i];
+                R v = ldb(gin, a, i);
+                if constexpr (REACT) {
+                    R gi;
+                    reactive_link<SQ, R>(i, q, v, gi);
+                    v = wall ? gi : v;
+                }
+                g[i] = v;
             }
         }
         if (any_unk) {
@@ -544,7 +596,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                     if (unk[i]) wu += swgt<SQ, R>(i);
                     else known += g[i];
                 }
-                const R deficit = (R(p.open_value[side]) - known) * rcp(wu);
+                const R deficit = (q.open_value[side] - known) * rcp(wu);
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     if (unk[i]) {
@@ -565,11 +617,12 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             for (int i = 1; i < 9; ++i) {
                 if (!shas<SQ>(i)) continue;
                 const int dx = x + ex(i);
-                if (dx < 0 || dx >= nx) tal[1] += (double)ldpop(gin, (size_t)spl<SQ>(i) * plane + s, i);
+                if (dx < 0 || dx >= nx) tal[1] += (double)ldb(gin, (O)spl<SQ>(i) * pl + s, i);
             }
         }
     }
-    // deposit gathered by solid nodes next to fluid (loads issued early too)
+    // deposit gathered by solid nodes next to fluid (loads issued early too):
+    // the fluid neighbour node + e_i is node - e_opp(i)
     bool fluid8 = false, fluid4 = false;
     double dep = 0.0;
     if constexpr (REACT) {
@@ -578,24 +631,22 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             for (int i = 1; i < 9; ++i) {
                 const int fxg = x + ex(i);
                 if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
-                if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
+                if (!((lk >> i) & 1u)) {
                     fluid8 = true;
                     if (i <= 4) fluid4 = true;
                 }
             }
             if (fluid8) {
                 const S *__restrict__ gin = (const S *)p.g[parity];
-                const R Cs = R(p.Cs);
 #pragma unroll
                 for (int i = 1; i < 9; ++i) {
                     if (!shas<SQ>(i)) continue;
                     const int fxg = x + ex(i);
                     if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
-                    if (smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) continue;
-                    const size_t fl = (size_t)wrapi(y + ey(i), ny) * nx + wrapi(fxg, nx);
-                    const R g_out = ldpop(gin, (size_t)spl<SQ>(opp(i)) * plane + fl, opp(i));
+                    if ((lk >> i) & 1u) continue;
+                    const R g_out = ldb(gin, (O)spl<SQ>(opp(i)) * pl + src[opp(i)], opp(i));
                     R gi;
-                    dep += (double)reactive_link<SQ, R>(i, p, Cs, g_out, gi);
+                    dep += (double)reactive_link<SQ, R>(i, q, g_out, gi);
                 }
             }
         }
@@ -606,35 +657,36 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     if constexpr (SC) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : R(p.rho_ref[c]) + drho[c];
+            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : q.rho_ref[c] + drho[c];
         for (int k = tid; k < (TX + 2) * (TY + 2); k += TX * TY) {
             const int hx = k % (TX + 2), hy = k / (TX + 2);
             const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
             if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
-            const int gx = wrapi(tx0 + hx - 1, nx), gy = wrapi(ty0 + hy - 1, ny);
-            const bool hsolid = smask[hy + 1][hx + 1] != 0;
+            const unsigned gx = (unsigned)wrapi(tx0 + hx - 1, nx), gy = (unsigned)wrapi(ty0 + hy - 1, ny);
+            const unsigned hl = links[(size_t)gy * nx + gx];
             R rr[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) rr[c] = R(0);
-            if (!hsolid) {
-                const size_t hs = (size_t)gy * nx + gx;
-                const int gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx == nx - 1) ? 0 : gx + 1;
-                const size_t hrm = (size_t)((gy == 0) ? ny - 1 : gy - 1) * nx;
-                const size_t hr0 = (size_t)gy * nx;
-                const size_t hrp = (size_t)((gy == ny - 1) ? 0 : gy + 1) * nx;
-                const size_t hsrc[9] = {hs,        hr0 + gxm, hrm + gx,  hr0 + gxp, hrp + gx,
-                                        hrm + gxm, hrm + gxp, hrp + gxp, hrp + gxm};
+            if (!(hl & 1u)) {
+                const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
+                const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
+                const O hs = brick_off<S, O>(gx, gy, pnx);
+                const O hsrc[9] = {hs,
+                                   brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
+                                   brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
+                                   brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
+                                   brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const S *__restrict__ fin = (const S *)p.f[parity][c];
-                    R acc = ldpop(fin, hs, 0);
+                    R acc = ldb(fin, hs, 0);
 #pragma unroll
                     for (int i = 1; i < 9; ++i) {
-                        const bool wall = smask[hy + 1 - ey(i)][hx + 1 - ex(i)] != 0;
-                        const size_t a = wall ? (size_t)opp(i) * plane + hs : (size_t)i * plane + hsrc[i];
-                        acc += ldpop(fin, a, i);
+                        const bool wall = (hl >> opp(i)) & 1u;
+                        const O a = wall ? (O)opp(i) * pl + hs : (O)i * pl + hsrc[i];
+                        acc += ldb(fin, a, i);
                     }
-                    rr[c] = R(p.rho_ref[c]) + acc;
+                    rr[c] = q.rho_ref[c] + acc;
                 }
             }
 #pragma unroll
@@ -647,9 +699,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     R rho[NC], Fx[NC], Fy[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        rho[c] = R(p.rho_ref[c]) + drho[c];
-        Fx[c] = R(p.force[c][0]) + rho[c] * R(p.accel[c][0]);
-        Fy[c] = R(p.force[c][1]) + rho[c] * R(p.accel[c][1]);
+        rho[c] = q.rho_ref[c] + drho[c];
+        Fx[c] = q.force[c][0] + rho[c] * q.accel[c][0];
+        Fy[c] = q.force[c][1] + rho[c] * q.accel[c][1];
     }
     if constexpr (SC && NC == 2) {
         if (valid) {
@@ -665,8 +717,8 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                Fx[c] += -R(p.G) * rho[c] * sx[c];
-                Fy[c] += -R(p.G) * rho[c] * sy[c];
+                Fx[c] += -q.G * rho[c] * sx[c];
+                Fy[c] += -q.G * rho[c] * sy[c];
             }
         }
     }
@@ -674,21 +726,21 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         R ax = R(0), ay = R(0);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const R sv = smask[ly + 2 + ey(i)][lx + 2 + ex(i)] ? R(1) : R(0);
+            const R sv = ((lk >> i) & 1u) ? R(1) : R(0);
             if (ex(i)) ax += wgt<R>(i) * (ex(i) > 0 ? sv : -sv);
             if (ey(i)) ay += wgt<R>(i) * (ey(i) > 0 ? sv : -sv);
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            Fx[c] += -R(p.Gads[c]) * rho[c] * ax;
-            Fy[c] += -R(p.Gads[c]) * rho[c] * ay;
+            Fx[c] += -q.Gads[c] * rho[c] * ax;
+            Fy[c] += -q.Gads[c] * rho[c] * ay;
         }
     }
     // 5. common velocity u' and per-component equilibrium velocities
     R nux = R(0), nuy = R(0), den = R(0), sjx = R(0), sjy = R(0), srh = R(0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const R om = R(p.omega[c]);
+        const R om = q.omega[c];
         nux += jx[c] * om;
         nuy += jy[c] * om;
         den += rho[c] * om;
@@ -698,119 +750,130 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     }
     const R iden = rcp(den);
     const R upx = nux * iden, upy = nuy * iden;
-    // 6. collide and store (one store per plane for the whole wavefront)
+    // 6. collide (in place)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
-        const R tau = R(p.tau[c]), om = R(p.omega[c]);
+        const R tau = q.tau[c], om = q.omega[c];
         const R irho = rcp(rho[c]);
         const R ux = upx + tau * Fx[c] * irho;
         const R uy = upy + tau * Fy[c] * irho;
         const R usq = R(1.5) * (ux * ux + uy * uy);
-        const R rr = R(p.rho_ref[c]);
+        const R rr = q.rho_ref[c];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
-            const R A = (i == 0) ? R(p.A0[c]) : R(p.A1[c]);
+            const R A = (i == 0) ? q.A0[c] : q.A1[c];
             const R deq = wgt<R>(i) * (rho[c] * A - rr + rho[c] * (R(3) * eu + R(4.5) * eu * eu - usq));
-            const R v = fluid ? d[c][i] + om * (deq - d[c][i]) : R(0);
-            if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
+            d[c][i] = fluid ? d[c][i] + om * (deq - d[c][i]) : R(0);
         }
     }
-    // 7. solute collision at the solvent velocity, one store per plane
+    // 7. solute collision at the solvent velocity (in place)
     if constexpr (SOL) {
         const R isrh = rcp(srh);
         const R usx = sjx * isrh, usy = sjy * isrh;
-        S *__restrict__ gout = (S *)p.g[parity ^ 1];
         R Cc = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (shas<SQ>(i)) Cc += g[i];
-        const R oms = R(p.omega_s);
+        const R oms = q.omega_s;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if (!shas<SQ>(i)) continue;
             const R eu = R(ex(i)) * usx + R(ey(i)) * usy;
             const R geq = swgt<SQ, R>(i) * Cc * (R(1) + sics2<SQ, R>() * eu);
-            const R v = fluid ? g[i] + oms * (geq - g[i]) : R(0);
-            if (store) gout[(size_t)spl<SQ>(i) * plane + s] = C::enc(v, i);
+            g[i] = fluid ? g[i] + oms * (geq - g[i]) : R(0);
+        }
+    }
+    // all stores of the lane in one region
+    if (store) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) stb(fout, (O)i * pl + s, C::enc(d[c][i], i));
+        }
+        if constexpr (SOL) {
+            S *__restrict__ gout = (S *)p.g[parity ^ 1];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (shas<SQ>(i)) stb(gout, (O)spl<SQ>(i) * pl + s, C::enc(g[i], i));
         }
     }
     if (valid && solid && REACT && fluid8) {
         // 8. solid node next to fluid: add the gathered deposit, then decide
         // growth from the post-deposit value
-        {
-            double bn = p.b[s] + dep;
-            if (fluid4) {
-                // candidates: E, N, W, S that are fluid, inside the solute
-                // domain and not on an open solute column
-                unsigned candbits = 0;
-                int m = 0;
+        double bn = p.b[srow] + dep;
+        if (fluid4) {
+            // candidates: E, N, W, S that are fluid, inside the solute
+            // domain and not on an open solute column
+            unsigned candbits = 0;
+            int m = 0;
 #pragma unroll
-                for (int i = 1; i <= 4; ++i) {
-                    const int cx = x + ex(i);
-                    if (!p.solute_xper && (cx <= 0 || cx >= nx - 1)) continue;
-                    if (!smask[ly + 2 + ey(i)][lx + 2 + ex(i)]) {
-                        candbits |= 1u << i;
-                        ++m;
-                    }
+            for (int i = 1; i <= 4; ++i) {
+                const int cx = x + ex(i);
+                if (!p.solute_xper && (cx <= 0 || cx >= nx - 1)) continue;
+                if (!((lk >> i) & 1u)) {
+                    candbits |= 1u << i;
+                    ++m;
                 }
-                uint8_t code = 0;
-                if (bn > p.bmax && m > 0) {
-                    const unsigned long long t = (unsigned long long)(*p.dstep) + 1ull;
-                    const unsigned long long h =
-                        splitmix64(p.seed ^ (t * (unsigned long long)plane + (unsigned long long)s));
-                    const int k = (int)(((h >> 32) * (unsigned long long)m) >> 32);
-                    // the k-th candidate in E, N, W, S order
-                    int seen = 0;
-#pragma unroll
-                    for (int i = 1; i <= 4; ++i)
-                        if (candbits & (1u << i)) {
-                            if (seen == k) code = (uint8_t)i;
-                            ++seen;
-                        }
-                    tal[2] += bn;
-                    bn = 0.0;
-                    p.gflag[parity] = 1u;
-                }
-                p.trig[s] = code;
             }
-            p.b[s] = bn;
+            uint8_t code = 0;
+            if (bn > p.bmax && m > 0) {
+                const unsigned long long t = (unsigned long long)(*p.dstep) + 1ull;
+                const unsigned long long h = splitmix64(
+                    p.seed ^ (t * (unsigned long long)nx * (unsigned long long)ny + (unsigned long long)srow));
+                const int k = (int)(((h >> 32) * (unsigned long long)m) >> 32);
+                // the k-th candidate in E, N, W, S order
+                int seen = 0;
+#pragma unroll
+                for (int i = 1; i <= 4; ++i)
+                    if (candbits & (1u << i)) {
+                        if (seen == k) code = (uint8_t)i;
+                        ++seen;
+                    }
+                tal[2] += bn;
+                bn = 0.0;
+                p.gflag[parity] = 1u;
+            }
+            p.trig[srow] = code;
         }
+        p.b[srow] = bn;
     }
 
     if constexpr (SOL) {
-        // running per-block tallies (inflow, outflow, consumed deposit):
-        // each block owns one slot and adds its step's sum in step order;
-        // the slots are summed in a fixed order only when budgets are read
+        // running per-wavefront tallies: each wavefront owns one slot and
+        // adds its step's sum in step order
         const bool has = tal[0] != 0.0 || tal[1] != 0.0 || tal[2] != 0.0;
-        if (__syncthreads_or(has)) {
-            double out[4];
-            block_sum<4>(tal, sred, out);
-            if (tid == 0) {
-                double *dst = p.partial + (size_t)blockIdx.x * 4;
-                dst[0] += out[0];
-                dst[1] += out[1];
-                dst[2] += out[2];
+        if (__any(has)) {
+            wave_sum3(tal);
+            if (lane == 0) {
+                double *dst = p.partial + ((size_t)blockIdx.x * (TX * TY / 64) + (tid >> 6)) * 4;
+                dst[0] += tal[0];
+                dst[1] += tal[1];
+                dst[2] += tal[2];
             }
         }
     }
 }
 
 // Growth: a fluid node turns solid when a direct neighbour's trigger points
-// at it; its populations' mass is tallied as removed, it gets deposit b0.
-// Per-block running tallies as in the step kernel; block 0 advances the
-// device step counter (read by the next step's growth decisions).
+// at it; its populations' mass is tallied as removed, it gets deposit b0,
+// and the link words of the node and of its eight neighbours are updated
+// (atomic OR on the 32-bit word holding each 16-bit link word: neighbours
+// of two new solids are shared).  A fixed grid strides over row segments,
+// so each block's running tally slot sees the same nodes in the same order
+// every step.  Block 0 advances the device step counter (read by the next
+// step's growth decisions).
+constexpr int kGrowBlocks = 1024;
+
 template <typename S, int NC, bool REACT>
 __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     using C = Codec<S>;
     __shared__ double sred[4 * 4];
     const int nx = p.nx, ny = p.ny;
-    const size_t plane = (size_t)nx * ny;
-    const int x = blockIdx.x * 256 + threadIdx.x;  // one row segment
-    const int y = blockIdx.y;
+    const size_t plane = p.pplane;
     // steps without any trigger (the common case) only advance the counter
-    const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
     if (!REACT || p.gflag[parity_new ^ 1] == 0u) {
         if (first) {
             *p.dstep += 1;
@@ -819,10 +882,17 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
         return;
     }
     double tal[4] = {0.0, 0.0, 0.0, 0.0};
-    bool grow = false;
+    bool any = false;
     if constexpr (REACT) {
-        if (x < nx && !p.mask[(size_t)y * nx + x]) {
+        const int segs_x = (nx + 255) / 256;
+        const int nseg = segs_x * ny;
+        for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+            const int x = (seg % segs_x) * 256 + threadIdx.x;
+            const int y = seg / segs_x;
+            if (x >= nx) continue;
             const size_t s = (size_t)y * nx + x;
+            if (p.mask[s]) continue;
+            bool grow = false;
 #pragma unroll
             for (int k = 1; k <= 4; ++k) {
                 const int sx = x + ex(k);
@@ -830,30 +900,39 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
                 const size_t sn = (size_t)wrapi(y + ey(k), ny) * nx + wrapi(sx, nx);
                 if (p.trig[sn] == (uint8_t)opp(k)) grow = true;
             }
-            if (grow) {
+            if (!grow) continue;
+            any = true;
+            const size_t ps = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const S *__restrict__ f = (const S *)p.f[parity_new][c];
-                    double r = 0.0;
-                    for (int i = 0; i < 9; ++i)
-                        r += wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + s], i);
-                    tal[c] = r;
-                }
-                const S *__restrict__ g = (const S *)p.g[parity_new];
-                double cc = 0.0;
-                for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + s], k);
-                tal[2] = cc;
-                tal[3] = 1.0;
-                p.mask[s] = 1;
-                p.b[s] = p.b0;
+            for (int c = 0; c < NC; ++c) {
+                const S *__restrict__ f = (const S *)p.f[parity_new][c];
+                double r = 0.0;
+                for (int i = 0; i < 9; ++i)
+                    r += wgt<double>(i) * p.cd.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
+                tal[c] += r;
+            }
+            const S *__restrict__ g = (const S *)p.g[parity_new];
+            double cc = 0.0;
+            for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], k);
+            tal[2] += cc;
+            tal[3] += 1.0;
+            p.mask[s] = 1;
+            p.b[s] = p.b0;
+            // link words: own bit 0; neighbour s + e_j sees s at e_opp(j)
+            unsigned *lw = (unsigned *)p.links;
+            atomicOr(lw + (s >> 1), 1u << (16u * (unsigned)(s & 1)));
+#pragma unroll
+            for (int j = 1; j < 9; ++j) {
+                const size_t n = (size_t)wrapi(y + ey(j), ny) * nx + wrapi(x + ex(j), nx);
+                atomicOr(lw + (n >> 1), (1u << opp(j)) << (16u * (unsigned)(n & 1)));
             }
         }
     }
-    if (__syncthreads_or(grow)) {
+    if (__syncthreads_or(any)) {
         double out[4];
         block_sum<4>(tal, sred, out);
         if (threadIdx.x == 0) {
-            double *dst = p.gpartial + (size_t)(blockIdx.x + blockIdx.y * gridDim.x) * 4;
+            double *dst = p.gpartial + (size_t)blockIdx.x * 4;
             for (int k = 0; k < 4; ++k) dst[k] += out[k];
         }
     }
@@ -863,8 +942,8 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     }
 }
 
-// Sums the per-block running tallies in a fixed order into totals
-// (LB2D_B_* indices 6..10, 12, 14).
+// Fixed-order sums of the running tally slots into totals[] (LB2D_B_*
+// indices).
 __global__ void __launch_bounds__(256) k_tally_final(FullParams p) {
     __shared__ double sred[4 * 8];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -961,11 +1040,11 @@ __global__ void k_raster_rects(uint8_t *mask, int nx, const int *rects) {
 // (computed in FP64, then shifted and encoded).
 template <typename S>
 __global__ void k_init_fluid(S *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             double A0, double A1, double rho_ref, unsigned nx, unsigned pnx,
                              size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t dst = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
+        const size_t dst = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
         const double r = rho[k], u = ux[k], v = uy[k];
         const double usq = 1.5 * (u * u + v * v);
 #pragma unroll
@@ -979,16 +1058,18 @@ __global__ void k_init_fluid(S *f, const double *rho, const double *ux, const do
 }
 
 template <typename S, int SQ>
-__global__ void k_init_solute(S *g, const double *Cc, const double *ux, const double *uy, size_t n) {
+__global__ void k_init_solute(S *g, const double *Cc, const double *ux, const double *uy, size_t n, unsigned nx,
+                              unsigned pnx, size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
         const double c = Cc[k], u = ux[k], v = uy[k];
+        const size_t dst = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if (!shas<SQ>(i)) continue;
             const double eu = ex(i) * u + ey(i) * v;
             const double ge = swgt<SQ, double>(i) * c * (1.0 + sics2<SQ, double>() * eu);
-            g[(size_t)spl<SQ>(i) * n + k] = C::enc((typename C::R)ge, i);
+            g[(size_t)spl<SQ>(i) * pplane + dst] = C::enc((typename C::R)ge, i);
         }
     }
 }
@@ -1002,19 +1083,19 @@ __global__ void k_init_b(double *b, const uint8_t *mask, double b0, size_t n) {
 // `shift` = w_i rho_ref.
 template <typename S>
 __global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, double shift,
-                               unsigned nx, int brick, unsigned pnx, size_t pplane) {
+                               unsigned nx, unsigned pnx, size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t a = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
+        const size_t a = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
         out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * pplane + a], i);
     }
 }
 template <typename S>
-__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift, unsigned nx, int brick,
+__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift, unsigned nx,
                                unsigned pnx, size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t a = pop_index<S>(brick, (unsigned)(k % nx), (unsigned)(k / nx), nx, pnx);
+        const size_t a = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
         f[(size_t)i * pplane + a] = C::enc((typename C::R)(in[k] - shift), i);
     }
 }
@@ -1025,7 +1106,7 @@ template <typename S>
 __device__ double node_rho(const FullParams &p, const S *f, int x, int y, double rho_ref) {
     using C = Codec<S>;
     const size_t plane = p.pplane;
-    const size_t s = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)p.nx, p.pnx);
+    const size_t s = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
     double r = rho_ref;
     for (int i = 0; i < 9; ++i) r += (double)C::dec(f[(size_t)i * plane + s], i);
     return r;
@@ -1041,7 +1122,7 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= nx) return;
     const size_t s = (size_t)y * nx + x;
-    const size_t ps = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)nx, p.pnx);
+    const size_t ps = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
     if (p.mask[s]) {
         orho[s] = -11.0;
         oux[s] = ouy[s] = 0.0;
@@ -1050,7 +1131,7 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
     double rho[2] = {0, 0}, jx[2] = {0, 0}, jy[2] = {0, 0};
     for (int c = 0; c < p.ncomp; ++c) {
         const S *f = (const S *)p.f[parity][c];
-        double r = p.rho_ref[c], mx = 0, my = 0;
+        double r = p.cd.rho_ref[c], mx = 0, my = 0;
         for (int i = 0; i < 9; ++i) {
             const double v = (double)C::dec(f[(size_t)i * plane + ps], i);
             r += v;
@@ -1064,20 +1145,20 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
     double R = 0, MX = 0, MY = 0;
     for (int c = 0; c < p.ncomp; ++c) {
         if (comp >= 0 && c != comp) continue;
-        double Fx = p.force[c][0] + rho[c] * p.accel[c][0];
-        double Fy = p.force[c][1] + rho[c] * p.accel[c][1];
-        if (p.ncomp == 2 && p.G != 0.0) {
+        double Fx = p.cd.force[c][0] + rho[c] * p.cd.accel[c][0];
+        double Fy = p.cd.force[c][1] + rho[c] * p.cd.accel[c][1];
+        if (p.ncomp == 2 && p.cd.G != 0.0) {
             double sx = 0, sy = 0;
             const S *fo = (const S *)p.f[parity][1 - c];
             for (int i = 1; i < 9; ++i) {
                 const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
                 if (p.mask[(size_t)gy * nx + gx]) continue;
-                const double rb = node_rho<S>(p, fo, gx, gy, p.rho_ref[1 - c]);
+                const double rb = node_rho<S>(p, fo, gx, gy, p.cd.rho_ref[1 - c]);
                 sx += wgt<double>(i) * rb * ex(i);
                 sy += wgt<double>(i) * rb * ey(i);
             }
-            Fx += -p.G * rho[c] * sx;
-            Fy += -p.G * rho[c] * sy;
+            Fx += -p.cd.G * rho[c] * sx;
+            Fy += -p.cd.G * rho[c] * sy;
         }
         if (p.has_ads) {
             double sx = 0, sy = 0;
@@ -1087,8 +1168,8 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
                 sx += wgt<double>(i) * sv * ex(i);
                 sy += wgt<double>(i) * sv * ey(i);
             }
-            Fx += -p.Gads[c] * rho[c] * sx;
-            Fy += -p.Gads[c] * rho[c] * sy;
+            Fx += -p.cd.Gads[c] * rho[c] * sx;
+            Fy += -p.cd.Gads[c] * rho[c] * sy;
         }
         R += rho[c];
         MX += jx[c] - 0.5 * Fx;
@@ -1108,7 +1189,8 @@ __global__ void k_solute_state(FullParams p, int parity, int reaction, double *o
         const bool sol = p.mask[k] != 0;
         if (!sol) {
             const S *g = (const S *)p.g[parity];
-            for (int j = 0; j < p.sq; ++j) c += (double)C::dec(g[(size_t)j * n + k], j);
+            const size_t a = brick_index<S>((unsigned)(k % p.nx), (unsigned)(k / p.nx), p.pnx);
+            for (int j = 0; j < p.sq; ++j) c += (double)C::dec(g[(size_t)j * p.pplane + a], j);
         }
         oc[k] = c;
         ob[k] = (sol && reaction) ? p.b[k] : 0.0;
@@ -1132,11 +1214,11 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
             continue;
         }
         v[6] += 1.0;
-        const size_t ps = pop_index<S>(p.brick, (unsigned)x, (unsigned)y, (unsigned)nx, p.pnx);
+        const size_t ps = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
         for (int c = 0; c < p.ncomp; ++c) {
             const S *f = (const S *)p.f[parity][c];
             for (int i = 0; i < 9; ++i) {
-                const double fv = wgt<double>(i) * p.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
+                const double fv = wgt<double>(i) * p.cd.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
                 v[c] += fv;
                 v[2] += ex(i) * fv;
                 v[3] += ey(i) * fv;
@@ -1144,7 +1226,7 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
         }
         if (has_solute) {
             const S *g = (const S *)p.g[parity];
-            for (int j = 0; j < p.sq; ++j) v[4] += (double)C::dec(g[(size_t)j * (size_t)p.nx * p.ny + s], j);
+            for (int j = 0; j < p.sq; ++j) v[4] += (double)C::dec(g[(size_t)j * plane + ps], j);
         }
     }
     double out[8];
@@ -1221,14 +1303,18 @@ hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int 
 }
 
 int full_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
-int growth_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
+int full_slots(int nx, int ny) { return full_tiles(nx, ny) * (kTX * kTY / 64); }
+int growth_blocks(int nx, int ny) {
+    const int segs = ((nx + 255) / 256) * ny;
+    return segs < kGrowBlocks ? segs : kGrowBlocks;
+}
 
-template <typename S, int SQ>
+template <typename S, typename O, int SQ>
 static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
 #define LB2D_FULL(NC_, SC_, REACT_) \
-    hipLaunchKernelGGL((k_full<S, NC_, SC_, SQ, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
+    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
             if (react) LB2D_FULL(2, true, true);
@@ -1244,12 +1330,21 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
 #undef LB2D_FULL
 }
 
+template <typename S, int SQ>
+static void full_dispatch_off(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
+    // 32-bit byte offsets when every population array (9 planes) is below 4 GiB
+    if ((unsigned long long)p.pplane * 9ull * sizeof(S) < (1ull << 32))
+        full_dispatch_sq<S, uint32_t, SQ>(p, parity, sc, react, st);
+    else
+        full_dispatch_sq<S, size_t, SQ>(p, parity, sc, react, st);
+}
+
 // The reaction needs a solute; the solute lattice is p.sq (0, 9 or 4).
 template <typename S>
 static void full_dispatch(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
-    if (p.sq == 9) full_dispatch_sq<S, 9>(p, parity, sc, react, st);
-    else if (p.sq == 4) full_dispatch_sq<S, 4>(p, parity, sc, react, st);
-    else full_dispatch_sq<S, 0>(p, parity, sc, false, st);
+    if (p.sq == 9) full_dispatch_off<S, 9>(p, parity, sc, react, st);
+    else if (p.sq == 4) full_dispatch_off<S, 4>(p, parity, sc, react, st);
+    else full_dispatch_off<S, 0>(p, parity, sc, false, st);
 }
 
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t stream) {
@@ -1259,7 +1354,7 @@ hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool re
 }
 
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t stream) {
-    const dim3 g = react ? dim3((p.nx + 255) / 256, p.ny) : dim3(1), b(256);
+    const dim3 g = react ? dim3(growth_blocks(p.nx, p.ny)) : dim3(1), b(256);
     if (st == kF64) {
         if (p.ncomp == 2) {
             if (react) hipLaunchKernelGGL((k_growth<double, 2, true>), g, b, 0, stream, p, parity_new);
@@ -1307,20 +1402,20 @@ hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int coun
     return hipGetLastError();
 }
 hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             double A0, double A1, double rho_ref, unsigned nx, unsigned pnx,
                              size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_init_fluid<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, rho, ux, uy, n,
-                                         A0, A1, rho_ref, nx, brick, pnx, pplane));
+                                         A0, A1, rho_ref, nx, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
-                              int sq, hipStream_t s) {
+                              int sq, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s) {
     if (sq == 4) {
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 4>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
-                                             uy, n));
+                                             uy, n, nx, pnx, pplane));
     } else {
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 9>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
-                                             uy, n));
+                                             uy, n, nx, pnx, pplane));
     }
     return hipGetLastError();
 }
@@ -1329,9 +1424,9 @@ hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hi
     return hipGetLastError();
 }
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
-                               double shift, unsigned nx, int brick, unsigned pnx, size_t pplane, hipStream_t s) {
+                               double shift, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, mask,
-                                         out, n, i, shift, nx, brick, pnx, pplane));
+                                         out, n, i, shift, nx, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s) {
@@ -1339,9 +1434,9 @@ hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hi
     return hipGetLastError();
 }
 hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
-                               int brick, unsigned pnx, size_t pplane, hipStream_t s) {
+                               unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_encode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, in, n, i,
-                                         shift, nx, brick, pnx, pplane));
+                                         shift, nx, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,

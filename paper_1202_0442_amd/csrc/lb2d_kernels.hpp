@@ -8,6 +8,9 @@ namespace lb2d {
 
 size_t storage_bytes(int st);
 int full_tiles(int nx, int ny);
+// Running tally slots of the general step (one per wavefront) and blocks
+// (= tally slots) of the growth kernel.
+int full_slots(int nx, int ny);
 int growth_blocks(int nx, int ny);
 
 // Tile (in nodes) covered by one 256-thread block of the one-fluid step.
@@ -27,18 +30,18 @@ hipError_t launch_raster_circles(uint8_t *mask, int nx, int ny, const int *cxy, 
                                  hipStream_t s);
 hipError_t launch_raster_rects(uint8_t *mask, int nx, const int *rects, int count, hipStream_t s);
 hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *ux, const double *uy, size_t n,
-                             double A0, double A1, double rho_ref, unsigned nx, int brick, unsigned pnx,
+                             double A0, double A1, double rho_ref, unsigned nx, unsigned pnx,
                              size_t pplane, hipStream_t s);
 // Solute populations at equilibrium on a D2Q9 (sq = 9) or D2Q4 (sq = 4)
-// lattice, sq planes of n.
+// lattice, sq brick-layout planes of pplane elements.
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
-                              int sq, hipStream_t s);
+                              int sq, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s);
 hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
-                               double shift, unsigned nx, int brick, unsigned pnx, size_t pplane, hipStream_t s);
+                               double shift, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s);
 hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
-                               int brick, unsigned pnx, size_t pplane, hipStream_t s);
+                               unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
                           hipStream_t s);
 hipError_t launch_solute_state(int st, const FullParams &p, int parity, int reaction, double *C, double *b,
