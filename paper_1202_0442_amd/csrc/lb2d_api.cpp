@@ -120,6 +120,7 @@ struct lb2d_batch {
     size_t max_tiles = 0;
     int ntiles = 0;
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
+    size_t max_plane = 0;  // largest population plane of the lattices
     hipGraphExec_t graph = nullptr;
     int64_t t = 0;
     int fail(int code, const char *fmt, ...) {
@@ -1111,7 +1112,11 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     b->max_tiles = max_tiles_for(b);
     plain_tile(b->storage, &b->tile_w, &b->tile_h);
     std::vector<PlainLattice> L;
-    for (auto *c : b->lat) L.push_back(plain_lattice(c));
+    b->max_plane = 0;
+    for (auto *c : b->lat) {
+        L.push_back(plain_lattice(c));
+        b->max_plane = std::max(b->max_plane, c->pplane);
+    }
     HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     int cus = 256;
@@ -1158,10 +1163,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->stream));
+            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->stream));
+                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1196,7 +1201,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 }
 
 static hipError_t batch_step(lb2d_batch *b, int parity, hipStream_t s) {
-    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, s);
+    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, s);
 }
 
 int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {

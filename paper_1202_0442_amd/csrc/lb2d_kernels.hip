@@ -142,6 +142,15 @@ __host__ __device__ __forceinline__ size_t brick_index(unsigned x, unsigned y, u
 }
 
 
+// Byte offset of node (x, y) in a brick-layout plane, computed in O
+// (32-bit when the population arrays are below 4 GiB: a uniform base
+// pointer plus a 32-bit lane offset needs no 64-bit lane arithmetic).
+template <typename S, typename O>
+__device__ __forceinline__ O brick_off(unsigned x, unsigned y, unsigned pnx) {
+    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
+    return (((O)(y / H) * (O)(pnx / W) + (O)(x / W)) * (O)(W * H) + (O)((y % H) * W + (x % W))) * (O)sizeof(S);
+}
+
 // Deterministic block sum of K doubles per thread into out[0..K) (valid in
 // thread 0).  `sh` must hold blockDim.x * blockDim.y * K doubles... to keep
 // LDS small the reduction goes through wavefront shuffles first.
@@ -255,7 +264,7 @@ __device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
     return a;
 }
 
-template <typename S>
+template <typename S, typename O>
 __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside) {
     using C = Codec<S>;
     using R = typename C::R;
@@ -272,10 +281,10 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     const unsigned long long gmask =
         (kGroup >= 64) ? ~0ull : (((1ull << (kGroup & 63)) - 1ull) << ((lane / kGroup) * kGroup));
     const bool store = (bal & gmask) != 0ull;
-    const size_t plane = L.plane;
-    const LB2D_GLOBAL S *__restrict__ fin = gbl(L.fin);
-    LB2D_GLOBAL S *__restrict__ fout = gbl(L.fout);
-    const size_t s = brick_index<S>((unsigned)x, (unsigned)y, pnx);
+    const O pl = (O)L.plane * (O)sizeof(S);  // bytes per plane
+    const LB2D_GLOBAL char *__restrict__ fin = (const LB2D_GLOBAL char *)gbl(L.fin);
+    LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(L.fout);
+    const O s = brick_off<S, O>((unsigned)x, (unsigned)y, pnx);
 
     R d[9];
     if (fluid) {
@@ -285,18 +294,18 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
         const unsigned ym = (yy == 0) ? ny - 1 : yy - 1;
         const unsigned yp = (yy == ny - 1) ? 0 : yy + 1;
         // node - e_i for each direction
-        const size_t src[9] = {s,
-                               brick_index<S>(xm, yy, pnx), brick_index<S>(xx, ym, pnx),
-                               brick_index<S>(xp, yy, pnx), brick_index<S>(xx, yp, pnx),
-                               brick_index<S>(xm, ym, pnx), brick_index<S>(xp, ym, pnx),
-                               brick_index<S>(xp, yp, pnx), brick_index<S>(xm, yp, pnx)};
-        d[0] = C::dec(fin[s], 0);
+        const O src[9] = {s,
+                          brick_off<S, O>(xm, yy, pnx), brick_off<S, O>(xx, ym, pnx),
+                          brick_off<S, O>(xp, yy, pnx), brick_off<S, O>(xx, yp, pnx),
+                          brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
+                          brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
+        d[0] = C::dec(*(const LB2D_GLOBAL S *)(fin + s), 0);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             // node - e_i is node + e_opp(i): solid -> bounce-back
             const bool wall = (lk >> opp(i)) & 1u;
-            const size_t a = wall ? (size_t)opp(i) * plane + s : (size_t)i * plane + src[i];
-            d[i] = C::dec(fin[a], i);
+            const O a = wall ? (O)opp(i) * pl + s : (O)i * pl + src[i];
+            d[i] = C::dec(*(const LB2D_GLOBAL S *)(fin + a), i);
         }
     } else {
 #pragma unroll
@@ -322,7 +331,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
         const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
         const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
         const R v = fluid ? d[i] + omega * (deq - d[i]) : R(0);
-        if (store) fout[(size_t)i * plane + s] = C::enc(v, i);
+        if (store) *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = C::enc(v, i);
     }
 }
 
@@ -337,19 +346,19 @@ __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
     ly = k / W;
 }
 
-template <typename S>
+template <typename S, typename O>
 __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity) {
     constexpr int TW = 256 / (kBrickW * brick_h_for(sizeof(S))) * kBrickW, TH = brick_h_for(sizeof(S));
     int lx, ly;
     brick_thread<S>(threadIdx.x, lx, ly);
     const int x = blockIdx.x * TW + lx;
     const int y = blockIdx.y * TH + ly;
-    plain_node<S>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny);
+    plain_node<S, O>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny);
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
 // independent lattices; `persistent` grids stride over the table.
-template <typename S>
+template <typename S, typename O>
 __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
                                               const Tile *__restrict__ tiles, int ntiles,
                                               int parity) {
@@ -361,7 +370,7 @@ __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ 
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
         const int x = x0 + lx;
         const int y = y0 + ly;
-        plain_node<S>(a, x, y, x < (int)a.nx && y < (int)a.ny);
+        plain_node<S, O>(a, x, y, x < (int)a.nx && y < (int)a.ny);
     }
 }
 
@@ -428,6 +437,23 @@ __device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
     ly = (b / BPR) * BH + k / BW;
 }
 
+// Halo slot j of a TX x TY tile's density ring -> position in the
+// (TX+2) x (TY+2) tile: bottom row, top row, then left/right columns.
+template <int TX, int TY>
+__device__ __forceinline__ void halo_slot(int j, int &hx, int &hy) {
+    if (j < TX + 2) {
+        hx = j;
+        hy = 0;
+    } else if (j < 2 * (TX + 2)) {
+        hx = j - (TX + 2);
+        hy = TY + 1;
+    } else {
+        const int k = j - 2 * (TX + 2);
+        hx = (k & 1) ? TX + 1 : 0;
+        hy = 1 + k / 2;
+    }
+}
+
 // Sum of three doubles over a wavefront (fixed butterfly order).
 __device__ __forceinline__ void wave_sum3(double (&v)[4]) {
 #pragma unroll
@@ -459,12 +485,6 @@ __device__ __forceinline__ void wave_sum3(double (&v)[4]) {
 // lane offset, no 64-bit lane arithmetic), 64-bit otherwise.
 // Tallies (inflow, outflow, consumed deposit) go to one running slot per
 // wavefront, summed in a fixed order only when budgets are read.
-// Byte offset of node (x, y) in a brick-layout plane, computed in O.
-template <typename S, typename O>
-__device__ __forceinline__ O brick_off(unsigned x, unsigned y, unsigned pnx) {
-    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
-    return (((O)(y / H) * (O)(pnx / W) + (O)(x / W)) * (O)(W * H) + (O)((y % H) * W + (x % W))) * (O)sizeof(S);
-}
 template <typename S, typename O>
 __device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, O off, int i) {
     return Codec<S>::dec(*(const S *)((const char *)base + off), i);
@@ -504,17 +524,67 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     tile_thread<TX>(tid, lx, ly);
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = (x < nx) && (y < ny);
-    const size_t srow = valid ? (size_t)y * nx + x : 0;
-    const unsigned lk = valid ? (unsigned)links[srow] : 1u;
+    // lanes past a ragged lattice edge stand for the periodic image of their
+    // position: the density tile needs its density, nothing else of theirs
+    // is loaded or stored
+    const unsigned ux_ = (unsigned)(x % nx), uy_ = (unsigned)(y % ny);
+    const size_t srow = (size_t)uy_ * nx + ux_;
+    const unsigned lk = links[srow];
     const bool solid = (lk & 1u) != 0u;
     const bool fluid = !solid;
+    const bool pull = fluid && (valid || SC);
     // a brick (32 lanes) is stored iff it holds a fluid node
-    const unsigned long long bal = __ballot(fluid);
+    const unsigned long long bal = __ballot(valid && fluid);
     const unsigned lane = __lane_id();
     const bool store = valid && ((bal >> (lane & 32u)) & 0xffffffffull) != 0ull;
 
+    // the ring of the density tile: the NH halo slots are dealt to the
+    // wavefronts in equal contiguous runs (lane l < PER of wavefront w owns
+    // slot w * PER + l); a slot's link word is loaded with the own one and
+    // its populations are pulled before the own ones, so that all loads of
+    // the step are in flight together and the halo sums free their
+    // registers first
+    constexpr int NH = SC ? 2 * (TX + 2) + 2 * TY : 0;
+    constexpr int NWV = TX * TY / 64, PER = (NH + NWV - 1) / NWV;
+    static_assert(PER <= 64, "halo run fits a wavefront");
+    const int hj = (tid & 63) < PER ? (tid >> 6) * PER + (tid & 63) : NH;  // NH: none
+    int hx = 0, hy = 0;
+    bool hpull = false;
+    R hrho[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) hrho[c] = R(0);
+    if constexpr (SC) {
+        if (hj < NH) {
+            halo_slot<TX, TY>(hj, hx, hy);
+            const unsigned gx = (unsigned)wrapi(tx0 + hx - 1, nx), gy = (unsigned)wrapi(ty0 + hy - 1, ny);
+            const unsigned hl = links[(size_t)gy * nx + gx];
+            hpull = !(hl & 1u);
+            if (hpull) {
+                const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
+                const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
+                const O hs = brick_off<S, O>(gx, gy, pnx);
+                const O hsrc[9] = {hs,
+                                   brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
+                                   brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
+                                   brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
+                                   brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const S *__restrict__ fin = (const S *)p.f[parity][c];
+                    R acc = ldb(fin, hs, 0);
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        const bool wall = (hl >> opp(i)) & 1u;
+                        const O a = wall ? (O)opp(i) * pl + hs : (O)i * pl + hsrc[i];
+                        acc += ldb(fin, a, i);
+                    }
+                    hrho[c] = q.rho_ref[c] + acc;
+                }
+            }
+        }
+    }
+
     // byte offsets of the node and of node - e_i (periodic) in a plane
-    const unsigned ux_ = valid ? (unsigned)x : 0u, uy_ = valid ? (unsigned)y : 0u;
     const unsigned xm = (ux_ == 0) ? nx - 1 : ux_ - 1, xp = (ux_ + 1 >= (unsigned)nx) ? 0 : ux_ + 1;
     const unsigned ym = (uy_ == 0) ? ny - 1 : uy_ - 1, yp = (uy_ + 1 >= (unsigned)ny) ? 0 : uy_ + 1;
     const O s = brick_off<S, O>(ux_, uy_, pnx);
@@ -531,7 +601,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     for (int c = 0; c < NC; ++c) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[c][i] = R(0);
-        if (fluid) {
+        if (pull) {
             const S *__restrict__ fin = (const S *)p.f[parity][c];
             d[c][0] = ldb(fin, s, 0);
 #pragma unroll
@@ -566,7 +636,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         bool any_unk = false;
         // lanes on an open x wall (only in the first and last tile columns)
         const bool edge = !p.solute_xper && (x == 0 || x == nx - 1);
-        if (fluid) {
+        if (valid && fluid) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 if (!shas<SQ>(i)) continue;
@@ -612,7 +682,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                     }
             }
         }
-        if (fluid && !p.solute_xper && (x == 0 || x == nx - 1)) {
+        if (valid && fluid && !p.solute_xper && (x == 0 || x == nx - 1)) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 if (!shas<SQ>(i)) continue;
@@ -652,45 +722,14 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         }
     }
 
-    // 3. density tile for the cohesion stencil: own nodes from registers,
-    // halo (and wrapped ragged-edge) nodes pulled again.
+    // 3. density tile for the cohesion stencil: own nodes (and periodic
+    // images past a ragged edge) and the pulled halo ring
     if constexpr (SC) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (valid) srho[c][ly + 1][lx + 1] = solid ? R(0) : q.rho_ref[c] + drho[c];
-        for (int k = tid; k < (TX + 2) * (TY + 2); k += TX * TY) {
-            const int hx = k % (TX + 2), hy = k / (TX + 2);
-            const bool inner = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
-            if (inner && (tx0 + hx - 1) < nx && (ty0 + hy - 1) < ny) continue;
-            const unsigned gx = (unsigned)wrapi(tx0 + hx - 1, nx), gy = (unsigned)wrapi(ty0 + hy - 1, ny);
-            const unsigned hl = links[(size_t)gy * nx + gx];
-            R rr[NC];
+        for (int c = 0; c < NC; ++c) srho[c][ly + 1][lx + 1] = solid ? R(0) : q.rho_ref[c] + drho[c];
+        if (hj < NH) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) rr[c] = R(0);
-            if (!(hl & 1u)) {
-                const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
-                const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
-                const O hs = brick_off<S, O>(gx, gy, pnx);
-                const O hsrc[9] = {hs,
-                                   brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
-                                   brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
-                                   brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
-                                   brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const S *__restrict__ fin = (const S *)p.f[parity][c];
-                    R acc = ldb(fin, hs, 0);
-#pragma unroll
-                    for (int i = 1; i < 9; ++i) {
-                        const bool wall = (hl >> opp(i)) & 1u;
-                        const O a = wall ? (O)opp(i) * pl + hs : (O)i * pl + hsrc[i];
-                        acc += ldb(fin, a, i);
-                    }
-                    rr[c] = q.rho_ref[c] + acc;
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = rr[c];
+            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = hpull ? hrho[c] : R(0);
         }
         __syncthreads();
     }
@@ -1271,15 +1310,21 @@ inline int grid1d(size_t n, int bs = 256) {
 
 // --------------------------------------------------------------- launchers
 
-#define LB2D_DISPATCH(st, CALL)                       \
-    switch (st) {                                     \
-        case kF64: { using S = double; CALL; break; } \
-        case kF32: { using S = float; CALL; break; }  \
-        case kF16: { using S = _Float16; CALL; break; } \
-        default: { using S = bf16s; CALL; break; }    \
-    }
+#define LB2D_DISPATCH(st, CALL)                             \
+    do {                                                    \
+        switch (st) {                                       \
+            case kF64: { using S = double; CALL; break; }   \
+            case kF32: { using S = float; CALL; break; }    \
+            case kF16: { using S = _Float16; CALL; break; } \
+            default: { using S = bf16s; CALL; break; }      \
+        }                                                   \
+    } while (0)
 
 size_t storage_bytes(int st) { return st == kF64 ? 8 : st == kF32 ? 4 : 2; }
+
+// Nine planes of `plane` values of `bytes` each are addressable with 32-bit
+// byte offsets.
+static bool fits32(size_t plane, size_t bytes) { return (unsigned long long)plane * 9ull * bytes < (1ull << 32); }
 
 void plain_tile(int st, int *tw, int *th) {
     const int h = brick_h_for((int)storage_bytes(st));
@@ -1291,14 +1336,22 @@ hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t s
     int tw, th;
     plain_tile(st, &tw, &th);
     const dim3 blk(256), grd((L.nx + tw - 1) / tw, (L.ny + th - 1) / th);
-    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_plain<S>, grd, blk, 0, stream, L, parity));
+    if (fits32(L.plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, uint32_t>), grd, blk, 0, stream, L, parity));
+    else
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, size_t>), grd, blk, 0, stream, L, parity));
     return hipGetLastError();
 }
 
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        hipStream_t stream) {
+                        size_t max_plane, hipStream_t stream) {
     dim3 blk(256);
-    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_batch<S>, dim3(grid), blk, 0, stream, lat, tiles, ntiles, parity));
+    if (fits32(max_plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
+                                             parity));
+    else
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
+                                             parity));
     return hipGetLastError();
 }
 
@@ -1333,7 +1386,7 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
 template <typename S, int SQ>
 static void full_dispatch_off(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     // 32-bit byte offsets when every population array (9 planes) is below 4 GiB
-    if ((unsigned long long)p.pplane * 9ull * sizeof(S) < (1ull << 32))
+    if (fits32(p.pplane, sizeof(S)))
         full_dispatch_sq<S, uint32_t, SQ>(p, parity, sc, react, st);
     else
         full_dispatch_sq<S, size_t, SQ>(p, parity, sc, react, st);
@@ -1410,13 +1463,12 @@ hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *u
 }
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
                               int sq, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s) {
-    if (sq == 4) {
+    if (sq == 4)
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 4>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
                                              uy, n, nx, pnx, pplane));
-    } else {
+    else
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_init_solute<S, 9>), dim3(grid1d(n)), dim3(256), 0, s, (S *)g, C, ux,
                                              uy, n, nx, pnx, pplane));
-    }
     return hipGetLastError();
 }
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s) {

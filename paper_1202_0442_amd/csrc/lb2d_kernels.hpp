@@ -16,8 +16,9 @@ int growth_blocks(int nx, int ny);
 // Tile (in nodes) covered by one 256-thread block of the one-fluid step.
 void plain_tile(int st, int *tw, int *th);
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t s);
+// max_plane: largest population plane (elements) of the batch's lattices.
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        hipStream_t s);
+                        size_t max_plane, hipStream_t s);
 // General step; the solute lattice (none, D2Q9, D2Q4) is p.sq.
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
