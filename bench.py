@@ -61,9 +61,11 @@ def measured_traffic(name):
     return float(m.group(1))
 
 
-def make_porous_lattice(lb2d, w, storage, stream):
+def make_porous_lattice(lb2d, w, storage, stream, rounding="nearest"):
     L = lb2d.Lattice(0)
     L.lattice("d2q9", w.nx, w.ny, w.tau)
+    if rounding != "nearest":
+        L.rounding(rounding, 2012)
     L.boundary_style("noslip")
     for (xc, yc, r) in w.discs:
         L.obstacle_circle(xc, yc, r)
@@ -111,8 +113,8 @@ def cpu_baseline(target_seconds=15.0):
                       f"{dt:.1f} s, FP64 plain C, 1 thread"}
 
 
-def run_variant_storage(lb2d, torch, w, storage, steps, warmup, stream):
-    L = make_porous_lattice(lb2d, w, storage, stream)
+def run_variant_storage(lb2d, torch, w, storage, steps, warmup, stream, rounding="nearest"):
+    L = make_porous_lattice(lb2d, w, storage, stream, rounding)
     L.iteration(warmup)
     ms = time_steps(torch, stream, L.iteration, steps)
     n = w.nx * w.ny
@@ -226,8 +228,9 @@ def run_precision(lb2d, torch, stream, ref_path, n=2048, steps=10000):
             w = inputs.porous(n=n, seed=4)
             rr, ru, rv = ref["porous_rho"], ref["porous_ux"], ref["porous_uy"]
         fl = rr != -11.0
-        for st in ("f32", "f16", "bf16"):
-            L = make_porous_lattice(lb2d, w, st, stream)
+        for key in ("f32", "f16", "bf16", "f16sr", "bf16sr"):
+            st = key[:-2] if key.endswith("sr") else key
+            L = make_porous_lattice(lb2d, w, st, stream, "stochastic" if key.endswith("sr") else "nearest")
             nfl = L.budgets()["fluid_nodes"]
             ms = time_steps(torch, stream, L.iteration, steps)
             g_r, g_u, g_v = L.moments(0)
@@ -236,7 +239,7 @@ def run_precision(lb2d, torch, stream, ref_path, n=2048, steps=10000):
             um = np.hypot(ru, rv)[fl]
             drho = np.abs(g_r - rr)[fl]
             per = ms / steps
-            res[f"{wl}_{st}"] = {
+            res[f"{wl}_{key}"] = {
                 "u_max_rel": float(du.max() / um.max()),
                 "u_l2_rel": float(np.sqrt((du ** 2).sum() / (um ** 2).sum())),
                 "rho_max_abs": float(drho.max()),
@@ -244,7 +247,7 @@ def run_precision(lb2d, torch, stream, ref_path, n=2048, steps=10000):
                 "mlups": n * n / (per * 1e-3) / 1e6,
                 "algorithmic_GBps": (nfl * 18 * STORE_BYTES[st] + n * n) / (per * 1e-3) / 1e9,
             }
-            log(f"precision {wl} {st}: {res[f'{wl}_{st}']}")
+            log(f"precision {wl} {key}: {res[f'{wl}_{key}']}")
             L.close()
             torch.cuda.empty_cache()
     return {"precision_sweep": res, "n": n, "steps": steps,
@@ -357,11 +360,13 @@ def main():
     variants = {}
     for st in ("f16", "bf16"):
         if st in want:
-            log(f"variant {st}")
-            variants[f"{st}_store"] = run_variant_storage(lb2d, torch, w, st, max(500, args.steps // 5),
-                                                          50, stream)
-            variants[f"{st}_store"]["speedup_vs_f32"] = variants[f"{st}_store"]["mlups"] / mlups
-            torch.cuda.empty_cache()
+            for rnd in ("nearest", "stochastic"):
+                key = f"{st}_store" if rnd == "nearest" else f"{st}_store_stochastic"
+                log(f"variant {key}")
+                variants[key] = run_variant_storage(lb2d, torch, w, st, max(500, args.steps // 5), 50, stream,
+                                                    rnd)
+                variants[key]["speedup_vs_f32"] = variants[key]["mlups"] / mlups
+                torch.cuda.empty_cache()
     if "sc" in want:
         log("variant two-component + solute 2048^2")
         variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 20, stream)

@@ -121,6 +121,18 @@ int lb2d_solute_opening(lb2d_ctx *ctx, const char *wall, const char *style,
  * every obstacle.  "slip", "mixed", "hybrid" return LB2D_E_UNSUPPORTED. */
 int lb2d_boundary_style(lb2d_ctx *ctx, const char *style);
 
+/* Rounding of 16-bit population storage (an extension; the paper stores
+ * FP64): "nearest" (round to nearest even, the default) or "stochastic"
+ * (round up or down with probabilities given by the distance to the two
+ * neighbouring 16-bit values, using the gfx950 hardware converts and a
+ * counter-based hash of (seed, step, node)).  Stochastic rounding keeps
+ * per-step changes smaller than half an ulp on average, so slowly forced
+ * flows do not stall; runs stay bitwise reproducible for a given seed.
+ * Before bind; at bind, "stochastic" needs FP16 or BF16 storage of a
+ * one-fluid lattice (LB2D_E_UNSUPPORTED otherwise) and population arrays
+ * below 4 GiB (LB2D_E_SIZE).  Batched lattices always round to nearest. */
+int lb2d_rounding(lb2d_ctx *ctx, const char *mode, uint64_t seed);
+
 /* obstacle command, rectangle: nodes x0..x1, y0..y1 (inclusive,
  * 0 <= x0 <= x1 < nx, 0 <= y0 <= y1 < ny) become solid. */
 int lb2d_obstacle_rect(lb2d_ctx *ctx, int x0, int x1, int y0, int y1);

@@ -65,6 +65,8 @@ struct lb2d_ctx {
     std::vector<double> C0, Cux, Cuy;
     int storage = kF32;
     bool storage_chosen = false;
+    bool sr = false;          // stochastic rounding of 16-bit storage
+    unsigned sr_seed = 0;
     // device
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -305,6 +307,8 @@ PlainLattice plain_lattice(const lb2d_ctx *c) {
     L.ax = c->accel[0][0];
     L.ay = c->accel[0][1];
     L.rho_ref = c->rho_ref[0];
+    L.step = (const unsigned long long *)c->dstep;
+    L.seed = c->sr_seed;
     return L;
 }
 
@@ -317,9 +321,14 @@ int pre_command(lb2d_ctx *c, bool need_lattice = true) {
     return LB2D_OK;
 }
 
-// One time step on the stream `s` at the current parity.
-hipError_t enqueue_step(lb2d_ctx *c, int parity, hipStream_t s) {
-    if (c->plain()) return launch_plain(c->storage, plain_lattice(c), parity, s);
+// One step on the stream `s` at the given parity; k: its offset in the launch group, tick: steps to add to the
+// device step counter after it (stochastic rounding keys its stream on it).
+hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s) {
+    if (c->plain()) {
+        hipError_t e = launch_plain(c->storage, plain_lattice(c), parity, c->sr, k, s);
+        if (e == hipSuccess && c->sr && tick) e = launch_tick((unsigned long long *)c->dstep, tick, s);
+        return e;
+    }
     const FullParams p = full_params(c);
     hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->reaction, s);
     if (e != hipSuccess) return e;
@@ -333,7 +342,8 @@ int build_graph(lb2d_ctx *c) {
     hipGraph_t gr = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(c, k & 1, c->cap_stream);
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+        e = enqueue_step(c, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
     if (e != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));
@@ -533,6 +543,17 @@ int lb2d_boundary_style(lb2d_ctx *c, const char *style) {
     return c->fail(LB2D_E_INVAL, "unknown boundary style %s", style);
 }
 
+int lb2d_rounding(lb2d_ctx *c, const char *mode, uint64_t seed) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!mode) return c->fail(LB2D_E_INVAL, "null mode");
+    if (!std::strcmp(mode, "nearest")) c->sr = false;
+    else if (!std::strcmp(mode, "stochastic")) c->sr = true;
+    else return c->fail(LB2D_E_INVAL, "rounding mode must be nearest or stochastic");
+    c->sr_seed = (unsigned)(seed ^ (seed >> 32));
+    return LB2D_OK;
+}
+
 int lb2d_obstacle_rect(lb2d_ctx *c, int x0, int x1, int y0, int y1) {
     int rc = pre_command(c);
     if (rc) return rc;
@@ -657,6 +678,8 @@ int lb2d_workspace_bytes(lb2d_ctx *c, int storage, size_t *bytes) {
     if (storage < kF64 || storage > kBF16) return c->fail(LB2D_E_INVAL, "unknown storage format");
     if (!c->plain() && (storage == kF16 || storage == kBF16))
         return c->fail(LB2D_E_UNSUPPORTED, "16-bit storage is implemented for the one-fluid step only");
+    if (c->sr && storage != kF16 && storage != kBF16)
+        return c->fail(LB2D_E_UNSUPPORTED, "stochastic rounding applies to 16-bit storage only");
     if (c->bound && storage != c->storage) return c->fail(LB2D_E_STATE, "already bound");
     *bytes = make_layout(c, storage).total;
     if (!c->bound) {
@@ -677,6 +700,15 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         return c->fail(LB2D_E_INVAL, "solute openings come in pairs (xlo and xhi)");
     const Layout L = make_layout(c, c->storage);
     if (bytes < L.total) return c->fail(LB2D_E_SIZE, "workspace of %zu bytes, %zu needed", bytes, L.total);
+    if (c->sr && c->storage != kF16 && c->storage != kBF16)
+        return c->fail(LB2D_E_UNSUPPORTED, "stochastic rounding applies to 16-bit storage only");
+    if (c->sr) {
+        unsigned pnx;
+        size_t pplane;
+        plane_geometry(c, c->storage, &pnx, &pplane);
+        if ((unsigned long long)pplane * 9ull * 2ull >= (1ull << 32))
+            return c->fail(LB2D_E_SIZE, "stochastic rounding needs population arrays below 4 GiB");
+    }
     HIPCHK(c, hipSetDevice(c->device));
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice ||
@@ -787,8 +819,9 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
             const int parity = (int)(c->t & 1);
             HIPCHK(c, hipEventRecord(c->ev0, c->stream));
             if (c->plain()) {
-                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->stream));
+                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->sr, 0, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+                if (c->sr) HIPCHK(c, launch_tick((unsigned long long *)c->dstep, 1, c->stream));
             } else {
                 const FullParams p = full_params(c);
                 HIPCHK(c, launch_full(c->storage, p, parity, c->sc(), c->reaction, c->stream));
@@ -805,7 +838,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
         return LB2D_OK;
     }
     if ((c->t & 1) && left > 0) {
-        HIPCHK(c, enqueue_step(c, 1, c->stream));
+        HIPCHK(c, enqueue_step(c, 1, 0, 1, c->stream));
         c->t += 1;
         --left;
     }
@@ -819,7 +852,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
         }
     }
     for (; left > 0; --left) {
-        HIPCHK(c, enqueue_step(c, (int)(c->t & 1), c->stream));
+        HIPCHK(c, enqueue_step(c, (int)(c->t & 1), 0, 1, c->stream));
         c->t += 1;
     }
     return LB2D_OK;

@@ -35,6 +35,9 @@ struct PlainLattice {
     double Fx, Fy;        // aveforce (summed vector)
     double ax, ay;        // aveacceleration (summed vector)
     double rho_ref;       // shift of the stored populations
+    const unsigned long long *step;  // completed steps (device; read only by
+                                     // the stochastically rounded step)
+    unsigned seed;        // key of the stochastic-rounding stream
 };
 
 // Tile of the batched step: lattice index and lower-left node.

@@ -108,11 +108,22 @@ struct Codec<float> {
 // brings all nine to a similar magnitude, then rounded to nearest even.
 __host__ __device__ constexpr float scale16(int i) { return i == 0 ? 2.0f : (i <= 4 ? 8.0f : 32.0f); }
 __host__ __device__ constexpr float iscale16(int i) { return i == 0 ? 0.5f : (i <= 4 ? 0.125f : 0.03125f); }
+// enc_sr rounds stochastically with the hardware converts of gfx950: the
+// value rounds away from zero with probability equal to the discarded
+// fraction of an ulp, decided by the high bits of the random word r (13 bits
+// for FP16, 16 bits for BF16).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 template <>
 struct Codec<_Float16> {
     using R = float;
     __device__ static float dec(_Float16 v, int i) { return (float)v * iscale16(i); }
     __device__ static _Float16 enc(float d, int i) { return (_Float16)(d * scale16(i)); }
+    __device__ static _Float16 enc_sr(float d, int i, unsigned r) {
+        half2_t h = {};
+        h = __builtin_amdgcn_cvt_sr_f16_f32(h, d * scale16(i), r, false);
+        return h[0];
+    }
 };
 template <>
 struct Codec<bf16s> {
@@ -127,7 +138,32 @@ struct Codec<bf16s> {
         u += 0x7fffu + ((u >> 16) & 1u);
         return (bf16s)(uint16_t)(u >> 16);
     }
+    __device__ static bf16s enc_sr(float d, int i, unsigned r) {
+        bf162_t h = {};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, d * scale16(i), r, false);
+        return (bf16s)__builtin_bit_cast(uint16_t, h[0]);
+    }
 };
+
+// Counter-based random words for stochastic rounding: the 32-bit integer
+// hash "lowbias32" (C. Wellons, hash-prospector, 2018) of the node and the
+// step, extended to five words per node by Marsaglia's xorshift32
+// recurrence (J. Stat. Softw. 8(14), 2003).  Each word serves two
+// populations: itself and itself shifted left by 16 bits.
+__device__ __forceinline__ unsigned lowbias32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ unsigned xorshift32(unsigned x) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
 
 __device__ __forceinline__ int wrapi(int a, int n) {
     a %= n;
@@ -264,8 +300,8 @@ __device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
     return a;
 }
 
-template <typename S, typename O>
-__device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside) {
+template <typename S, typename O, bool SR>
+__device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside, unsigned tkey) {
     using C = Codec<S>;
     using R = typename C::R;
     constexpr unsigned kGroup = kBrickW * brick_h_for(sizeof(S));  // lanes per brick
@@ -326,12 +362,23 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     const R ux = (jx + tau * Fx) * inv;
     const R uy = (jy + tau * Fy) * inv;
     const R usq = R(1.5) * (ux * ux + uy * uy);
+    unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
+    if constexpr (SR) {
+        w[0] = lowbias32((unsigned)(y * (int)nx + x) ^ tkey);
+#pragma unroll
+        for (int k = 1; k < 5; ++k) w[k] = xorshift32(w[k - 1]);
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
         const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
         const R v = fluid ? d[i] + omega * (deq - d[i]) : R(0);
-        if (store) *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = C::enc(v, i);
+        if (store) {
+            S e;
+            if constexpr (SR) e = C::enc_sr(v, i, (i & 1) ? (w[i >> 1] << 16) : w[i >> 1]);
+            else e = C::enc(v, i);
+            *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+        }
     }
 }
 
@@ -346,14 +393,18 @@ __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
     ly = k / W;
 }
 
-template <typename S, typename O>
-__global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity) {
+// k: offset of this step in its launch group (the step computed is the
+// device step count + k + 1; only stochastic rounding reads it).
+template <typename S, typename O, bool SR>
+__global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k) {
     constexpr int TW = 256 / (kBrickW * brick_h_for(sizeof(S))) * kBrickW, TH = brick_h_for(sizeof(S));
     int lx, ly;
     brick_thread<S>(threadIdx.x, lx, ly);
     const int x = blockIdx.x * TW + lx;
     const int y = blockIdx.y * TH + ly;
-    plain_node<S, O>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny);
+    unsigned tkey = 0u;
+    if constexpr (SR) tkey = lowbias32((unsigned)(*L.step + (unsigned long long)k + 1ull) ^ L.seed);
+    plain_node<S, O, SR>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
@@ -370,7 +421,7 @@ __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ 
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
         const int x = x0 + lx;
         const int y = y0 + ly;
-        plain_node<S, O>(a, x, y, x < (int)a.nx && y < (int)a.ny);
+        plain_node<S, O, false>(a, x, y, x < (int)a.nx && y < (int)a.ny, 0u);
     }
 }
 
@@ -1332,14 +1383,25 @@ void plain_tile(int st, int *tw, int *th) {
     *th = h;
 }
 
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t stream) {
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
     int tw, th;
     plain_tile(st, &tw, &th);
     const dim3 blk(256), grd((L.nx + tw - 1) / tw, (L.ny + th - 1) / th);
-    if (fits32(L.plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, uint32_t>), grd, blk, 0, stream, L, parity));
+    if (sr && st == kF16)
+        hipLaunchKernelGGL((k_plain<_Float16, uint32_t, true>), grd, blk, 0, stream, L, parity, k);
+    else if (sr && st == kBF16)
+        hipLaunchKernelGGL((k_plain<bf16s, uint32_t, true>), grd, blk, 0, stream, L, parity, k);
+    else if (fits32(L.plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, uint32_t, false>), grd, blk, 0, stream, L, parity, k));
     else
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, size_t>), grd, blk, 0, stream, L, parity));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, size_t, false>), grd, blk, 0, stream, L, parity, k));
+    return hipGetLastError();
+}
+
+__global__ void k_tick(unsigned long long *step, int n) { *step += (unsigned long long)n; }
+
+hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, step, n);
     return hipGetLastError();
 }
 

@@ -15,7 +15,11 @@ int growth_blocks(int nx, int ny);
 
 // Tile (in nodes) covered by one 256-thread block of the one-fluid step.
 void plain_tile(int st, int *tw, int *th);
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, hipStream_t s);
+// One-fluid step; sr: stochastic rounding (16-bit storage, 32-bit offsets),
+// k: offset of the step in its launch group.
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t s);
+// Adds n to the device step counter.
+hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
 // max_plane: largest population plane (elements) of the batch's lattices.
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
                         size_t max_plane, hipStream_t s);

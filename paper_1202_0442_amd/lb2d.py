@@ -50,6 +50,7 @@ _SIGS = {
     "lb2d_solute": [_P, _D, _I],
     "lb2d_solute_opening": [_P, ctypes.c_char_p, ctypes.c_char_p, _D],
     "lb2d_boundary_style": [_P, ctypes.c_char_p],
+    "lb2d_rounding": [_P, ctypes.c_char_p, ctypes.c_uint64],
     "lb2d_obstacle_rect": [_P, _I, _I, _I, _I],
     "lb2d_obstacle_circle": [_P, _I, _I, _D],
     "lb2d_obstacle_mask": [_P, _U8P],
@@ -177,6 +178,10 @@ class Lattice:
 
     def boundary_style(self, style):
         self._chk(_lib.lb2d_boundary_style(self._h, style.encode()))
+
+    def rounding(self, mode, seed=0):
+        """'nearest' or 'stochastic' rounding of 16-bit storage."""
+        self._chk(_lib.lb2d_rounding(self._h, mode.encode(), int(seed)))
 
     def obstacle_rect(self, x0, x1, y0, y1):
         self._chk(_lib.lb2d_obstacle_rect(self._h, x0, x1, y0, y1))

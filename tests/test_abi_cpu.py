@@ -173,3 +173,23 @@ def test_null_handles_do_not_crash():
     assert _lib.lb2d_iteration(None, 1) == -1
     assert _lib.lb2d_destroy(None) == -1
     assert _lib.lb2d_last_error(None) == b"null context"
+
+
+def test_rounding_command_checks():
+    lb2d = _lb2d()
+    L = lb2d.Lattice()
+    with pytest.raises(lb2d.LB2DError) as e:
+        L.rounding("stochastic")
+    assert e.value.code == lb2d.E_ORDER
+    L.lattice("d2q9", 16, 16, 1.0)
+    with pytest.raises(lb2d.LB2DError) as e:
+        L.rounding("truncate")
+    assert e.value.code == lb2d.E_INVAL
+    L.rounding("stochastic", 3)
+    for st in ("f32", "f64"):
+        with pytest.raises(lb2d.LB2DError) as e:
+            L.workspace_bytes(st)
+        assert e.value.code == lb2d.E_UNSUPPORTED
+    assert L.workspace_bytes("f16") > 0
+    L.rounding("nearest")
+    assert L.workspace_bytes("f32") > 0
