@@ -169,6 +169,74 @@ def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     return out
 
 
+def run_phase(lb2d, torch, n, steps, warmup, stream, storage="f32"):
+    """One-component Shan-Chen (psi form) phase separation, the paper's
+    parameters on an n x n box: throughput of the general step with the
+    psi density tile."""
+    from paper_1202_0442_amd import inputs
+    w = inputs.phase_separation(n=n)
+    e = w.extra
+    L = lb2d.Lattice(0)
+    L.lattice("d2q9", w.nx, w.ny, w.tau)
+    L.set_fields(0, e["rho"])
+    L.interforce(e["G"], e["psi0"], e["rho0"])
+    L.bind(storage, stream=stream)
+    m0 = L.budgets()["mass0"]
+    L.iteration(warmup)
+    ms = time_steps(torch, stream, L.iteration, steps)
+    L.set_timing(True)
+    L.iteration(20)
+    kms, _ = L.kernel_time()
+    L.set_timing(False)
+    nn = w.nx * w.ny
+    byt = nn * 73  # every node fluid: 9 loads + 9 stores of 4 bytes + link word
+    rho, _, _ = L.moments(0)
+    out = {"workload": f"one-component Shan-Chen phase separation {n}x{n} (G -120, psi0 4, rho0 200), {storage}",
+           "mlups": nn * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "step_kernel_ms": kms,
+           "step_kernel_algorithmic_GBps": byt / (kms * 1e-3) / 1e9,
+           "step_kernel_frac_hbm": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+           "rho_min": float(rho.min()), "rho_max": float(rho.max()),
+           "mass_drift": L.budgets()["mass0"] / m0 - 1.0, "steps": steps + warmup + 20}
+    L.close()
+    return out
+
+
+def run_growth_sweep(lb2d, torch, stream, storage="f64"):
+    """The paper's surface-growth sweep, Da = 4, 20, 40, 80 at its full
+    20 000 steps: grown nodes, perimeter per square root of area (larger =
+    less compact), solute-budget closure and time."""
+    import numpy as np
+    from paper_1202_0442_amd import inputs
+    out = {}
+    for kr in (5e-3, 0.025, 0.05, 0.1):
+        w = inputs.surface_growth(kr)
+        e = w.extra
+        L = lb2d.Lattice(0)
+        L.lattice("d2q9", w.nx, w.ny, w.tau)
+        L.solute(e["tau_s"], 4)
+        L.boundary_style("noslip")
+        for r in w.rects:
+            L.obstacle_rect(*r)
+        L.surface_reaction(e["kr"], e["Cs"], "growth", e["b0"], e["bmax"], e["rng_seed"])
+        L.set_fields(0, np.full(w.nx * w.ny, w.rho0))
+        L.set_concentration(np.full(w.nx * w.ny, e["C0"]))
+        L.bind(storage, stream=stream)
+        b0 = L.budgets()
+        ms = time_steps(torch, stream, L.iteration, w.steps)
+        b1 = L.budgets()
+        m = L.mask().astype(int)
+        per = (np.abs(np.diff(m, axis=0, append=m[:1])).sum() + np.abs(np.diff(m, axis=1, append=m[:, :1])).sum())
+        lhs = b1["solute"] + b1["deposit"] + b1["removed_solute"] + b1["consumed_deposit"] - e["b0"] * b1["grown_nodes"]
+        rhs = b0["solute"] + b0["deposit"]
+        out[f"Da{e['Da']:g}"] = {"kr": kr, "grown_nodes": b1["grown_nodes"],
+                                 "perimeter_per_sqrt_area": float(per / np.sqrt(m.sum())),
+                                 "solute_budget_rel_err": abs(lhs - rhs) / rhs, "ms": ms,
+                                 "mlups": w.nx * w.ny * w.steps / (ms * 1e-3) / 1e6}
+        L.close()
+    return {"workload": "paper's surface growth: 200x200 periodic, 11x11 seed, D2Q4 solute C0 1.5, Cs 0.5, "
+                        f"b0 0.5, bmax 1, tau = tau_s = 1, 20000 steps, {storage}", "sweep": out}
+
+
 def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
     from paper_1202_0442_amd import inputs
     ws = inputs.ensemble(count=count)
@@ -261,7 +329,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=4096, help="porous lattice side")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--variants", default="all", help="all | none | comma list of f16,bf16,sc,batch")
+    ap.add_argument("--variants", default="all", help="all | none | comma list of f16,bf16,sc,phase,growth,batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
     ap.add_argument("--sc-steps", type=int, default=2000, help="steps of the two-component variant")
@@ -288,6 +356,10 @@ def main():
         res = {}
         if "sc" in want:
             res["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 10, stream)
+        if "phase" in want:
+            res["phase"] = run_phase(lb2d, torch, 4096, args.sc_steps, 10, stream)
+        if "growth" in want:
+            res["growth"] = run_growth_sweep(lb2d, torch, stream)
         print(json.dumps(res), flush=True)
         lb2d.copy_bench(1 << 30, reps=3, stream=stream)
         return
@@ -356,7 +428,8 @@ def main():
     out["roofline"]["frac_of_copy"] = round(achieved / out["copy_ceiling_GBps"], 4)
 
     want = set() if args.variants == "none" else (
-        {"f16", "bf16", "sc", "batch"} if args.variants == "all" else set(args.variants.split(",")))
+        {"f16", "bf16", "sc", "phase", "growth", "batch"} if args.variants == "all"
+        else set(args.variants.split(",")))
     variants = {}
     for st in ("f16", "bf16"):
         if st in want:
@@ -370,6 +443,14 @@ def main():
     if "sc" in want:
         log("variant two-component + solute 2048^2")
         variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 20, stream)
+        torch.cuda.empty_cache()
+    if "phase" in want:
+        log("variant one-component Shan-Chen 4096^2")
+        variants["phase"] = run_phase(lb2d, torch, 4096, args.sc_steps, 20, stream)
+        torch.cuda.empty_cache()
+    if "growth" in want:
+        log("variant surface-growth sweep")
+        variants["growth"] = run_growth_sweep(lb2d, torch, stream)
         torch.cuda.empty_cache()
     if "batch" in want:
         log("variant batched ensemble")

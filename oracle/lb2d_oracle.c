@@ -28,7 +28,8 @@
  *     u_eq = u' + tau F / rho (fluids command, "equilibrium velocity as
  *     explained in Refs.");
  *   - Shan-Chen forces use the densities of the same step, after streaming;
- *     solid neighbours carry zero density in the cohesion sum;
+ *     solid neighbours carry zero density (two components) or zero psi (one
+ *     component, psi = psi0 exp(-rho0 / rho)) in the cohesion sum;
  *   - the solute lattice is D2Q9 (g_eq = w C (1 + 3 e.u)) or the paper's
  *     D2Q4 (g_eq = C/4 (1 + 2 e.u)); Q is a run parameter;
  *   - the reactive surface rule is applied per link (generalises the D2Q4
@@ -102,9 +103,13 @@ typedef struct orc {
     double force[2][2];          /* aveforce: summed force vector per comp */
     double accel[2][2];          /* aveacceleration: summed vector per comp */
     int has_inter;
-    double G;                    /* interforce (two components) */
+    double G;                    /* interforce strength */
     int has_ads[2];
     double Gads[2];              /* adhesiveforce per component */
+    int psi_inter, psi_ads;      /* one component: forces act through
+                                    psi(rho) = psi0 exp(-rho0 / rho) */
+    double psi0_i, rho0_i;       /* psi of interforce */
+    double psi0_a, rho0_a;       /* psi of adhesiveforce */
     int q;                       /* solute lattice: 0 = off, 4 or 9 */
     double tau_s;
     int open_style[2];           /* solute openings on xlo, xhi: 0 none,
@@ -210,6 +215,33 @@ int orc_interforce(orc *o, double G) {
     o->G = G;
     return 0;
 }
+
+/* interforce(G, psi0, rho0), one component (interforce command):
+ * F = -G psi(x) sum_i w_i psi(x + e_i) e_i, psi = psi0 exp(-rho0 / rho),
+ * with psi = 0 on solid neighbours (the force acts between fluid sites). */
+int orc_interforce_psi(orc *o, double G, double psi0, double rho0) {
+    if (o->ncomp != 1 || !(rho0 > 0.0)) return -1;
+    o->has_inter = 1;
+    o->psi_inter = 1;
+    o->G = G;
+    o->psi0_i = psi0;
+    o->rho0_i = rho0;
+    return 0;
+}
+
+/* adhesiveforce(G, psi0, rho0), one component (adhesiveforce command):
+ * F = -G psi(x) sum_i w_i s(x + e_i) e_i. */
+int orc_adhesiveforce_psi(orc *o, double G, double psi0, double rho0) {
+    if (o->ncomp != 1 || !(rho0 > 0.0)) return -1;
+    o->has_ads[0] = 1;
+    o->psi_ads = 1;
+    o->Gads[0] = G;
+    o->psi0_a = psi0;
+    o->rho0_a = rho0;
+    return 0;
+}
+
+static double psi_of(double psi0, double rho0, double rho) { return psi0 * exp(-rho0 / rho); }
 
 /* adhesiveforce(G_c, fluid) in the two-component form. */
 int orc_adhesiveforce(orc *o, int comp, double G) {
@@ -431,6 +463,19 @@ static void compute_forces(orc *o) {
                         Fx += -o->G * r * sx;
                         Fy += -o->G * r * sy;
                     }
+                    if (o->has_inter && o->psi_inter) {
+                        double sx = 0.0, sy = 0.0;
+                        for (int i = 1; i < 9; ++i) {
+                            long nb = idx(o, wrap(x + EX9[i], o->nx),
+                                          wrap(y + EY9[i], o->ny));
+                            double pb = o->mask[nb] ? 0.0 : psi_of(o->psi0_i, o->rho0_i, o->rho[0][nb]);
+                            sx += W9[i] * pb * EX9[i];
+                            sy += W9[i] * pb * EY9[i];
+                        }
+                        double ps = psi_of(o->psi0_i, o->rho0_i, r);
+                        Fx += -o->G * ps * sx;
+                        Fy += -o->G * ps * sy;
+                    }
                     if (o->has_ads[c]) {
                         double sx = 0.0, sy = 0.0;
                         for (int i = 1; i < 9; ++i) {
@@ -440,8 +485,10 @@ static void compute_forces(orc *o) {
                             sx += W9[i] * sv * EX9[i];
                             sy += W9[i] * sv * EY9[i];
                         }
-                        Fx += -o->Gads[c] * r * sx;
-                        Fy += -o->Gads[c] * r * sy;
+                        /* two components: rho_c; one component: psi(rho) */
+                        double a = o->psi_ads ? psi_of(o->psi0_a, o->rho0_a, r) : r;
+                        Fx += -o->Gads[c] * a * sx;
+                        Fy += -o->Gads[c] * a * sy;
                     }
                 }
                 o->Fx[c][s] = Fx;

@@ -48,7 +48,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
@@ -65,6 +65,8 @@ def _load():
         "orc_aveacceleration": (I, [P, I, I, D]),
         "orc_interforce": (I, [P, D]),
         "orc_adhesiveforce": (I, [P, I, D]),
+        "orc_interforce_psi": (I, [P, D, D, D]),
+        "orc_adhesiveforce_psi": (I, [P, D, D, D]),
         "orc_solute": (I, [P, I, D]),
         "orc_solute_opening": (I, [P, I, I, D]),
         "orc_surface_reaction": (I, [P, D, D, D, D, ctypes.c_uint64]),
@@ -180,11 +182,21 @@ class Oracle:
     def aveacceleration(self, mode, value, comp=0):
         self._chk(self.lib.orc_aveacceleration(self.h, comp, mode, value), "aveacceleration")
 
-    def interforce(self, G):
-        self._chk(self.lib.orc_interforce(self.h, G), "interforce")
+    def interforce(self, G, psi0=None, rho0=None):
+        """Two components: interforce(G); one component: interforce(G, psi0,
+        rho0) with psi = psi0 exp(-rho0 / rho)."""
+        if psi0 is None:
+            self._chk(self.lib.orc_interforce(self.h, G), "interforce")
+        else:
+            self._chk(self.lib.orc_interforce_psi(self.h, G, psi0, rho0), "interforce")
 
-    def adhesiveforce(self, G, comp):
-        self._chk(self.lib.orc_adhesiveforce(self.h, comp, G), "adhesiveforce")
+    def adhesiveforce(self, G, comp=0, psi0=None, rho0=None):
+        """Two components: adhesiveforce(G, comp); one component:
+        adhesiveforce(G, psi0=, rho0=)."""
+        if psi0 is None:
+            self._chk(self.lib.orc_adhesiveforce(self.h, comp, G), "adhesiveforce")
+        else:
+            self._chk(self.lib.orc_adhesiveforce_psi(self.h, G, psi0, rho0), "adhesiveforce")
 
     def solute(self, tau_s, q=9):
         self._chk(self.lib.orc_solute(self.h, q, tau_s), "solute")

@@ -49,6 +49,8 @@ struct lb2d_ctx {
     double force[2][2] = {{0, 0}, {0, 0}}, accel[2][2] = {{0, 0}, {0, 0}};
     bool inter = false;
     double G = 0.0;
+    double psi0 = 0.0, psi_rho0 = 1.0;  // one-component interforce psi
+    double psi0a = 0.0, rho0a = 1.0;  // one-component adhesiveforce psi
     bool ads[2] = {false, false};
     double Gads[2] = {0.0, 0.0};
     int q = 0;
@@ -104,7 +106,7 @@ struct lb2d_ctx {
     }
     size_t n() const { return (size_t)nx * ny; }
     bool plain() const { return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1]; }
-    bool sc() const { return ncomp == 2 && inter; }
+    bool sc() const { return inter; }  // cohesion: two components, or psi form
 };
 
 struct lb2d_batch {
@@ -243,7 +245,13 @@ FullParams full_params(const lb2d_ctx *c) {
         k8.Gads[k] = c->ads[k] ? c->Gads[k] : 0.0;
     }
     k8.G = c->inter ? c->G : 0.0;
+    k8.psi0 = c->psi0;
+    k8.rho0 = c->psi_rho0;
+    k8.psi0a = c->psi0a;
+    k8.rho0a = c->rho0a;
     p.has_ads = (c->ads[0] || c->ads[1]) ? 1 : 0;
+    p.ads_psi = (c->ncomp == 1 && c->ads[0]) ? 1 : 0;
+    p.psi = (c->ncomp == 1 && c->inter) ? 1 : 0;
     k8.omega_s = c->q ? 1.0 / c->tau_s : 0.0;
     p.solute_xper = (c->open_style[0] || c->open_style[1]) ? 0 : 1;
     for (int k = 0; k < 2; ++k) {
@@ -279,6 +287,10 @@ FullParams full_params(const lb2d_ctx *c) {
         k4.klink_inv[k] = (float)k8.klink_inv[k];
     }
     k4.G = (float)k8.G;
+    k4.psi0 = (float)k8.psi0;
+    k4.rho0 = (float)k8.rho0;
+    k4.psi0a = (float)k8.psi0a;
+    k4.rho0a = (float)k8.rho0a;
     k4.omega_s = (float)k8.omega_s;
     k4.Cs = (float)k8.Cs;
     p.b0 = c->b0;
@@ -646,14 +658,28 @@ int lb2d_aveacceleration(lb2d_ctx *c, int mode, double value, int comp) {
     return add_force(c, mode, value, comp, true);
 }
 
+// psi0, rho0 of the one-component forms: both given, psi0 finite, rho0 > 0;
+// the two-component forms take neither (NaN).
+static int psi_args(lb2d_ctx *c, double psi0, double rho0, const char *cmd) {
+    if (c->ncomp == 2) {
+        if (!is_nan(psi0) || !is_nan(rho0))
+            return c->fail(LB2D_E_INVAL, "%s: the two-component form takes no psi0, rho0 (pass NaN)", cmd);
+        return LB2D_OK;
+    }
+    if (!std::isfinite(psi0) || !(rho0 > 0.0) || !std::isfinite(rho0))
+        return c->fail(LB2D_E_INVAL, "%s: the one-component form needs finite psi0 and rho0 > 0", cmd);
+    return LB2D_OK;
+}
+
 int lb2d_interforce(lb2d_ctx *c, double G, double psi0, double rho0) {
     int rc = pre_command(c);
     if (rc) return rc;
-    if (!is_nan(psi0) || !is_nan(rho0) || c->ncomp != 2)
-        return c->fail(LB2D_E_UNSUPPORTED, "only the two-component interforce (psi0, rho0 omitted) is implemented");
+    if ((rc = psi_args(c, psi0, rho0, "interforce"))) return rc;
     if (!std::isfinite(G)) return c->fail(LB2D_E_INVAL, "G must be finite");
     c->inter = true;
     c->G = G;
+    c->psi0 = psi0;
+    c->psi_rho0 = rho0;
     c->have_force = true;
     return LB2D_OK;
 }
@@ -661,13 +687,15 @@ int lb2d_interforce(lb2d_ctx *c, double G, double psi0, double rho0) {
 int lb2d_adhesiveforce(lb2d_ctx *c, double G, double psi0, double rho0, int comp) {
     int rc = pre_command(c);
     if (rc) return rc;
-    if (!is_nan(psi0) || !is_nan(rho0) || c->ncomp != 2)
-        return c->fail(LB2D_E_UNSUPPORTED,
-                       "only the two-component adhesiveforce (psi0, rho0 omitted) is implemented");
-    if (comp < 0 || comp > 1) return c->fail(LB2D_E_INVAL, "component must be 0 or 1");
+    if ((rc = psi_args(c, psi0, rho0, "adhesiveforce"))) return rc;
+    if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
     if (!std::isfinite(G)) return c->fail(LB2D_E_INVAL, "G must be finite");
     c->ads[comp] = true;
     c->Gads[comp] = G;
+    if (c->ncomp == 1) {
+        c->psi0a = psi0;
+        c->rho0a = rho0;
+    }
     c->have_force = true;
     return LB2D_OK;
 }

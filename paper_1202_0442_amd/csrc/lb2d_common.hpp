@@ -55,8 +55,10 @@ struct StepCoef {
     R A0[2], A1[2];        // equilibrium coefficients A_0, A_{1..8}
     R rho_ref[2];          // shift of the stored populations
     R force[2][2], accel[2][2];
-    R G;                   // interforce (two components)
+    R G;                   // interforce strength
     R Gads[2];             // adhesiveforce per component (0 = off)
+    R psi0, rho0;          // one component: interforce psi = psi0 exp(-rho0/rho)
+    R psi0a, rho0a;        // one component: adhesiveforce psi
     R omega_s;             // 1 / tau_s
     R open_value[2];       // xlo, xhi opening values
     R Cs;                  // saturation concentration
@@ -83,7 +85,9 @@ struct FullParams {
     size_t pplane;        // elements per population plane
     int nx, ny;
     int ncomp;
+    int psi;              // one component: interforce acts through psi(rho)
     int has_ads;
+    int ads_psi;          // one component: adhesion acts through psi(rho)
     int sq;               // solute lattice: 9 (D2Q9, plane i = direction i) or
                           // 4 (D2Q4, plane i-1 = direction i = 1..4); 0 = none
     int solute_xper;      // 1: solute periodic in x

@@ -488,6 +488,11 @@ __device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
     ly = (b / BPR) * BH + k / BW;
 }
 
+// psi(rho) = psi0 exp(-rho0 / rho) of the one-component interforce and
+// adhesiveforce commands.
+__device__ __forceinline__ float psi_of(float psi0, float rho0, float rho) { return psi0 * expf(-rho0 / rho); }
+__device__ __forceinline__ double psi_of(double psi0, double rho0, double rho) { return psi0 * exp(-rho0 / rho); }
+
 // Halo slot j of a TX x TY tile's density ring -> position in the
 // (TX+2) x (TY+2) tile: bottom row, top row, then left/right columns.
 template <int TX, int TY>
@@ -774,13 +779,18 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     }
 
     // 3. density tile for the cohesion stencil: own nodes (and periodic
-    // images past a ragged edge) and the pulled halo ring
+    // images past a ragged edge) and the pulled halo ring; one component
+    // keeps psi(rho) instead of rho.  Solids hold 0.
     if constexpr (SC) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) srho[c][ly + 1][lx + 1] = solid ? R(0) : q.rho_ref[c] + drho[c];
+        for (int c = 0; c < NC; ++c) {
+            const R r = q.rho_ref[c] + drho[c];
+            srho[c][ly + 1][lx + 1] = solid ? R(0) : (NC == 1 ? psi_of(q.psi0, q.rho0, r) : r);
+        }
         if (hj < NH) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) srho[c][hy][hx] = hpull ? hrho[c] : R(0);
+            for (int c = 0; c < NC; ++c)
+                srho[c][hy][hx] = hpull ? (NC == 1 ? psi_of(q.psi0, q.rho0, hrho[c]) : hrho[c]) : R(0);
         }
         __syncthreads();
     }
@@ -812,6 +822,21 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             }
         }
     }
+    if constexpr (SC && NC == 1) {
+        // one component: F = -G psi(x) sum_i w_i psi(x + e_i) e_i
+        if (valid) {
+            R sx = R(0), sy = R(0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const R pb = srho[0][ly + 1 + ey(i)][lx + 1 + ex(i)];
+                if (ex(i)) sx += wgt<R>(i) * (ex(i) > 0 ? pb : -pb);
+                if (ey(i)) sy += wgt<R>(i) * (ey(i) > 0 ? pb : -pb);
+            }
+            const R ps = srho[0][ly + 1][lx + 1];
+            Fx[0] += -q.G * ps * sx;
+            Fy[0] += -q.G * ps * sy;
+        }
+    }
     if (p.has_ads) {
         R ax = R(0), ay = R(0);
 #pragma unroll
@@ -822,8 +847,10 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            Fx[c] += -q.Gads[c] * rho[c] * ax;
-            Fy[c] += -q.Gads[c] * rho[c] * ay;
+            // two components: rho_c; one component: psi(rho) of adhesiveforce
+            const R a = (NC == 1 && p.ads_psi) ? psi_of(q.psi0a, q.rho0a, rho[c]) : rho[c];
+            Fx[c] += -q.Gads[c] * a * ax;
+            Fy[c] += -q.Gads[c] * a * ay;
         }
     }
     // 5. common velocity u' and per-component equilibrium velocities
@@ -1250,6 +1277,21 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
             Fx += -p.cd.G * rho[c] * sx;
             Fy += -p.cd.G * rho[c] * sy;
         }
+        if (p.ncomp == 1 && p.psi) {
+            // one-component cohesion through psi(rho)
+            double sx = 0, sy = 0;
+            const S *fo = (const S *)p.f[parity][0];
+            for (int i = 1; i < 9; ++i) {
+                const int gx = wrapi(x + ex(i), nx), gy = wrapi(y + ey(i), ny);
+                if (p.mask[(size_t)gy * nx + gx]) continue;
+                const double pb = psi_of(p.cd.psi0, p.cd.rho0, node_rho<S>(p, fo, gx, gy, p.cd.rho_ref[0]));
+                sx += wgt<double>(i) * pb * ex(i);
+                sy += wgt<double>(i) * pb * ey(i);
+            }
+            const double ps = psi_of(p.cd.psi0, p.cd.rho0, rho[0]);
+            Fx += -p.cd.G * ps * sx;
+            Fy += -p.cd.G * ps * sy;
+        }
         if (p.has_ads) {
             double sx = 0, sy = 0;
             for (int i = 1; i < 9; ++i) {
@@ -1258,8 +1300,9 @@ __global__ void k_moments(FullParams p, int parity, int comp, double *orho, doub
                 sx += wgt<double>(i) * sv * ex(i);
                 sy += wgt<double>(i) * sv * ey(i);
             }
-            Fx += -p.cd.Gads[c] * rho[c] * sx;
-            Fy += -p.cd.Gads[c] * rho[c] * sy;
+            const double a = p.ads_psi ? psi_of(p.cd.psi0a, p.cd.rho0a, rho[c]) : rho[c];
+            Fx += -p.cd.Gads[c] * a * sx;
+            Fy += -p.cd.Gads[c] * a * sy;
         }
         R += rho[c];
         MX += jx[c] - 0.5 * Fx;
@@ -1439,8 +1482,13 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
             else LB2D_FULL(2, false, false);
         }
     } else {
-        if (react) LB2D_FULL(1, false, true);
-        else LB2D_FULL(1, false, false);
+        if (sc) {
+            if (react) LB2D_FULL(1, true, true);
+            else LB2D_FULL(1, true, false);
+        } else {
+            if (react) LB2D_FULL(1, false, true);
+            else LB2D_FULL(1, false, false);
+        }
     }
 #undef LB2D_FULL
 }

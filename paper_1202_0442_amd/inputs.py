@@ -211,6 +211,31 @@ def ensemble(count: int = 256, seed: int = 5, smin: int = 256, smax: int = 1536,
     return out
 
 
+def phase_separation(n: int = 100, seed: int = 1202, d0: float = 200.0, G: float = -120.0,
+                     psi0: float = 4.0, rho0: float = 200.0, steps: int = 20000) -> Workload:
+    """The paper's phase-separation set-up (section Phase separation): one
+    fluid in a periodic n x n box at rest with density d0 + U[0, 1],
+    interforce(G, psi0, rho0), tau = 1.  The initial densities are in
+    extra["rho"]."""
+    rng = np.random.default_rng(seed)
+    return Workload("phase", n, n, steps, tau=1.0, rho0=d0,
+                    extra={"G": G, "psi0": psi0, "rho0": rho0, "rho": d0 + rng.uniform(0.0, 1.0, n * n)})
+
+
+def surface_growth(kr: float, n: int = 200, side: int = 11, f0: float = 24.0, C0: float = 1.5,
+                   Cs: float = 0.5, b0: float = 0.5, bmax: float = 1.0, seed: int = 2012,
+                   steps: int = 20000) -> Workload:
+    """The paper's surface-growth set-up (section Surface growth): periodic
+    n x n box, one fluid at rest of density f0, a side x side solid seed in
+    the centre, D2Q4 solute C0, surface_reaction(kr, Cs, growth, b0, bmax),
+    tau = tau_s = 1; Da = kr L / D with L = n and D = (tau_s - 1/2)/2."""
+    h, c = side // 2, n // 2
+    return Workload("surface_growth", n, n, steps, tau=1.0, rho0=f0,
+                    rects=[(c - h, c + h, c - h, c + h)],
+                    extra={"kr": kr, "Cs": Cs, "b0": b0, "bmax": bmax, "C0": C0, "tau_s": 1.0,
+                           "rng_seed": seed, "Da": kr * n / 0.25})
+
+
 def random_populations(shape, seed: int, scale: float = 0.01) -> np.ndarray:
     """Deviations uniform in [-scale, scale] for tests that start away from
     equilibrium."""

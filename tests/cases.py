@@ -66,6 +66,24 @@ def surface_growth_case(kr, n=200, side=11, f0=24.0, C0=1.5, Cs=0.5, b0=0.5, bma
                 C=np.full(n * n, C0), reaction=(kr, Cs, b0, bmax, seed))
 
 
+def phase_case(nx, ny, seed, G=-120.0, psi0=4.0, rho0=200.0, d0=200.0, tau=1.0):
+    """The paper's phase-separation set-up (section Phase separation): one
+    fluid, density d0 + U[0, 1] at rest, interforce(G, psi0, rho0)."""
+    rng = np.random.default_rng(seed)
+    return dict(nx=nx, ny=ny, tau=tau, psi=(G, psi0, rho0),
+                fields={0: (d0 + rng.uniform(0, 1, nx * ny), None, None)})
+
+
+def contact_box_case(Gads, nx=201, ny=51, seed=5, G=-120.0, psi0=4.0, rho0=200.0):
+    """The paper's contact-angle box (section Contact angles I): solid
+    frame, fluid inside as in the phase-separation set-up, interforce and
+    the one-component adhesiveforce(Gads, psi0, rho0)."""
+    case = phase_case(nx, ny, seed, G, psi0, rho0)
+    case["rects"] = [(0, 0, 0, ny - 1), (nx - 1, nx - 1, 0, ny - 1), (0, nx - 1, 0, 0), (0, nx - 1, ny - 1, ny - 1)]
+    case["ads_psi"] = (Gads, psi0, rho0)
+    return case
+
+
 def build_oracle(case):
     o = Oracle(case["nx"], case["ny"])
     if "fluids" in case:
@@ -81,6 +99,11 @@ def build_oracle(case):
     if case.get("gads") is not None:
         o.adhesiveforce(case["gads"][0], 0)
         o.adhesiveforce(case["gads"][1], 1)
+    if case.get("psi") is not None:
+        o.interforce(*case["psi"])
+    if case.get("ads_psi") is not None:
+        G, psi0, rho0 = case["ads_psi"]
+        o.adhesiveforce(G, psi0=psi0, rho0=rho0)
     for r in case.get("rects", []):
         o.obstacle_rect(*r)
     for c in case.get("circles", []):
@@ -138,6 +161,11 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
     if case.get("gads") is not None:
         g.adhesiveforce(case["gads"][0], 0)
         g.adhesiveforce(case["gads"][1], 1)
+    if case.get("psi") is not None:
+        g.interforce(*case["psi"])
+    if case.get("ads_psi") is not None:
+        G, psi0, rho0 = case["ads_psi"]
+        g.adhesiveforce(G, 0, psi0, rho0)
     if bind:
         g.bind(storage, stream=stream)
     return g

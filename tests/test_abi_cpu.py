@@ -76,9 +76,7 @@ def test_unsupported_forms():
     lb2d = _lb2d()
     L = lb2d.Lattice()
     L.lattice("d2q9", 10, 10, 1.0)
-    cases = [lambda: L.boundary_style("slip"), lambda: L.boundary_style("mixed"),
-             lambda: L.interforce(-120, 4, 200),
-             lambda: L.adhesiveforce(-200, 0, 4, 200)]
+    cases = [lambda: L.boundary_style("slip"), lambda: L.boundary_style("mixed")]
     for call in cases:
         with pytest.raises(lb2d.LB2DError) as e:
             call()
@@ -193,3 +191,27 @@ def test_rounding_command_checks():
     assert L.workspace_bytes("f16") > 0
     L.rounding("nearest")
     assert L.workspace_bytes("f32") > 0
+
+
+def test_psi_force_forms():
+    """One component: interforce / adhesiveforce take psi0 and rho0 (psi
+    form); two components take neither."""
+    lb2d = _lb2d()
+    one = lb2d.Lattice()
+    one.lattice("d2q9", 12, 10, 1.0)
+    for call in (lambda: one.interforce(-120.0), lambda: one.interforce(-120.0, 4.0, 0.0),
+                 lambda: one.adhesiveforce(-200.0, 0), lambda: one.adhesiveforce(-200.0, 1, 4.0, 200.0)):
+        with pytest.raises(lb2d.LB2DError) as e:
+            call()
+        assert e.value.code == lb2d.E_INVAL
+    one.interforce(-120.0, 4.0, 200.0)
+    one.adhesiveforce(-200.0, 0, 4.0, 200.0)
+    two = lb2d.Lattice()
+    two.lattice("d2q9", 12, 10, 1.0)
+    two.fluids(1.0, 1.0)
+    for call in (lambda: two.interforce(0.9, 4.0, 200.0), lambda: two.adhesiveforce(0.3, 0, 4.0, 200.0)):
+        with pytest.raises(lb2d.LB2DError) as e:
+            call()
+        assert e.value.code == lb2d.E_INVAL
+    two.interforce(0.9)
+    two.adhesiveforce(0.3, 1)

@@ -97,3 +97,36 @@ def test_surface_growth_budget_closes_on_gpu():
     rhs = b0["solute"] + b0["deposit"]
     assert lhs == pytest.approx(rhs, rel=1e-12)
     assert b1["inflow"] == 0.0 and b1["outflow"] == 0.0
+
+
+def test_paper_surface_growth_sweep_full_size():
+    """The paper's Da sweep (Da = 4, 20, 40, 80) at its full 20 000 steps
+    in FP64: every final mask is bit-identical to the FP64 oracle's (stored
+    by tests/golden/make_surface_growth_sweep.py, which calls only the
+    oracle), the grown structure is less compact -- larger perimeter per
+    square root of area -- as Da grows (Fig. surface), and the solute
+    budget closes in every run."""
+    import hashlib
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "surface_growth_sweep.json")))
+    shape = []
+    for kr in (5e-3, 0.025, 0.05, 0.1):
+        g = build_gpu(surface_growth_case(kr), "f64")
+        b0 = g.budgets()
+        g.iteration(20000)
+        b1 = g.budgets()
+        ref = gold["runs"][repr(kr)]
+        assert hashlib.sha256(g.mask().astype("uint8").tobytes()).hexdigest() == ref["mask_sha256"]
+        assert int(b1["grown_nodes"]) == ref["grown_nodes"]
+        assert b1["solute"] == pytest.approx(ref["solute"], rel=1e-10)
+        assert b1["deposit"] == pytest.approx(ref["deposit"], rel=1e-10)
+        lhs = (b1["solute"] + b1["deposit"] + b1["removed_solute"] + b1["consumed_deposit"]
+               - 0.5 * b1["grown_nodes"])
+        assert lhs == pytest.approx(b0["solute"] + b0["deposit"], rel=1e-11)
+        m = g.mask().astype(int)
+        per = (np.abs(np.diff(m, axis=0, append=m[:1])).sum()
+               + np.abs(np.diff(m, axis=1, append=m[:, :1])).sum())
+        shape.append(per / np.sqrt(m.sum()))
+    print("perimeter / sqrt(area):", shape)
+    assert all(a < b for a, b in zip(shape, shape[1:]))

@@ -634,3 +634,112 @@ def test_results_do_not_depend_on_thread_count():
     for x, y in zip(a[:3], b[:3]):
         assert np.array_equal(x, y)
     assert a[3] == b[3]
+
+
+# ------------------------------------------- one-component Shan-Chen (psi)
+
+def _psi(rho, psi0, rho0):
+    return psi0 * np.exp(-rho0 / rho)
+
+
+def test_psi_cohesion_is_psi_gradient():
+    """interforce(G, psi0, rho0), one component: for psi quadratic in x, y the
+    stencil sum_i w_i psi(x + e_i) e_i is exactly grad(psi)/3, so the force is
+    -G psi grad(psi)/3.  The density field is built from the inverse of
+    psi = psi0 exp(-rho0/rho)."""
+    nx, ny, G, psi0, rho0 = 20, 18, -120.0, 4.0, 200.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    psi = 1.2 + 0.01 * x + 0.015 * y + 0.0008 * x * x - 0.0004 * x * y + 0.0006 * y * y
+    rho = -rho0 / np.log(psi / psi0)
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.interforce(G, psi0, rho0)
+    o.set_fields(0, rho)
+    Fx, Fy = o.forces(0)
+    gx = 0.01 + 0.0016 * x - 0.0004 * y
+    gy = 0.015 - 0.0004 * x + 0.0012 * y
+    sl = (slice(1, ny - 1), slice(1, nx - 1))
+    np.testing.assert_allclose(Fx[sl], -G * psi[sl] * gx[sl] / 3, rtol=1e-10)
+    np.testing.assert_allclose(Fy[sl], -G * psi[sl] * gy[sl] / 3, rtol=1e-10)
+
+
+def test_psi_adhesion_next_to_flat_wall():
+    """adhesiveforce(G, psi0, rho0), one component: a node beside a flat
+    solid row has sum_i w_i s(x + e_i) e_i = -n/6 (n: unit normal into the
+    fluid), so F = +G psi n / 6: towards the wall for G < 0."""
+    nx, ny, G, psi0, rho0 = 10, 8, -250.0, 4.0, 200.0
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.adhesiveforce(G, psi0=psi0, rho0=rho0)
+    o.obstacle_rect(0, nx - 1, 0, 0)
+    o.set_fields(0, 300.0)
+    Fx, Fy = o.forces(0)
+    p = _psi(300.0, psi0, rho0)
+    np.testing.assert_allclose(Fy[1], G * p / 6, rtol=1e-13)        # above the wall: n = +y
+    np.testing.assert_allclose(Fy[ny - 1], -G * p / 6, rtol=1e-13)  # below it (periodic): n = -y
+    assert np.all(Fx == 0.0) and np.all(Fy[2:ny - 1] == 0.0)
+
+
+def test_psi_cohesion_conserves_momentum():
+    """The cohesion sum pairs each link with its opposite, so over a periodic
+    box without solids the forces add to zero and the total momentum of a
+    separating fluid stays at its initial value (zero)."""
+    nx, ny = 48, 40
+    rng = np.random.default_rng(9)
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.interforce(-120.0, 4.0, 200.0)
+    o.set_fields(0, 200.0 + rng.uniform(0, 1, nx * ny))
+    b0 = o.budgets()
+    o.iteration(300)
+    b = o.budgets()
+    _, ux, _ = o.moments(0)
+    assert np.abs(ux).max() > 1e-3          # the fluid does move (separation)
+    assert abs(b["mom_x"]) <= 1e-9 * b0["mass0"]
+    assert abs(b["mom_y"]) <= 1e-9 * b0["mass0"]
+    assert b["mass0"] == pytest.approx(b0["mass0"], rel=1e-13)
+
+
+def test_flat_interface_has_equal_bulk_pressures():
+    """Steady flat liquid-vapour interface of the one-component model: the
+    cohesion force of a row is -(G/6) psi(y) (psi(y+1) - psi(y-1)), whose sum
+    over an interface telescopes to -(G/6)(psi_l^2 - psi_g^2); the momentum
+    balance with the bulk fluxes rho/3 then makes p = rho/3 + G psi^2/6 equal
+    in both bulk phases.  Also the phases are distinct (a density ratio
+    above 3).  The start is a smooth (tanh) slab: a step start also excites
+    the lattice's period-2 momentum mode, whose j^2/rho adds to the bulk
+    fluxes."""
+    nx, ny, G, psi0, rho0 = 4, 128, -120.0, 4.0, 200.0
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.interforce(G, psi0, rho0)
+    yy = np.repeat(np.arange(ny), nx).astype(float)
+    o.set_fields(0, 86.0 + 438.0 * 0.5 * (np.tanh((yy - 32) / 3) - np.tanh((yy - 96) / 3)))
+    o.iteration(40000)
+    rho, _, _ = o.moments(0)
+    rl, rg = rho[64].mean(), rho[0].mean()
+    p = lambda r: r / 3 + G * _psi(r, psi0, rho0) ** 2 / 6
+    assert rl > 3 * rg
+    assert p(rl) == pytest.approx(p(rg), rel=1e-9)
+
+
+def _perimeter_per_root_area(mask):
+    m = mask.astype(int)
+    per = (np.abs(np.diff(m, axis=0, append=m[:1])).sum()
+           + np.abs(np.diff(m, axis=1, append=m[:, :1])).sum())
+    return per / np.sqrt(m.sum())
+
+
+def test_surface_growth_more_dendritic_with_damkohler():
+    """The paper's surface-growth example (Fig. surface: 200 x 200, seed
+    square 11 x 11, C0 = 1.5, Cs = 0.5, b0 = 0.5, bmax = 1, D2Q4 solute):
+    the grown structure is less compact -- larger perimeter per square root
+    of area -- as Da = kr L / D grows through 4, 20, 40, 80."""
+    from cases import build_oracle, surface_growth_case
+    shape = []
+    for kr in (5e-3, 0.025, 0.05, 0.1):
+        o = build_oracle(surface_growth_case(kr))
+        o.iteration(4000)
+        assert o.budgets()["grown_nodes"] > 1000
+        shape.append(_perimeter_per_root_area(o.get_mask()))
+    assert all(a < b for a, b in zip(shape, shape[1:])), shape
