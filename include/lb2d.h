@@ -117,6 +117,27 @@ int lb2d_solute(lb2d_ctx *ctx, double tau_s, int q);
 int lb2d_solute_opening(lb2d_ctx *ctx, const char *wall, const char *style,
                         double value);
 
+/* inlet/outlet + inlet_momentum/outlet_momentum commands: nodes lo..hi
+ * (inclusive, along the wall) of wall "xlo", "xhi", "ylo" or "yhi" are an
+ * opening for fluid component comp; kind "inlet" or "outlet".  Styles:
+ *   "poiseuille": velocity along the wall normal with the paper's profile
+ *       v(k) = 4 v / L^2 [(L/2)^2 - ((2k - lo - hi)/2)^2], L = hi - lo + 1
+ *       (v = v_max);
+ *   "uniform":    velocity v along the wall normal;
+ *   "dirichlet":  density (pressure rho/3) rho held;
+ *   "gradient":   after the collision f(wall) = 2 f(wall+n) - f(wall+2n).
+ * Velocities point into the domain for inlets and out of it for outlets;
+ * the tangential velocity is zero.  The Zou-He closure (App. A) sets the
+ * three populations entering the domain after streaming and bounce-back;
+ * the opening nodes then collide as usual.  rho is also the density the
+ * opening nodes start with (velocity styles also start at their velocity).
+ * Openings override the periodic wrap only on their own nodes.  Up to 8
+ * openings; a node may belong to one opening per component; |v| < 1,
+ * rho > 0.  After lattice (and fluids), before bind. */
+int lb2d_momentum_opening(lb2d_ctx *ctx, const char *wall, int lo, int hi, int comp,
+                          const char *kind, const char *style, double v,
+                          double rho);
+
 /* boundary_style command: "noslip" (half-way bounce-back).  Must precede
  * every obstacle.  "slip", "mixed", "hybrid" return LB2D_E_UNSUPPORTED. */
 int lb2d_boundary_style(lb2d_ctx *ctx, const char *style);

@@ -120,6 +120,18 @@ typedef struct orc {
     uint64_t seed;
     int b_ready;                 /* b initialised to b0 on solids */
 
+    /* momentum openings (inlet_momentum / outlet_momentum) */
+    int nopen;
+    struct {
+        int wall;                /* 0 xlo, 1 xhi, 2 ylo, 3 yhi */
+        int lo, hi;              /* node range along the wall */
+        int comp;
+        int outlet;              /* 0 inlet, 1 outlet */
+        int style;               /* 1 poiseuille, 2 uniform, 3 dirichlet, 4 gradient */
+        double v, rho;
+    } open[16];
+    int open_ready;              /* opening nodes set to their initial state */
+
     double *f[2], *ftmp[2];      /* [9][n] populations, post-collision */
     double *g, *gtmp;            /* [9][n] solute populations */
     uint8_t *mask;               /* 1 = solid */
@@ -349,6 +361,7 @@ double orc_geq(int q, int i, double C, double ux, double uy) {
 int orc_set_fields(orc *o, int comp, const double *rho, const double *ux,
                    const double *uy) {
     if (comp < 0 || comp > 1) return -1;
+    o->open_ready = 0;  /* opening nodes are set again before the next use */
     for (long s = 0; s < o->n; ++s)
         for (int i = 0; i < 9; ++i)
             o->f[comp][i * o->n + s] =
@@ -369,6 +382,115 @@ int orc_set_concentration(orc *o, const double *C, const double *ux,
                     ? geq(o->q, i, C[s], ux ? ux[s] : 0.0, uy ? uy[s] : 0.0)
                     : 0.0;
     return 0;
+}
+
+/* -------------------------------------------------- momentum openings */
+
+/* inlet/outlet + inlet_momentum/outlet_momentum: nodes lo..hi of a wall of
+ * the box carry an opening for component comp.  Styles (inlet_momentum
+ * command): poiseuille (v = v_max of the parabolic profile), uniform (v),
+ * dirichlet (density rho held), gradient (extrapolation after collision).
+ * rho is the density the opening nodes start with. */
+int orc_momentum_opening(orc *o, int wall, int lo, int hi, int comp, int outlet, int style, double v,
+                         double rho) {
+    if (o->nopen >= 16 || wall < 0 || wall > 3 || comp < 0 || comp >= o->ncomp) return -1;
+    if (style < 1 || style > 4 || !(rho > 0.0)) return -1;
+    int len = wall < 2 ? o->ny : o->nx;
+    if (lo < 0 || hi < lo || hi >= len) return -1;
+    o->open[o->nopen].wall = wall;
+    o->open[o->nopen].lo = lo;
+    o->open[o->nopen].hi = hi;
+    o->open[o->nopen].comp = comp;
+    o->open[o->nopen].outlet = outlet ? 1 : 0;
+    o->open[o->nopen].style = style;
+    o->open[o->nopen].v = v;
+    o->open[o->nopen].rho = rho;
+    o->nopen++;
+    return 0;
+}
+
+/* Inward unit normal (nx_, ny_) of a wall and the node at coordinate k
+ * along it. */
+static void wall_geom(const orc *o, int wall, int k, int *x, int *y, int *nxw, int *nyw) {
+    switch (wall) {
+        case 0: *x = 0; *y = k; *nxw = 1; *nyw = 0; break;
+        case 1: *x = o->nx - 1; *y = k; *nxw = -1; *nyw = 0; break;
+        case 2: *x = k; *y = 0; *nxw = 0; *nyw = 1; break;
+        default: *x = k; *y = o->ny - 1; *nxw = 0; *nyw = -1; break;
+    }
+}
+
+/* Normal velocity u.n (n inward) imposed at coordinate k of a velocity
+ * opening: the speed into the domain for an inlet, out of it for an
+ * outlet; poiseuille: v(k) = 4 v_max / L^2 [(L/2)^2 - ((2k - lo - hi)/2)^2],
+ * L = hi - lo + 1 (inlet_momentum command). */
+static double opening_un(int outlet, int style, double v, int lo, int hi, int k) {
+    double sp = v;
+    if (style == 1) {
+        double L = hi - lo + 1.0, h = (2.0 * k - lo - hi) / 2.0;
+        sp = 4.0 * v / (L * L) * (L * L / 4.0 - h * h);
+    }
+    return outlet ? -sp : sp;
+}
+
+/* Zou-He closure at an opening node (inlet_momentum command, App. A), for
+ * the inward normal n and zero tangential velocity: with T the populations
+ * along the wall (e.n = 0) and O those leaving the domain (e.n = -1),
+ *   rho (1 - u.n) = sum_T f + 2 sum_O f;
+ * the entering populations (e.n = +1) are the opposite ones plus
+ *   (2/3) rho u.n  (axial),
+ *   -(1/2) (e.t) (f_t - f_-t) + (1/6) rho u.n  (diagonal),
+ * t the tangent.  Velocity styles give u.n and yield rho; dirichlet gives
+ * rho and yields u.n.  f holds the nine populations of the node. */
+static void zou_he(double *f, long n, long s, int nxw, int nyw, int pressure, double given) {
+    int txw = nyw != 0 ? 1 : 0, tyw = nxw != 0 ? 1 : 0;  /* tangent */
+    double sT = 0.0, sO = 0.0, ftp = 0.0, ftm = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        int en = EX9[i] * nxw + EY9[i] * nyw, et = EX9[i] * txw + EY9[i] * tyw;
+        double v = f[i * n + s];
+        if (en == 0) {
+            sT += v;
+            if (et == 1) ftp = v;
+            if (et == -1) ftm = v;
+        } else if (en < 0) {
+            sO += v;
+        }
+    }
+    double rho, un;
+    if (pressure) {
+        rho = given;
+        un = 1.0 - (sT + 2.0 * sO) / rho;
+    } else {
+        un = given;
+        rho = (sT + 2.0 * sO) / (1.0 - un);
+    }
+    for (int i = 0; i < 9; ++i) {
+        int en = EX9[i] * nxw + EY9[i] * nyw, et = EX9[i] * txw + EY9[i] * tyw;
+        if (en != 1) continue;
+        double fo = f[opposite(i) * n + s];
+        f[i * n + s] = (et == 0) ? fo + 2.0 / 3.0 * rho * un
+                                 : fo - 0.5 * et * (ftp - ftm) + 1.0 / 6.0 * rho * un;
+    }
+}
+
+/* Opening nodes start at equilibrium with the opening's density and
+ * velocity (the inlet/outlet commands override earlier settings). */
+static void init_openings(orc *o) {
+    if (o->open_ready) return;
+    o->open_ready = 1;
+    for (int k = 0; k < o->nopen; ++k)
+        for (int j = o->open[k].lo; j <= o->open[k].hi; ++j) {
+            int x, y, nxw, nyw;
+            wall_geom(o, o->open[k].wall, j, &x, &y, &nxw, &nyw);
+            long s = idx(o, x, y);
+            double un = (o->open[k].style <= 2)
+                            ? opening_un(o->open[k].outlet, o->open[k].style, o->open[k].v, o->open[k].lo,
+                                         o->open[k].hi, j)
+                            : 0.0;
+            for (int i = 0; i < 9; ++i)
+                o->f[o->open[k].comp][i * o->n + s] =
+                    o->mask[s] ? 0.0 : feq(i, o->open[k].rho, un * nxw, un * nyw, o->alpha[o->open[k].comp]);
+        }
 }
 
 /* ---------------------------------------------------- reactive link rule */
@@ -544,6 +666,7 @@ static void one_step(orc *o) {
     const long n = o->n;
     const int nx = o->nx, ny = o->ny;
     if (o->reaction) init_b(o);
+    init_openings(o);
 
     /* 1. Fluid streaming (pull): the population arriving at x along e_i left
      * x - e_i; if that node is solid, the population that x itself sent
@@ -563,6 +686,22 @@ static void one_step(orc *o) {
                     o->ftmp[c][i * n + s] = v;
                 }
             }
+
+    /* 1b. Zou-He closure of the velocity and pressure openings. */
+    for (int k = 0; k < o->nopen; ++k) {
+        if (o->open[k].style > 3) continue;
+        for (int j = o->open[k].lo; j <= o->open[k].hi; ++j) {
+            int x, y, nxw, nyw;
+            wall_geom(o, o->open[k].wall, j, &x, &y, &nxw, &nyw);
+            long s = idx(o, x, y);
+            if (o->mask[s]) continue;
+            int pressure = o->open[k].style == 3;
+            double given = pressure ? o->open[k].rho
+                                    : opening_un(o->open[k].outlet, o->open[k].style, o->open[k].v,
+                                                 o->open[k].lo, o->open[k].hi, j);
+            zou_he(o->ftmp[o->open[k].comp], n, s, nxw, nyw, pressure, given);
+        }
+    }
 
     /* 2. Moments after streaming. */
     compute_moments(o, o->ftmp);
@@ -606,6 +745,21 @@ static void one_step(orc *o) {
                 double fe = feq(i, r, ux, uy, o->alpha[c]);
                 o->f[c][i * n + s] = fi - (fi - fe) / o->tau[c];
             }
+        }
+    }
+
+    /* 5b. Gradient openings: after collision each population of an opening
+     * node is extrapolated from the next two nodes inward,
+     * f(wall) = 2 f(wall + n) - f(wall + 2n) (inlet_momentum command). */
+    for (int k = 0; k < o->nopen; ++k) {
+        if (o->open[k].style != 4) continue;
+        double *fc = o->f[o->open[k].comp];
+        for (int j = o->open[k].lo; j <= o->open[k].hi; ++j) {
+            int x, y, nxw, nyw;
+            wall_geom(o, o->open[k].wall, j, &x, &y, &nxw, &nyw);
+            long s = idx(o, x, y), s1 = idx(o, x + nxw, y + nyw), s2 = idx(o, x + 2 * nxw, y + 2 * nyw);
+            if (o->mask[s] || o->mask[s1] || o->mask[s2]) continue;
+            for (int i = 0; i < 9; ++i) fc[i * n + s] = 2.0 * fc[i * n + s1] - fc[i * n + s2];
         }
     }
 
@@ -811,6 +965,7 @@ int orc_step(orc *o, long nsteps) {
  * and zero velocity (write_restart convention). */
 int orc_moments(orc *o, int comp, double *rho, double *ux, double *uy) {
     if (comp < -1 || comp >= o->ncomp) return -1;
+    init_openings(o);
     compute_moments(o, o->f);
     compute_forces(o);
     for (long s = 0; s < o->n; ++s) {
@@ -852,6 +1007,7 @@ int orc_solute_state(orc *o, double *C, double *b) {
  * wrapper. */
 int orc_budgets(orc *o, double *out) {
     if (o->reaction) init_b(o);
+    init_openings(o);
     for (int k = 0; k < 16; ++k) out[k] = 0.0;
     long nfluid = 0;
     for (long s = 0; s < o->n; ++s) {
@@ -887,13 +1043,15 @@ int orc_budgets(orc *o, double *out) {
 long orc_step_count(const orc *o) { return o->t; }
 void orc_set_step_count(orc *o, long t) { o->t = t; }
 
-int orc_get_f(const orc *o, int comp, double *out) {
+int orc_get_f(orc *o, int comp, double *out) {
     if (comp < 0 || comp > 1) return -1;
+    init_openings(o);
     memcpy(out, o->f[comp], sizeof(double) * 9 * o->n);
     return 0;
 }
 int orc_set_f(orc *o, int comp, const double *in) {
     if (comp < 0 || comp > 1) return -1;
+    o->open_ready = 1;  /* raw populations are taken as given */
     memcpy(o->f[comp], in, sizeof(double) * 9 * o->n);
     return 0;
 }
@@ -926,6 +1084,7 @@ int orc_set_b(orc *o, const double *in) {
 /* Forces of the current (post-collision) state, for tests. */
 int orc_forces(orc *o, int comp, double *Fx, double *Fy) {
     if (comp < 0 || comp >= o->ncomp) return -1;
+    init_openings(o);
     compute_moments(o, o->f);
     compute_forces(o);
     memcpy(Fx, o->Fx[comp], sizeof(double) * o->n);

@@ -66,6 +66,7 @@ def _load():
         "orc_interforce": (I, [P, D]),
         "orc_adhesiveforce": (I, [P, I, D]),
         "orc_interforce_psi": (I, [P, D, D, D]),
+        "orc_momentum_opening": (I, [P, I, I, I, I, I, I, D, D]),
         "orc_adhesiveforce_psi": (I, [P, D, D, D]),
         "orc_solute": (I, [P, I, D]),
         "orc_solute_opening": (I, [P, I, I, D]),
@@ -181,6 +182,16 @@ class Oracle:
 
     def aveacceleration(self, mode, value, comp=0):
         self._chk(self.lib.orc_aveacceleration(self.h, comp, mode, value), "aveacceleration")
+
+    def momentum_opening(self, wall, lo, hi, comp, kind, style, v=0.0, rho=1.0):
+        """inlet/outlet + inlet_momentum/outlet_momentum: nodes lo..hi of
+        wall xlo/xhi/ylo/yhi; kind inlet/outlet; style poiseuille (v =
+        v_max), uniform (v), dirichlet (rho held) or gradient; rho = the
+        opening nodes' initial density."""
+        w = {"xlo": 0, "xhi": 1, "ylo": 2, "yhi": 3}[wall]
+        st = {"poiseuille": 1, "uniform": 2, "dirichlet": 3, "gradient": 4}[style]
+        self._chk(self.lib.orc_momentum_opening(self.h, w, lo, hi, comp, 1 if kind == "outlet" else 0, st,
+                                                v, rho), "momentum_opening")
 
     def interforce(self, G, psi0=None, rho0=None):
         """Two components: interforce(G); one component: interforce(G, psi0,

@@ -105,7 +105,13 @@ struct lb2d_ctx {
         return code;
     }
     size_t n() const { return (size_t)nx * ny; }
-    bool plain() const { return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1]; }
+    std::vector<OpenSpec> opens;  // momentum openings
+    bool plain() const { return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1] && opens.empty(); }
+    bool has_gradient() const {
+        for (const auto &o : opens)
+            if (o.style == 4) return true;
+        return false;
+    }
     bool sc() const { return inter; }  // cohesion: two components, or psi form
 };
 
@@ -259,6 +265,8 @@ FullParams full_params(const lb2d_ctx *c) {
         k8.open_value[k] = c->open_value[k];
     }
     k8.Cs = c->Cs;
+    p.nopen = (int)c->opens.size();
+    for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
     // links of a flat wall add up to kr) and the denominator of the link
     // concentration; D2Q4 has no diagonal links
@@ -343,6 +351,7 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
     }
     const FullParams p = full_params(c);
     hipError_t e = launch_full(c->storage, p, parity, c->sc(), c->reaction, s);
+    if (e == hipSuccess && c->has_gradient()) e = launch_open_gradient(c->storage, p, parity ^ 1, s);
     if (e != hipSuccess) return e;
     if (c->q) e = launch_growth(c->storage, p, parity ^ 1, c->reaction, s);
     return e;
@@ -492,6 +501,7 @@ int lb2d_fluids(lb2d_ctx *c, double tau1, double tau2, double alpha1, double alp
     int rc = pre_command(c);
     if (rc) return rc;
     if (c->have_fluids) return c->fail(LB2D_E_ORDER, "fluids given twice");
+    if (!c->opens.empty()) return c->fail(LB2D_E_ORDER, "fluids must precede the momentum openings");
     if (c->have_force || !c->rho0[0].empty())
         return c->fail(LB2D_E_ORDER, "fluids must precede forces and initial fields");
     if (!(tau1 > 0.5) || !(tau2 > 0.5)) return c->fail(LB2D_E_INVAL, "tau1, tau2 must exceed 1/2");
@@ -553,6 +563,56 @@ int lb2d_boundary_style(lb2d_ctx *c, const char *style) {
     if (!std::strcmp(style, "slip") || !std::strcmp(style, "mixed") || !std::strcmp(style, "hybrid"))
         return c->fail(LB2D_E_UNSUPPORTED, "boundary style %s is not implemented", style);
     return c->fail(LB2D_E_INVAL, "unknown boundary style %s", style);
+}
+
+int lb2d_momentum_opening(lb2d_ctx *c, const char *wall, int lo, int hi, int comp, const char *kind,
+                          const char *style, double v, double rho) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!wall || !kind || !style) return c->fail(LB2D_E_INVAL, "null wall, kind or style");
+    OpenSpec o{};
+    if (!std::strcmp(wall, "xlo")) o.wall = 0;
+    else if (!std::strcmp(wall, "xhi")) o.wall = 1;
+    else if (!std::strcmp(wall, "ylo")) o.wall = 2;
+    else if (!std::strcmp(wall, "yhi")) o.wall = 3;
+    else return c->fail(LB2D_E_INVAL, "wall must be xlo, xhi, ylo or yhi");
+    if (!std::strcmp(kind, "inlet")) o.outlet = 0;
+    else if (!std::strcmp(kind, "outlet")) o.outlet = 1;
+    else return c->fail(LB2D_E_INVAL, "kind must be inlet or outlet");
+    if (!std::strcmp(style, "poiseuille")) o.style = 1;
+    else if (!std::strcmp(style, "uniform")) o.style = 2;
+    else if (!std::strcmp(style, "dirichlet")) o.style = 3;
+    else if (!std::strcmp(style, "gradient")) o.style = 4;
+    else return c->fail(LB2D_E_INVAL, "style must be poiseuille, uniform, dirichlet or gradient");
+    if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+    const int len = o.wall < 2 ? c->ny : c->nx;
+    if (lo < 0 || hi < lo || hi >= len) return c->fail(LB2D_E_INVAL, "opening range %d..%d outside 0..%d", lo, hi, len - 1);
+    if (!(rho > 0.0) || !std::isfinite(rho)) return c->fail(LB2D_E_INVAL, "rho must be positive");
+    if (!std::isfinite(v) || std::fabs(v) >= 1.0) return c->fail(LB2D_E_INVAL, "|v| must be below 1");
+    if ((int)c->opens.size() >= kMaxOpen) return c->fail(LB2D_E_SIZE, "at most %d openings", kMaxOpen);
+    // no node may belong to two openings of one component: same wall and
+    // overlapping ranges, or perpendicular walls that both hold their corner
+    auto corner_in = [&](int w, int a, int b, int other) {
+        // coordinate along wall w of the corner it shares with wall `other`
+        const int k = (w < 2) ? (other == 2 ? 0 : c->ny - 1) : (other == 0 ? 0 : c->nx - 1);
+        return a <= k && k <= b;
+    };
+    for (const auto &q : c->opens) {
+        if (q.comp != comp) continue;
+        if (q.wall == o.wall) {
+            if (lo <= q.hi && q.lo <= hi) return c->fail(LB2D_E_INVAL, "openings overlap on one wall");
+        } else if ((q.wall < 2) != (o.wall < 2)) {
+            if (corner_in(o.wall, lo, hi, q.wall) && corner_in(q.wall, q.lo, q.hi, o.wall))
+                return c->fail(LB2D_E_INVAL, "two openings share a corner node");
+        }
+    }
+    o.lo = lo;
+    o.hi = hi;
+    o.comp = comp;
+    o.v = v;
+    o.rho = rho;
+    c->opens.push_back(o);
+    return LB2D_OK;
 }
 
 int lb2d_rounding(lb2d_ctx *c, const char *mode, uint64_t seed) {
@@ -802,12 +862,35 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     }
     // a2: populations at equilibrium of the initial fields
     for (int k = 0; k < c->ncomp; ++k) {
-        const double rr = c->rho0[k].empty() ? 1.0 : mean_of(c->rho0[k]);
+        // momentum openings override the initial fields on their nodes:
+        // their density and (velocity styles) their velocity
+        std::vector<double> r0 = c->rho0[k], ux0 = c->ux0[k], uy0 = c->uy0[k];
+        bool any = false;
+        for (const auto &o : c->opens) any |= o.comp == k;
+        if (any) {
+            if (r0.empty()) r0.assign(n, 1.0);
+            if (ux0.empty()) ux0.assign(n, 0.0);
+            if (uy0.empty()) uy0.assign(n, 0.0);
+            for (const auto &o : c->opens) {
+                if (o.comp != k) continue;
+                const int nxw = o.wall == 0 ? 1 : o.wall == 1 ? -1 : 0, nyw = o.wall == 2 ? 1 : o.wall == 3 ? -1 : 0;
+                for (int j = o.lo; j <= o.hi; ++j) {
+                    const int x = o.wall == 0 ? 0 : o.wall == 1 ? c->nx - 1 : j;
+                    const int y = o.wall == 2 ? 0 : o.wall == 3 ? c->ny - 1 : j;
+                    const size_t sidx = (size_t)y * c->nx + x;
+                    const double un = o.style <= 2 ? opening_normal_velocity(o, j) : 0.0;
+                    r0[sidx] = o.rho;
+                    ux0[sidx] = un * nxw;
+                    uy0[sidx] = un * nyw;
+                }
+            }
+        }
+        const double rr = r0.empty() ? 1.0 : mean_of(r0);
         c->rho_ref[k] = (double)(float)rr;
         int e;
-        if ((e = upload(c, c->staging, c->rho0[k], 1.0))) return e;
-        if ((e = upload(c, c->staging + n, c->ux0[k], 0.0))) return e;
-        if ((e = upload(c, c->staging + 2 * n, c->uy0[k], 0.0))) return e;
+        if ((e = upload(c, c->staging, r0, 1.0))) return e;
+        if ((e = upload(c, c->staging + n, ux0, 0.0))) return e;
+        if ((e = upload(c, c->staging + 2 * n, uy0, 0.0))) return e;
         HIPCHK(c, launch_init_fluid(c->storage, c->f[0][k], c->staging, c->staging + n, c->staging + 2 * n, n,
                                     2.25 * c->alpha[k], 1.8 * (1.0 - c->alpha[k]), c->rho_ref[k],
                                     (unsigned)c->nx, c->pnx, c->pplane, s));
@@ -853,6 +936,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
             } else {
                 const FullParams p = full_params(c);
                 HIPCHK(c, launch_full(c->storage, p, parity, c->sc(), c->reaction, c->stream));
+                if (c->has_gradient()) HIPCHK(c, launch_open_gradient(c->storage, p, parity ^ 1, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
                 if (c->q) HIPCHK(c, launch_growth(c->storage, p, parity ^ 1, c->reaction, c->stream));
             }

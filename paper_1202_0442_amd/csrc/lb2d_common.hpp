@@ -66,6 +66,18 @@ struct StepCoef {
     R klink_inv[2];        // 1 / (2 w_i + k_i): axial, diagonal links
 };
 
+// One momentum opening (inlet/outlet + inlet_momentum/outlet_momentum
+// commands): nodes lo..hi of a wall of the box, for one fluid component.
+struct OpenSpec {
+    int wall;             // 0 xlo, 1 xhi, 2 ylo, 3 yhi
+    int lo, hi;           // node range along the wall
+    int comp;
+    int outlet;           // 0 inlet, 1 outlet
+    int style;            // 1 poiseuille, 2 uniform, 3 dirichlet, 4 gradient
+    double v, rho;        // speed (v_max for poiseuille) and density
+};
+constexpr int kMaxOpen = 8;
+
 // Everything the general fused step needs: up to two fluid components with
 // Shan-Chen cohesion / adhesion and an optional solute (D2Q9 or D2Q4) with
 // openings, a reactive surface, FP64 deposits and growth triggers.
@@ -96,6 +108,8 @@ struct FullParams {
     unsigned long long seed;
     int nblk_main;        // tally slots of the step kernel (one per wavefront)
     int nblk_grow;        // blocks (tally slots) of the growth kernel
+    int nopen;            // momentum openings
+    OpenSpec open[kMaxOpen];
     StepCoef<double> cd;  // FP64 coefficients
     StepCoef<float> cf;   // the same rounded to FP32
 };

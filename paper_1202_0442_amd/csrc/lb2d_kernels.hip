@@ -28,6 +28,8 @@
 //    reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lb2d_common.hpp"
 #include "lb2d_kernels.hpp"
 
@@ -493,6 +495,88 @@ __device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
 __device__ __forceinline__ float psi_of(float psi0, float rho0, float rho) { return psi0 * expf(-rho0 / rho); }
 __device__ __forceinline__ double psi_of(double psi0, double rho0, double rho) { return psi0 * exp(-rho0 / rho); }
 
+// Zou-He closure at a node of a momentum opening on wall W (inlet_momentum
+// command, App. A), in deviation form d_i = f_i - w_i rho_ref.  With n the
+// inward normal, t the tangent, T the populations along the wall and O
+// those leaving the domain, rho (1 - u.n) = rho_ref + sum_T d + 2 sum_O d
+// (the weights of T and twice O add up to 1); each entering population is
+// its opposite plus (2/3) rho u.n (axial) or
+// -(1/2) (e.t)(d_t - d_-t) + (1/6) rho u.n (diagonal); zero tangential
+// velocity.  Velocity styles give u.n, dirichlet gives rho.
+template <int W>
+__host__ __device__ constexpr int wall_en(int i) {
+    return W == 0 ? ex(i) : W == 1 ? -ex(i) : W == 2 ? ey(i) : -ey(i);
+}
+template <int W>
+__host__ __device__ constexpr int wall_et(int i) {
+    return W < 2 ? ey(i) : ex(i);
+}
+template <int W, typename R>
+__device__ __forceinline__ void zou_he(R (&d)[9], bool pressure, R given, R rho_ref) {
+    R sT = R(0), sO = R(0), tp = R(0), tm = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (wall_en<W>(i) == 0) {
+            sT += d[i];
+            if (wall_et<W>(i) == 1) tp = d[i];
+            if (wall_et<W>(i) == -1) tm = d[i];
+        } else if (wall_en<W>(i) < 0) {
+            sO += d[i];
+        }
+    }
+    const R known = rho_ref + sT + R(2) * sO;
+    R rho, un;
+    if (pressure) {
+        rho = given;
+        un = R(1) - known / rho;
+    } else {
+        un = given;
+        rho = known / (R(1) - un);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (wall_en<W>(i) != 1) continue;
+        d[i] = (wall_et<W>(i) == 0) ? d[opp(i)] + R(2.0 / 3.0) * rho * un
+                                    : d[opp(i)] - R(0.5) * R(wall_et<W>(i)) * (tp - tm) + R(1.0 / 6.0) * rho * un;
+    }
+}
+
+// Normal velocity u.n (n inward) of a velocity opening at coordinate k
+// along its wall: the speed into the domain for an inlet, out of it for an
+// outlet; poiseuille: v(k) = 4 v_max / L^2 [(L/2)^2 - ((2k - lo - hi)/2)^2],
+// L = hi - lo + 1.
+template <typename R>
+__host__ __device__ __forceinline__ R opening_un(const OpenSpec &o, int k) {
+    R sp = R(o.v);
+    if (o.style == 1) {
+        const R L = R(o.hi - o.lo + 1), h = R(2 * k - o.lo - o.hi) / R(2);
+        sp = R(4) * R(o.v) / (L * L) * (L * L / R(4) - h * h);
+    }
+    return o.outlet ? -sp : sp;
+}
+
+// Applies the openings of component c that hold node (x, y) (Zou-He styles
+// only; gradient openings act after the collision, in k_open_gradient).
+template <typename R>
+__device__ __forceinline__ void apply_openings(const FullParams &p, int c, int x, int y, R (&d)[9], R rho_ref) {
+    for (int k = 0; k < p.nopen; ++k) {
+        const OpenSpec &o = p.open[k];
+        if (o.comp != c || o.style > 3) continue;
+        const int pos = o.wall < 2 ? y : x;
+        const bool on = (o.wall == 0 ? x == 0 : o.wall == 1 ? x == p.nx - 1 : o.wall == 2 ? y == 0 : y == p.ny - 1) &&
+                        pos >= o.lo && pos <= o.hi;
+        if (!on) continue;
+        const bool pressure = o.style == 3;
+        const R given = pressure ? R(o.rho) : opening_un<R>(o, pos);
+        switch (o.wall) {
+            case 0: zou_he<0>(d, pressure, given, rho_ref); break;
+            case 1: zou_he<1>(d, pressure, given, rho_ref); break;
+            case 2: zou_he<2>(d, pressure, given, rho_ref); break;
+            default: zou_he<3>(d, pressure, given, rho_ref); break;
+        }
+    }
+}
+
 // Halo slot j of a TX x TY tile's density ring -> position in the
 // (TX+2) x (TY+2) tile: bottom row, top row, then left/right columns.
 template <int TX, int TY>
@@ -556,7 +640,7 @@ __device__ __forceinline__ const StepCoef<double> &coef<double>(const FullParams
 template <>
 __device__ __forceinline__ const StepCoef<float> &coef<float>(const FullParams &p) { return p.cf; }
 
-template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, int TX, int TY>
+template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, bool OPEN, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
@@ -666,6 +750,11 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 const O a = wall ? (O)opp(i) * pl + s : (O)i * pl + src[i];
                 d[c][i] = ldb(fin, a, i);
             }
+        }
+        // momentum openings (only lanes on the box edge can hold one)
+        if constexpr (OPEN) {
+            if (valid && fluid && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1))
+                apply_openings<R>(p, c, x, y, d[c], q.rho_ref[c]);
         }
         drho[c] = jx[c] = jy[c] = R(0);
 #pragma unroll
@@ -970,6 +1059,33 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 dst[2] += tal[2];
             }
         }
+    }
+}
+
+// Gradient openings: after the collision each population of an opening
+// node is extrapolated from the next two nodes inward,
+// f(wall) = 2 f(wall + n) - f(wall + 2n) (inlet_momentum command); the
+// same holds for the deviations.  One thread per opening node
+// (blockIdx.y = opening).
+template <typename S>
+__global__ void __launch_bounds__(256) k_open_gradient(FullParams p, int parity_new) {
+    using C = Codec<S>;
+    const OpenSpec &o = p.open[blockIdx.y];
+    const int j = o.lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (o.style != 4 || j > o.hi) return;
+    const int nxw = o.wall == 0 ? 1 : o.wall == 1 ? -1 : 0;
+    const int nyw = o.wall == 2 ? 1 : o.wall == 3 ? -1 : 0;
+    const int x = o.wall == 0 ? 0 : o.wall == 1 ? p.nx - 1 : j;
+    const int y = o.wall == 2 ? 0 : o.wall == 3 ? p.ny - 1 : j;
+    const int x1 = x + nxw, y1 = y + nyw, x2 = x + 2 * nxw, y2 = y + 2 * nyw;
+    const size_t nx = (size_t)p.nx;
+    if (p.mask[y * nx + x] || p.mask[y1 * nx + x1] || p.mask[y2 * nx + x2]) return;
+    S *f = (S *)p.f[parity_new][o.comp];
+    const size_t s0 = brick_index<S>(x, y, p.pnx), s1 = brick_index<S>(x1, y1, p.pnx),
+                 s2 = brick_index<S>(x2, y2, p.pnx);
+    for (int i = 0; i < 9; ++i) {
+        const auto a = C::dec(f[(size_t)i * p.pplane + s1], i), b = C::dec(f[(size_t)i * p.pplane + s2], i);
+        f[(size_t)i * p.pplane + s0] = C::enc(a + a - b, i);
     }
 }
 
@@ -1467,12 +1583,12 @@ int growth_blocks(int nx, int ny) {
     return segs < kGrowBlocks ? segs : kGrowBlocks;
 }
 
-template <typename S, typename O, int SQ>
+template <typename S, typename O, int SQ, bool OPEN>
 static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
 #define LB2D_FULL(NC_, SC_, REACT_) \
-    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, kTX, kTY>), g, b, 0, st, p, parity)
+    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, OPEN, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
             if (react) LB2D_FULL(2, true, true);
@@ -1496,10 +1612,15 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
 template <typename S, int SQ>
 static void full_dispatch_off(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     // 32-bit byte offsets when every population array (9 planes) is below 4 GiB
-    if (fits32(p.pplane, sizeof(S)))
-        full_dispatch_sq<S, uint32_t, SQ>(p, parity, sc, react, st);
-    else
-        full_dispatch_sq<S, size_t, SQ>(p, parity, sc, react, st);
+    // the momentum-opening closure only in lattices that have openings
+    const bool open = p.nopen > 0;
+    if (fits32(p.pplane, sizeof(S))) {
+        if (open) full_dispatch_sq<S, uint32_t, SQ, true>(p, parity, sc, react, st);
+        else full_dispatch_sq<S, uint32_t, SQ, false>(p, parity, sc, react, st);
+    } else {
+        if (open) full_dispatch_sq<S, size_t, SQ, true>(p, parity, sc, react, st);
+        else full_dispatch_sq<S, size_t, SQ, false>(p, parity, sc, react, st);
+    }
 }
 
 // The reaction needs a solute; the solute lattice is p.sq (0, 9 or 4).
@@ -1513,6 +1634,19 @@ static void full_dispatch(const FullParams &p, int parity, bool sc, bool react, 
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t stream) {
     if (st == kF64) full_dispatch<double>(p, parity, sc, react, stream);
     else full_dispatch<float>(p, parity, sc, react, stream);
+    return hipGetLastError();
+}
+
+double opening_normal_velocity(const OpenSpec &o, int k) { return opening_un<double>(o, k); }
+
+hipError_t launch_open_gradient(int st, const FullParams &p, int parity_new, hipStream_t stream) {
+    int len = 0;
+    for (int k = 0; k < p.nopen; ++k)
+        if (p.open[k].style == 4) len = std::max(len, p.open[k].hi - p.open[k].lo + 1);
+    if (len == 0) return hipSuccess;
+    const dim3 g((len + 255) / 256, p.nopen), b(256);
+    if (st == kF64) hipLaunchKernelGGL(k_open_gradient<double>, g, b, 0, stream, p, parity_new);
+    else hipLaunchKernelGGL(k_open_gradient<float>, g, b, 0, stream, p, parity_new);
     return hipGetLastError();
 }
 

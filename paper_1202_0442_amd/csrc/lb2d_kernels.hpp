@@ -26,6 +26,11 @@ hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int 
 // General step; the solute lattice (none, D2Q9, D2Q4) is p.sq.
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
+// Normal velocity (inward) of velocity opening o at coordinate k along its
+// wall (poiseuille profile or uniform; negative for outlets).
+double opening_normal_velocity(const OpenSpec &o, int k);
+// Gradient-style momentum openings (after the step); no-op without them.
+hipError_t launch_open_gradient(int st, const FullParams &p, int parity_new, hipStream_t s);
 hipError_t launch_tally_final(const FullParams &p, hipStream_t s);
 
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s);

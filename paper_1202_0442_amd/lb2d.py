@@ -51,6 +51,8 @@ _SIGS = {
     "lb2d_solute_opening": [_P, ctypes.c_char_p, ctypes.c_char_p, _D],
     "lb2d_boundary_style": [_P, ctypes.c_char_p],
     "lb2d_rounding": [_P, ctypes.c_char_p, ctypes.c_uint64],
+    "lb2d_momentum_opening": [_P, ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
+                              ctypes.c_char_p, ctypes.c_double, ctypes.c_double],
     "lb2d_obstacle_rect": [_P, _I, _I, _I, _I],
     "lb2d_obstacle_circle": [_P, _I, _I, _D],
     "lb2d_obstacle_mask": [_P, _U8P],
@@ -178,6 +180,12 @@ class Lattice:
 
     def boundary_style(self, style):
         self._chk(_lib.lb2d_boundary_style(self._h, style.encode()))
+
+    def momentum_opening(self, wall, lo, hi, comp, kind, style, v=0.0, rho=1.0):
+        """inlet/outlet + inlet_momentum/outlet_momentum: nodes lo..hi of a
+        wall; style poiseuille, uniform, dirichlet or gradient."""
+        self._chk(_lib.lb2d_momentum_opening(self._h, wall.encode(), lo, hi, comp, kind.encode(), style.encode(),
+                                             float(v), float(rho)))
 
     def rounding(self, mode, seed=0):
         """'nearest' or 'stochastic' rounding of 16-bit storage."""

@@ -84,6 +84,25 @@ def contact_box_case(Gads, nx=201, ny=51, seed=5, G=-120.0, psi0=4.0, rho0=200.0
     return case
 
 
+def channel_flow_case(nx, ny, seed, wall="xlo", inlet=("poiseuille", 0.04, 1.0),
+                      outlet=("dirichlet", 0.0, 1.0), nd=4, tau=0.8):
+    """Through-flow channel: solid side walls, an inlet on `wall` and an
+    outlet on the opposite wall (inlet_momentum / outlet_momentum styles),
+    a few random discs inside."""
+    rng = np.random.default_rng(seed)
+    opp = {"xlo": "xhi", "xhi": "xlo", "ylo": "yhi", "yhi": "ylo"}[wall]
+    if wall in ("xlo", "xhi"):
+        rects = [(0, nx - 1, 0, 0), (0, nx - 1, ny - 1, ny - 1)]
+        lo, hi = 1, ny - 2
+    else:
+        rects = [(0, 0, 0, ny - 1), (nx - 1, nx - 1, 0, ny - 1)]
+        lo, hi = 1, nx - 2
+    circles = [(int(rng.integers(nx // 4, 3 * nx // 4)), int(rng.integers(ny // 4, 3 * ny // 4)),
+                float(rng.uniform(1.5, 3.5))) for _ in range(nd)]
+    mopen = [(wall, lo, hi, 0, "inlet", *inlet), (opp, lo, hi, 0, "outlet", *outlet)]
+    return dict(nx=nx, ny=ny, tau=tau, rects=rects, circles=circles, mopen=mopen)
+
+
 def build_oracle(case):
     o = Oracle(case["nx"], case["ny"])
     if "fluids" in case:
@@ -108,6 +127,8 @@ def build_oracle(case):
         o.obstacle_rect(*r)
     for c in case.get("circles", []):
         o.obstacle_circle(*c)
+    for op in case.get("mopen", []):
+        o.momentum_opening(*op)
     if case.get("mask") is not None:
         o.set_mask(np.maximum(o.get_mask(), case["mask"]))
     for comp, (rho, ux, uy) in case.get("fields", {}).items():
@@ -143,6 +164,8 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
         g.obstacle_rect(*r)
     for c in case.get("circles", []):
         g.obstacle_circle(*c)
+    for op in case.get("mopen", []):
+        g.momentum_opening(*op)
     if case.get("mask") is not None:
         g.obstacle_mask(case["mask"])
     if case.get("reaction") is not None:

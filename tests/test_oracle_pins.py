@@ -743,3 +743,98 @@ def test_surface_growth_more_dendritic_with_damkohler():
         assert o.budgets()["grown_nodes"] > 1000
         shape.append(_perimeter_per_root_area(o.get_mask()))
     assert all(a < b for a, b in zip(shape, shape[1:])), shape
+
+
+# ------------------------------------------------------ momentum openings
+
+def _opening_channel(wall_in, style_in, nx=30, ny=24, tau=0.8, v=0.04, rho_out=1.0, outlet_style="dirichlet"):
+    """Channel between two solid walls, flowing from wall_in to the opposite
+    wall: inlet with style_in, outlet with outlet_style."""
+    o = Oracle(nx, ny)
+    o.fluids(1, tau)
+    opp = {"xlo": "xhi", "xhi": "xlo", "ylo": "yhi", "yhi": "ylo"}[wall_in]
+    if wall_in in ("xlo", "xhi"):
+        o.obstacle_rect(0, nx - 1, 0, 0)
+        o.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+        lo, hi = 1, ny - 2
+    else:
+        o.obstacle_rect(0, 0, 0, ny - 1)
+        o.obstacle_rect(nx - 1, nx - 1, 0, ny - 1)
+        lo, hi = 1, nx - 2
+    o.momentum_opening(wall_in, lo, hi, 0, "inlet", style_in, v, 1.0)
+    o.momentum_opening(opp, lo, hi, 0, "outlet", outlet_style, 0.0, rho_out)
+    o.set_fields(0, 1.0)
+    return o, lo, hi, opp
+
+
+def _line(a, wall):
+    return {"xlo": a[:, 0], "xhi": a[:, -1], "ylo": a[0, :], "yhi": a[-1, :]}[wall]
+
+
+@pytest.mark.parametrize("wall", ["xlo", "xhi", "ylo", "yhi"])
+def test_velocity_inlet_and_pressure_outlet_hold_exactly(wall):
+    """Zou-He closure (inlet_momentum command, App. A): after any step the
+    inlet nodes move with exactly the prescribed velocity -- the paper's
+    parabolic profile v(y) = 4 v_max/L^2 [(L/2)^2 - ((2y - y0 - y1)/2)^2],
+    along the inward normal, zero tangential -- and the dirichlet outlet
+    nodes hold exactly the prescribed density."""
+    v, rho_out = 0.04, 0.995
+    o, lo, hi, opp = _opening_channel(wall, "poiseuille", v=v, rho_out=rho_out)
+    o.iteration(37)
+    rho, ux, uy = o.moments(0)
+    L = hi - lo + 1
+    k = np.arange(lo, hi + 1)
+    prof = 4 * v / L ** 2 * (L ** 2 / 4 - ((2 * k - lo - hi) / 2) ** 2)
+    normal = {"xlo": (1, 0), "xhi": (-1, 0), "ylo": (0, 1), "yhi": (0, -1)}[wall]
+    un = _line(ux, wall)[lo:hi + 1] * normal[0] + _line(uy, wall)[lo:hi + 1] * normal[1]
+    ut = _line(ux, wall)[lo:hi + 1] * normal[1] + _line(uy, wall)[lo:hi + 1] * normal[0]
+    np.testing.assert_allclose(un, prof, rtol=1e-12, atol=1e-16)
+    assert np.abs(ut).max() <= 1e-15
+    np.testing.assert_allclose(_line(rho, opp)[lo:hi + 1], rho_out, rtol=1e-14)
+    # the flow has come through: the density changed inside
+    assert np.abs(rho[rho != -11.0] - 1.0).max() > 1e-4
+
+
+@pytest.mark.parametrize("wall", ["xhi", "ylo"])
+def test_uniform_outlet_velocity_and_pressure_inlet(wall):
+    """The reverse pairing: dirichlet inlet (rho 1.004) and a uniform
+    velocity outlet (0.02 out of the domain)."""
+    nx, ny = 26, 20
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    inlet = {"xhi": "xlo", "ylo": "yhi"}[wall]
+    if wall == "xhi":
+        o.obstacle_rect(0, nx - 1, 0, 0)
+        o.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+        lo, hi = 1, ny - 2
+    else:
+        o.obstacle_rect(0, 0, 0, ny - 1)
+        o.obstacle_rect(nx - 1, nx - 1, 0, ny - 1)
+        lo, hi = 1, nx - 2
+    o.momentum_opening(inlet, lo, hi, 0, "inlet", "dirichlet", 0.0, 1.004)
+    o.momentum_opening(wall, lo, hi, 0, "outlet", "uniform", 0.02, 1.0)
+    o.set_fields(0, 1.0)
+    o.iteration(23)
+    rho, ux, uy = o.moments(0)
+    out = {"xhi": ux[lo:hi + 1, -1], "ylo": -uy[0, lo:hi + 1]}[wall]
+    np.testing.assert_allclose(out, 0.02, rtol=1e-12)
+    np.testing.assert_allclose(_line(rho, inlet)[lo:hi + 1], 1.004, rtol=1e-14)
+
+
+def test_gradient_outlet_extrapolates_populations():
+    """Gradient style: after the collision each population of the outlet
+    node equals 2 f(one node in) - f(two nodes in)."""
+    o, lo, hi, opp = _opening_channel("xlo", "uniform", v=0.03, outlet_style="gradient")
+    o.iteration(15)
+    f = o.get_f(0)
+    np.testing.assert_allclose(f[:, lo:hi + 1, -1], 2 * f[:, lo:hi + 1, -2] - f[:, lo:hi + 1, -3],
+                               rtol=1e-13, atol=1e-15)
+
+
+def test_openings_start_from_their_state():
+    """The opening nodes start at equilibrium with the opening's density and
+    velocity (the inlet/outlet commands override earlier settings)."""
+    o, lo, hi, opp = _opening_channel("ylo", "uniform", v=0.03, rho_out=0.99)
+    rho, ux, uy = o.moments(0)
+    np.testing.assert_allclose(uy[0, lo:hi + 1], 0.03, rtol=1e-13)
+    np.testing.assert_allclose(rho[-1, lo:hi + 1], 0.99, rtol=1e-14)
