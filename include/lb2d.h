@@ -108,12 +108,31 @@ int lb2d_fluids(lb2d_ctx *ctx, double tau1, double tau2, double alpha1,
  * Other q: LB2D_E_INVAL.  Needs the general (FP64/FP32) step. */
 int lb2d_solute(lb2d_ctx *ctx, double tau_s, int q);
 
-/* inlet_solute / outlet_solute on an x wall: wall "xlo" or "xhi", style
- * "dirichlet" (value = imposed C; the unknown populations share the
- * deficit C - C' in proportion to their weights) or "adiabatic" (zero
- * normal flux, each unknown copies its x-mirror).  Openings come in pairs
- * (one per x wall) and make the solute's x axis non-periodic; the fluid
- * stays periodic.  Needs solute. "flux" returns LB2D_E_UNSUPPORTED. */
+/* inlet/outlet + inlet_solute/outlet_solute commands: nodes lo..hi
+ * (inclusive, along the wall) of wall "xlo", "xhi", "ylo" or "yhi" are a
+ * solute opening; kind "inlet" or "outlet".  Styles:
+ *   "dirichlet": C = value after streaming; the unknown populations share
+ *                the deficit value - C' in proportion to their weights (a
+ *                single unknown takes all of it, as printed);
+ *   "adiabatic": zero normal flux, each unknown copies its mirror across
+ *                the wall (g3 = g1 on xhi);
+ *   "flux":      C = (v C0 + D C1)/(D + v) at an inlet and
+ *                (v C0 - D C1)/(v - D) at an outlet (App. B), C0 = value,
+ *                v > 0 the velocity of the injected solution (v != D at an
+ *                outlet, where the rule is singular), D the solute
+ *                diffusivity, C1 the concentration of the next node inward
+ *                at the previous time level; all populations of the node
+ *                are set to their equilibrium at C.
+ * An opening on a wall makes the solute non-periodic along that axis; the
+ * parts of the axis' two walls outside openings are impermeable to the
+ * solute (bounce-back).  The fluid stays periodic.  At most 8 openings,
+ * no node on two.  Needs solute; before bind. */
+int lb2d_solute_opening_range(lb2d_ctx *ctx, const char *wall, int lo, int hi,
+                              const char *kind, const char *style, double value,
+                              double v);
+/* The whole x wall "xlo" (inlet) or "xhi" (outlet) as a "dirichlet" or
+ * "adiabatic" solute opening (lb2d_solute_opening_range with lo = 0,
+ * hi = ny - 1). */
 int lb2d_solute_opening(lb2d_ctx *ctx, const char *wall, const char *style,
                         double value);
 

@@ -112,9 +112,15 @@ typedef struct orc {
     double psi0_a, rho0_a;       /* psi of adhesiveforce */
     int q;                       /* solute lattice: 0 = off, 4 or 9 */
     double tau_s;
-    int open_style[2];           /* solute openings on xlo, xhi: 0 none,
-                                    1 dirichlet, 2 adiabatic */
-    double open_value[2];
+    int nsopen;                  /* solute openings (inlet_solute/outlet_solute) */
+    struct {
+        int wall;                /* 0 xlo, 1 xhi, 2 ylo, 3 yhi */
+        int lo, hi;              /* node range along the wall */
+        int outlet;              /* 0 inlet, 1 outlet */
+        int style;               /* 1 dirichlet, 2 adiabatic, 3 flux */
+        double value;            /* dirichlet: imposed C; flux: C0 */
+        double v;                /* flux: velocity of the injected solution */
+    } sopen[16];
     int reaction;
     double kr, Cs, b0, bmax;
     uint64_t seed;
@@ -271,14 +277,33 @@ int orc_solute(orc *o, int q, double tau_s) {
     return 0;
 }
 
-/* inlet_solute / outlet_solute on the x walls: wall 0 = xlo, 1 = xhi;
- * style 1 = dirichlet (value = imposed C), 2 = adiabatic. An open x wall
- * makes the x axis non-periodic for the solute only. */
+/* inlet_solute / outlet_solute: nodes lo..hi of wall 0 xlo, 1 xhi, 2 ylo,
+ * 3 yhi are a solute opening; style 1 dirichlet (value = imposed C),
+ * 2 adiabatic, 3 flux (value = C0 of the injected solution, v its
+ * velocity).  An opening on a wall makes the solute non-periodic across
+ * that axis; nodes of the two walls of the axis outside the openings are
+ * then impermeable to the solute (bounce-back).  The fluid stays periodic. */
+int orc_solute_opening_range(orc *o, int wall, int lo, int hi, int outlet, int style, double value,
+                             double v) {
+    if (o->nsopen >= 16 || wall < 0 || wall > 3 || style < 1 || style > 3) return -1;
+    int len = wall < 2 ? o->ny : o->nx;
+    if (lo < 0 || hi < lo || hi >= len) return -1;
+    o->sopen[o->nsopen].wall = wall;
+    o->sopen[o->nsopen].lo = lo;
+    o->sopen[o->nsopen].hi = hi;
+    o->sopen[o->nsopen].outlet = outlet ? 1 : 0;
+    o->sopen[o->nsopen].style = style;
+    o->sopen[o->nsopen].value = value;
+    o->sopen[o->nsopen].v = v;
+    o->nsopen++;
+    return 0;
+}
+
+/* The whole x wall (wall 0 xlo, 1 xhi) as a dirichlet (1) or adiabatic (2)
+ * solute opening. */
 int orc_solute_opening(orc *o, int wall, int style, double value) {
     if (wall < 0 || wall > 1 || style < 1 || style > 2) return -1;
-    o->open_style[wall] = style;
-    o->open_value[wall] = value;
-    return 0;
+    return orc_solute_opening_range(o, wall, 0, o->ny - 1, wall, style, value, 0.0);
 }
 
 /* surface_reaction(kr, Cs, "growth", b0, bmax) plus the seed of the growth
@@ -539,14 +564,41 @@ int orc_pick(uint64_t h, int m) {
 
 /* ------------------------------------------------------------------ step */
 
-/* Solute openings come in pairs: with openings on the x walls the solute's
- * x axis is not periodic (the fluid stays periodic). */
-static int solute_x_periodic(const orc *o) {
-    return !(o->open_style[0] || o->open_style[1]);
+/* The solute is periodic along axis 0 (x) / 1 (y) unless a solute opening
+ * lies on one of that axis' walls. */
+static int solute_periodic(const orc *o, int axis) {
+    for (int k = 0; k < o->nsopen; ++k)
+        if ((o->sopen[k].wall < 2) == (axis == 0)) return 0;
+    return 1;
 }
 
-static int solute_x_open(const orc *o, int x) {
-    return !solute_x_periodic(o) && (x == 0 || x == o->nx - 1);
+/* Node (x,y) lies on a wall of a non-periodic solute axis. */
+static int solute_on_closed_wall(const orc *o, int x, int y) {
+    return (!solute_periodic(o, 0) && (x == 0 || x == o->nx - 1)) ||
+           (!solute_periodic(o, 1) && (y == 0 || y == o->ny - 1));
+}
+
+/* Index of the solute opening holding node (x,y) whose wall the pull along
+ * direction i crosses, or -1. */
+static int solute_opening_at(const orc *o, int x, int y, int i) {
+    for (int k = 0; k < o->nsopen; ++k) {
+        int w = o->sopen[k].wall, pos = w < 2 ? y : x;
+        int on = (w == 0 && x == 0) || (w == 1 && x == o->nx - 1) || (w == 2 && y == 0) ||
+                 (w == 3 && y == o->ny - 1);
+        if (!on || pos < o->sopen[k].lo || pos > o->sopen[k].hi) continue;
+        int sx = x - EX9[i], sy = y - EY9[i];
+        int cross = (w == 0 && sx < 0) || (w == 1 && sx >= o->nx) || (w == 2 && sy < 0) || (w == 3 && sy >= o->ny);
+        if (cross) return k;
+    }
+    return -1;
+}
+
+/* Index of the velocity mirrored across a wall of axis 0 (x) or 1 (y). */
+static int mirror_axis(int i, int axis) {
+    for (int k = 0; k < 9; ++k)
+        if (axis == 0 ? (EX9[k] == -EX9[i] && EY9[k] == EY9[i]) : (EX9[k] == EX9[i] && EY9[k] == -EY9[i]))
+            return k;
+    return -1;
 }
 
 /* Source of the pull along direction i into node (x,y) on the fluid lattice
@@ -650,12 +702,12 @@ static void init_b(orc *o) {
 static int growth_candidates(const orc *o, int x, int y, long *cand) {
     int m = 0;
     for (int i = 1; i <= 4; ++i) {
-        int cx = x + EX9[i], cy = wrap(y + EY9[i], o->ny);
-        if (cx < 0 || cx >= o->nx) {
-            if (o->q && !solute_x_periodic(o)) continue;
-            cx = wrap(cx, o->nx);
-        }
-        if (o->q && solute_x_open(o, cx)) continue;
+        int cx = x + EX9[i], cy = y + EY9[i];
+        if ((cx < 0 || cx >= o->nx) && !solute_periodic(o, 0)) continue;
+        if ((cy < 0 || cy >= o->ny) && !solute_periodic(o, 1)) continue;
+        cx = wrap(cx, o->nx);
+        cy = wrap(cy, o->ny);
+        if (solute_on_closed_wall(o, cx, cy)) continue;
         long c = idx(o, cx, cy);
         if (!o->mask[c]) cand[m++] = c;
     }
@@ -771,10 +823,15 @@ static void one_step(orc *o) {
     }
 
     /* 6. Solute streaming (pull) with bounce-back on solids (or the reactive
-     * link rule when the surface reaction is on) and the opening rules on
-     * open x walls.  o->g still holds the post-collision values of the
-     * previous step. */
+     * link rule when the surface reaction is on), bounce-back on the closed
+     * walls of a non-periodic axis and the opening rules at opening nodes.
+     * o->g still holds the post-collision values of the previous step. */
     const int q = o->q;
+    const int xper = solute_periodic(o, 0), yper = solute_periodic(o, 1);
+    const double Dsol = solute_cs2(q) * (o->tau_s - 0.5);
+    /* flux openings set the whole node to equilibrium at C (after the
+     * solvent velocity is known): C per node, or NAN */
+    double *Cflux = (double *)malloc(sizeof(double) * n);
     /* opening fluxes are summed per row, then over rows in order, so the
      * result does not depend on how rows are shared among threads */
     double *in_row = (double *)calloc(ny, sizeof(double));
@@ -783,20 +840,27 @@ static void one_step(orc *o) {
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             long s = idx(o, x, y);
+            Cflux[s] = NAN;
             for (int i = 0; i < 9; ++i) o->gtmp[i * n + s] = 0.0;
             if (o->mask[s]) continue;
             int unknown[9] = {0};
-            int any_unknown = 0;
+            int kopen = -1;
             for (int i = 0; i < 9; ++i) {
                 if (!solute_has(q, i)) continue;
-                int sxr = x - EX9[i];
-                if ((sxr < 0 || sxr >= nx) && !solute_x_periodic(o)) {
-                    unknown[i] = 1;
-                    any_unknown = 1;
+                int sxr = x - EX9[i], syr = y - EY9[i];
+                int cross = ((sxr < 0 || sxr >= nx) && !xper) || ((syr < 0 || syr >= ny) && !yper);
+                double g_out = o->g[opposite(i) * n + s];
+                if (cross) {
+                    int k = solute_opening_at(o, x, y, i);
+                    if (k >= 0) {
+                        unknown[i] = 1;
+                        kopen = k;
+                    } else {
+                        o->gtmp[i * n + s] = g_out; /* closed wall: bounce-back */
+                    }
                     continue;
                 }
-                long src = idx(o, wrap(sxr, nx), wrap(y - EY9[i], ny));
-                double g_out = o->g[opposite(i) * n + s];
+                long src = idx(o, wrap(sxr, nx), wrap(syr, ny));
                 double gi;
                 if (o->mask[src]) {
                     gi = g_out;
@@ -807,46 +871,61 @@ static void one_step(orc *o) {
                 }
                 o->gtmp[i * n + s] = gi;
             }
-            if (any_unknown) {
-                int side = (x == 0) ? 0 : 1;
-                if (o->open_style[side] == 1) {
+            if (kopen >= 0) {
+                double known = 0.0, wu = 0.0;
+                for (int i = 0; i < 9; ++i) {
+                    if (!solute_has(q, i)) continue;
+                    if (unknown[i])
+                        wu += solute_w(q, i);
+                    else
+                        known += o->gtmp[i * n + s];
+                }
+                int st = o->sopen[kopen].style, w = o->sopen[kopen].wall;
+                if (st == 1) {
                     /* dirichlet: C = Cbar after streaming; the deficit
                      * Cbar - C' (C' = sum of the known populations) is shared
                      * by the unknowns in proportion to their weights (a single
                      * unknown takes all of it, as in the command's rule). */
-                    double known = 0.0, wu = 0.0;
-                    for (int i = 0; i < 9; ++i) {
-                        if (!solute_has(q, i)) continue;
-                        if (unknown[i])
-                            wu += solute_w(q, i);
-                        else
-                            known += o->gtmp[i * n + s];
-                    }
-                    double deficit = o->open_value[side] - known;
+                    double deficit = o->sopen[kopen].value - known;
                     for (int i = 0; i < 9; ++i)
                         if (unknown[i]) {
                             double gi = solute_w(q, i) / wu * deficit;
                             o->gtmp[i * n + s] = gi;
                             in_row[y] += gi;
                         }
-                } else {
+                } else if (st == 2) {
                     /* adiabatic: zero normal flux; each unknown takes the
-                     * value of its x-mirror (g3 = g1 on xhi). */
+                     * value of its mirror across the wall (g3 = g1 on xhi). */
                     for (int i = 0; i < 9; ++i)
                         if (unknown[i]) {
-                            double gi = o->gtmp[mirror_x(i) * n + s];
+                            double gi = o->gtmp[mirror_axis(i, w < 2 ? 0 : 1) * n + s];
                             o->gtmp[i * n + s] = gi;
                             in_row[y] += gi;
                         }
+                } else {
+                    /* flux: C = (v C0 + D C1)/(D + v) at an inlet,
+                     * (v C0 - D C1)/(v - D) at an outlet (App. B), C1 the
+                     * concentration of the next node inward (previous time
+                     * level; 0 if that node is solid); all populations go to
+                     * equilibrium at C. */
+                    int nxw = w == 0 ? 1 : w == 1 ? -1 : 0, nyw = w == 2 ? 1 : w == 3 ? -1 : 0;
+                    long s1 = idx(o, x + nxw, y + nyw);
+                    double C1 = 0.0;
+                    if (!o->mask[s1])
+                        for (int i = 0; i < 9; ++i) C1 += o->g[i * n + s1];
+                    double v = o->sopen[kopen].v, C0 = o->sopen[kopen].value;
+                    double C = o->sopen[kopen].outlet ? (v * C0 - Dsol * C1) / (v - Dsol)
+                                                      : (v * C0 + Dsol * C1) / (Dsol + v);
+                    Cflux[s] = C;
+                    in_row[y] += C - known;
                 }
             }
-            /* Populations of the previous step that left through an open
-             * x wall. */
+            /* Populations of the previous step that left through an opening. */
             for (int i = 0; i < 9; ++i) {
                 if (!solute_has(q, i)) continue;
-                int dx = x + EX9[i];
-                if ((dx < 0 || dx >= nx) && !solute_x_periodic(o))
-                    out_row[y] += o->g[i * n + s];
+                int dx = x + EX9[i], dy = y + EY9[i];
+                int cross = ((dx < 0 || dx >= nx) && !xper) || ((dy < 0 || dy >= ny) && !yper);
+                if (cross && solute_opening_at(o, x, y, opposite(i)) >= 0) out_row[y] += o->g[i * n + s];
             }
         }
     for (int y = 0; y < ny; ++y) {
@@ -868,12 +947,10 @@ static void one_step(orc *o) {
                 double dep = 0.0;
                 for (int i = 1; i < 9; ++i) {
                     if (!solute_has(q, i)) continue;
-                    int fx = x + EX9[i];
-                    if (fx < 0 || fx >= nx) {
-                        if (!solute_x_periodic(o)) continue;
-                        fx = wrap(fx, nx);
-                    }
-                    long fl = idx(o, fx, wrap(y + EY9[i], ny));
+                    int fx = x + EX9[i], fy = y + EY9[i];
+                    if ((fx < 0 || fx >= nx) && !xper) continue;
+                    if ((fy < 0 || fy >= ny) && !yper) continue;
+                    long fl = idx(o, wrap(fx, nx), wrap(fy, ny));
                     if (o->mask[fl]) continue;
                     double g_out = o->g[opposite(i) * n + fl];
                     dep += orc_reactive_link(q, i, o->kr, o->Cs, g_out, NULL);
@@ -891,18 +968,21 @@ static void one_step(orc *o) {
         }
         double C = 0.0;
         for (int i = 0; i < 9; ++i) C += o->gtmp[i * n + s];
+        const int flux = !isnan(Cflux[s]);
+        if (flux) C = Cflux[s];
         for (int i = 0; i < 9; ++i) {
             if (!solute_has(q, i)) {
                 o->g[i * n + s] = 0.0;
                 continue;
             }
+            double ge = geq(q, i, C, usx[s], usy[s]);
             double gi = o->gtmp[i * n + s];
-            o->g[i * n + s] =
-                gi - (gi - geq(q, i, C, usx[s], usy[s])) / o->tau_s;
+            o->g[i * n + s] = flux ? ge : gi - (gi - ge) / o->tau_s;
         }
     }
     free(usx);
     free(usy);
+    free(Cflux);
 
     /* 9. Surface growth: every solid node whose deposit exceeds bmax turns
      * one of its direct fluid neighbours into solid, each candidate equally
@@ -949,8 +1029,6 @@ static void one_step(orc *o) {
 }
 
 int orc_step(orc *o, long nsteps) {
-    if (o->q && ((o->open_style[0] != 0) != (o->open_style[1] != 0)))
-        return -1; /* an opening on one x wall needs one on the other */
     for (long k = 0; k < nsteps; ++k) one_step(o);
     return 0;
 }

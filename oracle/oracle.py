@@ -70,6 +70,7 @@ def _load():
         "orc_adhesiveforce_psi": (I, [P, D, D, D]),
         "orc_solute": (I, [P, I, D]),
         "orc_solute_opening": (I, [P, I, I, D]),
+        "orc_solute_opening_range": (I, [P, I, I, I, I, I, D, D]),
         "orc_surface_reaction": (I, [P, D, D, D, D, ctypes.c_uint64]),
         "orc_obstacle_circle": (I, [P, I, I, D]),
         "orc_obstacle_rect": (I, [P, I, I, I, I]),
@@ -212,6 +213,15 @@ class Oracle:
     def solute(self, tau_s, q=9):
         self._chk(self.lib.orc_solute(self.h, q, tau_s), "solute")
         self.q = q
+
+    def solute_opening_range(self, wall, lo, hi, kind, style, value=0.0, v=0.0):
+        """inlet_solute / outlet_solute on nodes lo..hi of wall xlo/xhi/
+        ylo/yhi; style dirichlet (value = C), adiabatic, flux (value = C0,
+        v = velocity of the injected solution)."""
+        w = {"xlo": 0, "xhi": 1, "ylo": 2, "yhi": 3}[wall]
+        st = {"dirichlet": 1, "adiabatic": 2, "flux": 3}[style]
+        self._chk(self.lib.orc_solute_opening_range(self.h, w, lo, hi, 1 if kind == "outlet" else 0, st,
+                                                    value, v), "solute_opening")
 
     def solute_opening(self, wall, style, value=0.0):
         self._chk(self.lib.orc_solute_opening(self.h, WALL[wall], STYLE[style], value),

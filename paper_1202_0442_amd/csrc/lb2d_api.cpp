@@ -55,8 +55,7 @@ struct lb2d_ctx {
     double Gads[2] = {0.0, 0.0};
     int q = 0;
     double tau_s = 1.0;
-    int open_style[2] = {0, 0};
-    double open_value[2] = {0.0, 0.0};
+    std::vector<SoluteOpen> sopens;  // solute openings
     bool reaction = false;
     double kr = 0, Cs = 0, b0 = 0, bmax = 0;
     uint64_t seed = 0;
@@ -259,11 +258,14 @@ FullParams full_params(const lb2d_ctx *c) {
     p.ads_psi = (c->ncomp == 1 && c->ads[0]) ? 1 : 0;
     p.psi = (c->ncomp == 1 && c->inter) ? 1 : 0;
     k8.omega_s = c->q ? 1.0 / c->tau_s : 0.0;
-    p.solute_xper = (c->open_style[0] || c->open_style[1]) ? 0 : 1;
-    for (int k = 0; k < 2; ++k) {
-        p.open_style[k] = c->open_style[k];
-        k8.open_value[k] = c->open_value[k];
+    p.sxper = p.syper = 1;
+    p.nsopen = (int)c->sopens.size();
+    for (int k = 0; k < p.nsopen; ++k) {
+        p.sopen[k] = c->sopens[k];
+        if (c->sopens[k].wall < 2) p.sxper = 0;
+        else p.syper = 0;
     }
+    k8.Dsol = c->q ? (c->q == 4 ? 0.5 : 1.0 / 3.0) * (c->tau_s - 0.5) : 0.0;
     k8.Cs = c->Cs;
     p.nopen = (int)c->opens.size();
     for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
@@ -290,11 +292,11 @@ FullParams full_params(const lb2d_ctx *c) {
             k4.accel[k][d] = (float)k8.accel[k][d];
         }
         k4.Gads[k] = (float)k8.Gads[k];
-        k4.open_value[k] = (float)k8.open_value[k];
         k4.klink[k] = (float)k8.klink[k];
         k4.klink_inv[k] = (float)k8.klink_inv[k];
     }
     k4.G = (float)k8.G;
+    k4.Dsol = (float)k8.Dsol;
     k4.psi0 = (float)k8.psi0;
     k4.rho0 = (float)k8.rho0;
     k4.psi0a = (float)k8.psi0a;
@@ -530,26 +532,67 @@ int lb2d_solute(lb2d_ctx *c, double tau_s, int q) {
     return LB2D_OK;
 }
 
-int lb2d_solute_opening(lb2d_ctx *c, const char *wall, const char *style, double value) {
+// Node range overlap of two openings on the box edge: same wall and
+// overlapping ranges, or perpendicular walls that both hold their corner.
+static bool openings_share_node(const lb2d_ctx *c, int w1, int lo1, int hi1, int w2, int lo2, int hi2) {
+    if (w1 == w2) return lo1 <= hi2 && lo2 <= hi1;
+    if ((w1 < 2) == (w2 < 2)) return false;  // opposite walls
+    auto corner_in = [&](int w, int a, int b, int other) {
+        const int k = (w < 2) ? (other == 2 ? 0 : c->ny - 1) : (other == 0 ? 0 : c->nx - 1);
+        return a <= k && k <= b;
+    };
+    return corner_in(w1, lo1, hi1, w2) && corner_in(w2, lo2, hi2, w1);
+}
+
+int lb2d_solute_opening_range(lb2d_ctx *c, const char *wall, int lo, int hi, const char *kind, const char *style,
+                              double value, double v) {
     int rc = pre_command(c);
     if (rc) return rc;
     if (!c->have_solute) return c->fail(LB2D_E_ORDER, "solute openings need the solute command first");
-    if (!wall || !style) return c->fail(LB2D_E_INVAL, "null wall or style");
-    int w;
-    if (!std::strcmp(wall, "xlo")) w = 0;
-    else if (!std::strcmp(wall, "xhi")) w = 1;
-    else if (!std::strcmp(wall, "ylo") || !std::strcmp(wall, "yhi"))
-        return c->fail(LB2D_E_UNSUPPORTED, "solute openings on y walls are not implemented");
-    else return c->fail(LB2D_E_INVAL, "wall must be xlo or xhi");
-    int st;
-    if (!std::strcmp(style, "dirichlet")) st = 1;
-    else if (!std::strcmp(style, "adiabatic")) st = 2;
-    else if (!std::strcmp(style, "flux")) return c->fail(LB2D_E_UNSUPPORTED, "flux openings are not implemented");
-    else return c->fail(LB2D_E_INVAL, "style must be dirichlet or adiabatic");
-    if (!std::isfinite(value)) return c->fail(LB2D_E_INVAL, "opening value must be finite");
-    c->open_style[w] = st;
-    c->open_value[w] = value;
+    if (!wall || !style || !kind) return c->fail(LB2D_E_INVAL, "null wall, kind or style");
+    SoluteOpen o{};
+    if (!std::strcmp(wall, "xlo")) o.wall = 0;
+    else if (!std::strcmp(wall, "xhi")) o.wall = 1;
+    else if (!std::strcmp(wall, "ylo")) o.wall = 2;
+    else if (!std::strcmp(wall, "yhi")) o.wall = 3;
+    else return c->fail(LB2D_E_INVAL, "wall must be xlo, xhi, ylo or yhi");
+    if (!std::strcmp(kind, "inlet")) o.outlet = 0;
+    else if (!std::strcmp(kind, "outlet")) o.outlet = 1;
+    else return c->fail(LB2D_E_INVAL, "kind must be inlet or outlet");
+    if (!std::strcmp(style, "dirichlet")) o.style = 1;
+    else if (!std::strcmp(style, "adiabatic")) o.style = 2;
+    else if (!std::strcmp(style, "flux")) o.style = 3;
+    else return c->fail(LB2D_E_INVAL, "style must be dirichlet, adiabatic or flux");
+    const int len = o.wall < 2 ? c->ny : c->nx;
+    if (lo < 0 || hi < lo || hi >= len) return c->fail(LB2D_E_INVAL, "opening range %d..%d outside 0..%d", lo, hi, len - 1);
+    if (!std::isfinite(value) || !std::isfinite(v)) return c->fail(LB2D_E_INVAL, "opening values must be finite");
+    if (o.style == 3 && !(v > 0.0)) return c->fail(LB2D_E_INVAL, "flux openings need v > 0");
+    if (o.style == 3 && o.outlet) {
+        // the outlet rule C = (v C0 - D C1)/(v - D) is singular at v = D
+        const double D = (c->q == 4 ? 0.5 : 1.0 / 3.0) * (c->tau_s - 0.5);
+        if (std::fabs(v - D) <= 1e-9 * std::max(v, D))
+            return c->fail(LB2D_E_INVAL, "flux outlet with v equal to the diffusivity D = %g", D);
+    }
+    if ((int)c->sopens.size() >= kMaxOpen) return c->fail(LB2D_E_SIZE, "at most %d solute openings", kMaxOpen);
+    for (const auto &q : c->sopens)
+        if (openings_share_node(c, q.wall, q.lo, q.hi, o.wall, lo, hi))
+            return c->fail(LB2D_E_INVAL, "two solute openings share a node");
+    o.lo = lo;
+    o.hi = hi;
+    o.value = value;
+    o.v = v;
+    c->sopens.push_back(o);
     return LB2D_OK;
+}
+
+int lb2d_solute_opening(lb2d_ctx *c, const char *wall, const char *style, double value) {
+    if (!c) return LB2D_E_INVAL;
+    if (!wall || !style) return c->fail(LB2D_E_INVAL, "null wall or style");
+    if (std::strcmp(wall, "xlo") && std::strcmp(wall, "xhi")) return c->fail(LB2D_E_INVAL, "wall must be xlo or xhi");
+    if (!std::strcmp(style, "flux"))
+        return c->fail(LB2D_E_INVAL, "flux openings need a velocity: use lb2d_solute_opening_range");
+    return lb2d_solute_opening_range(c, wall, 0, c->have_lattice ? c->ny - 1 : 0,
+                                     std::strcmp(wall, "xlo") ? "outlet" : "inlet", style, value, 0.0);
 }
 
 int lb2d_boundary_style(lb2d_ctx *c, const char *style) {
@@ -590,22 +633,10 @@ int lb2d_momentum_opening(lb2d_ctx *c, const char *wall, int lo, int hi, int com
     if (!(rho > 0.0) || !std::isfinite(rho)) return c->fail(LB2D_E_INVAL, "rho must be positive");
     if (!std::isfinite(v) || std::fabs(v) >= 1.0) return c->fail(LB2D_E_INVAL, "|v| must be below 1");
     if ((int)c->opens.size() >= kMaxOpen) return c->fail(LB2D_E_SIZE, "at most %d openings", kMaxOpen);
-    // no node may belong to two openings of one component: same wall and
-    // overlapping ranges, or perpendicular walls that both hold their corner
-    auto corner_in = [&](int w, int a, int b, int other) {
-        // coordinate along wall w of the corner it shares with wall `other`
-        const int k = (w < 2) ? (other == 2 ? 0 : c->ny - 1) : (other == 0 ? 0 : c->nx - 1);
-        return a <= k && k <= b;
-    };
-    for (const auto &q : c->opens) {
-        if (q.comp != comp) continue;
-        if (q.wall == o.wall) {
-            if (lo <= q.hi && q.lo <= hi) return c->fail(LB2D_E_INVAL, "openings overlap on one wall");
-        } else if ((q.wall < 2) != (o.wall < 2)) {
-            if (corner_in(o.wall, lo, hi, q.wall) && corner_in(q.wall, q.lo, q.hi, o.wall))
-                return c->fail(LB2D_E_INVAL, "two openings share a corner node");
-        }
-    }
+    // no node may belong to two openings of one component
+    for (const auto &q : c->opens)
+        if (q.comp == comp && openings_share_node(c, q.wall, q.lo, q.hi, o.wall, lo, hi))
+            return c->fail(LB2D_E_INVAL, "two momentum openings of one component share a node");
     o.lo = lo;
     o.hi = hi;
     o.comp = comp;
@@ -784,8 +815,6 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     if (!c->storage_chosen) return c->fail(LB2D_E_ORDER, "call lb2d_workspace_bytes before lb2d_bind");
     if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0)
         return c->fail(LB2D_E_INVAL, "workspace must be a 256-byte aligned device pointer");
-    if ((c->open_style[0] != 0) != (c->open_style[1] != 0))
-        return c->fail(LB2D_E_INVAL, "solute openings come in pairs (xlo and xhi)");
     const Layout L = make_layout(c, c->storage);
     if (bytes < L.total) return c->fail(LB2D_E_SIZE, "workspace of %zu bytes, %zu needed", bytes, L.total);
     if (c->sr && c->storage != kF16 && c->storage != kBF16)

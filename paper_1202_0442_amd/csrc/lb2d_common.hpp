@@ -60,7 +60,7 @@ struct StepCoef {
     R psi0, rho0;          // one component: interforce psi = psi0 exp(-rho0/rho)
     R psi0a, rho0a;        // one component: adhesiveforce psi
     R omega_s;             // 1 / tau_s
-    R open_value[2];       // xlo, xhi opening values
+    R Dsol;                // solute diffusivity c_s^2 (tau_s - 1/2)
     R Cs;                  // saturation concentration
     R klink[2];            // per-link reaction rate k_i: axial, diagonal links
     R klink_inv[2];        // 1 / (2 w_i + k_i): axial, diagonal links
@@ -77,6 +77,18 @@ struct OpenSpec {
     double v, rho;        // speed (v_max for poiseuille) and density
 };
 constexpr int kMaxOpen = 8;
+
+// One solute opening (inlet_solute / outlet_solute commands): nodes lo..hi
+// of a wall.  An opening makes the solute non-periodic across its axis; the
+// rest of that axis' two walls is impermeable to the solute.
+struct SoluteOpen {
+    int wall;             // 0 xlo, 1 xhi, 2 ylo, 3 yhi
+    int lo, hi;           // node range along the wall
+    int outlet;           // 0 inlet, 1 outlet
+    int style;            // 1 dirichlet, 2 adiabatic, 3 flux
+    double value;         // dirichlet: imposed C; flux: C0 of the injected solution
+    double v;             // flux: velocity of the injected solution
+};
 
 // Everything the general fused step needs: up to two fluid components with
 // Shan-Chen cohesion / adhesion and an optional solute (D2Q9 or D2Q4) with
@@ -102,8 +114,9 @@ struct FullParams {
     int ads_psi;          // one component: adhesion acts through psi(rho)
     int sq;               // solute lattice: 9 (D2Q9, plane i = direction i) or
                           // 4 (D2Q4, plane i-1 = direction i = 1..4); 0 = none
-    int solute_xper;      // 1: solute periodic in x
-    int open_style[2];    // xlo, xhi: 1 dirichlet, 2 adiabatic
+    int sxper, syper;     // 1: solute periodic along x / y (no opening on that axis' walls)
+    int nsopen;           // solute openings
+    SoluteOpen sopen[kMaxOpen];
     double b0, bmax;
     unsigned long long seed;
     int nblk_main;        // tally slots of the step kernel (one per wavefront)

@@ -577,6 +577,33 @@ __device__ __forceinline__ void apply_openings(const FullParams &p, int c, int x
     }
 }
 
+// Solute openings.  Node (cx, cy) lies outside the box across a wall of a
+// non-periodic solute axis.
+__device__ __forceinline__ bool across_closed(const FullParams &p, int cx, int cy) {
+    return (!p.sxper && (cx < 0 || cx >= p.nx)) || (!p.syper && (cy < 0 || cy >= p.ny));
+}
+// Population i of a node on wall w enters the domain across that wall
+// (its source lies outside): e_i . n > 0, n the inward normal.
+template <int SQ>
+__device__ __forceinline__ bool enters_across(int w, int i) {
+    return shas<SQ>(i) && (w == 0 ? ex(i) > 0 : w == 1 ? ex(i) < 0 : w == 2 ? ey(i) > 0 : ey(i) < 0);
+}
+// y-mirror (ey -> -ey): 2<->4, 5<->8, 6<->7.
+__host__ __device__ constexpr int miry(int i) {
+    return i == 2 ? 4 : i == 4 ? 2 : i == 5 ? 8 : i == 8 ? 5 : i == 6 ? 7 : i == 7 ? 6 : i;
+}
+// The solute opening that holds node (x, y), or -1.
+__device__ __forceinline__ int find_solute_opening(const FullParams &p, int x, int y) {
+    int k = -1;
+    for (int j = 0; j < p.nsopen; ++j) {
+        const SoluteOpen &o = p.sopen[j];
+        const int pos = o.wall < 2 ? y : x;
+        const bool on = o.wall == 0 ? x == 0 : o.wall == 1 ? x == p.nx - 1 : o.wall == 2 ? y == 0 : y == p.ny - 1;
+        if (on && pos >= o.lo && pos <= o.hi) k = j;
+    }
+    return k;
+}
+
 // Halo slot j of a TX x TY tile's density ring -> position in the
 // (TX+2) x (TY+2) tile: bottom row, top row, then left/right columns.
 template <int TX, int TY>
@@ -776,64 +803,86 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         unk[i] = false;
     }
     double tal[4] = {0.0, 0.0, 0.0, 0.0};  // inflow, outflow, consumed deposit
+    bool flux = false;   // node of a flux opening: all populations to g_eq(Cf)
+    R Cf = R(0);
     if constexpr (SOL) {
         const S *__restrict__ gin = (const S *)p.g[parity];
-        bool any_unk = false;
-        // lanes on an open x wall (only in the first and last tile columns)
-        const bool edge = !p.solute_xper && (x == 0 || x == nx - 1);
+        // lanes on a wall of a non-periodic solute axis (edge tiles only)
+        const bool edge = valid && fluid &&
+                          ((!p.sxper && (x == 0 || x == nx - 1)) || (!p.syper && (y == 0 || y == ny - 1)));
+        const int kop = edge ? find_solute_opening(p, x, y) : -1;
+        const int kw = kop >= 0 ? p.sopen[kop].wall : -1;
         if (valid && fluid) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 if (!shas<SQ>(i)) continue;
-                const int sxr = x - ex(i);
-                const bool open = edge && (sxr < 0 || sxr >= nx);
-                unk[i] = open;
-                any_unk |= open;
-                // half-way wall: own population of the opposite direction
-                const bool wall = (lk >> opp(i)) & 1u;
-                const O a = wall ? (O)spl<SQ>(opp(i)) * pl + s : (O)spl<SQ>(i) * pl + src[i];
+                // a pull across a closed wall bounces back; across the wall
+                // of this node's opening the population is unknown
+                const int sxr = x - ex(i), syr = y - ey(i);
+                const bool cross = edge && ((!p.sxper && (sxr < 0 || sxr >= nx)) || (!p.syper && (syr < 0 || syr >= ny)));
+                unk[i] = kw >= 0 && enters_across<SQ>(kw, i);
+                const bool solid_src = ((lk >> opp(i)) & 1u) && !cross;
+                const bool bb = solid_src || cross;
+                const O a = bb ? (O)spl<SQ>(opp(i)) * pl + s : (O)spl<SQ>(i) * pl + src[i];
                 R v = ldb(gin, a, i);
                 if constexpr (REACT) {
                     R gi;
                     reactive_link<SQ, R>(i, q, v, gi);
-                    v = wall ? gi : v;
+                    v = solid_src ? gi : v;
                 }
                 g[i] = v;
             }
         }
-        if (any_unk) {
-            const int side = (x == 0) ? 0 : 1;
-            if (p.open_style[side] == 1) {
-                R known = R(0), wu = R(0);
+        if (kop >= 0) {
+            const SoluteOpen &o = p.sopen[kop];
+            R known = R(0), wu = R(0);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    if (!shas<SQ>(i)) continue;
-                    if (unk[i]) wu += swgt<SQ, R>(i);
-                    else known += g[i];
-                }
-                const R deficit = (q.open_value[side] - known) * rcp(wu);
+            for (int i = 0; i < 9; ++i) {
+                if (!shas<SQ>(i)) continue;
+                if (unk[i]) wu += swgt<SQ, R>(i);
+                else known += g[i];
+            }
+            if (o.style == 1) {
+                // dirichlet: the unknowns share Cbar - C' by weight
+                const R deficit = (R(o.value) - known) * rcp(wu);
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     if (unk[i]) {
                         g[i] = swgt<SQ, R>(i) * deficit;
                         tal[0] += (double)g[i];
                     }
-            } else {
+            } else if (o.style == 2) {
+                // adiabatic: each unknown copies its mirror across the wall
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
                     if (unk[i]) {
-                        g[i] = g[mirx(i)];
+                        g[i] = kw < 2 ? g[mirx(i)] : g[miry(i)];
                         tal[0] += (double)g[i];
                     }
-            }
-        }
-        if (valid && fluid && !p.solute_xper && (x == 0 || x == nx - 1)) {
+            } else {
+                // flux (App. B): C = (v C0 + D C1)/(D + v) at an inlet,
+                // (v C0 - D C1)/(v - D) at an outlet, C1 the concentration of
+                // the next node inward at the previous time level
+                // the next node inward, 0 if it is solid
+                const int nxw = kw == 0 ? 1 : kw == 1 ? -1 : 0, nyw = kw == 2 ? 1 : kw == 3 ? -1 : 0;
+                const int in_dir = kw == 0 ? 1 : kw == 1 ? 3 : kw == 2 ? 2 : 4;  // e_in = n
+                const O s1 = brick_off<S, O>((unsigned)(x + nxw), (unsigned)(y + nyw), pnx);
+                R C1 = R(0);
+                if (!((lk >> in_dir) & 1u)) {
 #pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                if (!shas<SQ>(i)) continue;
-                const int dx = x + ex(i);
-                if (dx < 0 || dx >= nx) tal[1] += (double)ldb(gin, (O)spl<SQ>(i) * pl + s, i);
+                    for (int i = 0; i < 9; ++i)
+                        if (shas<SQ>(i)) C1 += ldb(gin, (O)spl<SQ>(i) * pl + s1, i);
+                }
+                const R v = R(o.v), C0 = R(o.value), D = q.Dsol;
+                Cf = o.outlet ? (v * C0 - D * C1) / (v - D) : (v * C0 + D * C1) / (D + v);
+                flux = true;
+                tal[0] += (double)(Cf - known);
             }
+            // populations of the previous step that left through the opening
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                if (shas<SQ>(i) && enters_across<SQ>(kw, opp(i)))
+                    tal[1] += (double)ldb(gin, (O)spl<SQ>(i) * pl + s, i);
         }
     }
     // deposit gathered by solid nodes next to fluid (loads issued early too):
@@ -844,8 +893,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
         if (valid && solid) {
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                const int fxg = x + ex(i);
-                if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+                if (across_closed(p, x + ex(i), y + ey(i))) continue;
                 if (!((lk >> i) & 1u)) {
                     fluid8 = true;
                     if (i <= 4) fluid4 = true;
@@ -856,8 +904,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
 #pragma unroll
                 for (int i = 1; i < 9; ++i) {
                     if (!shas<SQ>(i)) continue;
-                    const int fxg = x + ex(i);
-                    if (!p.solute_xper && (fxg < 0 || fxg >= nx)) continue;
+                    if (across_closed(p, x + ex(i), y + ey(i))) continue;
                     if ((lk >> i) & 1u) continue;
                     const R g_out = ldb(gin, (O)spl<SQ>(opp(i)) * pl + src[opp(i)], opp(i));
                     R gi;
@@ -981,7 +1028,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (shas<SQ>(i)) Cc += g[i];
-        const R oms = q.omega_s;
+        if (flux) Cc = Cf;
+        // flux-opening nodes take the equilibrium itself (relaxation 1)
+        const R oms = flux ? R(1) : q.omega_s;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if (!shas<SQ>(i)) continue;
@@ -1016,8 +1065,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             int m = 0;
 #pragma unroll
             for (int i = 1; i <= 4; ++i) {
-                const int cx = x + ex(i);
-                if (!p.solute_xper && (cx <= 0 || cx >= nx - 1)) continue;
+                const int cx = x + ex(i), cy = y + ey(i);
+                // not across or on a wall of a non-periodic solute axis
+                if ((!p.sxper && (cx <= 0 || cx >= nx - 1)) || (!p.syper && (cy <= 0 || cy >= ny - 1))) continue;
                 if (!((lk >> i) & 1u)) {
                     candbits |= 1u << i;
                     ++m;
@@ -1128,9 +1178,9 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
             bool grow = false;
 #pragma unroll
             for (int k = 1; k <= 4; ++k) {
-                const int sx = x + ex(k);
-                if (!p.solute_xper && (sx < 0 || sx >= nx)) continue;
-                const size_t sn = (size_t)wrapi(y + ey(k), ny) * nx + wrapi(sx, nx);
+                const int sx = x + ex(k), sy = y + ey(k);
+                if (across_closed(p, sx, sy)) continue;
+                const size_t sn = (size_t)wrapi(sy, ny) * nx + wrapi(sx, nx);
                 if (p.trig[sn] == (uint8_t)opp(k)) grow = true;
             }
             if (!grow) continue;
@@ -1149,6 +1199,15 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
             for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], k);
             tal[2] += cc;
             tal[3] += 1.0;
+            // the node's fluid and solute are removed: its stored values are
+            // cleared as the step clears every solid node (deviation 0 for the
+            // fluid, 0 for the solute)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                S *__restrict__ f = (S *)p.f[parity_new][c];
+                for (int i = 0; i < 9; ++i) f[(size_t)i * plane + ps] = C::enc(0.0, i);
+            }
+            for (int k = 0; k < p.sq; ++k) ((S *)p.g[parity_new])[(size_t)k * plane + ps] = C::enc(0.0, k);
             p.mask[s] = 1;
             p.b[s] = p.b0;
             // link words: own bit 0; neighbour s + e_j sees s at e_opp(j)

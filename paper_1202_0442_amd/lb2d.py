@@ -51,6 +51,8 @@ _SIGS = {
     "lb2d_solute_opening": [_P, ctypes.c_char_p, ctypes.c_char_p, _D],
     "lb2d_boundary_style": [_P, ctypes.c_char_p],
     "lb2d_rounding": [_P, ctypes.c_char_p, ctypes.c_uint64],
+    "lb2d_solute_opening_range": [_P, ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p,
+                                  ctypes.c_double, ctypes.c_double],
     "lb2d_momentum_opening": [_P, ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
                               ctypes.c_char_p, ctypes.c_double, ctypes.c_double],
     "lb2d_obstacle_rect": [_P, _I, _I, _I, _I],
@@ -186,6 +188,12 @@ class Lattice:
         wall; style poiseuille, uniform, dirichlet or gradient."""
         self._chk(_lib.lb2d_momentum_opening(self._h, wall.encode(), lo, hi, comp, kind.encode(), style.encode(),
                                              float(v), float(rho)))
+
+    def solute_opening_range(self, wall, lo, hi, kind, style, value=0.0, v=0.0):
+        """inlet_solute / outlet_solute on nodes lo..hi of a wall; style
+        dirichlet, adiabatic or flux (value = C0, v = injection velocity)."""
+        self._chk(_lib.lb2d_solute_opening_range(self._h, wall.encode(), lo, hi, kind.encode(), style.encode(),
+                                                 float(value), float(v)))
 
     def rounding(self, mode, seed=0):
         """'nearest' or 'stochastic' rounding of 16-bit storage."""

@@ -143,6 +143,8 @@ def build_oracle(case):
         o.solute(case["solute"], case.get("q", 9))
         for wall, style, val in case.get("openings", []):
             o.solute_opening(wall, style, val)
+        for op in case.get("sopen", []):
+            o.solute_opening_range(*op)
         if case.get("reaction") is not None:
             o.surface_reaction(*case["reaction"])
         o.set_concentration(case.get("C", 0.0))
@@ -159,6 +161,8 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
         g.solute(case["solute"], case.get("q", 9))
         for wall, style, val in case.get("openings", []):
             g.solute_opening(wall, style, val)
+        for op in case.get("sopen", []):
+            g.solute_opening_range(*op)
     g.boundary_style("noslip")
     for r in case.get("rects", []):
         g.obstacle_rect(*r)

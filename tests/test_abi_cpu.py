@@ -83,8 +83,8 @@ def test_unsupported_forms():
         assert e.value.code == lb2d.E_UNSUPPORTED
     L.solute(1.0, 9)
     with pytest.raises(lb2d.LB2DError) as e:
-        L.solute_opening("xlo", "flux", 1.0)
-    assert e.value.code == lb2d.E_UNSUPPORTED
+        L.solute_opening("xlo", "flux", 1.0)      # the whole-wall form has no velocity
+    assert e.value.code == lb2d.E_INVAL
     with pytest.raises(lb2d.LB2DError) as e:
         L.lattice("d2q7", 10, 10, 1.0)
 
@@ -152,17 +152,40 @@ def test_iteration_before_bind_and_bind_checks():
     assert _lib.lb2d_bind(L.handle, ctypes.c_void_p(256), 10, None) == lb2d.E_SIZE
 
 
-def test_openings_come_in_pairs():
+def test_opening_commands_check_their_arguments():
+    """Solute and momentum openings: walls, ranges, styles, overlaps."""
     lb2d = _lb2d()
     L = lb2d.Lattice()
-    L.lattice("d2q9", 16, 16, 1.0)
+    L.lattice("d2q9", 16, 12, 1.0)
+    with pytest.raises(lb2d.LB2DError) as e:
+        L.solute_opening_range("xlo", 0, 11, "inlet", "dirichlet", 1.0)
+    assert e.value.code == lb2d.E_ORDER                       # needs solute first
     L.solute(0.8)
-    L.solute_opening("xlo", "dirichlet", 1.0)
-    L.workspace_bytes("f32")
-    import ctypes
-    from paper_1202_0442_amd.lb2d import _lib
-    assert _lib.lb2d_bind(L.handle, ctypes.c_void_p(256), 1 << 30, None) == lb2d.E_INVAL
-    assert "pairs" in _lib.lb2d_last_error(L.handle).decode()
+    bad = [lambda: L.solute_opening_range("zlo", 0, 3, "inlet", "dirichlet", 1.0),
+           lambda: L.solute_opening_range("xlo", 3, 2, "inlet", "dirichlet", 1.0),
+           lambda: L.solute_opening_range("xlo", 0, 12, "inlet", "dirichlet", 1.0),
+           lambda: L.solute_opening_range("ylo", 0, 3, "sideways", "dirichlet", 1.0),
+           lambda: L.solute_opening_range("ylo", 0, 3, "inlet", "flux", 1.0, 0.0),
+           lambda: L.momentum_opening("xlo", 0, 12, 0, "inlet", "uniform", 0.01, 1.0),
+           lambda: L.momentum_opening("xlo", 0, 3, 1, "inlet", "uniform", 0.01, 1.0),
+           lambda: L.momentum_opening("xlo", 0, 3, 0, "inlet", "uniform", 1.5, 1.0),
+           lambda: L.momentum_opening("xlo", 0, 3, 0, "inlet", "swirl", 0.01, 1.0)]
+    for call in bad:
+        with pytest.raises(lb2d.LB2DError) as e:
+            call()
+        assert e.value.code == lb2d.E_INVAL
+    L.solute_opening_range("xlo", 0, 5, "inlet", "flux", 1.0, 0.1)
+    L.solute_opening("xhi", "adiabatic")                      # one x wall open: no pair needed
+    for call in (lambda: L.solute_opening_range("xlo", 5, 9, "inlet", "dirichlet", 1.0),   # overlap
+                 lambda: L.solute_opening_range("ylo", 0, 4, "inlet", "dirichlet", 1.0)):  # corner (0,0)
+        with pytest.raises(lb2d.LB2DError) as e:
+            call()
+        assert e.value.code == lb2d.E_INVAL
+    L.solute_opening_range("ylo", 1, 4, "inlet", "dirichlet", 1.0)
+    L.momentum_opening("xlo", 1, 10, 0, "inlet", "poiseuille", 0.02, 1.0)
+    with pytest.raises(lb2d.LB2DError) as e:
+        L.momentum_opening("xlo", 10, 11, 0, "outlet", "dirichlet", 0.0, 1.0)
+    assert e.value.code == lb2d.E_INVAL
 
 
 def test_null_handles_do_not_crash():

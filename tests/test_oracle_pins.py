@@ -838,3 +838,83 @@ def test_openings_start_from_their_state():
     rho, ux, uy = o.moments(0)
     np.testing.assert_allclose(uy[0, lo:hi + 1], 0.03, rtol=1e-13)
     np.testing.assert_allclose(rho[-1, lo:hi + 1], 0.99, rtol=1e-14)
+
+
+# -------------------------------------------------------- solute openings
+
+@pytest.mark.parametrize("q", [4, 9])
+@pytest.mark.parametrize("kind", ["inlet", "outlet"])
+def test_solute_flux_opening_steady_profile(q, kind):
+    """Flux opening (inlet_solute / outlet_solute, App. B) on xlo of a
+    diffusion strip at rest, dirichlet C = 0 on xhi, tau_s = 1: the steady
+    profile is linear, C(x) = a (1 - x/(nx-1)), and the opening rule fixes
+    a: a (D + v) = v C0 + D C(1) for an inlet, a (v - D) = v C0 - D C(1)
+    for an outlet, with C(1) = a (1 - 1/(nx-1))."""
+    nx, ny, C0 = 20, 3, 1.0
+    v = 0.1 if kind == "inlet" else 0.5
+    D = 0.5 * 0.5 if q == 4 else 0.5 / 3
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.solute(1.0, q)
+    o.solute_opening_range("xlo", 0, ny - 1, kind, "flux", C0, v)
+    o.solute_opening_range("xhi", 0, ny - 1, "outlet", "dirichlet", 0.0)
+    o.set_fields(0, 1.0)
+    o.set_concentration(0.0)
+    o.iteration(40000)
+    C, _ = o.solute_state()
+    k = 1 - 1 / (nx - 1)
+    a = v * C0 / (D + v - D * k) if kind == "inlet" else v * C0 / (v - D + D * k)
+    np.testing.assert_allclose(C[1], a * (1 - np.arange(nx) / (nx - 1)), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("q", [4, 9])
+def test_solute_openings_on_y_walls_and_closed_wall_parts(q):
+    """A dirichlet opening on part of ylo holds C = Cbar on its nodes after
+    every step; the rest of the ylo and yhi walls is impermeable, so with
+    an adiabatic opening on part of yhi the solute budget
+    (solute + outflow - inflow) stays at its start value."""
+    nx, ny = 24, 16
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.aveacceleration(2, 1e-5)
+    o.solute(0.8, q)
+    o.solute_opening_range("ylo", 5, 14, "inlet", "dirichlet", 1.0)
+    o.solute_opening_range("yhi", 8, 20, "outlet", "adiabatic")
+    o.set_fields(0, 1.0)
+    o.set_concentration(0.2)
+    b0 = o.budgets()
+    for _ in range(3):
+        o.iteration(57)
+        C, _ = o.solute_state()
+        np.testing.assert_allclose(C[0, 5:15], 1.0, rtol=1e-13)
+    b = o.budgets()
+    assert b["inflow"] > 0 and b["outflow"] > 0
+    assert b["solute"] - b["inflow"] + b["outflow"] == pytest.approx(b0["solute"], rel=1e-12)
+
+
+def test_solute_budget_closes_with_openings_on_every_wall():
+    """Openings of all three styles on all four walls, reactive walls and
+    growth: solute + deposit + consumed deposit + removed solute - b0 per
+    grown node - inflow + outflow equals its start value."""
+    rng = np.random.default_rng(17)
+    nx, ny = 40, 36
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.aveacceleration(1, 2e-5)
+    o.solute(0.9, 9)
+    for _ in range(5):
+        o.obstacle_circle(int(rng.integers(8, 32)), int(rng.integers(8, 28)), float(rng.uniform(2, 4)))
+    o.solute_opening_range("xlo", 2, 30, "inlet", "flux", 1.0, 0.05)
+    o.solute_opening_range("xhi", 0, 35, "outlet", "adiabatic")
+    o.solute_opening_range("ylo", 4, 20, "inlet", "dirichlet", 0.7)
+    o.solute_opening_range("yhi", 10, 30, "outlet", "flux", 0.1, 0.2)
+    o.surface_reaction(0.02, 0.0, 0.003, 0.2, 9)
+    o.set_fields(0, 1.0)
+    o.set_concentration(0.3)
+    b0 = o.budgets()
+    o.iteration(300)
+    b = o.budgets()
+    assert b["grown_nodes"] > 0
+    lhs = (b["solute"] + b["deposit"] + b["consumed_deposit"] + b["removed_solute"] - 0.003 * b["grown_nodes"]
+           - b["inflow"] + b["outflow"])
+    assert lhs == pytest.approx(b0["solute"] + b0["deposit"], rel=1e-12)
