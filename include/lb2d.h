@@ -157,9 +157,30 @@ int lb2d_momentum_opening(lb2d_ctx *ctx, const char *wall, int lo, int hi, int c
                           const char *kind, const char *style, double v,
                           double rho);
 
-/* boundary_style command: "noslip" (half-way bounce-back).  Must precede
- * every obstacle.  "slip", "mixed", "hybrid" return LB2D_E_UNSUPPORTED. */
-int lb2d_boundary_style(lb2d_ctx *ctx, const char *style);
+/* boundary_style command (Commands section, boundary_style; Fig. slip).
+ * Must precede every obstacle; sets how the solids of the obstacles that
+ * follow, and the solids made by growth, treat a fluid population that
+ * hits them:
+ *   "noslip": half-way bounce-back (R = 0);
+ *   "slip":   a diagonal mode that hits a flat wall is mirrored and goes on
+ *             forward (R = 1); at a corner, or when the node it would land
+ *             on is solid, it bounces back; axis modes always bounce back;
+ *   "mixed":  a share R (0 <= R <= 1, the argument) goes forward by the
+ *             slip rule and 1 - R bounces back;
+ *   "hybrid": each obstacle carries its own style (lb2d_obstacle_style);
+ *             solids made by growth are noslip.
+ * R is read only by "mixed".  The solute always bounces back (or reacts).
+ * The step reads every solid's R per component: one FP64 array per
+ * component on the device.  Returns LB2D_E_INVAL for an unknown style or
+ * an R outside [0, 1]. */
+int lb2d_boundary_style(lb2d_ctx *ctx, const char *style, double R);
+
+/* Per-obstacle style of the hybrid boundary style (obstacle command's
+ * extra arguments, one style per component): component comp of the
+ * obstacles that follow uses "noslip", "slip" or "mixed" with share R.
+ * Only after boundary_style("hybrid") (LB2D_E_ORDER otherwise); comp must
+ * name a component of the fluids command. */
+int lb2d_obstacle_style(lb2d_ctx *ctx, int comp, const char *style, double R);
 
 /* Rounding of 16-bit population storage (an extension; the paper stores
  * FP64): "nearest" (round to nearest even, the default) or "stochastic"
@@ -216,20 +237,27 @@ int lb2d_aveforce(lb2d_ctx *ctx, int mode, double value, int comp);
 /* aveacceleration command: adds value * e_mode to the acceleration of comp;
  * the force is rho_comp times the summed acceleration. */
 int lb2d_aveacceleration(lb2d_ctx *ctx, int mode, double value, int comp);
-/* interforce command, two-component form F_c = -G rho_c(x) sum_{i=1..8}
- * w_i rho_cbar(x + e_i) e_i (rho_cbar = 0 on solids); psi0 and rho0 must be
- * NaN.  The one-component psi form returns LB2D_E_UNSUPPORTED.  Needs
- * fluids. */
+/* interforce command (Shan-Chen cohesion, computed from the densities
+ * after streaming of the same step).  Two-component form (psi0 and rho0
+ * NaN): F_c = -G rho_c(x) sum_{i=1..8} w_i rho_cbar(x + e_i) e_i, cbar the
+ * other component.  One-component form (one fluid; psi0 > 0 and rho0 > 0
+ * given): F = -G psi(x) sum_{i=1..8} w_i psi(x + e_i) e_i with
+ * psi = psi0 exp(-rho0 / rho).  Densities and psi are 0 on solids.
+ * LB2D_E_INVAL for a form that does not match the number of fluids. */
 int lb2d_interforce(lb2d_ctx *ctx, double G, double psi0, double rho0);
-/* adhesiveforce command, two-component form F_c += -G_c rho_c(x)
- * sum_{i=1..8} w_i s(x + e_i) e_i (s = 1 on solids); psi0, rho0 NaN. */
+/* adhesiveforce command.  Two-component form (psi0, rho0 NaN):
+ * F_c += -G_c rho_c(x) sum_{i=1..8} w_i s(x + e_i) e_i (s = 1 on solids).
+ * One-component form (one fluid, comp 0, psi0 and rho0 of its own):
+ * F += -G psi(x) sum_{i=1..8} w_i s(x + e_i) e_i. */
 int lb2d_adhesiveforce(lb2d_ctx *ctx, double G, double psi0, double rho0,
                        int comp);
 
 /* ------------------------------------------------------------- memory */
 
 /* Bytes of device memory one lattice needs with the given storage format
- * (LB2D_F64/F32/F16/BF16), after all commands above. */
+ * (LB2D_F64/F32/F16/BF16), after all commands above.  16-bit storage
+ * (F16, BF16) is implemented for one fluid without solute, forces between
+ * nodes, openings or slip/mixed solids (LB2D_E_UNSUPPORTED otherwise). */
 int lb2d_workspace_bytes(lb2d_ctx *ctx, int storage, size_t *bytes);
 /* Binds `bytes` of caller device memory at dev_ptr (256-byte aligned,
  * on the context's device) and the HIP stream `hip_stream` (NULL = the

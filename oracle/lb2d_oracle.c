@@ -141,6 +141,11 @@ typedef struct orc {
     double *f[2], *ftmp[2];      /* [9][n] populations, post-collision */
     double *g, *gtmp;            /* [9][n] solute populations */
     uint8_t *mask;               /* 1 = solid */
+    double *refl[2];             /* per node and component: share R of a
+                                    diagonal mode hitting this solid that
+                                    is reflected (0 noslip, 1 slip, R mixed) */
+    double style_R[2];           /* R given to the next obstacles */
+    double grow_R[2];            /* R of solids made by growth */
     double *b;                   /* deposited mass on solid nodes */
     double *bacc;                /* per-step deposit scratch */
     uint8_t *grow;               /* per-step growth marks */
@@ -165,6 +170,7 @@ orc *orc_create(int nx, int ny) {
     o->tau[0] = o->tau[1] = 1.0;
     o->alpha[0] = o->alpha[1] = 4.0 / 9.0;
     for (int c = 0; c < 2; ++c) {
+        o->refl[c] = (double *)calloc(o->n, sizeof(double));
         o->f[c] = (double *)calloc(9 * o->n, sizeof(double));
         o->ftmp[c] = (double *)calloc(9 * o->n, sizeof(double));
         o->rho[c] = (double *)calloc(o->n, sizeof(double));
@@ -185,6 +191,7 @@ orc *orc_create(int nx, int ny) {
 void orc_destroy(orc *o) {
     if (!o) return;
     for (int c = 0; c < 2; ++c) {
+        free(o->refl[c]);
         free(o->f[c]); free(o->ftmp[c]); free(o->rho[c]); free(o->jx[c]);
         free(o->jy[c]); free(o->Fx[c]); free(o->Fy[c]);
     }
@@ -328,7 +335,11 @@ static void circle_node(orc *o, int x, int y, int xc, int yc, double r) {
     if (o->nx - dx < dx) dx = o->nx - dx;
     if (o->ny - dy < dy) dy = o->ny - dy;
     double d2 = (double)(dx * dx + dy * dy);
-    if (d2 <= r * r) o->mask[idx(o, x, y)] = 1;
+    if (d2 <= r * r) {
+        o->mask[idx(o, x, y)] = 1;
+        o->refl[0][idx(o, x, y)] = o->style_R[0];
+        o->refl[1][idx(o, x, y)] = o->style_R[1];
+    }
 }
 
 int orc_obstacle_circle(orc *o, int xc, int yc, double r) {
@@ -351,7 +362,30 @@ int orc_obstacle_rect(orc *o, int x0, int x1, int y0, int y1) {
     if (x0 > x1 || y0 > y1 || x0 < 0 || y0 < 0 || x1 >= o->nx || y1 >= o->ny)
         return -1;
     for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x) o->mask[idx(o, x, y)] = 1;
+        for (int x = x0; x <= x1; ++x) {
+            o->mask[idx(o, x, y)] = 1;
+            o->refl[0][idx(o, x, y)] = o->style_R[0];
+            o->refl[1][idx(o, x, y)] = o->style_R[1];
+        }
+    return 0;
+}
+
+/* boundary_style(style, R): 0 noslip, 1 slip, 2 mixed with reflected
+ * share R, 3 hybrid (each obstacle carries its own style, see
+ * orc_obstacle_style; solids made by growth are noslip).  Sets the style
+ * of the obstacles that follow and of grown solids. */
+int orc_boundary_style(orc *o, int style, double R) {
+    if (style < 0 || style > 3 || (style == 2 && !(R >= 0.0 && R <= 1.0))) return -1;
+    double v = style == 1 ? 1.0 : style == 2 ? R : 0.0;
+    for (int c = 0; c < 2; ++c) o->style_R[c] = o->grow_R[c] = v;
+    return 0;
+}
+
+/* Hybrid style: the style of component comp for the obstacles that follow
+ * (obstacle command's extra arguments): R = 0 noslip, 1 slip, else mixed. */
+int orc_obstacle_style(orc *o, int comp, double R) {
+    if (comp < 0 || comp > 1 || !(R >= 0.0 && R <= 1.0)) return -1;
+    o->style_R[comp] = R;
     return 0;
 }
 
@@ -607,6 +641,52 @@ static long fluid_src(const orc *o, int x, int y, int i) {
     return idx(o, wrap(x - EX9[i], o->nx), wrap(y - EY9[i], o->ny));
 }
 
+/* ------------------------------------------- slip / mixed boundaries */
+
+static int solid_at(const orc *o, int x, int y) { return o->mask[idx(o, wrap(x, o->nx), wrap(y, o->ny))]; }
+
+/* Fate of the diagonal mode k of fluid node P = (px, py) heading into the
+ * solid T = P + e_k (boundary_style command, slip rule): 1 if it reflects
+ * off a horizontal wall (P + (0, ky) solid, P + (kx, 0) fluid) and lands on
+ * P + (2kx, 0), 2 if it reflects off a vertical wall (P + (kx, 0) solid,
+ * P + (0, ky) fluid) and lands on P + (0, 2ky), 0 if it bounces back (a
+ * corner, or the landing node is solid). */
+static int slip_branch(const orc *o, int px, int py, int k) {
+    int kx = EX9[k], ky = EY9[k];
+    int sy = solid_at(o, px, py + ky), sx = solid_at(o, px + kx, py);
+    if (sy && !sx && !solid_at(o, px + 2 * kx, py)) return 1;
+    if (sx && !sy && !solid_at(o, px, py + 2 * ky)) return 2;
+    return 0;
+}
+
+/* Population of diagonal direction i arriving at fluid node X = (x, y)
+ * whose source T = X - e_i is solid, with the reflected share R of T (0
+ * noslip, 1 slip, else mixed): X's own mode opp(i) that hit T comes back
+ * with weight 1 - R when it has a slip branch (1 otherwise), and modes
+ * mirrored off the wall at T arrive with weight R: from X - (2 ex_i, 0) by
+ * a horizontal reflection (mode (ex_i, -ey_i)) and from X - (0, 2 ey_i) by
+ * a vertical one (mode (-ex_i, ey_i)). */
+static double diagonal_at_wall(const orc *o, int c, int x, int y, int i) {
+    const long n = o->n;
+    int ax = EX9[i], ay = EY9[i];
+    double R = o->refl[c][idx(o, wrap(x - ax, o->nx), wrap(y - ay, o->ny))];
+    long s = idx(o, x, y);
+    int own = opposite(i);
+    double v = (R > 0.0 && slip_branch(o, x, y, own) ? 1.0 - R : 1.0) * o->f[c][own * n + s];
+    if (R > 0.0) {
+        int hx = x - 2 * ax, hy = y, kh = -1, vx = x, vy = y - 2 * ay, kv = -1;
+        for (int k = 5; k < 9; ++k) {
+            if (EX9[k] == ax && EY9[k] == -ay) kh = k;
+            if (EX9[k] == -ax && EY9[k] == ay) kv = k;
+        }
+        if (!solid_at(o, hx, hy) && slip_branch(o, wrap(hx, o->nx), hy, kh) == 1)
+            v += R * o->f[c][kh * n + idx(o, wrap(hx, o->nx), hy)];
+        if (!solid_at(o, vx, vy) && slip_branch(o, vx, wrap(vy, o->ny), kv) == 2)
+            v += R * o->f[c][kv * n + idx(o, vx, wrap(vy, o->ny))];
+    }
+    return v;
+}
+
 /* Forces on the fluid nodes from the densities in o->rho (which must hold
  * the post-streaming densities of the current step; equal to the
  * post-collision ones since BGK conserves each component's mass).
@@ -732,8 +812,12 @@ static void one_step(orc *o) {
                     double v = 0.0;
                     if (!o->mask[s]) {
                         long src = fluid_src(o, x, y, i);
-                        v = o->mask[src] ? o->f[c][opposite(i) * n + s]
-                                         : o->f[c][i * n + src];
+                        if (!o->mask[src])
+                            v = o->f[c][i * n + src];
+                        else if (i <= 4)
+                            v = o->f[c][opposite(i) * n + s];
+                        else
+                            v = diagonal_at_wall(o, c, x, y, i);
                     }
                     o->ftmp[c][i * n + s] = v;
                 }
@@ -1021,6 +1105,8 @@ static void one_step(orc *o) {
                 o->g[i * n + s] = 0.0;
             }
             o->removed_C += C;
+            o->refl[0][s] = o->grow_R[0];
+            o->refl[1][s] = o->grow_R[1];
             o->mask[s] = 1;
             o->b[s] = o->b0;
             o->grown_nodes += 1;

@@ -74,6 +74,8 @@ def _load():
         "orc_surface_reaction": (I, [P, D, D, D, D, ctypes.c_uint64]),
         "orc_obstacle_circle": (I, [P, I, I, D]),
         "orc_obstacle_rect": (I, [P, I, I, I, I]),
+        "orc_boundary_style": (I, [P, I, D]),
+        "orc_obstacle_style": (I, [P, I, D]),
         "orc_set_fields": (I, [P, I, DP, DP, DP]),
         "orc_set_concentration": (I, [P, DP, DP, DP]),
         "orc_step": (I, [P, L]),
@@ -230,6 +232,17 @@ class Oracle:
     def surface_reaction(self, kr, Cs, b0, bmax, seed):
         self._chk(self.lib.orc_surface_reaction(self.h, kr, Cs, b0, bmax, seed),
                   "surface_reaction")
+
+    def boundary_style(self, style, R=0.0):
+        """noslip, slip, mixed (reflected share R) or hybrid."""
+        st = {"noslip": 0, "slip": 1, "mixed": 2, "hybrid": 3}[style]
+        self._chk(self.lib.orc_boundary_style(self.h, st, float(R)), "boundary_style")
+
+    def obstacle_style(self, comp, style, R=0.0):
+        """Hybrid style: style of component comp for the obstacles that
+        follow (noslip, slip or mixed with share R)."""
+        v = {"noslip": 0.0, "slip": 1.0}.get(style, R)
+        self._chk(self.lib.orc_obstacle_style(self.h, comp, float(v)), "obstacle_style")
 
     def obstacle_circle(self, xc, yc, r):
         self._chk(self.lib.orc_obstacle_circle(self.h, int(xc), int(yc), float(r)), "circle")

@@ -35,6 +35,12 @@ struct Circle {
 struct Rect {
     int x0, x1, y0, y1;
 };
+// One obstacle command in order (0 circle, 1 rectangle, 2 host mask) with
+// the reflected share R of its solids per component.
+struct ObstacleOp {
+    int kind, index;
+    double R[2];
+};
 
 }  // namespace
 
@@ -105,7 +111,20 @@ struct lb2d_ctx {
     }
     size_t n() const { return (size_t)nx * ny; }
     std::vector<OpenSpec> opens;  // momentum openings
-    bool plain() const { return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1] && opens.empty(); }
+    int bstyle = 0;               // boundary_style: 0 noslip, 1 slip, 2 mixed, 3 hybrid
+    double style_R[2] = {0.0, 0.0};  // R given to the next obstacles
+    double grow_R = 0.0;             // R of solids made by growth
+    std::vector<ObstacleOp> oops;
+    double *refl_dev = nullptr;
+    bool slip_any() const {
+        if (grow_R > 0.0) return true;
+        for (const auto &o : oops)
+            if (o.R[0] > 0.0 || o.R[1] > 0.0) return true;
+        return false;
+    }
+    bool plain() const {
+        return ncomp == 1 && q == 0 && !inter && !ads[0] && !ads[1] && opens.empty() && !slip_any();
+    }
     bool has_gradient() const {
         for (const auto &o : opens)
             if (o.style == 4) return true;
@@ -155,7 +174,7 @@ bool is_nan(double v) { return std::isnan(v); }
 
 // Workspace layout of one lattice.
 struct Layout {
-    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, gflag, total;
+    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, gflag, refl, total;
     size_t staging_doubles;
 };
 
@@ -214,6 +233,9 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     off += align_up(8);
     L.gflag = off;
     off += align_up(8);
+    // reflected shares of slip/mixed solids, per component
+    L.refl = off;
+    if (c->slip_any()) off += align_up((size_t)c->ncomp * n * 8);
     L.total = off;
     return L;
 }
@@ -267,6 +289,11 @@ FullParams full_params(const lb2d_ctx *c) {
     }
     k8.Dsol = c->q ? (c->q == 4 ? 0.5 : 1.0 / 3.0) * (c->tau_s - 0.5) : 0.0;
     k8.Cs = c->Cs;
+    p.slip = c->refl_dev ? 1 : 0;
+    for (int k = 0; k < 2; ++k) {
+        p.refl[k] = (c->refl_dev && k < c->ncomp) ? c->refl_dev + (size_t)k * c->n() : nullptr;
+        p.grow_R[k] = c->grow_R;
+    }
     p.nopen = (int)c->opens.size();
     for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
@@ -595,17 +622,48 @@ int lb2d_solute_opening(lb2d_ctx *c, const char *wall, const char *style, double
                                      std::strcmp(wall, "xlo") ? "outlet" : "inlet", style, value, 0.0);
 }
 
-int lb2d_boundary_style(lb2d_ctx *c, const char *style) {
+int lb2d_boundary_style(lb2d_ctx *c, const char *style, double R) {
     int rc = pre_command(c);
     if (rc) return rc;
     if (!style) return c->fail(LB2D_E_INVAL, "null style");
+    double v;
     if (!std::strcmp(style, "noslip")) {
-        c->have_style = true;
-        return LB2D_OK;
+        c->bstyle = 0;
+        v = 0.0;
+    } else if (!std::strcmp(style, "slip")) {
+        c->bstyle = 1;
+        v = 1.0;
+    } else if (!std::strcmp(style, "mixed")) {
+        if (!(R >= 0.0 && R <= 1.0)) return c->fail(LB2D_E_INVAL, "the mixed style needs 0 <= R <= 1");
+        c->bstyle = 2;
+        v = R;
+    } else if (!std::strcmp(style, "hybrid")) {
+        c->bstyle = 3;
+        v = 0.0;
+    } else {
+        return c->fail(LB2D_E_INVAL, "unknown boundary style %s", style);
     }
-    if (!std::strcmp(style, "slip") || !std::strcmp(style, "mixed") || !std::strcmp(style, "hybrid"))
-        return c->fail(LB2D_E_UNSUPPORTED, "boundary style %s is not implemented", style);
-    return c->fail(LB2D_E_INVAL, "unknown boundary style %s", style);
+    c->style_R[0] = c->style_R[1] = v;
+    c->grow_R = c->bstyle == 3 ? 0.0 : v;
+    c->have_style = true;
+    return LB2D_OK;
+}
+
+int lb2d_obstacle_style(lb2d_ctx *c, int comp, const char *style, double R) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (c->bstyle != 3) return c->fail(LB2D_E_ORDER, "per-obstacle styles need boundary_style hybrid");
+    if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
+    if (!style) return c->fail(LB2D_E_INVAL, "null style");
+    if (!std::strcmp(style, "noslip")) c->style_R[comp] = 0.0;
+    else if (!std::strcmp(style, "slip")) c->style_R[comp] = 1.0;
+    else if (!std::strcmp(style, "mixed")) {
+        if (!(R >= 0.0 && R <= 1.0)) return c->fail(LB2D_E_INVAL, "the mixed style needs 0 <= R <= 1");
+        c->style_R[comp] = R;
+    } else {
+        return c->fail(LB2D_E_INVAL, "style must be noslip, slip or mixed");
+    }
+    return LB2D_OK;
 }
 
 int lb2d_momentum_opening(lb2d_ctx *c, const char *wall, int lo, int hi, int comp, const char *kind,
@@ -664,6 +722,7 @@ int lb2d_obstacle_rect(lb2d_ctx *c, int x0, int x1, int y0, int y1) {
     if (x0 < 0 || y0 < 0 || x1 >= c->nx || y1 >= c->ny || x0 > x1 || y0 > y1)
         return c->fail(LB2D_E_INVAL, "rectangle outside the lattice or empty");
     c->rects.push_back({x0, x1, y0, y1});
+    c->oops.push_back({1, (int)c->rects.size() - 1, {c->style_R[0], c->style_R[1]}});
     return LB2D_OK;
 }
 
@@ -674,6 +733,7 @@ int lb2d_obstacle_circle(lb2d_ctx *c, int xc, int yc, double r) {
     if (xc < 0 || yc < 0 || xc >= c->nx || yc >= c->ny || !(r >= 0.0) || !std::isfinite(r))
         return c->fail(LB2D_E_INVAL, "circle centre outside the lattice or bad radius");
     c->circles.push_back({xc, yc, r});
+    c->oops.push_back({0, (int)c->circles.size() - 1, {c->style_R[0], c->style_R[1]}});
     return LB2D_OK;
 }
 
@@ -683,6 +743,7 @@ int lb2d_obstacle_mask(lb2d_ctx *c, const uint8_t *host_mask) {
     if (!c->have_style) return c->fail(LB2D_E_ORDER, "obstacle must follow boundary_style");
     if (!host_mask) return c->fail(LB2D_E_INVAL, "null mask");
     c->host_masks.emplace_back(host_mask, host_mask + c->n());
+    c->oops.push_back({2, (int)c->host_masks.size() - 1, {c->style_R[0], c->style_R[1]}});
     return LB2D_OK;
 }
 
@@ -851,6 +912,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->totals = (double *)(c->ws + L.totals);
     c->dstep = (long long *)(c->ws + L.dstep);
     c->gflag = (unsigned *)(c->ws + L.gflag);
+    c->refl_dev = c->slip_any() ? (double *)(c->ws + L.refl) : nullptr;
     const size_t n = c->n();
     hipStream_t s = c->stream;
 
@@ -932,6 +994,42 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
         if ((e = upload(c, c->staging + 2 * n, c->Cuy, 0.0))) return e;
         HIPCHK(c, launch_init_solute(c->storage, c->g[0], c->staging, c->staging + n, c->staging + 2 * n, n, c->q,
                                      (unsigned)c->nx, c->pnx, c->pplane, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (c->refl_dev) {
+        // reflected shares, obstacle commands in order (a later obstacle
+        // overrides an earlier one on shared nodes); circles use the same
+        // minimum-image rule as the rasteriser
+        std::vector<double> rf((size_t)c->ncomp * n, 0.0);
+        auto put = [&](size_t node, const double *R) {
+            for (int k = 0; k < c->ncomp; ++k) rf[(size_t)k * n + node] = R[k];
+        };
+        for (const auto &op : c->oops) {
+            if (op.kind == 0) {
+                const Circle &ci = c->circles[op.index];
+                const int h = (ci.r < (double)(c->nx + c->ny)) ? (int)ci.r + 1 : c->nx + c->ny;
+                const bool all = 2 * h + 1 >= c->nx || 2 * h + 1 >= c->ny;
+                const int ylo = all ? 0 : ci.yc - h, yhi = all ? c->ny - 1 : ci.yc + h;
+                const int xlo = all ? 0 : ci.xc - h, xhi = all ? c->nx - 1 : ci.xc + h;
+                for (int yy = ylo; yy <= yhi; ++yy)
+                    for (int xx = xlo; xx <= xhi; ++xx) {
+                        const int gx = ((xx % c->nx) + c->nx) % c->nx, gy = ((yy % c->ny) + c->ny) % c->ny;
+                        long dx = ((gx - ci.xc) % c->nx + c->nx) % c->nx, dy = ((gy - ci.yc) % c->ny + c->ny) % c->ny;
+                        if (c->nx - dx < dx) dx = c->nx - dx;
+                        if (c->ny - dy < dy) dy = c->ny - dy;
+                        if ((double)(dx * dx + dy * dy) <= ci.r * ci.r) put((size_t)gy * c->nx + gx, op.R);
+                    }
+            } else if (op.kind == 1) {
+                const Rect &re = c->rects[op.index];
+                for (int yy = re.y0; yy <= re.y1; ++yy)
+                    for (int xx = re.x0; xx <= re.x1; ++xx) put((size_t)yy * c->nx + xx, op.R);
+            } else {
+                const auto &hm = c->host_masks[op.index];
+                for (size_t k = 0; k < n; ++k)
+                    if (hm[k]) put(k, op.R);
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->refl_dev, rf.data(), rf.size() * 8, hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (c->reaction) HIPCHK(c, launch_init_b(c->b, c->mask, c->b0, n, s));

@@ -123,6 +123,10 @@ struct FullParams {
     int nblk_grow;        // blocks (tally slots) of the growth kernel
     int nopen;            // momentum openings
     OpenSpec open[kMaxOpen];
+    int slip;             // some solid reflects diagonal modes (slip/mixed/hybrid)
+    double *refl[2];      // per node and component: reflected share R of a
+                          // diagonal mode hitting this solid (0 noslip, 1 slip)
+    double grow_R[2];     // R of solids made by growth
     StepCoef<double> cd;  // FP64 coefficients
     StepCoef<float> cf;   // the same rounded to FP32
 };

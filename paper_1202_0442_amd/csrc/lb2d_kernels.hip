@@ -555,6 +555,73 @@ __host__ __device__ __forceinline__ R opening_un(const OpenSpec &o, int k) {
     return o.outlet ? -sp : sp;
 }
 
+// Population loads and stores at byte offsets from an array base.
+template <typename S, typename O>
+__device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, O off, int i) {
+    return Codec<S>::dec(*(const S *)((const char *)base + off), i);
+}
+template <typename S, typename O>
+__device__ __forceinline__ void stb(S *__restrict__ base, O off, S v) {
+    *(S *)((char *)base + off) = v;
+}
+
+// Slip rule of the boundary_style command at diagonal mode k of node
+// (lx, ly) of the tile (mask tile sm with a kSlipRing-node ring): 1 if
+// the mode, heading into a solid, reflects off a horizontal wall (cell
+// across y solid, cell across x fluid) and lands two nodes along x, 2 if it
+// reflects off a vertical wall and lands two nodes along y, 0 if it bounces
+// back (a corner, or a solid landing node).  Reads the mask at most two
+// nodes from (lx, ly) on each axis.
+constexpr int kSlipRing = 3;
+template <int MH, int MW>
+__device__ __forceinline__ int slip_branch(const uint8_t (&sm)[MH][MW], int lx, int ly, int k) {
+    const int kx = ex(k), ky = ey(k);
+    const int cx = lx + kSlipRing, cy = ly + kSlipRing;
+    const bool sy = sm[cy + ky][cx] != 0, sx = sm[cy][cx + kx] != 0;
+    if (sy && !sx && !sm[cy][cx + 2 * kx]) return 1;
+    if (sx && !sy && !sm[cy + 2 * ky][cx]) return 2;
+    return 0;
+}
+
+// Diagonal population i arriving at fluid node (x, y) (tile position
+// lx, ly) whose source T = node - e_i is solid with reflected share R:
+// the node's own mode opp(i) that hit T returns with weight 1 - R when it
+// has a slip branch (1 otherwise); modes mirrored off the wall at T arrive
+// with weight R from node - (2 ex_i, 0) (horizontal wall, mode
+// (ex_i, -ey_i)) and from node - (0, 2 ey_i) (vertical wall, mode
+// (-ex_i, ey_i)).  own = the bounce-back value d_opp(i)(node).  Values are
+// stored shifted by w rho_ref (the same w = 1/36 for every diagonal), so
+// the weights' sum minus one times w rho_ref is added back: the rule moves
+// mass between nodes and its weights need not sum to one at a node.
+template <typename S, typename O, typename R, int MH, int MW>
+__device__ __forceinline__ R slip_diagonal(const FullParams &p, int c, const S *__restrict__ fin, O pl,
+                                           const uint8_t (&sm)[MH][MW], int lx, int ly, int x, int y, int i,
+                                           R own, R rho_ref) {
+    const int ax = ex(i), ay = ey(i);
+    const double Rt = p.refl[c][(size_t)wrapi(y - ay, p.ny) * p.nx + wrapi(x - ax, p.nx)];
+    if (!(Rt > 0.0)) return own;
+    const R RR = R(Rt);
+    const bool mine = slip_branch(sm, lx, ly, opp(i)) != 0;
+    R v = mine ? (R(1) - RR) * own : own;
+    R extra = mine ? -RR : R(0);
+    const int cx = lx + kSlipRing, cy = ly + kSlipRing;
+    // partner across x (horizontal wall): mode kh = (ax, -ay)
+    const int kh = ax > 0 ? (ay > 0 ? 8 : 5) : (ay > 0 ? 7 : 6);
+    if (!sm[cy][cx - 2 * ax] && slip_branch(sm, lx - 2 * ax, ly, kh) == 1) {
+        const O a = brick_off<S, O>((unsigned)wrapi(x - 2 * ax, p.nx), (unsigned)y, p.pnx);
+        v += RR * ldb(fin, (O)kh * pl + a, kh);
+        extra += RR;
+    }
+    // partner across y (vertical wall): mode kv = (-ax, ay)
+    const int kv = ax > 0 ? (ay > 0 ? 6 : 7) : (ay > 0 ? 5 : 8);
+    if (!sm[cy - 2 * ay][cx] && slip_branch(sm, lx, ly - 2 * ay, kv) == 2) {
+        const O a = brick_off<S, O>((unsigned)x, (unsigned)wrapi(y - 2 * ay, p.ny), p.pnx);
+        v += RR * ldb(fin, (O)kv * pl + a, kv);
+        extra += RR;
+    }
+    return v + R(1.0 / 36.0) * rho_ref * extra;
+}
+
 // Applies the openings of component c that hold node (x, y) (Zou-He styles
 // only; gradient openings act after the collision, in k_open_gradient).
 template <typename R>
@@ -635,8 +702,10 @@ __device__ __forceinline__ void wave_sum3(double (&v)[4]) {
 // TX x TY tile:
 //  1. one 16-bit link word per node (bit 0: solid; bit i: node + e_i
 //     solid) gives every bounce-back, adhesion and surface decision;
-//  2. pull both components (fluid lanes); solute pull with bounce-back or
-//     reactive link at walls and the opening rules on open x walls;
+//  2. pull both components (fluid lanes), with the slip/mixed rule for
+//     diagonal modes that hit such solids and the Zou-He closure at
+//     momentum openings; solute pull with bounce-back or reactive link at
+//     walls and the opening rules on open walls;
 //     solid lanes next to fluid gather the deposit of their reactive links;
 //  3. densities of the tile plus a one-node halo in LDS -- the halo nodes'
 //     populations are pulled again (from L2) so that the Shan-Chen force
@@ -652,14 +721,6 @@ __device__ __forceinline__ void wave_sum3(double (&v)[4]) {
 // lane offset, no 64-bit lane arithmetic), 64-bit otherwise.
 // Tallies (inflow, outflow, consumed deposit) go to one running slot per
 // wavefront, summed in a fixed order only when budgets are read.
-template <typename S, typename O>
-__device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, O off, int i) {
-    return Codec<S>::dec(*(const S *)((const char *)base + off), i);
-}
-template <typename S, typename O>
-__device__ __forceinline__ void stb(S *__restrict__ base, O off, S v) {
-    *(S *)((char *)base + off) = v;
-}
 template <typename R>
 __device__ __forceinline__ const StepCoef<R> &coef(const FullParams &p);
 template <>
@@ -667,7 +728,7 @@ __device__ __forceinline__ const StepCoef<double> &coef<double>(const FullParams
 template <>
 __device__ __forceinline__ const StepCoef<float> &coef<float>(const FullParams &p) { return p.cf; }
 
-template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, bool OPEN, int TX, int TY>
+template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, bool BND, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
@@ -676,6 +737,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     static_assert(brick_h_for(sizeof(S)) == 4, "general step: 8x4 bricks");
     static_assert(TX % kBrickW == 0 && TY % 4 == 0, "tile of whole bricks");
     __shared__ R srho[SC ? NC : 1][SC ? TY + 2 : 1][SC ? TX + 2 : 1];
+    // mask tile with a kSlipRing-node ring for the slip rules: the rule
+    // reads two nodes around a node, and the density halo lies one node out
+    __shared__ uint8_t smask[BND ? TY + 2 * kSlipRing : 1][BND ? TX + 2 * kSlipRing : 1];
     const StepCoef<R> &q = coef<R>(p);
 
     const int nx = p.nx, ny = p.ny;
@@ -704,6 +768,17 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     const unsigned long long bal = __ballot(valid && fluid);
     const unsigned lane = __lane_id();
     const bool store = valid && ((bal >> (lane & 32u)) & 0xffffffffull) != 0ull;
+
+    if constexpr (BND) {
+        if (p.slip) {
+            constexpr int MW = TX + 2 * kSlipRing, MH = TY + 2 * kSlipRing;
+            for (int k = tid; k < MW * MH; k += TX * TY) {
+                const int mx = k % MW, my = k / MW;
+                smask[my][mx] = p.mask[(size_t)wrapi(ty0 + my - kSlipRing, ny) * nx + wrapi(tx0 + mx - kSlipRing, nx)];
+            }
+            __syncthreads();
+        }
+    }
 
     // the ring of the density tile: the NH halo slots are dealt to the
     // wavefronts in equal contiguous runs (lane l < PER of wavefront w owns
@@ -743,7 +818,13 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                     for (int i = 1; i < 9; ++i) {
                         const bool wall = (hl >> opp(i)) & 1u;
                         const O a = wall ? (O)opp(i) * pl + hs : (O)i * pl + hsrc[i];
-                        acc += ldb(fin, a, i);
+                        R v = ldb(fin, a, i);
+                        if constexpr (BND) {
+                            if (p.slip && i >= 5 && wall)
+                                v = slip_diagonal<S, O, R>(p, c, fin, pl, smask, hx - 1, hy - 1, (int)gx, (int)gy, i,
+                                                           v, q.rho_ref[c]);
+                        }
+                        acc += v;
                     }
                     hrho[c] = q.rho_ref[c] + acc;
                 }
@@ -778,9 +859,18 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 d[c][i] = ldb(fin, a, i);
             }
         }
-        // momentum openings (only lanes on the box edge can hold one)
-        if constexpr (OPEN) {
-            if (valid && fluid && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1))
+        if constexpr (BND) {
+            // slip / mixed solids: diagonal modes reflected off flat walls
+            if (p.slip && pull) {
+                const S *__restrict__ fin = (const S *)p.f[parity][c];
+#pragma unroll
+                for (int i = 5; i < 9; ++i)
+                    if ((lk >> opp(i)) & 1u)
+                        d[c][i] = slip_diagonal<S, O, R>(p, c, fin, pl, smask, lx, ly, (int)ux_, (int)uy_, i,
+                                                         d[c][i], q.rho_ref[c]);
+            }
+            // momentum openings (only lanes on the box edge can hold one)
+            if (p.nopen > 0 && valid && fluid && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1))
                 apply_openings<R>(p, c, x, y, d[c], q.rho_ref[c]);
         }
         drho[c] = jx[c] = jy[c] = R(0);
@@ -1208,6 +1298,8 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
                 for (int i = 0; i < 9; ++i) f[(size_t)i * plane + ps] = C::enc(0.0, i);
             }
             for (int k = 0; k < p.sq; ++k) ((S *)p.g[parity_new])[(size_t)k * plane + ps] = C::enc(0.0, k);
+            if (p.slip)
+                for (int c = 0; c < NC; ++c) p.refl[c][s] = p.grow_R[c];
             p.mask[s] = 1;
             p.b[s] = p.b0;
             // link words: own bit 0; neighbour s + e_j sees s at e_opp(j)
@@ -1642,12 +1734,12 @@ int growth_blocks(int nx, int ny) {
     return segs < kGrowBlocks ? segs : kGrowBlocks;
 }
 
-template <typename S, typename O, int SQ, bool OPEN>
+template <typename S, typename O, int SQ, bool BND>
 static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
 #define LB2D_FULL(NC_, SC_, REACT_) \
-    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, OPEN, kTX, kTY>), g, b, 0, st, p, parity)
+    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, BND, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
             if (react) LB2D_FULL(2, true, true);
@@ -1671,8 +1763,9 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
 template <typename S, int SQ>
 static void full_dispatch_off(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     // 32-bit byte offsets when every population array (9 planes) is below 4 GiB
-    // the momentum-opening closure only in lattices that have openings
-    const bool open = p.nopen > 0;
+    // the boundary features (momentum openings, slip solids) only in
+    // lattices that have them
+    const bool open = p.nopen > 0 || p.slip;
     if (fits32(p.pplane, sizeof(S))) {
         if (open) full_dispatch_sq<S, uint32_t, SQ, true>(p, parity, sc, react, st);
         else full_dispatch_sq<S, uint32_t, SQ, false>(p, parity, sc, react, st);

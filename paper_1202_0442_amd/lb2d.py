@@ -49,7 +49,8 @@ _SIGS = {
     "lb2d_fluids": [_P, _D, _D, _D, _D],
     "lb2d_solute": [_P, _D, _I],
     "lb2d_solute_opening": [_P, ctypes.c_char_p, ctypes.c_char_p, _D],
-    "lb2d_boundary_style": [_P, ctypes.c_char_p],
+    "lb2d_boundary_style": [_P, ctypes.c_char_p, ctypes.c_double],
+    "lb2d_obstacle_style": [_P, ctypes.c_int, ctypes.c_char_p, ctypes.c_double],
     "lb2d_rounding": [_P, ctypes.c_char_p, ctypes.c_uint64],
     "lb2d_solute_opening_range": [_P, ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p,
                                   ctypes.c_double, ctypes.c_double],
@@ -180,8 +181,11 @@ class Lattice:
     def solute_opening(self, wall, style, value=0.0):
         self._chk(_lib.lb2d_solute_opening(self._h, wall.encode(), style.encode(), value))
 
-    def boundary_style(self, style):
-        self._chk(_lib.lb2d_boundary_style(self._h, style.encode()))
+    def boundary_style(self, style, R=0.0):
+        self._chk(_lib.lb2d_boundary_style(self._h, style.encode(), float(R)))
+
+    def obstacle_style(self, comp, style, R=0.0):
+        self._chk(_lib.lb2d_obstacle_style(self._h, int(comp), style.encode(), float(R)))
 
     def momentum_opening(self, wall, lo, hi, comp, kind, style, v=0.0, rho=1.0):
         """inlet/outlet + inlet_momentum/outlet_momentum: nodes lo..hi of a

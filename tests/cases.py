@@ -103,6 +103,49 @@ def channel_flow_case(nx, ny, seed, wall="xlo", inlet=("poiseuille", 0.04, 1.0),
     return dict(nx=nx, ny=ny, tau=tau, rects=rects, circles=circles, mopen=mopen)
 
 
+def _ordered_obstacles(side, case):
+    """The case's "obstacles": (kind, args, styles) in order, after the
+    rectangles and circles; styles = [(comp, style, R), ...] (hybrid
+    boundary style) or None."""
+    for kind, args, styles in case.get("obstacles", []):
+        for comp, style, R in styles or []:
+            side.obstacle_style(comp, style, R)
+        if kind == "rect":
+            side.obstacle_rect(*args)
+        else:
+            side.obstacle_circle(*args)
+
+
+def slip_box_case(nx, ny, seed, style=("hybrid", 0.0), two=True, G=None, accel=1e-4, nob=10):
+    """Periodic box with random rectangles and discs under a boundary style;
+    under the hybrid style each obstacle draws its own style per component
+    (noslip, slip or mixed with a random share).  One or two fluids with a
+    random start and a body force along x."""
+    rng = np.random.default_rng(seed)
+    obstacles = []
+    for k in range(nob):
+        styles = None
+        if style[0] == "hybrid":
+            styles = [(0, ("noslip", "slip", "mixed")[k % 3], float(rng.uniform(0, 1)))]
+            if two:
+                styles.append((1, ("slip", "mixed", "noslip")[k % 3], float(rng.uniform(0, 1))))
+        if k % 2:
+            obstacles.append(("circle", (int(rng.integers(0, nx)), int(rng.integers(0, ny)),
+                                         float(rng.uniform(1.5, 4.5))), styles))
+        else:
+            x0, y0 = int(rng.integers(0, nx - 7)), int(rng.integers(0, ny - 7))
+            obstacles.append(("rect", (x0, x0 + int(rng.integers(0, 6)), y0, y0 + int(rng.integers(0, 6))), styles))
+    n = nx * ny
+    fields = {0: (0.6 + 0.1 * rng.uniform(0, 1, n), 0.02 * rng.uniform(-1, 1, n), 0.02 * rng.uniform(-1, 1, n))}
+    case = dict(nx=nx, ny=ny, tau=0.8, style=style, obstacles=obstacles, fields=fields, accel=[(1, accel, 0)])
+    if two:
+        fields[1] = (0.4 + 0.1 * rng.uniform(0, 1, n), 0.02 * rng.uniform(-1, 1, n), 0.02 * rng.uniform(-1, 1, n))
+        case["fluids"] = (0.8, 1.1)
+        if G is not None:
+            case["G"] = G
+    return case
+
+
 def build_oracle(case):
     o = Oracle(case["nx"], case["ny"])
     if "fluids" in case:
@@ -123,10 +166,12 @@ def build_oracle(case):
     if case.get("ads_psi") is not None:
         G, psi0, rho0 = case["ads_psi"]
         o.adhesiveforce(G, psi0=psi0, rho0=rho0)
+    o.boundary_style(*case.get("style", ("noslip", 0.0)))
     for r in case.get("rects", []):
         o.obstacle_rect(*r)
     for c in case.get("circles", []):
         o.obstacle_circle(*c)
+    _ordered_obstacles(o, case)
     for op in case.get("mopen", []):
         o.momentum_opening(*op)
     if case.get("mask") is not None:
@@ -163,11 +208,12 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
             g.solute_opening(wall, style, val)
         for op in case.get("sopen", []):
             g.solute_opening_range(*op)
-    g.boundary_style("noslip")
+    g.boundary_style(*case.get("style", ("noslip", 0.0)))
     for r in case.get("rects", []):
         g.obstacle_rect(*r)
     for c in case.get("circles", []):
         g.obstacle_circle(*c)
+    _ordered_obstacles(g, case)
     for op in case.get("mopen", []):
         g.momentum_opening(*op)
     if case.get("mask") is not None:

@@ -76,11 +76,23 @@ def test_unsupported_forms():
     lb2d = _lb2d()
     L = lb2d.Lattice()
     L.lattice("d2q9", 10, 10, 1.0)
-    cases = [lambda: L.boundary_style("slip"), lambda: L.boundary_style("mixed")]
-    for call in cases:
+    L.fluids(1, 1.0)
+    for call in (lambda: L.boundary_style("mixed", 1.5), lambda: L.boundary_style("mixed", -0.1),
+                 lambda: L.boundary_style("sticky")):
         with pytest.raises(lb2d.LB2DError) as e:
             call()
-        assert e.value.code == lb2d.E_UNSUPPORTED
+        assert e.value.code == lb2d.E_INVAL
+    L.boundary_style("slip")
+    with pytest.raises(lb2d.LB2DError) as e:
+        L.obstacle_style(0, "slip")                 # only under the hybrid style
+    assert e.value.code == lb2d.E_ORDER
+    L.boundary_style("hybrid")
+    for call in (lambda: L.obstacle_style(2, "slip"), lambda: L.obstacle_style(0, "mixed", 2.0),
+                 lambda: L.obstacle_style(0, "hybrid")):
+        with pytest.raises(lb2d.LB2DError) as e:
+            call()
+        assert e.value.code == lb2d.E_INVAL
+    L.obstacle_style(0, "mixed", 0.3)
     L.solute(1.0, 9)
     with pytest.raises(lb2d.LB2DError) as e:
         L.solute_opening("xlo", "flux", 1.0)      # the whole-wall form has no velocity

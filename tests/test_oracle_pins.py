@@ -918,3 +918,105 @@ def test_solute_budget_closes_with_openings_on_every_wall():
     lhs = (b["solute"] + b["deposit"] + b["consumed_deposit"] + b["removed_solute"] - 0.003 * b["grown_nodes"]
            - b["inflow"] + b["outflow"])
     assert lhs == pytest.approx(b0["solute"] + b0["deposit"], rel=1e-12)
+
+
+# ------------------------------------------------- slip / mixed boundaries
+
+def _lone_mode(style, R, wall):
+    """One unit of f5 at P = (3, 5) next to a flat wall (boundary_style
+    command, Fig. slip): after one step the node masses and momenta."""
+    nx, ny = 12, 12
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.boundary_style(style, R)
+    if wall == "horizontal":
+        o.obstacle_rect(0, nx - 1, 6, 6)     # row above P
+    else:
+        o.obstacle_rect(4, 4, 0, ny - 1)     # column right of P
+    o.set_fields(0, 1.0)                       # fluid at rest, rho = 1 ...
+    f = o.get_f(0)
+    f[5, 5, 3] += 1.0                          # ... plus one unit of f5 at P
+    o.set_f(f, 0)
+    o.iteration(1)
+    g = o.get_f(0)
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    solid = o.get_mask().astype(bool)
+    # the uniform rest state streams onto itself, so node mass above 1 and
+    # the momentum are the unit's
+    return np.where(solid, 0.0, g.sum(0) - 1.0), np.tensordot(ex, g, 1), np.tensordot(ey, g, 1)
+
+
+@pytest.mark.parametrize("wall", ["horizontal", "vertical"])
+@pytest.mark.parametrize("style,R", [("noslip", 0.0), ("slip", 1.0), ("mixed", 0.3)])
+def test_diagonal_mode_at_flat_wall(wall, style, R):
+    """Slip rule of the boundary_style command: f5 leaving (i, j) towards a
+    solid (i+1, j+1) on a horizontal wall lands on (i+2, j) as f8, on a
+    vertical wall on (i, j+2) as f6; noslip bounces it back to (i, j) as f7;
+    mixed sends the share R forward and 1 - R back.  Mass and momentum move
+    with the populations (one BGK step conserves both per node)."""
+    rho, jx, jy = _lone_mode(style, R, wall)
+    land, e = ((5, 5), (1, -1)) if wall == "horizontal" else ((3, 7), (-1, 1))
+    assert rho[5, 3] == pytest.approx(1.0 - R, abs=1e-15)
+    assert (jx[5, 3], jy[5, 3]) == pytest.approx((-(1.0 - R), -(1.0 - R)), abs=1e-15)
+    assert rho[land[1], land[0]] == pytest.approx(R, abs=1e-15)
+    assert (jx[land[1], land[0]], jy[land[1], land[0]]) == pytest.approx((R * e[0], R * e[1]), abs=1e-15)
+    assert rho.sum() == pytest.approx(1.0, rel=1e-13)
+    others = np.ones_like(rho, bool)
+    others[5, 3] = others[land[1], land[0]] = False
+    assert np.abs(rho[others]).max() <= 1e-15 and np.abs(jx[others]).max() <= 1e-15
+
+
+def test_slip_channel_is_plug_flow():
+    """Full-slip flat walls take no x momentum (the diagonal modes reflect
+    specularly, the axial ones carry none along the wall): a forced
+    channel's momentum grows by exactly the total force each step and the
+    profile stays flat; noslip loses momentum to the walls."""
+    nx, ny, a = 8, 20, 1e-5
+    out = {}
+    for style in ("noslip", "mixed", "slip"):
+        o = Oracle(nx, ny)
+        o.fluids(1, 0.9)
+        o.boundary_style(style, 0.5)
+        o.obstacle_rect(0, nx - 1, 0, 0)
+        o.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+        o.aveacceleration(1, a)
+        o.set_fields(0, 1.0)
+        m0 = o.budgets()["mass0"]
+        o.iteration(500)
+        b = o.budgets()
+        _, ux, _ = o.moments(0)
+        out[style] = b["mom_x"]
+        assert b["mass0"] == pytest.approx(m0, rel=1e-13)
+        if style == "slip":
+            assert b["mom_x"] == pytest.approx(500 * a * m0, rel=1e-12)
+            assert np.ptp(ux[1:-1]) <= 1e-15
+    assert out["noslip"] < out["mixed"] < out["slip"]
+
+
+def test_hybrid_obstacles_conserve_mass():
+    """Hybrid style: obstacles with their own styles (noslip, slip, mixed
+    shares) in a periodic box with a random start; every mode that hits a
+    solid is sent back or forward, never lost: the mass is conserved."""
+    rng = np.random.default_rng(23)
+    nx, ny = 40, 34
+    o = Oracle(nx, ny)
+    o.fluids(2, 0.8, 1.1)
+    o.boundary_style("hybrid")
+    for k in range(10):
+        o.obstacle_style(0, ("noslip", "slip", "mixed")[k % 3], float(rng.uniform(0, 1)))
+        o.obstacle_style(1, ("slip", "mixed", "noslip")[k % 3], float(rng.uniform(0, 1)))
+        if k % 2:
+            o.obstacle_circle(int(rng.integers(0, nx)), int(rng.integers(0, ny)), float(rng.uniform(1.5, 4)))
+        else:
+            x0, y0 = int(rng.integers(0, nx - 6)), int(rng.integers(0, ny - 6))
+            o.obstacle_rect(x0, x0 + int(rng.integers(0, 5)), y0, y0 + int(rng.integers(0, 5)))
+    n = nx * ny
+    o.set_fields(0, 0.6 + 0.1 * rng.uniform(0, 1, n), 0.02 * rng.uniform(-1, 1, n), 0.02 * rng.uniform(-1, 1, n))
+    o.set_fields(1, 0.4 + 0.1 * rng.uniform(0, 1, n), 0.02 * rng.uniform(-1, 1, n), 0.02 * rng.uniform(-1, 1, n))
+    o.aveacceleration(1, 1e-4, 0)
+    b0 = o.budgets()
+    o.iteration(200)
+    b = o.budgets()
+    for c in (0, 1):
+        assert b[f"mass{c}"] == pytest.approx(b0[f"mass{c}"], rel=1e-13)
