@@ -36,7 +36,11 @@
  *     rule of the surface_reaction command and App. C to any Q, and reduces
  *     to it exactly for Q = 4);
  *   - growth candidates are the 4 direct fluid neighbours E,N,W,S, picked by
- *     a counter-based SplitMix64 hash (Steele, Lea & Flood, OOPSLA 2014).
+ *     a counter-based SplitMix64 hash (Steele, Lea & Flood, OOPSLA 2014);
+ *   - the intersolute force uses the concentrations of the same step after
+ *     streaming (as interforce does); psi is 0 on solids, where C <= 0 and
+ *     across a wall of a non-periodic solute axis, and the velocity term
+ *     tau_s F / C is added only where C > 0.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -112,6 +116,8 @@ typedef struct orc {
     double psi0_a, rho0_a;       /* psi of adhesiveforce */
     int q;                       /* solute lattice: 0 = off, 4 or 9 */
     double tau_s;
+    int isol;                    /* intersolute command */
+    double G_s, psi0_s, C0_s;    /* its strength and psi = psi0 exp(-C0/C) */
     int nsopen;                  /* solute openings (inlet_solute/outlet_solute) */
     struct {
         int wall;                /* 0 xlo, 1 xhi, 2 ylo, 3 yhi */
@@ -367,6 +373,19 @@ int orc_obstacle_rect(orc *o, int x0, int x1, int y0, int y1) {
             o->refl[0][idx(o, x, y)] = o->style_R[0];
             o->refl[1][idx(o, x, y)] = o->style_R[1];
         }
+    return 0;
+}
+
+/* intersolute(G, psi0, C0): adds tau_s F / C to the solvent velocity in
+ * the solute equilibrium, F = -G psi(x) sum_{i=1..4} psi(x + e_i) e_i over
+ * the four axis neighbours (no weights), psi = psi0 exp(-C0 / C)
+ * (intersolute command). */
+int orc_intersolute(orc *o, double G, double psi0, double C0) {
+    if (!o->q || !(C0 > 0.0)) return -1;
+    o->isol = 1;
+    o->G_s = G;
+    o->psi0_s = psi0;
+    o->C0_s = C0;
     return 0;
 }
 
@@ -1043,7 +1062,43 @@ static void one_step(orc *o) {
             }
     }
 
-    /* 8. Solute collision towards g_eq(C, u_s). */
+    /* 7b. intersolute force from the concentrations after streaming (the
+     * ones the collision uses, as for interforce): psi = psi0 exp(-C0/C)
+     * on fluid nodes with C > 0, 0 on solids, where C <= 0 and across a
+     * wall of a non-periodic solute axis. */
+    double *Fsx = NULL, *Fsy = NULL;
+    if (o->isol) {
+        double *psi = (double *)malloc(sizeof(double) * n);
+        Fsx = (double *)calloc(n, sizeof(double));
+        Fsy = (double *)calloc(n, sizeof(double));
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < n; ++s) {
+            double C = 0.0;
+            for (int i = 0; i < 9; ++i) C += o->gtmp[i * n + s];
+            if (!isnan(Cflux[s])) C = Cflux[s];
+            psi[s] = (!o->mask[s] && C > 0.0) ? o->psi0_s * exp(-o->C0_s / C) : 0.0;
+        }
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long s = idx(o, x, y);
+                if (o->mask[s]) continue;
+                double sx = 0.0, sy = 0.0;
+                for (int i = 1; i <= 4; ++i) {
+                    int cx = x + EX9[i], cy = y + EY9[i];
+                    if (((cx < 0 || cx >= nx) && !xper) || ((cy < 0 || cy >= ny) && !yper)) continue;
+                    double pn = psi[idx(o, wrap(cx, nx), wrap(cy, ny))];
+                    sx += EX9[i] * pn;
+                    sy += EY9[i] * pn;
+                }
+                Fsx[s] = -o->G_s * psi[s] * sx;
+                Fsy[s] = -o->G_s * psi[s] * sy;
+            }
+        free(psi);
+    }
+
+    /* 8. Solute collision towards g_eq(C, u_s), u_s the solvent velocity
+     * plus tau_s F / C of intersolute. */
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < n; ++s) {
         if (o->mask[s]) {
@@ -1054,12 +1109,17 @@ static void one_step(orc *o) {
         for (int i = 0; i < 9; ++i) C += o->gtmp[i * n + s];
         const int flux = !isnan(Cflux[s]);
         if (flux) C = Cflux[s];
+        double ux = usx[s], uy = usy[s];
+        if (o->isol && C > 0.0) {
+            ux = ux + o->tau_s * Fsx[s] / C;
+            uy = uy + o->tau_s * Fsy[s] / C;
+        }
         for (int i = 0; i < 9; ++i) {
             if (!solute_has(q, i)) {
                 o->g[i * n + s] = 0.0;
                 continue;
             }
-            double ge = geq(q, i, C, usx[s], usy[s]);
+            double ge = geq(q, i, C, ux, uy);
             double gi = o->gtmp[i * n + s];
             o->g[i * n + s] = flux ? ge : gi - (gi - ge) / o->tau_s;
         }
@@ -1067,6 +1127,8 @@ static void one_step(orc *o) {
     free(usx);
     free(usy);
     free(Cflux);
+    free(Fsx);
+    free(Fsy);
 
     /* 9. Surface growth: every solid node whose deposit exceeds bmax turns
      * one of its direct fluid neighbours into solid, each candidate equally

@@ -69,6 +69,7 @@ def _load():
         "orc_momentum_opening": (I, [P, I, I, I, I, I, I, D, D]),
         "orc_adhesiveforce_psi": (I, [P, D, D, D]),
         "orc_solute": (I, [P, I, D]),
+        "orc_intersolute": (I, [P, D, D, D]),
         "orc_solute_opening": (I, [P, I, I, D]),
         "orc_solute_opening_range": (I, [P, I, I, I, I, I, D, D]),
         "orc_surface_reaction": (I, [P, D, D, D, D, ctypes.c_uint64]),
@@ -203,6 +204,10 @@ class Oracle:
             self._chk(self.lib.orc_interforce(self.h, G), "interforce")
         else:
             self._chk(self.lib.orc_interforce_psi(self.h, G, psi0, rho0), "interforce")
+
+    def intersolute(self, G, psi0, C0):
+        """intersolute(G, psi0, C0); after solute."""
+        self._chk(self.lib.orc_intersolute(self.h, float(G), float(psi0), float(C0)), "intersolute")
 
     def adhesiveforce(self, G, comp=0, psi0=None, rho0=None):
         """Two components: adhesiveforce(G, comp); one component:

@@ -1020,3 +1020,79 @@ def test_hybrid_obstacles_conserve_mass():
     b = o.budgets()
     for c in (0, 1):
         assert b[f"mass{c}"] == pytest.approx(b0[f"mass{c}"], rel=1e-13)
+
+
+# ------------------------------------------------------------- intersolute
+
+def _flat_solute_interface(q, tau_s, G, Cl, Cg, steps, psi0=1.0, C0=5e-3, nx=4, ny=128):
+    """A solute slab (tanh profile along y, periodic box) in a fluid at
+    rest under the intersolute force; the concentration profile after
+    `steps` steps."""
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.set_fields(0, 1.0)
+    o.solute(tau_s, q)
+    o.intersolute(G, psi0, C0)
+    yy = np.repeat(np.arange(ny), nx).astype(float)
+    o.set_concentration(Cg + (Cl - Cg) * 0.5 * (np.tanh((yy - ny / 4) / 4.0) - np.tanh((yy - 3 * ny / 4) / 4.0)))
+    o.iteration(steps)
+    C, _ = o.solute_state()
+    return C
+
+
+@pytest.mark.parametrize("q,tau_s,G,Cl,Cg", [(4, 5.0, -0.01, 0.01094, 0.002342),
+                                              (9, 5.0, -0.007, 0.01216, 0.002111)])
+def test_intersolute_flat_interface_balance(q, tau_s, G, Cl, Cg):
+    """A steady flat solute interface carries no flux across any link.
+    Summing the zero-flux condition across the interface (the force stencil
+    F = -G psi(x) [psi(x+e) - psi(x-e)] telescopes over products
+    psi(x) psi(x+e)) fixes a quantity that is equal in the two bulk phases:
+    p = (D / tau_s) C + G psi(C)^2, D = c_s^2 (tau_s - 1/2) the solute
+    diffusivity (c_s^2 = 1/2 on D2Q4, 1/3 on D2Q9) -- the tau_s of the
+    velocity term tau_s F / C turns D into D / tau_s.  A missing tau_s, a
+    weighted or eight-neighbour stencil, or a wrong sign breaks either the
+    equality or the phase contrast."""
+    C = _flat_solute_interface(q, tau_s, G, Cl, Cg, 20000)
+    cl, cg = C[64].mean(), C[0].mean()
+    D = (0.5 if q == 4 else 1.0 / 3.0) * (tau_s - 0.5)
+    p = lambda c: D / tau_s * c + G * math.exp(-5e-3 / c) ** 2
+    assert cl > 4 * cg
+    assert np.ptp(C[56:72]) <= 1e-9 * cl and np.ptp(C[:8]) <= 1e-9 * cl   # flat bulk phases
+    assert p(cl) == pytest.approx(p(cg), rel=1e-9)
+
+
+def test_intersolute_without_strength_changes_nothing():
+    """G = 0: the run equals the one without the command, bit for bit."""
+    nx, ny = 30, 22
+    runs = []
+    for with_cmd in (False, True):
+        o = Oracle(nx, ny)
+        o.fluids(1, 0.9)
+        o.set_fields(0, 1.0, 0.01, 0.0)
+        o.obstacle_circle(10, 10, 3.0)
+        o.solute(0.8, 4)
+        if with_cmd:
+            o.intersolute(0.0, 1.0, 5e-3)
+        o.set_concentration(5e-3 * (1 + 0.1 * np.sin(np.arange(nx * ny))))
+        o.iteration(40)
+        runs.append(o.get_g())
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_intersolute_conserves_solute_momentum():
+    """The force is antisymmetric between neighbour pairs, so on a periodic
+    box with the solvent at rest and tau_s = 1 the solute momentum after a
+    step, sum C u' = tau_s sum F, is zero while the local fluxes are not."""
+    rng = np.random.default_rng(8)
+    nx, ny = 24, 20
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.set_fields(0, 1.0)
+    o.solute(1.0, 9)
+    o.intersolute(-5e-3, 1.0, 5e-3)
+    o.set_concentration(5e-3 * (1 + 0.5 * rng.uniform(-1, 1, nx * ny)))
+    o.iteration(1)
+    g = o.get_g()
+    jx, jy = np.tensordot(EX, g, 1), np.tensordot(EY, g, 1)
+    assert np.abs(jx).max() > 1e-6
+    assert abs(jx.sum()) <= 1e-16 * nx * ny and abs(jy.sum()) <= 1e-16 * nx * ny
