@@ -252,6 +252,16 @@ int lb2d_interforce(lb2d_ctx *ctx, double G, double psi0, double rho0);
 int lb2d_adhesiveforce(lb2d_ctx *ctx, double G, double psi0, double rho0,
                        int comp);
 
+/* intersolute command: adds tau_s F / C to the solvent velocity in the
+ * solute equilibrium, with F = -G psi(x) sum_{i=1..4} psi(x + e_i) e_i
+ * over the four axis neighbours (no lattice weights) and
+ * psi = psi0 exp(-C0 / C).  The concentrations are those of the same step
+ * after streaming (as for interforce); psi is 0 on solids, where C <= 0
+ * and across a wall of a non-periodic solute axis, and the term is added
+ * only where C > 0.  Needs the solute command (LB2D_E_ORDER otherwise);
+ * G and psi0 finite, C0 > 0 (LB2D_E_INVAL).  Before bind. */
+int lb2d_intersolute(lb2d_ctx *ctx, double G, double psi0, double C0);
+
 /* ------------------------------------------------------------- memory */
 
 /* Bytes of device memory one lattice needs with the given storage format

@@ -61,6 +61,8 @@ struct lb2d_ctx {
     double Gads[2] = {0.0, 0.0};
     int q = 0;
     double tau_s = 1.0;
+    bool isol = false;               // intersolute command
+    double is_G = 0.0, is_psi0 = 0.0, is_C0 = 1.0;
     std::vector<SoluteOpen> sopens;  // solute openings
     bool reaction = false;
     double kr = 0, Cs = 0, b0 = 0, bmax = 0;
@@ -294,6 +296,11 @@ FullParams full_params(const lb2d_ctx *c) {
         p.refl[k] = (c->refl_dev && k < c->ncomp) ? c->refl_dev + (size_t)k * c->n() : nullptr;
         p.grow_R[k] = c->grow_R;
     }
+    p.isol = c->isol ? 1 : 0;
+    p.is_G = c->is_G;
+    p.is_psi0 = c->is_psi0;
+    p.is_C0 = c->is_C0;
+    p.tau_s = c->tau_s;
     p.nopen = (int)c->opens.size();
     for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
@@ -556,6 +563,19 @@ int lb2d_solute(lb2d_ctx *c, double tau_s, int q) {
     c->q = q;
     c->tau_s = tau_s;
     c->have_solute = true;
+    return LB2D_OK;
+}
+
+int lb2d_intersolute(lb2d_ctx *c, double G, double psi0, double C0) {
+    int rc = pre_command(c);
+    if (rc) return rc;
+    if (!c->have_solute) return c->fail(LB2D_E_ORDER, "intersolute needs the solute command first");
+    if (!std::isfinite(G) || !std::isfinite(psi0)) return c->fail(LB2D_E_INVAL, "G and psi0 must be finite");
+    if (!(C0 > 0.0) || !std::isfinite(C0)) return c->fail(LB2D_E_INVAL, "C0 must be positive");
+    c->isol = true;
+    c->is_G = G;
+    c->is_psi0 = psi0;
+    c->is_C0 = C0;
     return LB2D_OK;
 }
 

@@ -127,6 +127,9 @@ struct FullParams {
     double *refl[2];      // per node and component: reflected share R of a
                           // diagonal mode hitting this solid (0 noslip, 1 slip)
     double grow_R[2];     // R of solids made by growth
+    int isol;             // intersolute force on the solute
+    double is_G, is_psi0, is_C0;  // its strength and psi = psi0 exp(-C0 / C)
+    double tau_s;         // solute relaxation time
     StepCoef<double> cd;  // FP64 coefficients
     StepCoef<float> cf;   // the same rounded to FP32
 };

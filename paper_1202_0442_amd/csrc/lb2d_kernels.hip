@@ -712,10 +712,14 @@ __device__ __forceinline__ void wave_sum3(double (&v)[4]) {
 //     sees the post-stream densities of this step;
 //  4. forces (aveforce, aveacceleration, cohesion, adhesion), the common
 //     velocity u' and each component's equilibrium velocity, collision;
-//  5. solute collision at the solvent velocity of Eq. (u_solvent);
+//  5. solute collision at the solvent velocity of Eq. (u_solvent), plus
+//     tau_s F / C of the intersolute force (psi(C) of the tile and its ring
+//     in LDS, from the concentrations after streaming);
 //  6. deposits and growth decisions of solid lanes next to fluid.
 // A brick is stored iff it holds a fluid node (solid lanes store zeros),
 // so every store writes whole lines and all-solid bricks move no data.
+// EXT instantiations carry the features most lattices lack (momentum
+// openings, slip/mixed solids, intersolute), each switched on at run time.
 // Population addresses are byte offsets of type O from the array base:
 // 32-bit when the arrays are below 4 GiB (a uniform base plus a 32-bit
 // lane offset, no 64-bit lane arithmetic), 64-bit otherwise.
@@ -728,7 +732,99 @@ __device__ __forceinline__ const StepCoef<double> &coef<double>(const FullParams
 template <>
 __device__ __forceinline__ const StepCoef<float> &coef<float>(const FullParams &p) { return p.cf; }
 
-template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, bool BND, int TX, int TY>
+// Solute populations arriving at fluid node (x, y) (inside the box) after
+// streaming (solute command): bounce-back, or the reactive link rule, at
+// solid sources; bounce-back across a closed wall of a non-periodic solute
+// axis; and the rules of the solute opening that holds the node
+// (inlet_solute/outlet_solute, App. B).  lk is the node's link word, s and
+// src the brick offsets of the node and of node - e_i.  Adds the opening's
+// inflow to tal[0] and the populations that left through it to tal[1]; a
+// node of a flux opening returns flux = true and its concentration Cf.
+template <typename S, typename O, int SQ, bool REACT, typename R>
+__device__ __forceinline__ void solute_pull(const FullParams &p, const StepCoef<R> &q, const S *__restrict__ gin,
+                                            O pl, int x, int y, unsigned lk, O s, const O (&src)[9], R (&g)[9],
+                                            double (&tal)[4], bool &flux, R &Cf) {
+    const int nx = p.nx, ny = p.ny;
+    const unsigned pnx = p.pnx;
+    // nodes on a wall of a non-periodic solute axis
+    const bool edge = (!p.sxper && (x == 0 || x == nx - 1)) || (!p.syper && (y == 0 || y == ny - 1));
+    const int kop = edge ? find_solute_opening(p, x, y) : -1;
+    const int kw = kop >= 0 ? p.sopen[kop].wall : -1;
+    bool unk[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        unk[i] = false;
+        if (!shas<SQ>(i)) continue;
+        // a pull across a closed wall bounces back; across the wall of this
+        // node's opening the population is unknown
+        const int sxr = x - ex(i), syr = y - ey(i);
+        const bool cross = edge && ((!p.sxper && (sxr < 0 || sxr >= nx)) || (!p.syper && (syr < 0 || syr >= ny)));
+        unk[i] = kw >= 0 && enters_across<SQ>(kw, i);
+        const bool solid_src = ((lk >> opp(i)) & 1u) && !cross;
+        const bool bb = solid_src || cross;
+        const O a = bb ? (O)spl<SQ>(opp(i)) * pl + s : (O)spl<SQ>(i) * pl + src[i];
+        R v = ldb(gin, a, i);
+        if constexpr (REACT) {
+            R gi;
+            reactive_link<SQ, R>(i, q, v, gi);
+            v = solid_src ? gi : v;
+        }
+        g[i] = v;
+    }
+    if (kop >= 0) {
+        const SoluteOpen &o = p.sopen[kop];
+        R known = R(0), wu = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if (!shas<SQ>(i)) continue;
+            if (unk[i]) wu += swgt<SQ, R>(i);
+            else known += g[i];
+        }
+        if (o.style == 1) {
+            // dirichlet: the unknowns share Cbar - C' by weight
+            const R deficit = (R(o.value) - known) * rcp(wu);
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (unk[i]) {
+                    g[i] = swgt<SQ, R>(i) * deficit;
+                    tal[0] += (double)g[i];
+                }
+        } else if (o.style == 2) {
+            // adiabatic: each unknown copies its mirror across the wall
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (unk[i]) {
+                    g[i] = kw < 2 ? g[mirx(i)] : g[miry(i)];
+                    tal[0] += (double)g[i];
+                }
+        } else {
+            // flux (App. B): C = (v C0 + D C1)/(D + v) at an inlet,
+            // (v C0 - D C1)/(v - D) at an outlet, C1 the concentration of
+            // the next node inward at the previous time level (0 if it is
+            // solid)
+            const int nxw = kw == 0 ? 1 : kw == 1 ? -1 : 0, nyw = kw == 2 ? 1 : kw == 3 ? -1 : 0;
+            const int in_dir = kw == 0 ? 1 : kw == 1 ? 3 : kw == 2 ? 2 : 4;  // e_in = n
+            const O s1 = brick_off<S, O>((unsigned)(x + nxw), (unsigned)(y + nyw), pnx);
+            R C1 = R(0);
+            if (!((lk >> in_dir) & 1u)) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    if (shas<SQ>(i)) C1 += ldb(gin, (O)spl<SQ>(i) * pl + s1, i);
+            }
+            const R v = R(o.v), C0 = R(o.value), D = q.Dsol;
+            Cf = o.outlet ? (v * C0 - D * C1) / (v - D) : (v * C0 + D * C1) / (D + v);
+            flux = true;
+            tal[0] += (double)(Cf - known);
+        }
+        // populations of the previous step that left through the opening
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            if (shas<SQ>(i) && enters_across<SQ>(kw, opp(i)))
+                tal[1] += (double)ldb(gin, (O)spl<SQ>(i) * pl + s, i);
+    }
+}
+
+template <typename S, typename O, int NC, bool SC, int SQ, bool REACT, bool EXT, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using C = Codec<S>;
     using R = typename C::R;
@@ -739,7 +835,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     __shared__ R srho[SC ? NC : 1][SC ? TY + 2 : 1][SC ? TX + 2 : 1];
     // mask tile with a kSlipRing-node ring for the slip rules: the rule
     // reads two nodes around a node, and the density halo lies one node out
-    __shared__ uint8_t smask[BND ? TY + 2 * kSlipRing : 1][BND ? TX + 2 * kSlipRing : 1];
+    __shared__ uint8_t smask[EXT ? TY + 2 * kSlipRing : 1][EXT ? TX + 2 * kSlipRing : 1];
+    // psi(C) of the intersolute force with a one-node ring
+    __shared__ R spsi[EXT && SOL ? TY + 2 : 1][EXT && SOL ? TX + 2 : 1];
     const StepCoef<R> &q = coef<R>(p);
 
     const int nx = p.nx, ny = p.ny;
@@ -769,7 +867,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     const unsigned lane = __lane_id();
     const bool store = valid && ((bal >> (lane & 32u)) & 0xffffffffull) != 0ull;
 
-    if constexpr (BND) {
+    if constexpr (EXT) {
         if (p.slip) {
             constexpr int MW = TX + 2 * kSlipRing, MH = TY + 2 * kSlipRing;
             for (int k = tid; k < MW * MH; k += TX * TY) {
@@ -819,7 +917,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                         const bool wall = (hl >> opp(i)) & 1u;
                         const O a = wall ? (O)opp(i) * pl + hs : (O)i * pl + hsrc[i];
                         R v = ldb(fin, a, i);
-                        if constexpr (BND) {
+                        if constexpr (EXT) {
                             if (p.slip && i >= 5 && wall)
                                 v = slip_diagonal<S, O, R>(p, c, fin, pl, smask, hx - 1, hy - 1, (int)gx, (int)gy, i,
                                                            v, q.rho_ref[c]);
@@ -859,7 +957,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 d[c][i] = ldb(fin, a, i);
             }
         }
-        if constexpr (BND) {
+        if constexpr (EXT) {
             // slip / mixed solids: diagonal modes reflected off flat walls
             if (p.slip && pull) {
                 const S *__restrict__ fin = (const S *)p.f[parity][c];
@@ -884,95 +982,72 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
 
     // 2. solute pull (issued before the density-tile barrier so that its
     // latency overlaps the halo pulls): bounce-back or reactive link at
-    // walls, the opening rules on open x walls
+    // walls, the opening rules on open walls
     R g[9];
-    bool unk[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        g[i] = R(0);
-        unk[i] = false;
-    }
+    for (int i = 0; i < 9; ++i) g[i] = R(0);
     double tal[4] = {0.0, 0.0, 0.0, 0.0};  // inflow, outflow, consumed deposit
     bool flux = false;   // node of a flux opening: all populations to g_eq(Cf)
     R Cf = R(0);
     if constexpr (SOL) {
         const S *__restrict__ gin = (const S *)p.g[parity];
-        // lanes on a wall of a non-periodic solute axis (edge tiles only)
-        const bool edge = valid && fluid &&
-                          ((!p.sxper && (x == 0 || x == nx - 1)) || (!p.syper && (y == 0 || y == ny - 1)));
-        const int kop = edge ? find_solute_opening(p, x, y) : -1;
-        const int kw = kop >= 0 ? p.sopen[kop].wall : -1;
-        if (valid && fluid) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                if (!shas<SQ>(i)) continue;
-                // a pull across a closed wall bounces back; across the wall
-                // of this node's opening the population is unknown
-                const int sxr = x - ex(i), syr = y - ey(i);
-                const bool cross = edge && ((!p.sxper && (sxr < 0 || sxr >= nx)) || (!p.syper && (syr < 0 || syr >= ny)));
-                unk[i] = kw >= 0 && enters_across<SQ>(kw, i);
-                const bool solid_src = ((lk >> opp(i)) & 1u) && !cross;
-                const bool bb = solid_src || cross;
-                const O a = bb ? (O)spl<SQ>(opp(i)) * pl + s : (O)spl<SQ>(i) * pl + src[i];
-                R v = ldb(gin, a, i);
-                if constexpr (REACT) {
-                    R gi;
-                    reactive_link<SQ, R>(i, q, v, gi);
-                    v = solid_src ? gi : v;
-                }
-                g[i] = v;
-            }
+        // lanes past a ragged edge pull too when the intersolute stencil
+        // needs their concentration (their tallies are dropped)
+        if ((valid || (EXT && p.isol)) && fluid)
+            solute_pull<S, O, SQ, REACT, R>(p, q, gin, pl, (int)ux_, (int)uy_, lk, s, src, g, tal, flux, Cf);
+        if constexpr (EXT) {
+            if (!valid) tal[0] = tal[1] = 0.0;
         }
-        if (kop >= 0) {
-            const SoluteOpen &o = p.sopen[kop];
-            R known = R(0), wu = R(0);
+    }
+    // intersolute: psi(C) of the tile and of its one-node ring, from the
+    // concentrations after streaming (the ring nodes' solute populations are
+    // pulled again); 0 on solids, where C <= 0 and across a wall of a
+    // non-periodic solute axis
+    if constexpr (EXT && SOL) {
+        if (p.isol) {
+            const R psi0 = R(p.is_psi0), C0 = R(p.is_C0);
+            R Cn = R(0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                if (!shas<SQ>(i)) continue;
-                if (unk[i]) wu += swgt<SQ, R>(i);
-                else known += g[i];
-            }
-            if (o.style == 1) {
-                // dirichlet: the unknowns share Cbar - C' by weight
-                const R deficit = (R(o.value) - known) * rcp(wu);
+            for (int i = 0; i < 9; ++i)
+                if (shas<SQ>(i)) Cn += g[i];
+            if (flux) Cn = Cf;
+            spsi[ly + 1][lx + 1] = (fluid && !across_closed(p, x, y) && Cn > R(0)) ? psi_of(psi0, C0, Cn) : R(0);
+            const S *__restrict__ gin = (const S *)p.g[parity];
+            for (int j = tid; j < 2 * (TX + 2) + 2 * TY; j += TX * TY) {
+                int rx, ry;
+                halo_slot<TX, TY>(j, rx, ry);
+                const int cx = tx0 + rx - 1, cy = ty0 + ry - 1;
+                R ps = R(0);
+                if (!across_closed(p, cx, cy)) {
+                    const unsigned gx = (unsigned)wrapi(cx, nx), gy = (unsigned)wrapi(cy, ny);
+                    const unsigned hl = links[(size_t)gy * nx + gx];
+                    if (!(hl & 1u)) {
+                        const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
+                        const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
+                        const O hs = brick_off<S, O>(gx, gy, pnx);
+                        const O hsrc[9] = {hs,
+                                           brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
+                                           brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
+                                           brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
+                                           brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
+                        R gh[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    if (unk[i]) {
-                        g[i] = swgt<SQ, R>(i) * deficit;
-                        tal[0] += (double)g[i];
+                        for (int i = 0; i < 9; ++i) gh[i] = R(0);
+                        double th[4] = {0.0, 0.0, 0.0, 0.0};
+                        bool fh = false;
+                        R Ch = R(0);
+                        solute_pull<S, O, SQ, REACT, R>(p, q, gin, pl, (int)gx, (int)gy, hl, hs, hsrc, gh, th, fh, Ch);
+                        R Cr = R(0);
+#pragma unroll
+                        for (int i = 0; i < 9; ++i)
+                            if (shas<SQ>(i)) Cr += gh[i];
+                        if (fh) Cr = Ch;
+                        if (Cr > R(0)) ps = psi_of(psi0, C0, Cr);
                     }
-            } else if (o.style == 2) {
-                // adiabatic: each unknown copies its mirror across the wall
-#pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    if (unk[i]) {
-                        g[i] = kw < 2 ? g[mirx(i)] : g[miry(i)];
-                        tal[0] += (double)g[i];
-                    }
-            } else {
-                // flux (App. B): C = (v C0 + D C1)/(D + v) at an inlet,
-                // (v C0 - D C1)/(v - D) at an outlet, C1 the concentration of
-                // the next node inward at the previous time level
-                // the next node inward, 0 if it is solid
-                const int nxw = kw == 0 ? 1 : kw == 1 ? -1 : 0, nyw = kw == 2 ? 1 : kw == 3 ? -1 : 0;
-                const int in_dir = kw == 0 ? 1 : kw == 1 ? 3 : kw == 2 ? 2 : 4;  // e_in = n
-                const O s1 = brick_off<S, O>((unsigned)(x + nxw), (unsigned)(y + nyw), pnx);
-                R C1 = R(0);
-                if (!((lk >> in_dir) & 1u)) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        if (shas<SQ>(i)) C1 += ldb(gin, (O)spl<SQ>(i) * pl + s1, i);
                 }
-                const R v = R(o.v), C0 = R(o.value), D = q.Dsol;
-                Cf = o.outlet ? (v * C0 - D * C1) / (v - D) : (v * C0 + D * C1) / (D + v);
-                flux = true;
-                tal[0] += (double)(Cf - known);
+                spsi[ry][rx] = ps;
             }
-            // populations of the previous step that left through the opening
-#pragma unroll
-            for (int i = 1; i < 9; ++i)
-                if (shas<SQ>(i) && enters_across<SQ>(kw, opp(i)))
-                    tal[1] += (double)ldb(gin, (O)spl<SQ>(i) * pl + s, i);
+            __syncthreads();
         }
     }
     // deposit gathered by solid nodes next to fluid (loads issued early too):
@@ -1113,12 +1188,24 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     // 7. solute collision at the solvent velocity (in place)
     if constexpr (SOL) {
         const R isrh = rcp(srh);
-        const R usx = sjx * isrh, usy = sjy * isrh;
+        R usx = sjx * isrh, usy = sjy * isrh;
         R Cc = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (shas<SQ>(i)) Cc += g[i];
         if (flux) Cc = Cf;
+        if constexpr (EXT) {
+            // intersolute: u_s + tau_s F / C, F = -G psi(x) sum_{i=1..4}
+            // psi(x + e_i) e_i over the four axis neighbours
+            if (p.isol && Cc > R(0)) {
+                const R ps = spsi[ly + 1][lx + 1];
+                const R sx = spsi[ly + 1][lx + 2] - spsi[ly + 1][lx];
+                const R sy = spsi[ly + 2][lx + 1] - spsi[ly][lx + 1];
+                const R G = R(p.is_G), ts = R(p.tau_s);
+                usx = usx + ts * (-G * ps * sx) / Cc;
+                usy = usy + ts * (-G * ps * sy) / Cc;
+            }
+        }
         // flux-opening nodes take the equilibrium itself (relaxation 1)
         const R oms = flux ? R(1) : q.omega_s;
 #pragma unroll
@@ -1734,12 +1821,12 @@ int growth_blocks(int nx, int ny) {
     return segs < kGrowBlocks ? segs : kGrowBlocks;
 }
 
-template <typename S, typename O, int SQ, bool BND>
+template <typename S, typename O, int SQ, bool EXT>
 static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     const int nblk = full_tiles(p.nx, p.ny);
     const dim3 g(nblk), b(kTX * kTY);
 #define LB2D_FULL(NC_, SC_, REACT_) \
-    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, BND, kTX, kTY>), g, b, 0, st, p, parity)
+    hipLaunchKernelGGL((k_full<S, O, NC_, SC_, SQ, REACT_, EXT, kTX, kTY>), g, b, 0, st, p, parity)
     if (p.ncomp == 2) {
         if (sc) {
             if (react) LB2D_FULL(2, true, true);
@@ -1763,9 +1850,9 @@ static void full_dispatch_sq(const FullParams &p, int parity, bool sc, bool reac
 template <typename S, int SQ>
 static void full_dispatch_off(const FullParams &p, int parity, bool sc, bool react, hipStream_t st) {
     // 32-bit byte offsets when every population array (9 planes) is below 4 GiB
-    // the boundary features (momentum openings, slip solids) only in
-    // lattices that have them
-    const bool open = p.nopen > 0 || p.slip;
+    // the extended features (momentum openings, slip solids, intersolute)
+    // only in lattices that have them
+    const bool open = p.nopen > 0 || p.slip || p.isol;
     if (fits32(p.pplane, sizeof(S))) {
         if (open) full_dispatch_sq<S, uint32_t, SQ, true>(p, parity, sc, react, st);
         else full_dispatch_sq<S, uint32_t, SQ, false>(p, parity, sc, react, st);

@@ -50,6 +50,7 @@ _SIGS = {
     "lb2d_solute": [_P, _D, _I],
     "lb2d_solute_opening": [_P, ctypes.c_char_p, ctypes.c_char_p, _D],
     "lb2d_boundary_style": [_P, ctypes.c_char_p, ctypes.c_double],
+    "lb2d_intersolute": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "lb2d_obstacle_style": [_P, ctypes.c_int, ctypes.c_char_p, ctypes.c_double],
     "lb2d_rounding": [_P, ctypes.c_char_p, ctypes.c_uint64],
     "lb2d_solute_opening_range": [_P, ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p,
@@ -180,6 +181,9 @@ class Lattice:
 
     def solute_opening(self, wall, style, value=0.0):
         self._chk(_lib.lb2d_solute_opening(self._h, wall.encode(), style.encode(), value))
+
+    def intersolute(self, G, psi0, C0):
+        self._chk(_lib.lb2d_intersolute(self._h, float(G), float(psi0), float(C0)))
 
     def boundary_style(self, style, R=0.0):
         self._chk(_lib.lb2d_boundary_style(self._h, style.encode(), float(R)))

@@ -146,6 +146,17 @@ def slip_box_case(nx, ny, seed, style=("hybrid", 0.0), two=True, G=None, accel=1
     return case
 
 
+def intersolute_case(nx, ny, seed, q=4, tau_s=1.0, isol=(-5e-3, 1.0, 5e-3), C0=5e-3, noise=0.1, nd=0):
+    """The paper's intersolute example (G = -5e-3, psi0 = 1, C0 = 5e-3):
+    one fluid at rest, solute of mean C0 with a uniform random noise of
+    relative size `noise`, optionally a few discs."""
+    rng = np.random.default_rng(seed)
+    circles = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), float(rng.uniform(1.5, 4.0))) for _ in range(nd)]
+    n = nx * ny
+    return dict(nx=nx, ny=ny, tau=1.0, circles=circles, solute=tau_s, q=q, isol=isol,
+                C=C0 * (1 + noise * rng.uniform(-1, 1, n)))
+
+
 def build_oracle(case):
     o = Oracle(case["nx"], case["ny"])
     if "fluids" in case:
@@ -192,6 +203,8 @@ def build_oracle(case):
             o.solute_opening_range(*op)
         if case.get("reaction") is not None:
             o.surface_reaction(*case["reaction"])
+        if case.get("isol") is not None:
+            o.intersolute(*case["isol"])
         o.set_concentration(case.get("C", 0.0))
     return o
 
@@ -208,6 +221,8 @@ def build_gpu(case, storage="f32", bind=True, stream=None):
             g.solute_opening(wall, style, val)
         for op in case.get("sopen", []):
             g.solute_opening_range(*op)
+        if case.get("isol") is not None:
+            g.intersolute(*case["isol"])
     g.boundary_style(*case.get("style", ("noslip", 0.0)))
     for r in case.get("rects", []):
         g.obstacle_rect(*r)

@@ -66,10 +66,17 @@ def test_solute_commands_need_solute():
     L.lattice("d2q9", 10, 10, 1.0)
     for call in (lambda: L.solute_opening("xlo", "dirichlet", 1.0),
                  lambda: L.surface_reaction(1e-3, 0.0, "growth", 0.0, 1.0, 1),
-                 lambda: L.set_concentration(np.zeros(100))):
+                 lambda: L.set_concentration(np.zeros(100)),
+                 lambda: L.intersolute(-5e-3, 1.0, 5e-3)):
         with pytest.raises(lb2d.LB2DError) as e:
             call()
         assert e.value.code == lb2d.E_ORDER
+    L.solute(1.0, 4)
+    for args in ((-5e-3, 1.0, 0.0), (-5e-3, 1.0, -1.0), (float("nan"), 1.0, 5e-3), (-5e-3, float("inf"), 5e-3)):
+        with pytest.raises(lb2d.LB2DError) as e:
+            L.intersolute(*args)
+        assert e.value.code == lb2d.E_INVAL
+    L.intersolute(-5e-3, 1.0, 5e-3)
 
 
 def test_unsupported_forms():
