@@ -242,6 +242,21 @@ __device__ __forceinline__ LB2D_GLOBAL T *gbl(T *p) {
     return (LB2D_GLOBAL T *)p;
 }
 
+// Streaming store of one population value (a vector global store with the
+// non-temporal hint): the new populations are not read again in the same
+// step, so they need not stay in the caches.  16-bit values are stored
+// through their bit pattern.
+template <typename S>
+__device__ __forceinline__ void st_stream(LB2D_GLOBAL S *p, S v) {
+    if constexpr (sizeof(S) == 2) {
+        uint16_t bits;
+        __builtin_memcpy(&bits, &v, 2);
+        __builtin_nontemporal_store(bits, (LB2D_GLOBAL uint16_t *)p);
+    } else {
+        __builtin_nontemporal_store(v, p);
+    }
+}
+
 // Wavefront-uniform copy of one step's lattice parameters (scalar registers).
 template <typename S>
 struct PlainArgs {
@@ -379,7 +394,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
             S e;
             if constexpr (SR) e = C::enc_sr(v, i, (i & 1) ? (w[i >> 1] << 16) : w[i >> 1]);
             else e = C::enc(v, i);
-            *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+            st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
         }
     }
 }
@@ -562,7 +577,7 @@ __device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, 
 }
 template <typename S, typename O>
 __device__ __forceinline__ void stb(S *__restrict__ base, O off, S v) {
-    *(S *)((char *)base + off) = v;
+    st_stream((LB2D_GLOBAL S *)((LB2D_GLOBAL char *)gbl(base) + off), v);
 }
 
 // Slip rule of the boundary_style command at diagonal mode k of node
@@ -1734,18 +1749,25 @@ __global__ void __launch_bounds__(256) k_budget_final(const double *part, int nb
 }
 
 // Plain copy kernel (read + write n floats) used to measure the practical
-// HBM ceiling next to the stencil.
+// HBM ceiling next to the stencil.  Streaming (non-temporal) loads and
+// stores: the fastest plain copy measured on the MI355X.
 __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n4) {
     // each block copies 4 consecutive chunks of 256 float4: four loads in
     // flight per thread before the stores
     const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
-    float4 v[4];
+    const LB2D_GLOBAL float *ga = (const LB2D_GLOBAL float *)gbl(a);
+    LB2D_GLOBAL float *gb = (LB2D_GLOBAL float *)gbl(b);
+    float v[4][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (base + 256 * k < n4) v[k] = a[base + 256 * k];
+        if (base + 256 * k < n4)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[k][c] = __builtin_nontemporal_load(ga + 4 * (base + 256 * k) + c);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (base + 256 * k < n4) b[base + 256 * k] = v[k];
+        if (base + 256 * k < n4)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(v[k][c], gb + 4 * (base + 256 * k) + c);
 }
 
 inline int grid1d(size_t n, int bs = 256) {
