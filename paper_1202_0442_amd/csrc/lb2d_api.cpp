@@ -183,7 +183,8 @@ struct Layout {
 // Padded plane geometry of the populations for the given storage.
 void plane_geometry(const lb2d_ctx *c, int storage, unsigned *pnx, size_t *pplane) {
     const unsigned bh = (unsigned)brick_h_for((int)storage_bytes(storage));
-    const unsigned px = (unsigned)((c->nx + kBrickW - 1) / kBrickW * kBrickW);
+    const unsigned bw = (unsigned)brick_w_for((int)storage_bytes(storage));
+    const unsigned px = (unsigned)((c->nx + bw - 1) / bw * bw);
     const unsigned py = (unsigned)((c->ny + bh - 1) / bh * bh);
     *pnx = px;
     *pplane = (size_t)px * py;

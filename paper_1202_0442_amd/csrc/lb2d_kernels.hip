@@ -175,7 +175,7 @@ __device__ __forceinline__ int wrapi(int a, int n) {
 // Element index of node (x, y) in a brick-layout plane of padded width pnx.
 template <typename S>
 __host__ __device__ __forceinline__ size_t brick_index(unsigned x, unsigned y, unsigned pnx) {
-    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
+    constexpr unsigned W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
     return ((size_t)(y / H) * (pnx / W) + (x / W)) * (W * H) + (y % H) * W + (x % W);
 }
 
@@ -185,7 +185,7 @@ __host__ __device__ __forceinline__ size_t brick_index(unsigned x, unsigned y, u
 // pointer plus a 32-bit lane offset needs no 64-bit lane arithmetic).
 template <typename S, typename O>
 __device__ __forceinline__ O brick_off(unsigned x, unsigned y, unsigned pnx) {
-    constexpr unsigned W = kBrickW, H = brick_h_for(sizeof(S));
+    constexpr unsigned W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
     return (((O)(y / H) * (O)(pnx / W) + (O)(x / W)) * (O)(W * H) + (O)((y % H) * W + (x % W))) * (O)sizeof(S);
 }
 
@@ -229,11 +229,14 @@ __device__ void block_sum(double (&v)[K], double *sh, double *out) {
 //    solid, so the nine population addresses (own opposite population when
 //    the source is solid: noslip bounce-back) are known after one load and
 //    the nine loads are issued together;
-//  * a wavefront with at least one fluid lane stores all its lanes (solid
-//    lanes store zeros, which nothing ever reads), so every store writes
-//    whole 128-byte lines -- partial lines along obstacle edges would make
-//    HBM read-modify-write them; wavefronts that are entirely solid do no
-//    memory work at all.
+//  * a brick with at least one fluid node stores all its nodes (solid
+//    nodes store zeros, which nothing ever reads), so every store writes
+//    whole bricks -- partial segments along obstacle edges would make the
+//    memory read-modify-write them; bricks that are entirely solid are
+//    never written, and wavefronts that are entirely solid do no memory
+//    work at all;
+//  * the stores are streaming (non-temporal): nothing reads the new
+//    populations in the same step.
 // Pointers known to address global memory (so the compiler emits global_*
 // rather than flat_* instructions for pointers read from device tables).
 #define LB2D_GLOBAL __attribute__((address_space(1)))
@@ -321,7 +324,7 @@ template <typename S, typename O, bool SR>
 __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside, unsigned tkey) {
     using C = Codec<S>;
     using R = typename C::R;
-    constexpr unsigned kGroup = kBrickW * brick_h_for(sizeof(S));  // lanes per brick
+    constexpr unsigned kGroup = brick_w_for(sizeof(S)) * brick_h_for(sizeof(S));  // lanes per brick
     const unsigned nx = L.nx, ny = L.ny, pnx = L.pnx;
     const unsigned s_row = inside ? (unsigned)y * nx + (unsigned)x : 0u;
     const unsigned lk = inside ? (unsigned)gbl(L.links)[s_row] : 1u;
@@ -404,7 +407,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
 // one brick, so each store of a wavefront writes whole bricks.
 template <typename S>
 __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
-    constexpr int W = kBrickW, H = brick_h_for(sizeof(S));
+    constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
     const int b = t / (W * H), k = t % (W * H);
     lx = b * W + k % W;
     ly = k / W;
@@ -414,7 +417,8 @@ __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
 // device step count + k + 1; only stochastic rounding reads it).
 template <typename S, typename O, bool SR>
 __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k) {
-    constexpr int TW = 256 / (kBrickW * brick_h_for(sizeof(S))) * kBrickW, TH = brick_h_for(sizeof(S));
+    constexpr int TW = 256 / (brick_w_for(sizeof(S)) * brick_h_for(sizeof(S))) * brick_w_for(sizeof(S)),
+                  TH = brick_h_for(sizeof(S));
     int lx, ly;
     brick_thread<S>(threadIdx.x, lx, ly);
     const int x = blockIdx.x * TW + lx;
@@ -444,7 +448,7 @@ __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ 
 
 // --------------------------------------------------------- general step
 
-constexpr int kTX = 32;   // tile width (nodes, whole 8-node bricks)
+constexpr int kTX = 32;   // tile width (nodes, whole bricks)
 constexpr int kTY = 8;    // tile height (nodes, whole 4-node bricks); measured:
                           // 32x8 and 16x16 beat 64x4, 32x4, 64x8, 128x4, 128x8
 
@@ -493,13 +497,13 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
     return (k < len) ? start + k : -1;
 }
 
-// Node of a TX x TY tile handled by thread t: 32 consecutive threads cover
-// one 8x4 brick, the tile's bricks in row-major order, so a wavefront's
-// loads and stores of one plane touch two whole 128-byte brick lines (FP32)
-// or four (FP64).
-template <int TX>
+// Node of a TX x TY tile handled by thread t: BW x 4 consecutive threads
+// cover one brick, the tile's bricks in row-major order, so a wavefront's
+// loads and stores of one plane touch whole bricks (four 64-byte FP32
+// bricks, two 256-byte FP64 bricks).
+template <int TX, int BW>
 __device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
-    constexpr int BW = kBrickW, BH = 4, BPR = TX / BW;
+    constexpr int BH = 4, BPR = TX / BW;
     const int b = t / (BW * BH), k = t % (BW * BH);
     lx = (b % BPR) * BW + k % BW;
     ly = (b / BPR) * BH + k / BW;
@@ -845,8 +849,8 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using R = typename C::R;
     constexpr bool SOL = SQ != 0;
     constexpr O SB = (O)sizeof(S);
-    static_assert(brick_h_for(sizeof(S)) == 4, "general step: 8x4 bricks");
-    static_assert(TX % kBrickW == 0 && TY % 4 == 0, "tile of whole bricks");
+    static_assert(brick_h_for(sizeof(S)) == 4, "general step: bricks of 4 rows");
+    static_assert(TX % brick_w_for(sizeof(S)) == 0 && TY % 4 == 0, "tile of whole bricks");
     __shared__ R srho[SC ? NC : 1][SC ? TY + 2 : 1][SC ? TX + 2 : 1];
     // mask tile with a kSlipRing-node ring for the slip rules: the rule
     // reads two nodes around a node, and the density halo lies one node out
@@ -865,7 +869,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
     const int tid = threadIdx.x;
     int lx, ly;
-    tile_thread<TX>(tid, lx, ly);
+    tile_thread<TX, brick_w_for(sizeof(S))>(tid, lx, ly);
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = (x < nx) && (y < ny);
     // lanes past a ragged lattice edge stand for the periodic image of their
@@ -877,10 +881,11 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     const bool solid = (lk & 1u) != 0u;
     const bool fluid = !solid;
     const bool pull = fluid && (valid || SC);
-    // a brick (32 lanes) is stored iff it holds a fluid node
+    // a brick is stored iff it holds a fluid node
     const unsigned long long bal = __ballot(valid && fluid);
     const unsigned lane = __lane_id();
-    const bool store = valid && ((bal >> (lane & 32u)) & 0xffffffffull) != 0ull;
+    constexpr unsigned kG = brick_w_for(sizeof(S)) * 4;  // lanes per brick
+    const bool store = valid && ((bal >> ((lane / kG) * kG)) & ((1ull << kG) - 1ull)) != 0ull;
 
     if constexpr (EXT) {
         if (p.slip) {
@@ -1798,7 +1803,8 @@ static bool fits32(size_t plane, size_t bytes) { return (unsigned long long)plan
 
 void plain_tile(int st, int *tw, int *th) {
     const int h = brick_h_for((int)storage_bytes(st));
-    *tw = 256 / (kBrickW * h) * kBrickW;
+    const int bw = brick_w_for((int)storage_bytes(st));
+    *tw = 256 / (bw * h) * bw;
     *th = h;
 }
 
