@@ -1,0 +1,143 @@
+"""Lattices whose population arrays exceed 4 GiB: the step kernels then
+address populations with 64-bit byte offsets instead of 32-bit ones.
+
+An 11600 x 11600 lattice (1.35e8 nodes; nine FP32 planes are 4.8 GB per
+component) is stepped on the GPU and sampled patches are compared with the
+oracle run on windows around them, as in the full-size tests: after k
+steps a node depends only on the initial state within k nodes (2k with
+the Shan-Chen stencil), so an oracle window of the patch plus that light
+cone, the obstacles reaching into it and the same initial fields gives
+the exact values of the patch interior.  Patches sit near the far corner
+too, where node offsets themselves need more than 32 bits.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1202_0442_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N = 11600
+RMIN, RMAX = 8.0, 24.0
+
+
+def _discs():
+    return inputs.boolean_discs(N, N, RMIN, RMAX, 0.3, seed=11600)
+
+
+def _window(discs, x0, y0, W):
+    """Discs reaching into the window [x0, x0+W) x [y0, y0+W) of the
+    periodic box, in window coordinates."""
+    d = np.array(discs)
+    dx = (d[:, 0] - x0) % N
+    dy = (d[:, 1] - y0) % N
+    dx = np.where(dx > N / 2, dx - N, dx)
+    dy = np.where(dy > N / 2, dy - N, dy)
+    r = d[:, 2]
+    sel = (dx >= -r - 1) & (dx <= W + r) & (dy >= -r - 1) & (dy <= W + r)
+    return [(int(a), int(b), float(c)) for a, b, c in zip(dx[sel], dy[sel], r[sel])]
+
+
+def _patches(rng, count):
+    pts = [(N - 5, N - 9), (N // 2 + 3, N - 2)]
+    pts += [(int(rng.integers(0, N)), int(rng.integers(0, N))) for _ in range(count - len(pts))]
+    return pts
+
+
+def _cut(a, x0, y0, W):
+    ys = (np.arange(W) + y0) % N
+    xs = (np.arange(W) + x0) % N
+    return a[np.ix_(ys, xs)]
+
+
+def test_one_fluid_fp32_above_4gib_sampled_patches():
+    from paper_1202_0442_amd import lb2d
+    import torch
+    discs = _discs()
+    tau, accel, k = 0.8, 1e-5, 32
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", N, N, tau)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in discs:
+        g.obstacle_circle(xc, yc, r)
+    g.aveacceleration(1, accel)
+    nbytes = g.workspace_bytes("f32")
+    print(f"workspace {nbytes / 2**30:.1f} GiB")
+    assert nbytes > 2 * 9 * 4 * N * N > 2 * 2**32
+    g.bind("f32", stream=torch.cuda.Stream())
+    g.iteration(k)
+    rho, ux, uy = g.moments(0)
+    gm = g.mask()
+    P, ring = 8, k + 2 * int(RMAX) + 2
+    W = P + 2 * ring
+    worst = 0.0
+    for (px, py) in _patches(np.random.default_rng(5), 6):
+        x0, y0 = (px - ring) % N, (py - ring) % N
+        o = Oracle(W, W)
+        o.fluids(1, tau)
+        o.aveacceleration(1, accel)
+        for c in _window(discs, x0, y0, W):
+            o.obstacle_circle(*c)
+        o.set_fields(0, 1.0)
+        sl = (slice(ring, ring + P), slice(ring, ring + P))
+        gsl = lambda a: _cut(a, x0, y0, W)[sl]
+        assert np.array_equal(gsl(gm), o.get_mask()[sl])
+        o.iteration(k)
+        orr, ox, oy = o.moments(0)
+        scale = max(np.abs(ox).max(), 1e-12)
+        err = max(np.abs(gsl(ux) - ox[sl]).max(), np.abs(gsl(uy) - oy[sl]).max()) / scale
+        fl = o.get_mask()[sl] == 0
+        if fl.any():
+            assert np.abs(gsl(rho)[fl] - orr[sl][fl]).max() <= 1e-5
+        worst = max(worst, err)
+    print(f"worst patch rel u err {worst:.3e}")
+    assert worst <= 1e-5
+
+
+def test_two_fluid_shan_chen_fp32_above_4gib_sampled_patches():
+    from paper_1202_0442_amd import lb2d
+    import torch
+    discs = _discs()
+    k, G = 16, 0.9
+    rng = np.random.default_rng(77)
+    ra = 0.5 + 0.2 * rng.uniform(-1, 1, (N, N))
+    rb = 0.5 + 0.2 * rng.uniform(-1, 1, (N, N))
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", N, N, 1.0)
+    g.fluids(1.0, 1.0)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in discs:
+        g.obstacle_circle(xc, yc, r)
+    g.set_fields(0, ra.ravel())
+    g.set_fields(1, rb.ravel())
+    g.interforce(G)
+    g.aveacceleration(1, 1e-5, 0)
+    g.bind("f32", stream=torch.cuda.Stream())
+    g.iteration(k)
+    got = [g.moments(c) for c in (0, 1)]
+    P, ring = 8, 2 * k + 2 * int(RMAX) + 2
+    W = P + 2 * ring
+    worst_r = worst_u = 0.0
+    for (px, py) in _patches(np.random.default_rng(6), 5):
+        x0, y0 = (px - ring) % N, (py - ring) % N
+        o = Oracle(W, W)
+        o.fluids(2, 1.0, 1.0)
+        o.interforce(G)
+        o.aveacceleration(1, 1e-5, 0)
+        for c in _window(discs, x0, y0, W):
+            o.obstacle_circle(*c)
+        o.set_fields(0, _cut(ra, x0, y0, W).ravel())
+        o.set_fields(1, _cut(rb, x0, y0, W).ravel())
+        o.iteration(k)
+        sl = (slice(ring, ring + P), slice(ring, ring + P))
+        fl = o.get_mask()[sl] == 0
+        for c in (0, 1):
+            orr, ox, oy = o.moments(c)
+            grr, gx, gy = (_cut(a, x0, y0, W)[sl] for a in got[c])
+            scale = max(np.abs(ox).max(), np.abs(oy).max(), 1e-12)
+            worst_u = max(worst_u, np.abs(gx - ox[sl]).max() / scale, np.abs(gy - oy[sl]).max() / scale)
+            if fl.any():
+                worst_r = max(worst_r, np.abs(grr[fl] - orr[sl][fl]).max() / np.abs(orr[sl][fl]).max())
+    print(f"worst patch rel rho err {worst_r:.3e}, rel u err {worst_u:.3e}")
+    assert worst_r <= 1e-5 and worst_u <= 1e-4
