@@ -151,6 +151,7 @@ struct lb2d_batch {
     int ntiles = 0;
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
     size_t max_plane = 0;  // largest population plane of the lattices
+    bool nt = false;       // streaming stores: the lattices' populations exceed the last-level cache
     hipGraphExec_t graph = nullptr;
     int64_t t = 0;
     int fail(int code, const char *fmt, ...) {
@@ -242,6 +243,16 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     L.total = off;
     return L;
 }
+
+// Bytes of all population buffers of a bound lattice (both parities, every
+// fluid component and the solute).
+static size_t population_bytes(const lb2d_ctx *c) {
+    return 2ull * (size_t)(c->ncomp + (c->q ? 1 : 0)) * 9ull * c->pplane * storage_bytes(c->storage);
+}
+// Streaming stores once the populations no longer fit in the last-level
+// cache (measured: plain stores win while the next step can find the
+// populations there).
+static bool stream_stores(const lb2d_ctx *c) { return population_bytes(c) > kLastLevelCache; }
 
 FullParams full_params(const lb2d_ctx *c) {
     FullParams p{};
@@ -382,7 +393,7 @@ int pre_command(lb2d_ctx *c, bool need_lattice = true) {
 // device step counter after it (stochastic rounding keys its stream on it).
 hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s) {
     if (c->plain()) {
-        hipError_t e = launch_plain(c->storage, plain_lattice(c), parity, c->sr, k, s);
+        hipError_t e = launch_plain(c->storage, plain_lattice(c), parity, c->sr, stream_stores(c), k, s);
         if (e == hipSuccess && c->sr && tick) e = launch_tick((unsigned long long *)c->dstep, tick, s);
         return e;
     }
@@ -1078,7 +1089,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
             const int parity = (int)(c->t & 1);
             HIPCHK(c, hipEventRecord(c->ev0, c->stream));
             if (c->plain()) {
-                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->sr, 0, c->stream));
+                HIPCHK(c, launch_plain(c->storage, plain_lattice(c), parity, c->sr, stream_stores(c), 0, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
                 if (c->sr) HIPCHK(c, launch_tick((unsigned long long *)c->dstep, 1, c->stream));
             } else {
@@ -1406,10 +1417,13 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     plain_tile(b->storage, &b->tile_w, &b->tile_h);
     std::vector<PlainLattice> L;
     b->max_plane = 0;
+    size_t pop_bytes = 0;
     for (auto *c : b->lat) {
         L.push_back(plain_lattice(c));
         b->max_plane = std::max(b->max_plane, c->pplane);
+        pop_bytes += population_bytes(c);
     }
+    b->nt = pop_bytes > kLastLevelCache;
     HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
     int cus = 256;
@@ -1456,10 +1470,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->stream));
+            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->stream));
+                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1494,7 +1508,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 }
 
 static hipError_t batch_step(lb2d_batch *b, int parity, hipStream_t s) {
-    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, s);
+    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, b->nt, s);
 }
 
 int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {

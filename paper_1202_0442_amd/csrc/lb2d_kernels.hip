@@ -235,8 +235,9 @@ __device__ void block_sum(double (&v)[K], double *sh, double *out) {
 //    memory read-modify-write them; bricks that are entirely solid are
 //    never written, and wavefronts that are entirely solid do no memory
 //    work at all;
-//  * the stores are streaming (non-temporal): nothing reads the new
-//    populations in the same step.
+//  * the stores are streaming (non-temporal) when the populations exceed
+//    the last-level cache: nothing reads the new populations in the same
+//    step.
 // Pointers known to address global memory (so the compiler emits global_*
 // rather than flat_* instructions for pointers read from device tables).
 #define LB2D_GLOBAL __attribute__((address_space(1)))
@@ -247,8 +248,11 @@ __device__ __forceinline__ LB2D_GLOBAL T *gbl(T *p) {
 
 // Streaming store of one population value (a vector global store with the
 // non-temporal hint): the new populations are not read again in the same
-// step, so they need not stay in the caches.  16-bit values are stored
-// through their bit pattern.
+// step, so they need not stay in the caches.  Used when a lattice's
+// populations exceed the 256 MB last-level cache (Infinity Cache) of the
+// MI355X; smaller lattices keep plain stores, so that the next step finds
+// its populations in that cache.  16-bit values are stored through their
+// bit pattern.
 template <typename S>
 __device__ __forceinline__ void st_stream(LB2D_GLOBAL S *p, S v) {
     if constexpr (sizeof(S) == 2) {
@@ -320,7 +324,7 @@ __device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
     return a;
 }
 
-template <typename S, typename O, bool SR>
+template <typename S, typename O, bool SR, bool NT>
 __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside, unsigned tkey) {
     using C = Codec<S>;
     using R = typename C::R;
@@ -397,7 +401,8 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
             S e;
             if constexpr (SR) e = C::enc_sr(v, i, (i & 1) ? (w[i >> 1] << 16) : w[i >> 1]);
             else e = C::enc(v, i);
-            st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
+            if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
+            else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
         }
     }
 }
@@ -415,7 +420,7 @@ __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
 
 // k: offset of this step in its launch group (the step computed is the
 // device step count + k + 1; only stochastic rounding reads it).
-template <typename S, typename O, bool SR>
+template <typename S, typename O, bool SR, bool NT>
 __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k) {
     constexpr int TW = 256 / (brick_w_for(sizeof(S)) * brick_h_for(sizeof(S))) * brick_w_for(sizeof(S)),
                   TH = brick_h_for(sizeof(S));
@@ -425,12 +430,12 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
     const int y = blockIdx.y * TH + ly;
     unsigned tkey = 0u;
     if constexpr (SR) tkey = lowbias32((unsigned)(*L.step + (unsigned long long)k + 1ull) ^ L.seed);
-    plain_node<S, O, SR>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
+    plain_node<S, O, SR, NT>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
 // independent lattices; `persistent` grids stride over the table.
-template <typename S, typename O>
+template <typename S, typename O, bool NT>
 __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
                                               const Tile *__restrict__ tiles, int ntiles,
                                               int parity) {
@@ -442,7 +447,7 @@ __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ 
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
         const int x = x0 + lx;
         const int y = y0 + ly;
-        plain_node<S, O, false>(a, x, y, x < (int)a.nx && y < (int)a.ny, 0u);
+        plain_node<S, O, false, NT>(a, x, y, x < (int)a.nx && y < (int)a.ny, 0u);
     }
 }
 
@@ -579,6 +584,10 @@ template <typename S, typename O>
 __device__ __forceinline__ typename Codec<S>::R ldb(const S *__restrict__ base, O off, int i) {
     return Codec<S>::dec(*(const S *)((const char *)base + off), i);
 }
+// The general step always stores streaming: a uniform run-time choice
+// between streaming and plain stores measured 7% slower on the two-fluid +
+// solute workload than either form alone, and streaming stores won on
+// every general-step workload measured.
 template <typename S, typename O>
 __device__ __forceinline__ void stb(S *__restrict__ base, O off, S v) {
     st_stream((LB2D_GLOBAL S *)((LB2D_GLOBAL char *)gbl(base) + off), v);
@@ -1236,7 +1245,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             g[i] = fluid ? g[i] + oms * (geq - g[i]) : R(0);
         }
     }
-    // all stores of the lane in one region
+    // all stores of the lane in one region (streaming stores)
     if (store) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1808,18 +1817,24 @@ void plain_tile(int st, int *tw, int *th) {
     *th = h;
 }
 
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
+template <bool NT>
+static void plain_dispatch(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
     int tw, th;
     plain_tile(st, &tw, &th);
     const dim3 blk(256), grd((L.nx + tw - 1) / tw, (L.ny + th - 1) / th);
     if (sr && st == kF16)
-        hipLaunchKernelGGL((k_plain<_Float16, uint32_t, true>), grd, blk, 0, stream, L, parity, k);
+        hipLaunchKernelGGL((k_plain<_Float16, uint32_t, true, NT>), grd, blk, 0, stream, L, parity, k);
     else if (sr && st == kBF16)
-        hipLaunchKernelGGL((k_plain<bf16s, uint32_t, true>), grd, blk, 0, stream, L, parity, k);
+        hipLaunchKernelGGL((k_plain<bf16s, uint32_t, true, NT>), grd, blk, 0, stream, L, parity, k);
     else if (fits32(L.plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, uint32_t, false>), grd, blk, 0, stream, L, parity, k));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, uint32_t, false, NT>), grd, blk, 0, stream, L, parity, k));
     else
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, size_t, false>), grd, blk, 0, stream, L, parity, k));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_plain<S, size_t, false, NT>), grd, blk, 0, stream, L, parity, k));
+}
+
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t stream) {
+    if (nt) plain_dispatch<true>(st, L, parity, sr, k, stream);
+    else plain_dispatch<false>(st, L, parity, sr, k, stream);
     return hipGetLastError();
 }
 
@@ -1830,15 +1845,22 @@ hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, hipStream_t stream) {
+template <bool NT>
+static void batch_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                           size_t max_plane, hipStream_t stream) {
     dim3 blk(256);
     if (fits32(max_plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                                             parity));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t, NT>), dim3(grid), blk, 0, stream, lat, tiles,
+                                             ntiles, parity));
     else
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                                             parity));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t, NT>), dim3(grid), blk, 0, stream, lat, tiles,
+                                             ntiles, parity));
+}
+
+hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                        size_t max_plane, bool nt, hipStream_t stream) {
+    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, stream);
+    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, stream);
     return hipGetLastError();
 }
 

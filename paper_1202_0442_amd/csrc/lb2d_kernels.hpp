@@ -16,13 +16,16 @@ int growth_blocks(int nx, int ny);
 // Tile (in nodes) covered by one 256-thread block of the one-fluid step.
 void plain_tile(int st, int *tw, int *th);
 // One-fluid step; sr: stochastic rounding (16-bit storage, 32-bit offsets),
-// k: offset of the step in its launch group.
-hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t s);
+// nt: streaming stores, k: offset of the step in its launch group.
+hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
 // Adds n to the device step counter.
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
 // max_plane: largest population plane (elements) of the batch's lattices.
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, hipStream_t s);
+                        size_t max_plane, bool nt, hipStream_t s);
+// Streaming stores pay off once the populations (all buffers) no longer
+// fit in the last-level cache.
+constexpr size_t kLastLevelCache = 256ull << 20;
 // General step; the solute lattice (none, D2Q9, D2Q4) is p.sq.
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
