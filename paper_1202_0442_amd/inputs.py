@@ -9,7 +9,7 @@ Workloads (node counts, x fastest):
 
 * ``poiseuille``  -- 128x64 channel, solid rows y=0 and y=ny-1, periodic in x,
   tau=1, rho0=1, acceleration 1e-6 along e1 (the paper's Poiseuille
-  application with a BASELINE-size channel).
+  application on a 128x64 channel).
 * ``porous``      -- square lattice with non-overlapping discs, radius uniform
   in [8,24], random sequential addition with a minimum gap of one node on the
   periodic box until the disc area reaches 40 % (porosity 0.6), tau=0.8,
