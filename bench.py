@@ -127,6 +127,40 @@ def run_variant_storage(lb2d, torch, w, storage, steps, warmup, stream, rounding
     return out
 
 
+def run_channel(lb2d, torch, stream, nx=128, ny=64, accel=1e-6, tau=1.0, steps=5000):
+    """The plain channel in FP64 (128 x 64 nodes, walls at rows 0 and 63,
+    g = 1e-6, tau = 1, from rest): MLUPS of the 5000-step start-up, its
+    velocity profile against the start-up solution of the force-driven
+    channel (Fourier series, walls half-way at y = 0.5 and ny - 1.5) and the
+    mass drift.  A lattice this small is launch-bound, not HBM-bound."""
+    import numpy as np
+    L = lb2d.Lattice(0)
+    L.lattice("d2q9", nx, ny, tau)
+    L.boundary_style("noslip")
+    L.obstacle_rect(0, nx - 1, 0, 0)
+    L.obstacle_rect(0, nx - 1, ny - 1, ny - 1)
+    L.aveacceleration(1, accel)
+    L.bind("f64", stream=stream)
+    m0 = L.budgets()["mass0"]
+    ms = time_steps(torch, stream, L.iteration, steps)
+    _, ux, _ = L.moments(0)
+    nu = (tau - 0.5) / 3.0
+    H = ny - 2.0
+    y = np.arange(1, ny - 1, dtype=float)
+    xi, eta = y - 0.5, y - (ny - 1) / 2.0
+    u = accel / (2 * nu) * ((H / 2) ** 2 - eta ** 2)
+    for k in range(1, 400, 2):
+        u -= 4 * accel * H ** 2 / (nu * math.pi ** 3 * k ** 3) * np.sin(k * math.pi * xi / H) \
+            * math.exp(-nu * k * k * math.pi ** 2 * steps / H ** 2)
+    umax = accel * H * H / (8 * nu)
+    out = {"workload": f"channel {nx}x{ny}, walls at rows 0 and {ny - 1}, g {accel}, tau {tau}, f64, from rest",
+           "steps": steps, "mlups": nx * ny * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
+           "u_err_vs_startup_series": float(np.abs(ux[1:-1, :] - u[:, None]).max() / umax),
+           "mass_drift": (L.budgets()["mass0"] - m0) / m0}
+    L.close()
+    return out
+
+
 def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     from paper_1202_0442_amd import inputs
     w = inputs.sc_solute(n=n)
@@ -329,7 +363,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=4096, help="porous lattice side")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--variants", default="all", help="all | none | comma list of f16,bf16,sc,phase,growth,batch")
+    ap.add_argument("--variants", default="all",
+                    help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
     ap.add_argument("--sc-steps", type=int, default=2000, help="steps of the two-component variant")
@@ -428,7 +463,7 @@ def main():
     out["roofline"]["frac_of_copy"] = round(achieved / out["copy_ceiling_GBps"], 4)
 
     want = set() if args.variants == "none" else (
-        {"f16", "bf16", "sc", "phase", "growth", "batch"} if args.variants == "all"
+        {"f16", "bf16", "sc", "phase", "growth", "batch", "channel"} if args.variants == "all"
         else set(args.variants.split(",")))
     variants = {}
     for st in ("f16", "bf16"):
@@ -452,6 +487,9 @@ def main():
         log("variant surface-growth sweep")
         variants["growth"] = run_growth_sweep(lb2d, torch, stream)
         torch.cuda.empty_cache()
+    if "channel" in want:
+        log("variant channel 128x64 f64")
+        variants["channel"] = run_channel(lb2d, torch, stream)
     if "batch" in want:
         log("variant batched ensemble")
         variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 20, stream)
