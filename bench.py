@@ -87,14 +87,14 @@ def time_steps(torch, stream, fn, steps):
     return e0.elapsed_time(e1)
 
 
-def cpu_baseline(target_seconds=15.0):
-    """The FP64 oracle, as it stands, on a 512 x 512 sample of the porous
-    workload (same generator, seed and parameters), one thread."""
+def _oracle_rate(n, threads, target_seconds):
+    """MLUPS of the FP64 oracle, as it stands, on an n x n sample of the
+    porous workload (same generator, seed and parameters)."""
     from oracle import Oracle
     from oracle.oracle import set_threads
     from paper_1202_0442_amd import inputs
-    set_threads(1)
-    w = inputs.porous(n=512, seed=2)
+    used = set_threads(threads)
+    w = inputs.porous(n=n, seed=2)
     o = Oracle(w.nx, w.ny)
     o.fluids(1, w.tau)
     for (xc, yc, r) in w.discs:
@@ -108,9 +108,20 @@ def cpu_baseline(target_seconds=15.0):
         o.iteration(5)
         steps += 5
     dt = time.perf_counter() - t0
-    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"porous {w.nx}x{w.ny} (discs r 8..24, porosity 0.6, seed 2), {steps} steps, "
-                      f"{dt:.1f} s, FP64 plain C, 1 thread"}
+    sample = (f"porous {w.nx}x{w.ny} (discs r 8..24, porosity 0.6, seed 2), {steps} steps, {dt:.1f} s, "
+              f"FP64 plain C, {used} thread{'s' if used > 1 else ''}")
+    return w.nx * w.ny * steps / dt / 1e6, used, sample
+
+
+def cpu_baseline(target_seconds=15.0):
+    """The FP64 oracle on one host thread (the reported baseline), and the
+    same oracle with its OpenMP rows over the host threads this process may
+    use, on a larger sample."""
+    v1, _, s1 = _oracle_rate(512, 1, target_seconds)
+    nthr = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    vn, used, sn = _oracle_rate(1024, nthr, 8.0)
+    return {"value": v1, "unit": "MLUPS", "cores": 1, "kind": "oracle", "sample": s1,
+            "all_threads": {"value": vn, "unit": "MLUPS", "cores": used, "sample": sn}}
 
 
 def run_variant_storage(lb2d, torch, w, storage, steps, warmup, stream, rounding="nearest"):
