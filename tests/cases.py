@@ -84,6 +84,24 @@ def contact_box_case(Gads, nx=201, ny=51, seed=5, G=-120.0, psi0=4.0, rho0=200.0
     return case
 
 
+def two_fluid_contact_case(g1=0.2, g2=-0.2, Nx=200, Ny=50, base=51):
+    """The paper's contact-angles II set-up (section Contact angles II and its
+    script): a box of (Nx+1) x (Ny+1) nodes with solid walls on all four
+    sides, fluid 1 dense (2) and fluid 2 dilute (0.1) inside a centred
+    rectangle of the given base spanning the box height, the reverse
+    elsewhere, G = 0.9, adhesion g1 (fluid 1) and g2 (fluid 2), tau = 1.
+    The script's initial state holds each density in the rest population;
+    here the nodes start at their equilibrium at rest (same densities)."""
+    nx, ny = Nx + 1, Ny + 1
+    x = np.tile(np.arange(nx), ny)
+    inside = (x >= Nx // 2 - base // 2) & (x <= Nx // 2 + base // 2)
+    rho1 = np.where(inside, 2.0, 0.1)
+    rho2 = np.where(inside, 0.1, 2.0)
+    rects = [(0, nx - 1, 0, 0), (0, nx - 1, ny - 1, ny - 1), (0, 0, 0, ny - 1), (nx - 1, nx - 1, 0, ny - 1)]
+    return dict(nx=nx, ny=ny, tau=1.0, fluids=(1.0, 1.0), G=0.9, gads=(g1, g2), rects=rects,
+                fields={0: (rho1, None, None), 1: (rho2, None, None)})
+
+
 def channel_flow_case(nx, ny, seed, wall="xlo", inlet=("poiseuille", 0.04, 1.0),
                       outlet=("dirichlet", 0.0, 1.0), nd=4, tau=0.8):
     """Through-flow channel: solid side walls, an inlet on `wall` and an

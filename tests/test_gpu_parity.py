@@ -241,3 +241,43 @@ def test_fully_blocked_rows_and_isolated_pockets():
     o.iteration(60)
     g.iteration(60)
     _cmp_fluid(g, o, [0], 1e-12, 1e-12)
+
+
+def test_paper_two_fluid_contact_box_matches_oracle_fp64():
+    """The paper's contact-angles II set-up: FP64 parity over the first 300
+    steps (interfaces sharpen, walls on all four sides)."""
+    from cases import two_fluid_contact_case
+    case = two_fluid_contact_case()
+    o, g = build_oracle(case), build_gpu(case, "f64")
+    o.iteration(300)
+    g.iteration(300)
+    _cmp_fluid(g, o, [0, 1], 1e-10, 1e-11)
+
+
+def test_paper_two_fluid_contact_angles_are_complementary():
+    """The paper's contact-angles II run (201 x 51 nodes, 20 000 steps): with
+    the paper's adhesion signs one bridge of fluid 1 remains in the middle
+    of the box, and the signs set complementary contact angles.  With the printed force
+    F = -G_c rho_c sum w_i s e_i, G_1 = +0.2 repels fluid 1 from the walls
+    and G_2 = -0.2 draws fluid 2 to them, so the fluid-1 bridge is narrower
+    along the walls than at mid-height; exchanging the signs widens it
+    there.  Both components' masses are conserved."""
+    from cases import two_fluid_contact_case
+    from scipy import ndimage
+    widths = {}
+    for sign in (1.0, -1.0):
+        g = build_gpu(two_fluid_contact_case(0.2 * sign, -0.2 * sign), "f64")
+        b0 = g.budgets()
+        g.iteration(20000)
+        b1 = g.budgets()
+        for c in (0, 1):
+            assert b1[f"mass{c}"] == pytest.approx(b0[f"mass{c}"], rel=1e-12)
+        r1, _, _ = g.moments(0)
+        dense = r1 > 1.0
+        if sign > 0:                       # the paper's signs: a single fluid-1 region
+            assert ndimage.label(dense)[1] == 1
+        widths[sign] = (dense[1].sum() + dense[-2].sum()) / 2.0, float(dense[25].sum())
+    print("fluid-1 width at the walls / mid-height:", widths)
+    wall_p, mid_p = widths[1.0]
+    wall_m, mid_m = widths[-1.0]
+    assert wall_p < mid_p and wall_m > mid_m
