@@ -281,3 +281,33 @@ def test_paper_two_fluid_contact_angles_are_complementary():
     wall_p, mid_p = widths[1.0]
     wall_m, mid_m = widths[-1.0]
     assert wall_p < mid_p and wall_m > mid_m
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_paper_poiseuille_application(storage, tol):
+    """The paper's Poiseuille application (61 x 31 nodes, initial
+    populations 4 for the rest and slow modes and 1 for the fast ones, so
+    rho = 24 off equilibrium, g from the printed formula, 10 000 steps) on
+    the GPU: the same populations as the oracle's, and the profile of
+    Eq. (profile) with u_max = 0.07."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "poiseuille_application.json")))
+    Nx, Ny, tau, umax = gold["Nx"], gold["Ny"], gold["tau"], gold["u_max"]
+    acc = 4.0 / 3.0 * umax * (2 * tau - 1) / (Ny - 1) ** 2
+    case = dict(nx=Nx + 1, ny=Ny + 1, tau=tau, accel=[(1, acc, 0)], rects=[(0, Nx, 0, 0), (0, Nx, Ny, Ny)],
+                fields={0: (np.full((Nx + 1) * (Ny + 1), 24.0), None, None)})
+    o, g = build_oracle(case), build_gpu(case, storage)
+    init = np.array([gold["pop_rest_slow"]] * 5 + [gold["pop_fast"]] * 4)
+    f0 = np.broadcast_to(init[:, None, None], (9, Ny + 1, Nx + 1)).copy()
+    f0[:, 0, :] = 0.0
+    f0[:, Ny, :] = 0.0
+    o.set_f(f0, 0)
+    g.set_populations(f0, 0)
+    o.iteration(gold["steps"])
+    g.iteration(gold["steps"])
+    _cmp_fluid(g, o, [0], tol, tol)
+    _, ux, _ = g.moments(0)
+    y = np.arange(1, Ny)
+    prof = 3 * acc / (2 * tau - 1) * (((Ny - 1) / 2) ** 2 - (y - Ny / 2) ** 2)
+    np.testing.assert_allclose(ux[1:Ny, 7], prof, atol=5e-3 * umax)
