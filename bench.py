@@ -505,6 +505,11 @@ def main():
         log("variant batched ensemble")
         variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 20, stream)
         torch.cuda.empty_cache()
+        log("variant batched ensemble, FP16 storage")
+        variants["ensemble_f16"] = run_ensemble(lb2d, torch, 256, 500, 20, stream, storage="f16")
+        variants["ensemble_f16"]["speedup_vs_f32_batched"] = (variants["ensemble_f16"]["batched_mlups"]
+                                                             / variants["ensemble"]["batched_mlups"])
+        torch.cuda.empty_cache()
     if variants:
         out["variants"] = variants
     if not args.no_cpu_baseline:
