@@ -406,6 +406,10 @@ def main():
             res["phase"] = run_phase(lb2d, torch, 4096, args.sc_steps, 10, stream)
         if "growth" in want:
             res["growth"] = run_growth_sweep(lb2d, torch, stream)
+        if "batch" in want:
+            res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 20, stream)
+        if "channel" in want:
+            res["channel"] = run_channel(lb2d, torch, stream)
         print(json.dumps(res), flush=True)
         lb2d.copy_bench(1 << 30, reps=3, stream=stream)
         return
