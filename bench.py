@@ -193,6 +193,7 @@ def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     L.adhesiveforce(e["Gads"][0], 0)
     L.adhesiveforce(e["Gads"][1], 1)
     L.bind("f32", stream=stream)
+    b0 = L.budgets()
     L.iteration(warmup)
     ms = time_steps(torch, stream, L.iteration, steps)
     # step-kernel time alone (growth/tally kernel excluded), event-bracketed
@@ -205,11 +206,19 @@ def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     nfl = b["fluid_nodes"]
     # per fluid node: 2 comps + solute, 9 loads + 9 stores of 4 bytes; mask 1 byte
     byt = nfl * 3 * 72 + nn
+    # budgets since bind: solute + deposit + solute removed by growth +
+    # deposit consumed by growth - b0 per grown node + outflow - inflow is
+    # conserved; each component's mass plus the mass removed by growth too
+    sol = lambda d: (d["solute"] + d["deposit"] + d["removed_solute"] + d["consumed_deposit"]
+                     - e["b0"] * d["grown_nodes"] + d["outflow"] - d["inflow"])
     out = {"workload": f"two-component Shan-Chen + D2Q9 solute + growth, {w.nx}x{w.ny}",
            "mlups": nn * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
            "step_kernel_ms": kms, "step_kernel_algorithmic_GBps": byt / (kms * 1e-3) / 1e9,
            "step_kernel_frac_hbm": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
-           "grown_nodes": b["grown_nodes"], "steps": steps}
+           "grown_nodes": b["grown_nodes"], "steps": warmup + steps + 20,
+           "solute_budget_rel_err": abs(sol(b) - sol(b0)) / max(abs(b["inflow"]), abs(sol(b0)), 1e-300),
+           "mass_rel_err": max(abs(b[f"mass{c}"] + b[f"removed_mass{c}"] - b0[f"mass{c}"]) / b0[f"mass{c}"]
+                               for c in (0, 1))}
     L.close()
     return out
 
@@ -378,7 +387,9 @@ def main():
                     help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
-    ap.add_argument("--sc-steps", type=int, default=2000, help="steps of the two-component variant")
+    ap.add_argument("--sc-steps", type=int, default=20000,
+                    help="steps of the two-component, phase and ensemble variants run with --no-main; "
+                         "the two-component variant's configuration runs 20000")
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: run only the selected variants (no headline line)")
     ap.add_argument("--precision", action="store_true",
