@@ -336,7 +336,7 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     const unsigned long long bal = __ballot(fluid);
     if (bal == 0ull) return;
     if (!inside) return;
-    // a brick (one or two whole lines) is written iff it holds a fluid node
+    // a brick (one 64- to 256-byte segment) is written iff it holds a fluid node
     const unsigned lane = __lane_id();
     const unsigned long long gmask =
         (kGroup >= 64) ? ~0ull : (((1ull << (kGroup & 63)) - 1ull) << ((lane / kGroup) * kGroup));
