@@ -78,7 +78,9 @@ typedef struct lb2d_batch lb2d_batch;
 
 /* New empty context on HIP device `hip_device`.  *out receives it. */
 int lb2d_create(lb2d_ctx **out, int hip_device);
-/* Frees the context and its graphs (not the caller's device memory). */
+/* Waits for the work queued on the bound stream, then frees the context
+ * and its graphs (not the caller's device memory, which may be freed once
+ * this returns). */
 int lb2d_destroy(lb2d_ctx *ctx);
 /* Message of the last failed call on ctx ("" if none; static text for a
  * NULL ctx). */
@@ -320,6 +322,8 @@ int lb2d_step_count(lb2d_ctx *ctx, int64_t *t);
  * one launch per time step.  Tile shape and the order of tiles are picked
  * by an autotuner at finalize (results never depend on them). */
 int lb2d_batch_create(lb2d_batch **out, int hip_device);
+/* Waits for the batch's queued work, then frees the batch (not its
+ * lattices, nor the caller's device memory). */
 int lb2d_batch_destroy(lb2d_batch *b);
 const char *lb2d_batch_last_error(const lb2d_batch *b);
 /* Adds a bound lattice (the batch does not own it). */

@@ -512,9 +512,14 @@ int lb2d_create(lb2d_ctx **out, int hip_device) {
 
 int lb2d_destroy(lb2d_ctx *c) {
     if (!c) return LB2D_E_INVAL;
+    // work still queued on the bound stream reads the caller's workspace:
+    // finish it before the caller may free that memory
+    if (c->bound) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+    }
     if (c->graph || c->cap_stream || c->ev0) {
         (void)hipSetDevice(c->device);
-        if (c->bound) (void)hipStreamSynchronize(c->stream);
         if (c->graph) (void)hipGraphExecDestroy(c->graph);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1339,9 +1344,12 @@ int lb2d_batch_create(lb2d_batch **out, int hip_device) {
 
 int lb2d_batch_destroy(lb2d_batch *b) {
     if (!b) return LB2D_E_INVAL;
-    if (b->graph || b->cap_stream) {
+    if (b->ws) {
         (void)hipSetDevice(b->device);
         (void)hipStreamSynchronize(b->stream);
+    }
+    if (b->graph || b->cap_stream) {
+        (void)hipSetDevice(b->device);
         if (b->graph) (void)hipGraphExecDestroy(b->graph);
         if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     }
