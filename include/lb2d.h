@@ -312,7 +312,12 @@ int lb2d_set_populations(lb2d_ctx *ctx, int comp, const double *in);
 /* Raw deposit array (nx*ny doubles, all nodes) and step counter. */
 int lb2d_get_deposit(lb2d_ctx *ctx, double *b);
 int lb2d_set_deposit(lb2d_ctx *ctx, const double *b);
+/* Replaces the solid mask (nx*ny bytes, 1 = solid; for checkpoints) and
+ * rebuilds the link words; pending growth triggers are cleared.  The
+ * reflected shares of slip/mixed solids are not changed: a node made solid
+ * here keeps the share it last had (0, noslip, if it never was solid). */
 int lb2d_set_mask(lb2d_ctx *ctx, const uint8_t *m);
+/* Steps completed since bind. */
 int lb2d_step_count(lb2d_ctx *ctx, int64_t *t);
 
 /* ------------------------------------------------------- batched lattices */
