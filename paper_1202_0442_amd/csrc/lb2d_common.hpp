@@ -12,13 +12,13 @@ enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 // Brick layout of every population plane (fluid components and solute):
 // each plane is cut into bricks of BW x BH nodes stored contiguously, in
 // row-major brick order over the plane padded to whole bricks: 4x4 for
-// 4-byte values (64 bytes), 8x4 for 8-byte values (256 bytes) and 8x8 for
-// 2-byte values (128 bytes).  A brick covers a compact 2-D patch, so bricks
-// that lie entirely inside obstacles are never read or written; the 4x4
-// FP32 brick halves the patch of the 8x4 one and skips more of the solid
-// area next to obstacle boundaries (measured faster on the porous
-// workload, while 2x4 bricks lose to the shorter memory segments).
-inline constexpr int brick_w_for(int value_bytes) { return value_bytes == 4 ? 4 : 8; }
+// 4-byte values (64 bytes), 4x8 for 2-byte values (64 bytes) and 8x4 for
+// 8-byte values (256 bytes).  A brick covers a compact 2-D patch, so bricks
+// that lie entirely inside obstacles are never read or written; the
+// 64-byte bricks skip more of the solid area next to obstacle boundaries
+// than 128-byte ones (measured faster on the porous workload, while 32-byte
+// bricks lose to the shorter memory segments).
+inline constexpr int brick_w_for(int value_bytes) { return value_bytes == 8 ? 8 : 4; }
 inline constexpr int brick_h_for(int value_bytes) { return value_bytes == 2 ? 8 : 4; }
 
 // One single-fluid lattice for the plain fused step (and for one entry of

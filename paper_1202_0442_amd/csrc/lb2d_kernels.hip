@@ -134,11 +134,8 @@ struct Codec<bf16s> {
         return __uint_as_float((uint32_t)(uint16_t)v << 16) * iscale16(i);
     }
     __device__ static bf16s enc(float d, int i) {
-        // round to nearest even on the upper 16 bits (NaN stays NaN)
-        uint32_t u = __float_as_uint(d * scale16(i));
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16s)(uint16_t)((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (bf16s)(uint16_t)(u >> 16);
+        // round to nearest even: the gfx950 convert (v_cvt_pk_bf16_f32)
+        return (bf16s)__builtin_bit_cast(uint16_t, (__bf16)(d * scale16(i)));
     }
     __device__ static bf16s enc_sr(float d, int i, unsigned r) {
         bf162_t h = {};
@@ -408,8 +405,8 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
 }
 
 // Thread t of a 256-thread block -> node of a brick-aligned tile of
-// (256 / (BW*BH)) bricks side by side: 32 (or 64) consecutive lanes cover
-// one brick, so each store of a wavefront writes whole bricks.
+// (256 / (BW*BH)) bricks side by side: BW*BH (16 to 32) consecutive lanes
+// cover one brick, so each store of a wavefront writes whole bricks.
 template <typename S>
 __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
     constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
