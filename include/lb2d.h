@@ -222,11 +222,13 @@ int lb2d_surface_reaction(lb2d_ctx *ctx, double kr, double Cs,
 /* position0 / momentum0: initial density and velocity of component comp
  * (0 or 1), host arrays of nx*ny doubles (ux, uy may be NULL = 0).  The
  * populations start at their equilibrium (Fig. "algorithm").  Components
- * never set start at rho = 1, u = 0.  Before bind. */
+ * never set start at rho = 1, u = 0.  Densities must be positive and
+ * finite, velocities finite (LB2D_E_INVAL).  Before bind. */
 int lb2d_set_fields(lb2d_ctx *ctx, int comp, const double *rho,
                     const double *ux, const double *uy);
 /* concentration0: initial solute concentration (nx*ny doubles) and the
- * velocity of its equilibrium (NULL = 0).  Default C = 0.  Needs solute. */
+ * velocity of its equilibrium (NULL = 0), all finite (LB2D_E_INVAL).
+ * Default C = 0.  Needs solute. */
 int lb2d_set_concentration(lb2d_ctx *ctx, const double *C, const double *ux,
                            const double *uy);
 

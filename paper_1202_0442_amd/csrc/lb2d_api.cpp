@@ -807,8 +807,11 @@ int lb2d_set_fields(lb2d_ctx *c, int comp, const double *rho, const double *ux, 
     if (comp < 0 || comp >= c->ncomp) return c->fail(LB2D_E_INVAL, "component %d does not exist", comp);
     if (!rho) return c->fail(LB2D_E_INVAL, "null density");
     const size_t n = c->n();
-    for (size_t k = 0; k < n; ++k)
+    for (size_t k = 0; k < n; ++k) {
         if (!(rho[k] > 0.0) || !std::isfinite(rho[k])) return c->fail(LB2D_E_INVAL, "density must be positive");
+        if ((ux && !std::isfinite(ux[k])) || (uy && !std::isfinite(uy[k])))
+            return c->fail(LB2D_E_INVAL, "velocity must be finite");
+    }
     c->rho0[comp].assign(rho, rho + n);
     if (ux) c->ux0[comp].assign(ux, ux + n); else c->ux0[comp].clear();
     if (uy) c->uy0[comp].assign(uy, uy + n); else c->uy0[comp].clear();
@@ -821,6 +824,9 @@ int lb2d_set_concentration(lb2d_ctx *c, const double *C, const double *ux, const
     if (!c->have_solute) return c->fail(LB2D_E_ORDER, "concentration0 needs the solute command first");
     if (!C) return c->fail(LB2D_E_INVAL, "null concentration");
     const size_t n = c->n();
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(C[k]) || (ux && !std::isfinite(ux[k])) || (uy && !std::isfinite(uy[k])))
+            return c->fail(LB2D_E_INVAL, "concentration and velocity must be finite");
     c->C0.assign(C, C + n);
     if (ux) c->Cux.assign(ux, ux + n); else c->Cux.clear();
     if (uy) c->Cuy.assign(uy, uy + n); else c->Cuy.clear();

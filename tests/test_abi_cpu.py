@@ -257,3 +257,23 @@ def test_psi_force_forms():
         assert e.value.code == lb2d.E_INVAL
     two.interforce(0.9)
     two.adhesiveforce(0.3, 1)
+
+
+def test_initial_fields_must_be_finite():
+    lb2d = _lb2d()
+    L = lb2d.Lattice()
+    L.lattice("d2q9", 6, 5, 1.0)
+    ok = np.ones(30)
+    bad = ok.copy()
+    bad[7] = float("nan")
+    for args in ((0, bad), (0, ok, bad), (0, ok, None, bad * float("inf")), (0, -ok)):
+        with pytest.raises(lb2d.LB2DError) as e:
+            L.set_fields(*args)
+        assert e.value.code == lb2d.E_INVAL
+    L.set_fields(0, ok, 0.01 * ok, None)
+    L.solute(1.0, 9)
+    for args in ((bad,), (ok, bad)):
+        with pytest.raises(lb2d.LB2DError) as e:
+            L.set_concentration(*args)
+        assert e.value.code == lb2d.E_INVAL
+    L.set_concentration(ok)
