@@ -296,14 +296,14 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
     ws = inputs.ensemble(count=count)
     lats = [make_porous_lattice(lb2d, w, storage, stream) for w in ws]
     ntot = sum(w.nx * w.ny for w in ws)
-    # one at a time, plain kernel, launch per step
+    # one lattice at a time with the one-fluid kernel: each lattice runs its
+    # k steps (graph-launched) before the next one starts
     for L in lats:
         L.iteration(2)
 
     def seq(k):
-        for _ in range(k):
-            for L in lats:
-                L.iteration(1)
+        for L in lats:
+            L.iteration(k)
     ms_seq = time_steps(torch, stream, seq, seq_steps)
     B = lb2d.Batch(0)
     for L in lats:
