@@ -172,7 +172,7 @@ def run_channel(lb2d, torch, stream, nx=128, ny=64, accel=1e-6, tau=1.0, steps=5
     return out
 
 
-def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
+def run_sc_solute(lb2d, torch, n, steps, warmup, stream, storage="f32", rounding="nearest"):
     from paper_1202_0442_amd import inputs
     w = inputs.sc_solute(n=n)
     e = w.extra
@@ -192,7 +192,8 @@ def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     L.interforce(e["G"])
     L.adhesiveforce(e["Gads"][0], 0)
     L.adhesiveforce(e["Gads"][1], 1)
-    L.bind("f32", stream=stream)
+    L.rounding(rounding, 1)
+    L.bind(storage, stream=stream)
     b0 = L.budgets()
     L.iteration(warmup)
     ms = time_steps(torch, stream, L.iteration, steps)
@@ -204,14 +205,15 @@ def run_sc_solute(lb2d, torch, n, steps, warmup, stream):
     b = L.budgets()
     nn = w.nx * w.ny
     nfl = b["fluid_nodes"]
-    # per fluid node: 2 comps + solute, 9 loads + 9 stores of 4 bytes; mask 1 byte
-    byt = nfl * 3 * 72 + nn
+    # per fluid node: 2 comps + solute, 9 loads + 9 stores; mask 1 byte
+    byt = nfl * 3 * 18 * STORE_BYTES[storage] + nn
     # budgets since bind: solute + deposit + solute removed by growth +
     # deposit consumed by growth - b0 per grown node + outflow - inflow is
     # conserved; each component's mass plus the mass removed by growth too
     sol = lambda d: (d["solute"] + d["deposit"] + d["removed_solute"] + d["consumed_deposit"]
                      - e["b0"] * d["grown_nodes"] + d["outflow"] - d["inflow"])
-    out = {"workload": f"two-component Shan-Chen + D2Q9 solute + growth, {w.nx}x{w.ny}",
+    out = {"workload": f"two-component Shan-Chen + D2Q9 solute + growth, {w.nx}x{w.ny}, {storage}, "
+                       f"{rounding} rounding",
            "mlups": nn * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps,
            "step_kernel_ms": kms, "step_kernel_algorithmic_GBps": byt / (kms * 1e-3) / 1e9,
            "step_kernel_frac_hbm": byt / (kms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
@@ -505,6 +507,14 @@ def main():
         log("variant two-component + solute 2048^2")
         variants["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 20, stream)
         torch.cuda.empty_cache()
+        for st in ("f16", "bf16"):
+            for rnd in ("nearest", "stochastic"):
+                log(f"variant two-component + solute 2048^2, {st} storage, {rnd} rounding")
+                key = f"sc_solute_{st}" + ("_sr" if rnd == "stochastic" else "")
+                variants[key] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 20, stream, storage=st,
+                                              rounding=rnd)
+                variants[key]["speedup_vs_f32"] = variants[key]["mlups"] / variants["sc_solute"]["mlups"]
+                torch.cuda.empty_cache()
     if "phase" in want:
         log("variant one-component Shan-Chen 4096^2")
         variants["phase"] = run_phase(lb2d, torch, 4096, args.sc_steps, 20, stream)

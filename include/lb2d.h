@@ -188,12 +188,16 @@ int lb2d_obstacle_style(lb2d_ctx *ctx, int comp, const char *style, double R);
  * FP64): "nearest" (round to nearest even, the default) or "stochastic"
  * (round up or down with probabilities given by the distance to the two
  * neighbouring 16-bit values, using the gfx950 hardware converts and a
- * counter-based hash of (seed, step, node)).  Stochastic rounding keeps
- * per-step changes smaller than half an ulp on average, so slowly forced
- * flows do not stall; runs stay bitwise reproducible for a given seed.
- * Before bind; at bind, "stochastic" needs FP16 or BF16 storage of a
- * one-fluid lattice (LB2D_E_UNSUPPORTED otherwise) and population arrays
- * below 4 GiB (LB2D_E_SIZE).  Batched lattices always round to nearest. */
+ * counter-based hash of (seed, step, node, and in the general step the
+ * plane group: component 0, component 1, solute)).  Stochastic rounding
+ * keeps per-step changes smaller than half an ulp on average, so slowly
+ * forced flows do not stall and near-steady states do not drift in mass;
+ * runs stay bitwise reproducible for a given seed.  The step kernels round
+ * this way; populations written outside them (initial fields, gradient
+ * openings, lb2d_set_populations) round to nearest.
+ * Before bind; at bind, "stochastic" needs FP16 or BF16 storage
+ * (LB2D_E_UNSUPPORTED otherwise) and population arrays below 4 GiB
+ * (LB2D_E_SIZE).  Batched lattices always round to nearest. */
 int lb2d_rounding(lb2d_ctx *ctx, const char *mode, uint64_t seed);
 
 /* obstacle command, rectangle: nodes x0..x1, y0..y1 (inclusive,
@@ -269,9 +273,10 @@ int lb2d_intersolute(lb2d_ctx *ctx, double G, double psi0, double C0);
 /* ------------------------------------------------------------- memory */
 
 /* Bytes of device memory one lattice needs with the given storage format
- * (LB2D_F64/F32/F16/BF16), after all commands above.  16-bit storage
- * (F16, BF16) is implemented for one fluid without solute, forces between
- * nodes, openings or slip/mixed solids (LB2D_E_UNSUPPORTED otherwise). */
+ * (LB2D_F64/F32/F16/BF16), after all commands above.  Every lattice can
+ * store FP16 or BF16 (FP32 arithmetic), rounded to nearest or
+ * stochastically; stochastic rounding of FP32 or FP64 storage is
+ * LB2D_E_UNSUPPORTED. */
 int lb2d_workspace_bytes(lb2d_ctx *ctx, int storage, size_t *bytes);
 /* Binds `bytes` of caller device memory at dev_ptr (256-byte aligned,
  * on the context's device) and the HIP stream `hip_stream` (NULL = the

@@ -313,6 +313,8 @@ FullParams full_params(const lb2d_ctx *c) {
     p.is_psi0 = c->is_psi0;
     p.is_C0 = c->is_C0;
     p.tau_s = c->tau_s;
+    p.sr = c->sr ? 1 : 0;
+    p.sr_seed = c->sr_seed;
     p.nopen = (int)c->opens.size();
     for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
@@ -402,6 +404,7 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
     if (e == hipSuccess && c->has_gradient()) e = launch_open_gradient(c->storage, p, parity ^ 1, s);
     if (e != hipSuccess) return e;
     if (c->q) e = launch_growth(c->storage, p, parity ^ 1, c->reaction, s);
+    else if (c->sr) e = launch_tick((unsigned long long *)c->dstep, 1, s);
     return e;
 }
 
@@ -899,8 +902,6 @@ int lb2d_workspace_bytes(lb2d_ctx *c, int storage, size_t *bytes) {
     if (!c || !bytes) return LB2D_E_INVAL;
     if (!c->have_lattice) return c->fail(LB2D_E_ORDER, "the lattice command must come first");
     if (storage < kF64 || storage > kBF16) return c->fail(LB2D_E_INVAL, "unknown storage format");
-    if (!c->plain() && (storage == kF16 || storage == kBF16))
-        return c->fail(LB2D_E_UNSUPPORTED, "16-bit storage is implemented for the one-fluid step only");
     if (c->sr && storage != kF16 && storage != kBF16)
         return c->fail(LB2D_E_UNSUPPORTED, "stochastic rounding applies to 16-bit storage only");
     if (c->bound && storage != c->storage) return c->fail(LB2D_E_STATE, "already bound");
@@ -1109,6 +1110,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
                 if (c->has_gradient()) HIPCHK(c, launch_open_gradient(c->storage, p, parity ^ 1, c->stream));
                 HIPCHK(c, hipEventRecord(c->ev1, c->stream));
                 if (c->q) HIPCHK(c, launch_growth(c->storage, p, parity ^ 1, c->reaction, c->stream));
+                else if (c->sr) HIPCHK(c, launch_tick((unsigned long long *)c->dstep, 1, c->stream));
             }
             HIPCHK(c, hipEventSynchronize(c->ev1));
             float ms = 0.f;
@@ -1248,7 +1250,7 @@ int lb2d_get_populations(lb2d_ctx *c, int comp, double *out) {
             std::memset(out + (size_t)i * n, 0, n * 8);
             continue;
         }
-        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
+        HIPCHK(c, launch_decode_plane(c->storage, buf, c->mask, c->staging, n, pl, i, kW[i] * ref, (unsigned)c->nx,
                                       c->pnx, c->pplane, c->stream));
         HIPCHK(c, hipMemcpyAsync(out + (size_t)i * n, c->staging, n * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1274,7 +1276,7 @@ int lb2d_set_populations(lb2d_ctx *c, int comp, const double *in) {
         const int pl = comp >= 0 ? i : solute_plane(c->q, i);
         if (pl < 0) continue;
         HIPCHK(c, hipMemcpyAsync(c->staging, in + (size_t)i * n, n * 8, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, pl, kW[i] * ref, (unsigned)c->nx,
+        HIPCHK(c, launch_encode_plane(c->storage, buf, c->staging, n, pl, i, kW[i] * ref, (unsigned)c->nx,
                                       c->pnx, c->pplane, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }

@@ -132,6 +132,8 @@ struct FullParams {
     int isol;             // intersolute force on the solute
     double is_G, is_psi0, is_C0;  // its strength and psi = psi0 exp(-C0 / C)
     double tau_s;         // solute relaxation time
+    int sr;               // 16-bit storage rounds stochastically
+    unsigned sr_seed;     // its key
     StepCoef<double> cd;  // FP64 coefficients
     StepCoef<float> cf;   // the same rounded to FP32
 };

@@ -80,6 +80,9 @@ template <int SQ>
 __host__ __device__ constexpr int spl(int i) {
     return SQ == 9 ? i : i - 1;
 }
+// Direction stored in solute plane k (the inverse of spl): D2Q4 keeps
+// directions 1..4 in planes 0..3.
+__host__ __device__ constexpr int splane_dir(int sq, int k) { return sq == 4 ? k + 1 : k; }
 
 // Reciprocal: the hardware's (1 ulp) in FP32, exact division in FP64.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -499,13 +502,13 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
     return (k < len) ? start + k : -1;
 }
 
-// Node of a TX x TY tile handled by thread t: BW x 4 consecutive threads
+// Node of a TX x TY tile handled by thread t: BW x BH consecutive threads
 // cover one brick, the tile's bricks in row-major order, so a wavefront's
 // loads and stores of one plane touch whole bricks (four 64-byte FP32
-// bricks, two 256-byte FP64 bricks).
-template <int TX, int BW>
+// bricks, two 64-byte 16-bit bricks, two 256-byte FP64 bricks).
+template <int TX, int BW, int BH>
 __device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
-    constexpr int BH = 4, BPR = TX / BW;
+    constexpr int BPR = TX / BW;
     const int b = t / (BW * BH), k = t % (BW * BH);
     lx = (b % BPR) * BW + k % BW;
     ly = (b / BPR) * BH + k / BW;
@@ -855,8 +858,8 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     using R = typename C::R;
     constexpr bool SOL = SQ != 0;
     constexpr O SB = (O)sizeof(S);
-    static_assert(brick_h_for(sizeof(S)) == 4, "general step: bricks of 4 rows");
-    static_assert(TX % brick_w_for(sizeof(S)) == 0 && TY % 4 == 0, "tile of whole bricks");
+    constexpr int BW = brick_w_for(sizeof(S)), BH = brick_h_for(sizeof(S));
+    static_assert(TX % BW == 0 && TY % BH == 0, "tile of whole bricks");
     __shared__ R srho[SC ? NC : 1][SC ? TY + 2 : 1][SC ? TX + 2 : 1];
     // mask tile with a kSlipRing-node ring for the slip rules: the rule
     // reads two nodes around a node, and the density halo lies one node out
@@ -875,7 +878,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     const int tx0 = (tile % tiles_x) * TX, ty0 = (tile / tiles_x) * TY;
     const int tid = threadIdx.x;
     int lx, ly;
-    tile_thread<TX, brick_w_for(sizeof(S))>(tid, lx, ly);
+    tile_thread<TX, BW, BH>(tid, lx, ly);
     const int x = tx0 + lx, y = ty0 + ly;
     const bool valid = (x < nx) && (y < ny);
     // lanes past a ragged lattice edge stand for the periodic image of their
@@ -890,7 +893,7 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     // a brick is stored iff it holds a fluid node
     const unsigned long long bal = __ballot(valid && fluid);
     const unsigned lane = __lane_id();
-    constexpr unsigned kG = brick_w_for(sizeof(S)) * 4;  // lanes per brick
+    constexpr unsigned kG = BW * BH;  // lanes per brick
     const bool store = valid && ((bal >> ((lane / kG) * kG)) & ((1ull << kG) - 1ull)) != 0ull;
 
     if constexpr (EXT) {
@@ -1244,17 +1247,44 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     }
     // all stores of the lane in one region (streaming stores)
     if (store) {
+        bool rne = true;
+        if constexpr (sizeof(S) == 2) {
+            if (p.sr) {
+                rne = false;
+                // stochastic rounding: five random words per node and plane
+                // group (component 0, component 1, solute), keyed on the node,
+                // the step being computed and the group
+                const unsigned tkey = lowbias32((unsigned)(*p.dstep + 1ll) ^ p.sr_seed);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+                for (int c = 0; c < NC + (SOL ? 1 : 0); ++c) {
+                    unsigned w[5];
+                    w[0] = lowbias32((unsigned)srow ^ tkey ^ (0x9E3779B9u * (unsigned)(c + 1)));
 #pragma unroll
-            for (int i = 0; i < 9; ++i) stb(fout, (O)i * pl + s, C::enc(d[c][i], i));
+                    for (int k = 1; k < 5; ++k) w[k] = xorshift32(w[k - 1]);
+                    const bool sol = c == NC;
+                    S *__restrict__ out = sol ? (S *)p.g[parity ^ 1] : (S *)p.f[parity ^ 1][c < NC ? c : 0];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const unsigned r = (i & 1) ? (w[i >> 1] << 16) : w[i >> 1];
+                        if (!sol) stb(out, (O)i * pl + s, C::enc_sr(d[c < NC ? c : 0][i], i, r));
+                        else if (shas<SQ>(i)) stb(out, (O)spl<SQ>(i) * pl + s, C::enc_sr(g[i], i, r));
+                    }
+                }
+            }
         }
-        if constexpr (SOL) {
-            S *__restrict__ gout = (S *)p.g[parity ^ 1];
+        if (rne) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                if (shas<SQ>(i)) stb(gout, (O)spl<SQ>(i) * pl + s, C::enc(g[i], i));
+            for (int c = 0; c < NC; ++c) {
+                S *__restrict__ fout = (S *)p.f[parity ^ 1][c];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) stb(fout, (O)i * pl + s, C::enc(d[c][i], i));
+            }
+            if constexpr (SOL) {
+                S *__restrict__ gout = (S *)p.g[parity ^ 1];
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    if (shas<SQ>(i)) stb(gout, (O)spl<SQ>(i) * pl + s, C::enc(g[i], i));
+            }
         }
     }
     if (valid && solid && REACT && fluid8) {
@@ -1399,7 +1429,7 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
             }
             const S *__restrict__ g = (const S *)p.g[parity_new];
             double cc = 0.0;
-            for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], k);
+            for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], splane_dir(p.sq, k));
             tal[2] += cc;
             tal[3] += 1.0;
             // the node's fluid and solute are removed: its stored values are
@@ -1579,21 +1609,21 @@ __global__ void k_init_b(double *b, const uint8_t *mask, double b0, size_t n) {
 // Raw state <-> FP64 row-major staging (one plane at a time);
 // `shift` = w_i rho_ref.
 template <typename S>
-__global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, double shift,
+__global__ void k_decode_plane(const S *f, const uint8_t *mask, double *out, size_t n, int i, int dir, double shift,
                                unsigned nx, unsigned pnx, size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
         const size_t a = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
-        out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * pplane + a], i);
+        out[k] = mask[k] ? 0.0 : shift + (double)C::dec(f[(size_t)i * pplane + a], dir);
     }
 }
 template <typename S>
-__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, double shift, unsigned nx,
+__global__ void k_encode_plane(S *f, const double *in, size_t n, int i, int dir, double shift, unsigned nx,
                                unsigned pnx, size_t pplane) {
     using C = Codec<S>;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
         const size_t a = brick_index<S>((unsigned)(k % nx), (unsigned)(k / nx), pnx);
-        f[(size_t)i * pplane + a] = C::enc((typename C::R)(in[k] - shift), i);
+        f[(size_t)i * pplane + a] = C::enc((typename C::R)(in[k] - shift), dir);
     }
 }
 
@@ -1703,7 +1733,7 @@ __global__ void k_solute_state(FullParams p, int parity, int reaction, double *o
         if (!sol) {
             const S *g = (const S *)p.g[parity];
             const size_t a = brick_index<S>((unsigned)(k % p.nx), (unsigned)(k / p.nx), p.pnx);
-            for (int j = 0; j < p.sq; ++j) c += (double)C::dec(g[(size_t)j * p.pplane + a], j);
+            for (int j = 0; j < p.sq; ++j) c += (double)C::dec(g[(size_t)j * p.pplane + a], splane_dir(p.sq, j));
         }
         oc[k] = c;
         ob[k] = (sol && reaction) ? p.b[k] : 0.0;
@@ -1739,7 +1769,7 @@ __global__ void __launch_bounds__(256) k_budget_partial(FullParams p, int parity
         }
         if (has_solute) {
             const S *g = (const S *)p.g[parity];
-            for (int j = 0; j < p.sq; ++j) v[4] += (double)C::dec(g[(size_t)j * plane + ps], j);
+            for (int j = 0; j < p.sq; ++j) v[4] += (double)C::dec(g[(size_t)j * plane + ps], splane_dir(p.sq, j));
         }
     }
     double out[8];
@@ -1918,8 +1948,7 @@ static void full_dispatch(const FullParams &p, int parity, bool sc, bool react, 
 }
 
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t stream) {
-    if (st == kF64) full_dispatch<double>(p, parity, sc, react, stream);
-    else full_dispatch<float>(p, parity, sc, react, stream);
+    LB2D_DISPATCH(st, full_dispatch<S>(p, parity, sc, react, stream));
     return hipGetLastError();
 }
 
@@ -1931,30 +1960,24 @@ hipError_t launch_open_gradient(int st, const FullParams &p, int parity_new, hip
         if (p.open[k].style == 4) len = std::max(len, p.open[k].hi - p.open[k].lo + 1);
     if (len == 0) return hipSuccess;
     const dim3 g((len + 255) / 256, p.nopen), b(256);
-    if (st == kF64) hipLaunchKernelGGL(k_open_gradient<double>, g, b, 0, stream, p, parity_new);
-    else hipLaunchKernelGGL(k_open_gradient<float>, g, b, 0, stream, p, parity_new);
+    LB2D_DISPATCH(st, hipLaunchKernelGGL(k_open_gradient<S>, g, b, 0, stream, p, parity_new));
     return hipGetLastError();
+}
+
+template <typename S>
+static void growth_dispatch(const FullParams &p, int parity_new, bool react, dim3 g, dim3 b, hipStream_t stream) {
+    if (p.ncomp == 2) {
+        if (react) hipLaunchKernelGGL((k_growth<S, 2, true>), g, b, 0, stream, p, parity_new);
+        else hipLaunchKernelGGL((k_growth<S, 2, false>), g, b, 0, stream, p, parity_new);
+    } else {
+        if (react) hipLaunchKernelGGL((k_growth<S, 1, true>), g, b, 0, stream, p, parity_new);
+        else hipLaunchKernelGGL((k_growth<S, 1, false>), g, b, 0, stream, p, parity_new);
+    }
 }
 
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t stream) {
     const dim3 g = react ? dim3(growth_blocks(p.nx, p.ny)) : dim3(1), b(256);
-    if (st == kF64) {
-        if (p.ncomp == 2) {
-            if (react) hipLaunchKernelGGL((k_growth<double, 2, true>), g, b, 0, stream, p, parity_new);
-            else hipLaunchKernelGGL((k_growth<double, 2, false>), g, b, 0, stream, p, parity_new);
-        } else {
-            if (react) hipLaunchKernelGGL((k_growth<double, 1, true>), g, b, 0, stream, p, parity_new);
-            else hipLaunchKernelGGL((k_growth<double, 1, false>), g, b, 0, stream, p, parity_new);
-        }
-    } else {
-        if (p.ncomp == 2) {
-            if (react) hipLaunchKernelGGL((k_growth<float, 2, true>), g, b, 0, stream, p, parity_new);
-            else hipLaunchKernelGGL((k_growth<float, 2, false>), g, b, 0, stream, p, parity_new);
-        } else {
-            if (react) hipLaunchKernelGGL((k_growth<float, 1, true>), g, b, 0, stream, p, parity_new);
-            else hipLaunchKernelGGL((k_growth<float, 1, false>), g, b, 0, stream, p, parity_new);
-        }
-    }
+    LB2D_DISPATCH(st, growth_dispatch<S>(p, parity_new, react, g, b, stream));
     return hipGetLastError();
 }
 
@@ -2005,20 +2028,20 @@ hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hi
     hipLaunchKernelGGL(k_init_b, dim3(grid1d(n)), dim3(256), 0, s, b, mask, b0, n);
     return hipGetLastError();
 }
-hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
+hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i, int dir,
                                double shift, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_decode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (const S *)f, mask,
-                                         out, n, i, shift, nx, pnx, pplane));
+                                         out, n, i, dir, shift, nx, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s) {
     hipLaunchKernelGGL(k_links, dim3((nx + 255) / 256, ny), dim3(256), 0, s, mask, links, nx, ny);
     return hipGetLastError();
 }
-hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
-                               unsigned pnx, size_t pplane, hipStream_t s) {
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, int dir, double shift,
+                               unsigned nx, unsigned pnx, size_t pplane, hipStream_t s) {
     LB2D_DISPATCH(st, hipLaunchKernelGGL(k_encode_plane<S>, dim3(grid1d(n)), dim3(256), 0, s, (S *)f, in, n, i,
-                                         shift, nx, pnx, pplane));
+                                         dir, shift, nx, pnx, pplane));
     return hipGetLastError();
 }
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,

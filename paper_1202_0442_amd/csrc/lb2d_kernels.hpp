@@ -50,11 +50,13 @@ hipError_t launch_init_fluid(int st, void *f, const double *rho, const double *u
 hipError_t launch_init_solute(int st, void *g, const double *C, const double *ux, const double *uy, size_t n,
                               int sq, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_init_b(double *b, const uint8_t *mask, double b0, size_t n, hipStream_t s);
-hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i,
+// Plane i of a population array <-> FP64 row-major values; dir: the
+// direction stored in that plane (it sets the 16-bit scale).
+hipError_t launch_decode_plane(int st, const void *f, const uint8_t *mask, double *out, size_t n, int i, int dir,
                                double shift, unsigned nx, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_links(const uint8_t *mask, uint16_t *links, int nx, int ny, hipStream_t s);
-hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, double shift, unsigned nx,
-                               unsigned pnx, size_t pplane, hipStream_t s);
+hipError_t launch_encode_plane(int st, void *f, const double *in, size_t n, int i, int dir, double shift,
+                               unsigned nx, unsigned pnx, size_t pplane, hipStream_t s);
 hipError_t launch_moments(int st, const FullParams &p, int parity, int comp, double *rho, double *ux, double *uy,
                           hipStream_t s);
 hipError_t launch_solute_state(int st, const FullParams &p, int parity, int reaction, double *C, double *b,

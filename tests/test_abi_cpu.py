@@ -129,15 +129,20 @@ def test_bad_arguments():
         L.set_fields(0, np.ones(79))
 
 
-def test_sixteen_bit_only_for_one_fluid():
+def test_sixteen_bit_storage_and_stochastic_rounding_forms():
+    """16-bit storage and its stochastic rounding for every lattice;
+    stochastic rounding of FP32 or FP64 storage is refused."""
     lb2d = _lb2d()
     L = lb2d.Lattice()
     L.lattice("d2q9", 16, 16, 1.0)
     L.fluids(1.0, 1.0)
-    with pytest.raises(lb2d.LB2DError) as e:
-        L.workspace_bytes("f16")
-    assert e.value.code == lb2d.E_UNSUPPORTED
-    assert L.workspace_bytes("f32") > 0
+    assert L.workspace_bytes("f16") < L.workspace_bytes("f32")
+    L.rounding("stochastic", 1)
+    assert L.workspace_bytes("bf16") == L.workspace_bytes("f16")
+    for st in ("f32", "f64"):
+        with pytest.raises(lb2d.LB2DError) as e:
+            L.workspace_bytes(st)
+        assert e.value.code == lb2d.E_UNSUPPORTED
 
 
 def test_workspace_sizes_scale_with_storage():

@@ -125,13 +125,3 @@ def test_slip_walls_with_momentum_openings(storage, tol):
     o.iteration(300)
     g.iteration(300)
     _cmp(g, o, 1, tol, tol)
-
-
-def test_sixteen_bit_storage_rejects_slip():
-    """16-bit storage runs the one-fluid noslip step only."""
-    from paper_1202_0442_amd import lb2d
-    case = poiseuille_case(nx=16, ny=12)
-    case["style"] = ("slip", 1.0)
-    g = build_gpu(case, "f16", bind=False)
-    with pytest.raises(lb2d.LB2DError):
-        g.bind("f16")
