@@ -293,10 +293,10 @@ def run_growth_sweep(lb2d, torch, stream, storage="f64"):
                         f"b0 0.5, bmax 1, tau = tau_s = 1, 20000 steps, {storage}", "sweep": out}
 
 
-def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
+def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", rounding="nearest"):
     from paper_1202_0442_amd import inputs
     ws = inputs.ensemble(count=count)
-    lats = [make_porous_lattice(lb2d, w, storage, stream) for w in ws]
+    lats = [make_porous_lattice(lb2d, w, storage, stream, rounding) for w in ws]
     ntot = sum(w.nx * w.ny for w in ws)
     # one lattice at a time with the one-fluid kernel: each lattice runs its
     # k steps (graph-launched) before the next one starts
@@ -313,7 +313,8 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32"):
     B.finalize(stream=stream)
     B.iteration(4)
     ms_b = time_steps(torch, stream, B.iteration, steps)
-    out = {"workload": f"{count} porous lattices, sides log-uniform 256..1536, {ntot} nodes, {storage}",
+    out = {"workload": f"{count} porous lattices, sides log-uniform 256..1536, {ntot} nodes, {storage}"
+                       + ("" if rounding == "nearest" else f", {rounding} rounding"),
            "batched_mlups": ntot * steps / (ms_b * 1e-3) / 1e6,
            "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6,
            "tuned": B.config(), "steps": steps, "sequential_steps": seq_steps}
@@ -534,6 +535,12 @@ def main():
         variants["ensemble_f16"] = run_ensemble(lb2d, torch, 256, 500, 20, stream, storage="f16")
         variants["ensemble_f16"]["speedup_vs_f32_batched"] = (variants["ensemble_f16"]["batched_mlups"]
                                                              / variants["ensemble"]["batched_mlups"])
+        torch.cuda.empty_cache()
+        log("variant batched ensemble, FP16 storage, stochastic rounding")
+        variants["ensemble_f16_sr"] = run_ensemble(lb2d, torch, 256, 500, 20, stream, storage="f16",
+                                                   rounding="stochastic")
+        variants["ensemble_f16_sr"]["speedup_vs_f32_batched"] = (variants["ensemble_f16_sr"]["batched_mlups"]
+                                                                / variants["ensemble"]["batched_mlups"])
         torch.cuda.empty_cache()
     if variants:
         out["variants"] = variants

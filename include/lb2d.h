@@ -197,7 +197,7 @@ int lb2d_obstacle_style(lb2d_ctx *ctx, int comp, const char *style, double R);
  * openings, lb2d_set_populations) round to nearest.
  * Before bind; at bind, "stochastic" needs FP16 or BF16 storage
  * (LB2D_E_UNSUPPORTED otherwise) and population arrays below 4 GiB
- * (LB2D_E_SIZE).  Batched lattices always round to nearest. */
+ * (LB2D_E_SIZE).  A batch of such lattices rounds as each would alone. */
 int lb2d_rounding(lb2d_ctx *ctx, const char *mode, uint64_t seed);
 
 /* obstacle command, rectangle: nodes x0..x1, y0..y1 (inclusive,
@@ -338,7 +338,11 @@ int lb2d_batch_create(lb2d_batch **out, int hip_device);
  * lattices, nor the caller's device memory). */
 int lb2d_batch_destroy(lb2d_batch *b);
 const char *lb2d_batch_last_error(const lb2d_batch *b);
-/* Adds a bound lattice (the batch does not own it). */
+/* Adds a bound lattice (the batch does not own it).  All lattices of a
+ * batch share one storage format and one rounding mode (LB2D_E_INVAL
+ * otherwise); with stochastic rounding each keeps its own seed and step
+ * count, so a batched run equals the lattices stepped one by one, bit for
+ * bit. */
 int lb2d_batch_add(lb2d_batch *b, lb2d_ctx *lattice);
 /* Device bytes for the batch's tables (after all adds). */
 int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes);

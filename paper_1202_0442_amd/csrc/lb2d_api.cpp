@@ -152,6 +152,7 @@ struct lb2d_batch {
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
     size_t max_plane = 0;  // largest population plane of the lattices
     bool nt = false;       // streaming stores: the lattices' populations exceed the last-level cache
+    bool sr = false;       // stochastic rounding (every lattice of the batch asked for it)
     hipGraphExec_t graph = nullptr;
     int64_t t = 0;
     int fail(int code, const char *fmt, ...) {
@@ -1376,10 +1377,12 @@ int lb2d_batch_add(lb2d_batch *b, lb2d_ctx *c) {
     if (!b->lat.empty()) {
         if (c->storage != b->storage) return b->fail(LB2D_E_INVAL, "all lattices need the same storage format");
         if ((c->t & 1) != (b->lat[0]->t & 1)) return b->fail(LB2D_E_STATE, "lattices at different step parity");
+        if (c->sr != b->sr) return b->fail(LB2D_E_INVAL, "all lattices need the same rounding");
     }
     for (auto *o : b->lat)
         if (o == c) return b->fail(LB2D_E_INVAL, "lattice added twice");
     b->storage = c->storage;
+    b->sr = c->sr;
     b->lat.push_back(c);
     return LB2D_OK;
 }
@@ -1486,10 +1489,12 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt, b->stream));
+            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt,
+                                   b->sr, 0, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt, b->stream));
+                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
+                                       b->nt, b->sr, 0, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1523,8 +1528,13 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     return LB2D_OK;
 }
 
-static hipError_t batch_step(lb2d_batch *b, int parity, hipStream_t s) {
-    return launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, b->nt, s);
+// One batched step at offset k of its launch group; tick: steps to add to
+// the lattices' step counters after it (stochastic rounding only).
+static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
+    hipError_t e = launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, b->nt,
+                                b->sr, k, s);
+    if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, s);
+    return e;
 }
 
 int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
@@ -1536,7 +1546,7 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
     HIPCHK(b, hipSetDevice(b->device));
     int64_t left = nsteps;
     if ((b->t & 1) && left > 0) {
-        HIPCHK(b, batch_step(b, 1, b->stream));
+        HIPCHK(b, batch_step(b, 1, 0, 1, b->stream));
         b->t += 1;
         --left;
     }
@@ -1545,7 +1555,8 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         hipGraph_t gr = nullptr;
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = batch_step(b, k & 1, b->cap_stream);
+        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+            e = batch_step(b, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess) return b->fail(LB2D_E_HIP, "batch graph capture failed");
         HIPCHK(b, hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0));
@@ -1557,7 +1568,7 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         left -= kGraphSteps;
     }
     for (; left > 0; --left) {
-        HIPCHK(b, batch_step(b, (int)(b->t & 1), b->stream));
+        HIPCHK(b, batch_step(b, (int)(b->t & 1), 0, 1, b->stream));
         b->t += 1;
     }
     for (auto *c : b->lat) c->t = b->t;

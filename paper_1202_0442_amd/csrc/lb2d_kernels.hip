@@ -434,20 +434,26 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
-// independent lattices; `persistent` grids stride over the table.
-template <typename S, typename O, bool NT>
+// independent lattices; `persistent` grids stride over the table.  With
+// stochastic rounding each lattice draws the random words it would draw
+// stepped alone (its own step counter, seed and node numbering); k is the
+// step's offset in its launch group, as in k_plain.
+template <typename S, typename O, bool SR, bool NT>
 __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
                                               const Tile *__restrict__ tiles, int ntiles,
-                                              int parity) {
+                                              int parity, int k) {
     int lx, ly;
     brick_thread<S>(threadIdx.x, lx, ly);
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int li = (int)ufl((unsigned)tiles[t].lattice);
         const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
+        unsigned tkey = 0u;
+        if constexpr (SR)
+            tkey = ufl(lowbias32((unsigned)(*lat[li].step + (unsigned long long)k + 1ull) ^ lat[li].seed));
         const int x = x0 + lx;
         const int y = y0 + ly;
-        plain_node<S, O, false, NT>(a, x, y, x < (int)a.nx && y < (int)a.ny, 0u);
+        plain_node<S, O, SR, NT>(a, x, y, x < (int)a.nx && y < (int)a.ny, tkey);
     }
 }
 
@@ -1874,20 +1880,38 @@ hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {
 
 template <bool NT>
 static void batch_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                           size_t max_plane, hipStream_t stream) {
+                           size_t max_plane, bool sr, int k, hipStream_t stream) {
     dim3 blk(256);
-    if (fits32(max_plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t, NT>), dim3(grid), blk, 0, stream, lat, tiles,
-                                             ntiles, parity));
+    // stochastic rounding: every lattice's arrays are below 4 GiB (checked at bind)
+    if (sr && st == kF16)
+        hipLaunchKernelGGL((k_batch<_Float16, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
+                           parity, k);
+    else if (sr && st == kBF16)
+        hipLaunchKernelGGL((k_batch<bf16s, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
+                           parity, k);
+    else if (fits32(max_plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t, false, NT>), dim3(grid), blk, 0, stream, lat,
+                                             tiles, ntiles, parity, k));
     else
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t, NT>), dim3(grid), blk, 0, stream, lat, tiles,
-                                             ntiles, parity));
+        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t, false, NT>), dim3(grid), blk, 0, stream, lat,
+                                             tiles, ntiles, parity, k));
 }
 
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, bool nt, hipStream_t stream) {
-    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, stream);
-    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, stream);
+                        size_t max_plane, bool nt, bool sr, int k, hipStream_t stream) {
+    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, stream);
+    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, stream);
+    return hipGetLastError();
+}
+
+// Advances the step counter of every lattice of a batch by n.
+__global__ void k_tick_batch(const PlainLattice *__restrict__ lat, int nlat, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nlat) *(unsigned long long *)lat[i].step += (unsigned long long)n;
+}
+
+hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_tick_batch, dim3((nlat + 255) / 256), dim3(256), 0, s, lat, nlat, n);
     return hipGetLastError();
 }
 

@@ -20,9 +20,12 @@ void plain_tile(int st, int *tw, int *th);
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
 // Adds n to the device step counter.
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
-// max_plane: largest population plane (elements) of the batch's lattices.
+// max_plane: largest population plane (elements) of the batch's lattices;
+// sr, nt, k as for launch_plain.
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, bool nt, hipStream_t s);
+                        size_t max_plane, bool nt, bool sr, int k, hipStream_t s);
+// Adds n to the step counter of each of the nlat lattices of a batch.
+hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, hipStream_t s);
 // Streaming stores pay off once the populations (all buffers) no longer
 // fit in the last-level cache.
 constexpr size_t kLastLevelCache = 256ull << 20;

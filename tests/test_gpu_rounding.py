@@ -75,3 +75,45 @@ def test_stochastic_stream_same_for_graph_and_single_steps():
     for _ in range(64):
         b.iteration(1)
     assert np.array_equal(a.get_populations(0), b.get_populations(0))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_batch_with_stochastic_rounding_equals_single_lattices(storage):
+    """Each lattice of a batch draws the random words it draws alone (its
+    own seed, step count and node numbering): batched runs of 75 steps (two
+    32-step graphs and single steps) and of 1 + 74 steps (a first step at
+    odd parity) equal the lattices stepped one by one, bit for bit."""
+    from paper_1202_0442_amd import lb2d
+    cases = [porous_case(nx, ny, 20 + k, tau=0.6 + 0.1 * k) for k, (nx, ny) in
+             enumerate([(64, 40), (131, 77), (33, 200), (256, 9)])]
+    for chunks in ((75,), (1, 74)):
+        singles = [_gpu(c, storage, "stochastic", seed=11 + k) for k, c in enumerate(cases)]
+        members = [_gpu(c, storage, "stochastic", seed=11 + k) for k, c in enumerate(cases)]
+        for s in singles:
+            s.iteration(chunks[0])
+        batch = lb2d.Batch(0)
+        if len(chunks) > 1:
+            for m in members:
+                m.iteration(chunks[0])
+        for m in members:
+            batch.add(m)
+        batch.finalize()
+        for s in singles:
+            for n in chunks[1:] if len(chunks) > 1 else ():
+                s.iteration(n)
+        batch.iteration(sum(chunks[1:]) if len(chunks) > 1 else chunks[0])
+        for s, m in zip(singles, members):
+            assert m.step_count() == 75
+            assert np.array_equal(s.get_populations(0), m.get_populations(0))
+        batch.close()
+
+
+def test_batch_refuses_mixed_rounding():
+    from paper_1202_0442_amd import lb2d
+    a = _gpu(porous_case(32, 16, 1), "f16", "stochastic")
+    b = _gpu(porous_case(32, 16, 2), "f16", "nearest")
+    batch = lb2d.Batch(0)
+    batch.add(a)
+    with pytest.raises(lb2d.LB2DError) as e:
+        batch.add(b)
+    assert e.value.code == lb2d.E_INVAL
