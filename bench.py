@@ -172,6 +172,35 @@ def run_channel(lb2d, torch, stream, nx=128, ny=64, accel=1e-6, tau=1.0, steps=5
     return out
 
 
+def run_droplet(lb2d, torch, stream, storage):
+    """The paper's parallelization example (351 x 201 nodes, two components,
+    a droplet on a solid row): the 500 steps the paper times, on one GPU.
+    The paper plots its CPU timings without numbers, so this is context, not
+    a comparison.  A lattice this small is launch-bound."""
+    from paper_1202_0442_amd import inputs
+    w = inputs.parallel_droplet()
+    e = w.extra
+    L = lb2d.Lattice(0)
+    L.lattice("d2q9", w.nx, w.ny, w.tau)
+    L.fluids(w.tau, e["tau2"])
+    L.boundary_style("noslip")
+    for r in w.rects:
+        L.obstacle_rect(*r)
+    L.set_fields(0, e["rho"][0])
+    L.set_fields(1, e["rho"][1])
+    L.interforce(e["G"])
+    L.adhesiveforce(e["Gads"][0], 0)
+    L.adhesiveforce(e["Gads"][1], 1)
+    L.bind(storage, stream=stream)
+    L.iteration(2)
+    ms = time_steps(torch, stream, L.iteration, w.steps)
+    out = {"workload": f"paper's parallelization droplet, {w.nx}x{w.ny}, two components, {storage}",
+           "steps": w.steps, "ms_total": ms, "ms_per_step": ms / w.steps,
+           "mlups": w.nx * w.ny * w.steps / (ms * 1e-3) / 1e6}
+    L.close()
+    return out
+
+
 def run_sc_solute(lb2d, torch, n, steps, warmup, stream, storage="f32", rounding="nearest"):
     from paper_1202_0442_amd import inputs
     w = inputs.sc_solute(n=n)
@@ -387,7 +416,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="porous lattice side")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="all",
-                    help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel")
+                    help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel,droplet")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
     ap.add_argument("--sc-steps", type=int, default=20000,
@@ -424,6 +453,9 @@ def main():
             res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 20, stream)
         if "channel" in want:
             res["channel"] = run_channel(lb2d, torch, stream)
+        if "droplet" in want:
+            for st in ("f64", "f32"):
+                res[f"droplet_{st}"] = run_droplet(lb2d, torch, stream, st)
         print(json.dumps(res), flush=True)
         lb2d.copy_bench(1 << 30, reps=3, stream=stream)
         return
@@ -492,7 +524,7 @@ def main():
     out["roofline"]["frac_of_copy"] = round(achieved / out["copy_ceiling_GBps"], 4)
 
     want = set() if args.variants == "none" else (
-        {"f16", "bf16", "sc", "phase", "growth", "batch", "channel"} if args.variants == "all"
+        {"f16", "bf16", "sc", "phase", "growth", "batch", "channel", "droplet"} if args.variants == "all"
         else set(args.variants.split(",")))
     variants = {}
     for st in ("f16", "bf16"):
@@ -527,6 +559,10 @@ def main():
     if "channel" in want:
         log("variant channel 128x64 f64")
         variants["channel"] = run_channel(lb2d, torch, stream)
+    if "droplet" in want:
+        log("variant the paper's parallelization droplet")
+        for st in ("f64", "f32"):
+            variants[f"droplet_{st}"] = run_droplet(lb2d, torch, stream, st)
     if "batch" in want:
         log("variant batched ensemble")
         variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 20, stream)

@@ -22,6 +22,9 @@ Workloads (node counts, x fastest):
 * ``ensemble``    -- many independent porous lattices with log-uniform sides,
   overlapping (Boolean) discs of radius [4,20], porosity U[0.4,0.8],
   tau U[0.6,1.2], acceleration 1e-5.
+* ``phase_separation``, ``surface_growth``, ``parallel_droplet`` -- the
+  paper's own examples (phase separation, surface growth, the droplet of its
+  parallelization section), with their printed parameters.
 
 The paper uses no public dataset; these generators stand in for its
 hand-built geometries (channel, random porous media, droplets).
@@ -234,6 +237,23 @@ def surface_growth(kr: float, n: int = 200, side: int = 11, f0: float = 24.0, C0
                     rects=[(c - h, c + h, c - h, c + h)],
                     extra={"kr": kr, "Cs": Cs, "b0": b0, "bmax": bmax, "C0": C0, "tau_s": 1.0,
                            "rng_seed": seed, "Da": kr * n / 0.25})
+
+
+def parallel_droplet(Nx: int = 350, Ny: int = 200, L: int = 64, steps: int = 500) -> Workload:
+    """The paper's parallelization example (section Parallelization):
+    (Nx+1) x (Ny+1) nodes, the bottom row solid, periodic otherwise, two
+    components with tau = 1; fluid 1 dense (2) and fluid 2 dilute (0.1) in
+    the square x in [Nx/2-L, Nx/2+L], y in [0, 2L] on the wall, the reverse
+    elsewhere; interforce G = 0.9, adhesion +0.3 (fluid 1) and -0.3
+    (fluid 2).  The paper times 500 steps of it.  The initial densities of
+    the two components are in extra["rho"]."""
+    nx, ny = Nx + 1, Ny + 1
+    x = np.tile(np.arange(nx), ny)
+    y = np.repeat(np.arange(ny), nx)
+    inside = (x >= Nx // 2 - L) & (x <= Nx // 2 + L) & (y <= 2 * L)
+    rho = (np.where(inside, 2.0, 0.1), np.where(inside, 0.1, 2.0))
+    return Workload("parallel_droplet", nx, ny, steps, tau=1.0, rects=[(0, nx - 1, 0, 0)],
+                    extra={"G": 0.9, "Gads": (0.3, -0.3), "tau2": 1.0, "rho": rho})
 
 
 def random_populations(shape, seed: int, scale: float = 0.01) -> np.ndarray:

@@ -102,6 +102,17 @@ def two_fluid_contact_case(g1=0.2, g2=-0.2, Nx=200, Ny=50, base=51):
                 fields={0: (rho1, None, None), 1: (rho2, None, None)})
 
 
+def parallel_droplet_case(Nx=350, Ny=200, L=64):
+    """The paper's parallelization example (section Parallelization and its
+    script; the workload generator states it).  The nodes start at their
+    equilibrium at rest."""
+    from paper_1202_0442_amd import inputs
+    w = inputs.parallel_droplet(Nx, Ny, L)
+    e = w.extra
+    return dict(nx=w.nx, ny=w.ny, tau=w.tau, fluids=(w.tau, e["tau2"]), G=e["G"], gads=e["Gads"], rects=w.rects,
+                fields={0: (e["rho"][0], None, None), 1: (e["rho"][1], None, None)})
+
+
 def channel_flow_case(nx, ny, seed, wall="xlo", inlet=("poiseuille", 0.04, 1.0),
                       outlet=("dirichlet", 0.0, 1.0), nd=4, tau=0.8):
     """Through-flow channel: solid side walls, an inlet on `wall` and an

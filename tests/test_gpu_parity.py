@@ -283,6 +283,44 @@ def test_paper_two_fluid_contact_angles_are_complementary():
     assert wall_p < mid_p and wall_m > mid_m
 
 
+def test_paper_parallel_droplet_matches_oracle_fp64():
+    """The paper's parallelization example (351 x 201 nodes, a square of
+    fluid 1 on a solid bottom row, periodic elsewhere): FP64 parity over the
+    first 200 steps."""
+    from cases import parallel_droplet_case
+    case = parallel_droplet_case()
+    o, g = build_oracle(case), build_gpu(case, "f64")
+    o.iteration(200)
+    g.iteration(200)
+    _cmp_fluid(g, o, [0, 1], 1e-10, 1e-11)
+
+
+def test_paper_parallel_droplet_is_hydrophobic():
+    """The same run for 20 000 steps: the square of fluid 1 becomes a
+    single droplet sitting on the wall, which it does not wet (contact
+    angle above 90 degrees, since G_1 = +0.3 repels fluid 1 from solids):
+    the droplet is narrower where it touches the wall than at its widest,
+    and it stays clear of the solid row seen through the periodic top.
+    Both components' masses are conserved."""
+    from cases import parallel_droplet_case
+    from scipy import ndimage
+    g = build_gpu(parallel_droplet_case(), "f64")
+    b0 = g.budgets()
+    g.iteration(20000)
+    b1 = g.budgets()
+    for c in (0, 1):
+        assert b1[f"mass{c}"] == pytest.approx(b0[f"mass{c}"], rel=1e-12)
+    r1, _, _ = g.moments(0)
+    dense = r1 > 1.0
+    widths = dense.sum(axis=1)
+    rows = np.nonzero(widths)[0]
+    print(f"droplet rows {rows.min()}..{rows.max()}, width at the wall {widths[1]}, widest {widths.max()} "
+          f"at row {widths.argmax()}")
+    assert ndimage.label(dense)[1] == 1
+    assert widths[1] > 0 and widths[1] < widths.max()
+    assert widths[-1] == 0
+
+
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_paper_poiseuille_application(storage, tol):
     """The paper's Poiseuille application (61 x 31 nodes, initial
