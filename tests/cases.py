@@ -113,6 +113,40 @@ def parallel_droplet_case(Nx=350, Ny=200, L=64):
                 fields={0: (e["rho"][0], None, None), 1: (e["rho"][1], None, None)})
 
 
+def flat_coexistence(G, ny=96, steps=20000):
+    """Bulk densities (major, minor) of a converged flat two-component
+    Shan-Chen interface on the oracle: a slab of A across a periodic
+    4 x ny strip, both tau = 1."""
+    nx = 4
+    yy = np.repeat(np.arange(ny), nx)
+    slab = (yy >= ny // 4) & (yy < 3 * ny // 4)
+    o = Oracle(nx, ny)
+    o.fluids(2, 1.0, 1.0)
+    o.interforce(G)
+    o.set_fields(0, np.where(slab, 1.0, 0.05))
+    o.set_fields(1, np.where(slab, 0.05, 1.0))
+    o.iteration(steps)
+    ra, _, _ = o.moments(0)
+    return float(ra[ny // 2, 0]), float(ra[0, 0])
+
+
+def droplet_fields(n, R, hi, lo):
+    """(rho_A, rho_B) of a droplet of A of radius R at the centre of an
+    n x n box: A-rich bulk densities (hi, lo) inside, (lo, hi) outside."""
+    yy, xx = np.mgrid[0:n, 0:n]
+    inside = ((xx - n / 2) ** 2 + (yy - n / 2) ** 2 < R * R).ravel()
+    return np.where(inside, hi, lo), np.where(inside, lo, hi)
+
+
+def laplace_jump(ra, rb, G):
+    """Equivalent radius from the A-rich area and the pressure jump, with
+    p = (rho_A + rho_B + G rho_A rho_B)/3, between the box centre and its
+    corner."""
+    n = ra.shape[0]
+    p = (ra + rb + G * ra * rb) / 3
+    return float(np.sqrt((ra > rb).sum() / np.pi)), float(p[n // 2, n // 2] - p[0, 0])
+
+
 def channel_flow_case(nx, ny, seed, wall="xlo", inlet=("poiseuille", 0.04, 1.0),
                       outlet=("dirichlet", 0.0, 1.0), nd=4, tau=0.8):
     """Through-flow channel: solid side walls, an inlet on `wall` and an
