@@ -146,3 +146,97 @@ def test_sc_solute_2048_properties():
     rhs = b0["solute"] + b0["deposit"] + b1["inflow"] - b1["outflow"]
     assert lhs == pytest.approx(rhs, rel=1e-5)
     assert b1["grown_nodes"] == 0
+
+
+def _sc_window_case(w, rho_a, rho_b, x0, y0, W):
+    """Oracle case for the window [x0, x0+W) x [y0, y0+W) of the
+    two-component + solute workload (periodic wrap in y; windows stay
+    inside the x walls), with the discs that reach into it.  No solute
+    opening: the window keeps away from the solute's inlet and outlet."""
+    e = w.extra
+    nx, ny = w.nx, w.ny
+    circles = []
+    for (xc, yc, r) in w.discs:
+        dx = (xc - x0) % nx
+        dy = (yc - y0) % ny
+        if dx > nx / 2:
+            dx -= nx
+        if dy > ny / 2:
+            dy -= ny
+        if -r - 1 <= dx <= W + r and -r - 1 <= dy <= W + r:
+            circles.append((int(dx), int(dy), r))
+    ys = (np.arange(W) + y0) % ny
+    xs = (np.arange(W) + x0) % nx
+    cut = lambda a: a[np.ix_(ys, xs)].ravel()
+    return dict(nx=W, ny=W, tau=w.tau, fluids=(w.tau, e["tau2"]), G=e["G"], gads=e["Gads"], circles=circles,
+                fields={0: (cut(rho_a), None, None), 1: (cut(rho_b), None, None)},
+                solute=e["tau_s"], q=9, C=np.zeros(W * W),
+                reaction=(e["kr"], e["Cs"], e["b0"], e["bmax"], e["rng_seed"]))
+
+
+@pytest.mark.parametrize("storage,tol_r,tol_u", [("f64", 1e-11, 1e-10), ("f32", 1e-5, 1e-4)])
+def test_sc_solute_2048_sampled_patches(storage, tol_r, tol_u):
+    """The two-component + solute + reaction workload at its full 2048^2
+    size, stepped by one 32-step graph launch as the benchmark steps it,
+    against the oracle on windows around sampled patches.  After k steps a
+    node depends on the initial state within 2k nodes (the Shan-Chen
+    stencil reads post-streaming densities of the neighbours), and discs
+    centred just outside a periodic window wrap onto its far side, so the
+    ring is 2k + 2 r_max + 2.  The patches lie more than k nodes from the
+    solute inlet, where the solute is still exactly zero, which both sides
+    must show.  FP32: densities within 1e-5; velocities within 1e-4 of the
+    largest (the forces are differences of neighbouring densities, which
+    amplify the storage rounding, as in the tests above 4 GiB)."""
+    from cases import build_oracle
+    from paper_1202_0442_amd import lb2d
+    import torch
+    w = inputs.sc_solute(n=2048)
+    e = w.extra
+    rho_a, rho_b = inputs.sc_initial_fields(w)
+    g = lb2d.Lattice(0)
+    g.lattice("d2q9", w.nx, w.ny, w.tau)
+    g.fluids(w.tau, e["tau2"])
+    g.solute(e["tau_s"], 9)
+    g.solute_opening("xlo", "dirichlet", e["C_in"])
+    g.solute_opening("xhi", "adiabatic", 0.0)
+    g.boundary_style("noslip")
+    for (xc, yc, r) in w.discs:
+        g.obstacle_circle(xc, yc, r)
+    g.surface_reaction(e["kr"], e["Cs"], "growth", e["b0"], e["bmax"], e["rng_seed"])
+    g.set_fields(0, rho_a.ravel())
+    g.set_fields(1, rho_b.ravel())
+    g.interforce(e["G"])
+    g.adhesiveforce(e["Gads"][0], 0)
+    g.adhesiveforce(e["Gads"][1], 1)
+    g.bind(storage, stream=torch.cuda.Stream())
+    k = 32
+    g.iteration(k)
+    got = [g.moments(c) for c in (0, 1)]
+    Cg, bg = g.solute_state()
+    gm = g.mask()
+    P, ring = 8, 2 * k + 2 * 30 + 2
+    W = P + 2 * ring
+    rng = np.random.default_rng(2048)
+    worst_r = worst_u = 0.0
+    for _ in range(6):
+        px, py = int(rng.integers(ring, w.nx - ring - P)), int(rng.integers(0, w.ny))
+        x0, y0 = px - ring, (py - ring) % w.ny
+        o = build_oracle(_sc_window_case(w, rho_a, rho_b, x0, y0, W))
+        ys = (np.arange(ring, ring + P) + y0) % w.ny
+        xs = np.arange(ring, ring + P) + x0
+        sl = (slice(ring, ring + P), slice(ring, ring + P))
+        assert np.array_equal(gm[np.ix_(ys, xs)], o.get_mask()[sl])
+        o.iteration(k)
+        fl = o.get_mask()[sl] == 0
+        for c in (0, 1):
+            orr, ox, oy = o.moments(c)
+            grr, gx, gy = (a[np.ix_(ys, xs)] for a in got[c])
+            scale = max(np.abs(ox).max(), np.abs(oy).max(), 1e-12)
+            worst_u = max(worst_u, np.abs(gx - ox[sl]).max() / scale, np.abs(gy - oy[sl]).max() / scale)
+            if fl.any():
+                worst_r = max(worst_r, np.abs(grr[fl] - orr[sl][fl]).max() / np.abs(orr[sl][fl]).max())
+        Co, bo = o.solute_state()
+        assert np.all(Cg[np.ix_(ys, xs)] == 0.0) and np.all(Co[sl] == 0.0)
+        assert np.all(bg[np.ix_(ys, xs)] == bo[sl])
+    print(f"{storage}: worst patch rel rho err {worst_r:.3e}, rel u err {worst_u:.3e}")
+    assert worst_r <= tol_r and worst_u <= tol_u
