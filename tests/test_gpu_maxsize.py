@@ -105,10 +105,15 @@ def test_one_fluid_above_4gib_sampled_patches(storage, n, tol_u):
     assert worst_r <= tol_rho and worst <= tol_u
 
 
-def test_two_fluid_shan_chen_fp32_above_4gib_sampled_patches():
+@pytest.mark.parametrize("storage,n,tol_r,tol_u", [("f32", N, 1e-5, 1e-4),
+                                                    ("f16", 15500, 2 * 2.0 ** -11, 20 * 2.0 ** -11)])
+def test_two_fluid_shan_chen_above_4gib_sampled_patches(storage, n, tol_r, tol_u):
+    """Two components with Shan-Chen cohesion: FP32 at 11600^2, FP16 at
+    15500^2 (the general step's 64-bit offset path), bounds as above."""
     from paper_1202_0442_amd import lb2d
     import torch
-    discs = _discs()
+    N = n
+    discs = _discs(n)
     k, G = 16, 0.9
     rng = np.random.default_rng(77)
     ra = 0.5 + 0.2 * rng.uniform(-1, 1, (N, N))
@@ -123,31 +128,31 @@ def test_two_fluid_shan_chen_fp32_above_4gib_sampled_patches():
     g.set_fields(1, rb.ravel())
     g.interforce(G)
     g.aveacceleration(1, 1e-5, 0)
-    g.bind("f32", stream=torch.cuda.Stream())
+    g.bind(storage, stream=torch.cuda.Stream())
     g.iteration(k)
     got = [g.moments(c) for c in (0, 1)]
     P, ring = 8, 2 * k + 2 * int(RMAX) + 2
     W = P + 2 * ring
     worst_r = worst_u = 0.0
-    for (px, py) in _patches(np.random.default_rng(6), 5):
+    for (px, py) in _patches(np.random.default_rng(6), 5, n):
         x0, y0 = (px - ring) % N, (py - ring) % N
         o = Oracle(W, W)
         o.fluids(2, 1.0, 1.0)
         o.interforce(G)
         o.aveacceleration(1, 1e-5, 0)
-        for c in _window(discs, x0, y0, W):
+        for c in _window(discs, x0, y0, W, n):
             o.obstacle_circle(*c)
-        o.set_fields(0, _cut(ra, x0, y0, W).ravel())
-        o.set_fields(1, _cut(rb, x0, y0, W).ravel())
+        o.set_fields(0, _cut(ra, x0, y0, W, n).ravel())
+        o.set_fields(1, _cut(rb, x0, y0, W, n).ravel())
         o.iteration(k)
         sl = (slice(ring, ring + P), slice(ring, ring + P))
         fl = o.get_mask()[sl] == 0
         for c in (0, 1):
             orr, ox, oy = o.moments(c)
-            grr, gx, gy = (_cut(a, x0, y0, W)[sl] for a in got[c])
+            grr, gx, gy = (_cut(a, x0, y0, W, n)[sl] for a in got[c])
             scale = max(np.abs(ox).max(), np.abs(oy).max(), 1e-12)
             worst_u = max(worst_u, np.abs(gx - ox[sl]).max() / scale, np.abs(gy - oy[sl]).max() / scale)
             if fl.any():
                 worst_r = max(worst_r, np.abs(grr[fl] - orr[sl][fl]).max() / np.abs(orr[sl][fl]).max())
-    print(f"worst patch rel rho err {worst_r:.3e}, rel u err {worst_u:.3e}")
-    assert worst_r <= 1e-5 and worst_u <= 1e-4
+    print(f"{storage}: worst patch rel rho err {worst_r:.3e}, rel u err {worst_u:.3e}")
+    assert worst_r <= tol_r and worst_u <= tol_u
