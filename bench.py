@@ -430,7 +430,8 @@ def main():
                     help="npz written by `python -m oracle.reference_fields` (else computed here)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus must be 1 "
+              "(several GPUs would shard the lattice in y slabs, which is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
