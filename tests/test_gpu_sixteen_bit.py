@@ -190,3 +190,33 @@ def test_stochastic_rounding_keeps_mass_over_long_runs(storage, which):
     sr = _mass_drift(case, storage, "stochastic", 10000, comps)
     print(f"{storage} {which}: mass drift nearest {rne:.2e}, stochastic {sr:.2e} (eps {EPS[storage]:.1e})")
     assert sr <= rne / 10 and sr <= EPS[storage] / 2
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_stochastic_rounding_with_extended_features(storage):
+    """Stochastic rounding through the extended step (openings between slip
+    walls, the psi forces, intersolute): the doubled nearest bounds."""
+    eps = EPS[storage]
+    case = channel_flow_case(60, 31, 4, inlet=("uniform", 0.04, 1.0))
+    case["style"] = ("slip", 1.0)
+    o, g = build_oracle(case), _sr_gpu(case, storage, 5)
+    o.iteration(300)
+    g.iteration(300)
+    er, eu = _fluid_errs(g, o, 1)
+    assert er <= 4 * eps and eu <= 40 * eps
+    case = phase_case(70, 45, 31)
+    o, g = build_oracle(case), _sr_gpu(case, storage, 6)
+    o.iteration(25)
+    g.iteration(25)
+    er2, eu2 = _fluid_errs(g, o, 1)
+    assert er2 <= 4 * eps and eu2 <= 40 * eps
+    case = intersolute_case(90, 70, 11, q=4, nd=4)
+    o, g = build_oracle(case), _sr_gpu(case, storage, 7)
+    o.iteration(100)
+    g.iteration(100)
+    Cg, _ = g.solute_state()
+    Co, _ = o.solute_state()
+    ec = rel_err(Cg, Co)
+    print(f"{storage} stochastic: slip channel rho {er:.2e} u {eu:.2e}; psi rho {er2:.2e} u {eu2:.2e}; "
+          f"intersolute C {ec:.2e} (eps {eps:.1e})")
+    assert ec <= 16 * eps
