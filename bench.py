@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="all",
                     help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel,droplet")
+    ap.add_argument("--rounding", default="nearest", choices=("nearest", "stochastic"),
+                    help="rounding of 16-bit storage in the --no-main two-component + solute run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-readout", action="store_true")
     ap.add_argument("--sc-steps", type=int, default=20000,
@@ -456,7 +458,8 @@ def main():
         want = set(args.variants.split(",")) if args.variants not in ("all", "none") else set()
         res = {}
         if "sc" in want:
-            res["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 10, stream)
+            res["sc_solute"] = run_sc_solute(lb2d, torch, 2048, args.sc_steps, 10, stream, storage=args.storage,
+                                             rounding=args.rounding)
         if "phase" in want:
             res["phase"] = run_phase(lb2d, torch, 4096, args.sc_steps, 10, stream)
         if "growth" in want:
