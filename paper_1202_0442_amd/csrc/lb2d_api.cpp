@@ -153,6 +153,7 @@ struct lb2d_batch {
     size_t max_plane = 0;  // largest population plane of the lattices
     bool nt = false;       // streaming stores: the lattices' populations exceed the last-level cache
     bool sr = false;       // stochastic rounding (every lattice of the batch asked for it)
+    unsigned long long *d_step = nullptr;  // device step count shared by the lattices (stochastic rounding)
     hipGraphExec_t graph = nullptr;
     int64_t t = 0;
     int fail(int code, const char *fmt, ...) {
@@ -1404,7 +1405,7 @@ int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
     if (!b || !bytes) return LB2D_E_INVAL;
     if (b->lat.empty()) return b->fail(LB2D_E_STATE, "empty batch");
     const size_t tiles = max_tiles_for(b);
-    *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile));
+    *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile)) + align_up(8);
     return LB2D_OK;
 }
 
@@ -1433,6 +1434,14 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     b->d_lat = (PlainLattice *)b->ws;
     b->d_tiles = (Tile *)(b->ws + align_up(b->lat.size() * sizeof(PlainLattice)));
     b->max_tiles = max_tiles_for(b);
+    b->d_step = (unsigned long long *)((char *)b->d_tiles + align_up(b->max_tiles * sizeof(Tile)));
+    {
+        // every lattice of a batch is at the same step, and a lattice that
+        // rounds stochastically has its device counter at that step
+        const unsigned long long t0 = (unsigned long long)b->lat[0]->t;
+        HIPCHK(b, hipMemcpyAsync(b->d_step, &t0, 8, hipMemcpyHostToDevice, (hipStream_t)hip_stream));
+        HIPCHK(b, hipStreamSynchronize((hipStream_t)hip_stream));
+    }
     plain_tile(b->storage, &b->tile_w, &b->tile_h);
     std::vector<PlainLattice> L;
     b->max_plane = 0;
@@ -1490,11 +1499,11 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
             HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt,
-                                   b->sr, 0, b->stream));
+                                   b->sr, 0, b->d_step, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
                 HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
-                                       b->nt, b->sr, 0, b->stream));
+                                       b->nt, b->sr, 0, b->d_step, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1532,8 +1541,8 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 // the lattices' step counters after it (stochastic rounding only).
 static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
     hipError_t e = launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, b->nt,
-                                b->sr, k, s);
-    if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, s);
+                                b->sr, k, b->d_step, s);
+    if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
 

@@ -436,21 +436,24 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
 // independent lattices; `persistent` grids stride over the table.  With
 // stochastic rounding each lattice draws the random words it would draw
-// stepped alone (its own step counter, seed and node numbering); k is the
+// stepped alone (its seed and node numbering, and the step count, which
+// all lattices of a batch share: `bstep`, read once per block); k is the
 // step's offset in its launch group, as in k_plain.
 template <typename S, typename O, bool SR, bool NT>
 __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
                                               const Tile *__restrict__ tiles, int ntiles,
-                                              int parity, int k) {
+                                              int parity, int k,
+                                              const unsigned long long *__restrict__ bstep) {
     int lx, ly;
     brick_thread<S>(threadIdx.x, lx, ly);
+    unsigned long long step = 0ull;
+    if constexpr (SR) step = *bstep + (unsigned long long)k + 1ull;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int li = (int)ufl((unsigned)tiles[t].lattice);
         const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
         unsigned tkey = 0u;
-        if constexpr (SR)
-            tkey = ufl(lowbias32((unsigned)(*lat[li].step + (unsigned long long)k + 1ull) ^ lat[li].seed));
+        if constexpr (SR) tkey = ufl(lowbias32((unsigned)step ^ lat[li].seed));
         const int x = x0 + lx;
         const int y = y0 + ly;
         plain_node<S, O, SR, NT>(a, x, y, x < (int)a.nx && y < (int)a.ny, tkey);
@@ -1880,38 +1883,41 @@ hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {
 
 template <bool NT>
 static void batch_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                           size_t max_plane, bool sr, int k, hipStream_t stream) {
+                           size_t max_plane, bool sr, int k, const unsigned long long *bstep, hipStream_t stream) {
     dim3 blk(256);
     // stochastic rounding: every lattice's arrays are below 4 GiB (checked at bind)
     if (sr && st == kF16)
         hipLaunchKernelGGL((k_batch<_Float16, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                           parity, k);
+                           parity, k, bstep);
     else if (sr && st == kBF16)
         hipLaunchKernelGGL((k_batch<bf16s, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                           parity, k);
+                           parity, k, bstep);
     else if (fits32(max_plane, storage_bytes(st)))
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t, false, NT>), dim3(grid), blk, 0, stream, lat,
-                                             tiles, ntiles, parity, k));
+                                             tiles, ntiles, parity, k, bstep));
     else
         LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t, false, NT>), dim3(grid), blk, 0, stream, lat,
-                                             tiles, ntiles, parity, k));
+                                             tiles, ntiles, parity, k, bstep));
 }
 
 hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, bool nt, bool sr, int k, hipStream_t stream) {
-    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, stream);
-    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, stream);
+                        size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+                        hipStream_t stream) {
+    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
     return hipGetLastError();
 }
 
-// Advances the step counter of every lattice of a batch by n.
-__global__ void k_tick_batch(const PlainLattice *__restrict__ lat, int nlat, int n) {
+// Advances the batch's step counter and that of every lattice of the batch
+// (which each lattice reads when stepped alone) by n.
+__global__ void k_tick_batch(const PlainLattice *__restrict__ lat, int nlat, int n, unsigned long long *bstep) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nlat) *(unsigned long long *)lat[i].step += (unsigned long long)n;
+    if (i == 0) *bstep += (unsigned long long)n;
 }
 
-hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_tick_batch, dim3((nlat + 255) / 256), dim3(256), 0, s, lat, nlat, n);
+hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, unsigned long long *bstep, hipStream_t s) {
+    hipLaunchKernelGGL(k_tick_batch, dim3((nlat + 255) / 256), dim3(256), 0, s, lat, nlat, n, bstep);
     return hipGetLastError();
 }
 
