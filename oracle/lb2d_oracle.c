@@ -154,6 +154,9 @@ typedef struct orc {
     double grow_R[2];            /* R of solids made by growth */
     double *b;                   /* deposited mass on solid nodes */
     double *bacc;                /* per-step deposit scratch */
+    double *bdec;                /* deposits the growth decisions of the last
+                                    step were taken from (after its deposit,
+                                    before any reset); a record for tests */
     uint8_t *grow;               /* per-step growth marks */
     double *rho[2], *jx[2], *jy[2], *Fx[2], *Fy[2]; /* per-step scratch */
 
@@ -191,6 +194,7 @@ orc *orc_create(int nx, int ny) {
     o->grow = (uint8_t *)calloc(o->n, 1);
     o->b = (double *)calloc(o->n, sizeof(double));
     o->bacc = (double *)calloc(o->n, sizeof(double));
+    o->bdec = (double *)calloc(o->n, sizeof(double));
     return o;
 }
 
@@ -203,6 +207,7 @@ void orc_destroy(orc *o) {
     }
     free(o->g); free(o->gtmp); free(o->mask); free(o->grow); free(o->b);
     free(o->bacc);
+    free(o->bdec);
     free(o);
 }
 
@@ -1137,6 +1142,7 @@ static void one_step(orc *o) {
      * a node chosen twice grows once. */
     if (o->reaction) {
         memset(o->grow, 0, n);
+        memcpy(o->bdec, o->b, sizeof(double) * n);
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long sd = idx(o, x, y);
@@ -1300,6 +1306,12 @@ int orc_set_mask(orc *o, const uint8_t *in) {
 int orc_get_b(orc *o, double *out) {
     if (o->reaction) init_b(o);
     memcpy(out, o->b, sizeof(double) * o->n);
+    return 0;
+}
+/* Deposits at the growth decisions of the last step (after its deposit,
+ * before the triggering deposits were reset). */
+int orc_get_bdec(orc *o, double *out) {
+    memcpy(out, o->bdec, sizeof(double) * o->n);
     return 0;
 }
 int orc_set_b(orc *o, const double *in) {

@@ -30,27 +30,34 @@ STYLE = {"dirichlet": 1, "adiabatic": 2}
 WALL = {"xlo": 0, "xhi": 1}
 
 
+# plain -O2, no fast-math, no contraction; OpenMP over rows (results do not
+# depend on the thread count)
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC"]
+
+
+def compile_source(src: str, out: str, extra=()) -> str:
+    """gcc build of an oracle source file into the shared library `out`."""
+    subprocess.check_call(["gcc", *CFLAGS, *extra, src, "-o", out + ".tmp", "-lm"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction;
-    OpenMP over rows -- results do not depend on the thread count)."""
+    """Compile the oracle with gcc."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-shared",
-               "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
 _lib = None
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB)
+def load_library(path):
+    """ctypes handle of an oracle library built at `path`, with the call
+    signatures set.  The default library is built from ``lb2d_oracle.c``;
+    tests also build deliberately broken copies of it to check that the
+    pins catch plausible mistakes."""
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.c_double
     I = ctypes.c_int
@@ -92,6 +99,7 @@ def _load():
         "orc_get_mask": (I, [P, U8P]),
         "orc_set_mask": (I, [P, U8P]),
         "orc_get_b": (I, [P, DP]),
+        "orc_get_bdec": (I, [P, DP]),
         "orc_set_b": (I, [P, DP]),
         "orc_forces": (I, [P, I, DP, DP]),
         "orc_feq": (D, [I, D, D, D, D]),
@@ -105,8 +113,17 @@ def _load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = load_library(_LIB)
+    return _lib
 
 
 def _dp(a):
@@ -156,8 +173,8 @@ def set_threads(n=0):
 class Oracle:
     """One lattice.  Command methods mirror the paper's commands."""
 
-    def __init__(self, nx, ny):
-        self.lib = _load()
+    def __init__(self, nx, ny, lib=None):
+        self.lib = _load() if lib is None else lib
         self.nx, self.ny = int(nx), int(ny)
         self.n = self.nx * self.ny
         self.h = self.lib.orc_create(self.nx, self.ny)
@@ -335,6 +352,14 @@ class Oracle:
     def get_b(self):
         out = np.empty(self.n)
         self.lib.orc_get_b(self.h, _dp(out))
+        return out.reshape(self.ny, self.nx)
+
+    def get_bdec(self):
+        """Deposits the growth decisions of the last step were taken from
+        (after that step's deposit, before the triggering solids were reset
+        to zero)."""
+        out = np.empty(self.n)
+        self.lib.orc_get_bdec(self.h, _dp(out))
         return out.reshape(self.ny, self.nx)
 
     def set_b(self, b):

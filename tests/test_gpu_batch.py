@@ -1,0 +1,92 @@
+"""The batched ensemble (many uneven one-fluid lattices advanced by one
+launch per step) against the FP64 oracle, lattice by lattice.
+
+The lattices come from the ensemble generator (sides log-uniform in
+[256, 1536], Boolean discs r 4..20 to porosity U[0.4, 0.8], tau U[0.6, 1.2],
+acceleration 1e-5 along e1): the first eight of its 256 lattices whose sides
+are both at most 512 nodes, batched on their own.  Bars: FP32 within 1e-5 of
+the largest velocity and of the density; FP16 storage within the bounds of
+the one-lattice FP16 test (3e-2 of the largest velocity, 3e-4 in density).
+"""
+import numpy as np
+import pytest
+
+from cases import build_gpu, build_oracle, porous_case
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"f32": (1e-5, 1e-5), "f16": (3e-2, 3e-4)}
+
+
+def ensemble_cases(count=8, side_max=512):
+    from paper_1202_0442_amd import inputs
+    out = []
+    for w in inputs.ensemble():
+        if max(w.nx, w.ny) <= side_max:
+            out.append(dict(nx=w.nx, ny=w.ny, tau=w.tau, accel=[(1, w.accel_x, 0)], circles=w.discs))
+        if len(out) == count:
+            break
+    return out
+
+
+def _errors(g, o):
+    gr, gx, gy = g.moments(0)
+    orr, ox, oy = o.moments(0)
+    solid = orr == -11.0
+    assert np.array_equal(gr == -11.0, solid)
+    uscale = max(np.abs(ox).max(), np.abs(oy).max(), 1e-30)
+    eu = max(np.abs(gx - ox).max(), np.abs(gy - oy).max()) / uscale
+    er = np.abs(gr - orr)[~solid].max() / np.abs(orr[~solid]).max()
+    return eu, er
+
+
+def _batch(members, tune_cache=None):
+    from paper_1202_0442_amd import lb2d
+    b = lb2d.Batch(0)
+    for m in members:
+        b.add(m)
+    b.finalize(tune_cache=tune_cache)
+    return b
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_ensemble_lattices_batched_match_oracle(storage):
+    """Eight generator lattices batched alone, 320 steps (ten 32-step
+    graphs), every member against its own oracle run."""
+    cases = ensemble_cases()
+    assert len(cases) == 8
+    members = [build_gpu(c, storage) for c in cases]
+    batch = _batch(members)
+    print("tuned", batch.config())
+    batch.iteration(320)
+    tol_u, tol_r = BARS[storage]
+    for c, m in zip(cases, members):
+        o = build_oracle(c)
+        assert np.array_equal(m.mask(), o.get_mask())
+        o.iteration(320)
+        eu, er = _errors(m, o)
+        print(f"{c['nx']}x{c['ny']} tau {c['tau']:.3f}: rel u err {eu:.2e}, rel rho err {er:.2e}")
+        assert m.step_count() == 320
+        assert eu <= tol_u and er <= tol_r
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_toy_batch_matches_oracle_and_single_lattices(storage):
+    """Four ragged lattices (one of 9 rows, one of 33 columns): 75 steps
+    batched (two graphs and single steps) equal the lattices stepped alone
+    bit for bit, and each matches its oracle run."""
+    cases = [porous_case(nx, ny, 20 + k, tau=0.6 + 0.1 * k) for k, (nx, ny) in
+             enumerate([(64, 40), (131, 77), (33, 200), (256, 9)])]
+    singles = [build_gpu(c, storage) for c in cases]
+    members = [build_gpu(c, storage) for c in cases]
+    batch = _batch(members)
+    for s in singles:
+        s.iteration(75)
+    batch.iteration(75)
+    tol_u, tol_r = BARS[storage]
+    for c, s, m in zip(cases, singles, members):
+        assert np.array_equal(s.get_populations(0), m.get_populations(0))
+        o = build_oracle(c)
+        o.iteration(75)
+        eu, er = _errors(m, o)
+        assert eu <= tol_u and er <= tol_r, (eu, er)

@@ -105,7 +105,7 @@ def test_one_fluid_above_4gib_sampled_patches(storage, n, tol_u):
     assert worst_r <= tol_rho and worst <= tol_u
 
 
-@pytest.mark.parametrize("storage,n,tol_r,tol_u", [("f32", N, 1e-5, 1e-4),
+@pytest.mark.parametrize("storage,n,tol_r,tol_u", [("f32", N, 1e-5, 1e-5),
                                                     ("f16", 15500, 2 * 2.0 ** -11, 20 * 2.0 ** -11)])
 def test_two_fluid_shan_chen_above_4gib_sampled_patches(storage, n, tol_r, tol_u):
     """Two components with Shan-Chen cohesion: FP32 at 11600^2, FP16 at

@@ -117,21 +117,14 @@ def test_sc_solute_fp32_matches_oracle_without_growth():
 
 
 def test_sc_solute_fp32_growth_mask_protocol():
-    """FP32 with growth: the mask stays identical to the oracle's while
-    deposit margins exceed the FP32 error; report the first divergence."""
-    case = sc_solute_case(96, 80, 13, react=True)
-    o, g = build_oracle(case), build_gpu(case, "f32")
-    first = None
-    for step in range(15):
-        o.iteration(20)
-        g.iteration(20)
-        if first is None and not np.array_equal(g.mask(), o.get_mask()):
-            first = o.t
-    ham = int((g.mask() != o.get_mask()).sum())
-    print(f"first mask divergence: {first}, final Hamming distance {ham}, "
-          f"grown {o.budgets()['grown_nodes']}")
-    assert o.budgets()["grown_nodes"] > 5
-    assert ham <= max(2, 0.05 * o.budgets()["grown_nodes"])
+    """FP32 with growth: every step where the GPU takes a growth decision
+    the oracle does not (or the reverse) must have an oracle decision
+    deposit within the FP32 error bound of b_max; the protocol
+    (tests/test_gpu_growth.py) checks each such step and continues from the
+    oracle's state."""
+    from test_gpu_growth import growth_protocol
+    first, events, grown = growth_protocol(sc_solute_case(96, 80, 13, react=True), 300)
+    assert grown > 5
 
 
 def test_solute_budget_closes_on_gpu():
@@ -193,26 +186,6 @@ def test_graph_launch_equals_single_launches(kind):
     assert k == 70 and ms > 0
     assert np.array_equal(a.get_populations(0), b.get_populations(0))
     assert np.array_equal(a.mask(), b.mask())
-
-
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_batch_equals_single_lattices(storage):
-    from paper_1202_0442_amd import lb2d
-    cases = [porous_case(nx, ny, 20 + k, tau=0.6 + 0.1 * k) for k, (nx, ny) in
-             enumerate([(64, 40), (131, 77), (33, 200), (256, 9)])]
-    singles = [build_gpu(c, storage) for c in cases]
-    members = [build_gpu(c, storage) for c in cases]
-    batch = lb2d.Batch(0)
-    for m in members:
-        batch.add(m)
-    batch.finalize()
-    print(batch.config())
-    for s in singles:
-        s.iteration(75)
-    batch.iteration(75)
-    for s, m in zip(singles, members):
-        assert m.step_count() == 75
-        assert np.array_equal(s.get_populations(0), m.get_populations(0))
 
 
 def test_minimum_lattice_and_zero_steps():

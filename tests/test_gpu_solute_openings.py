@@ -69,3 +69,45 @@ def test_flux_opening_steady_profile_on_gpu(kind):
     k = 1 - 1 / (nx - 1)
     a = v * C0 / (D + v - D * k) if kind == "inlet" else v * C0 / (v - D + D * k)
     np.testing.assert_allclose(C.reshape(ny, nx)[1], a * (1 - np.arange(nx) / (nx - 1)), rtol=1e-12, atol=1e-14)
+
+
+def _mirror_case(nx, ny, q, width=None, seed=44, uy=0.03):
+    """Dirichlet xlo (C = 1) and, on xhi, an adiabatic opening (width None)
+    or a dirichlet one on a strip of `width` nodes whose initial
+    concentration is the mirror image of the nx-node strip's about its
+    column nx - 1; one fluid flowing along the walls."""
+    rng = np.random.default_rng(seed)
+    C = 0.2 + 0.5 * rng.uniform(0, 1, (ny, nx))
+    w = nx if width is None else width
+    if width is not None:
+        C = np.concatenate([C, C[:, -2::-1]], axis=1)
+    xhi = ("xhi", 0, ny - 1, "outlet", "adiabatic" if width is None else "dirichlet", 1.0, 0.0)
+    return dict(nx=w, ny=ny, tau=1.0, solute=0.7, q=q, C=C.ravel(),
+                fields={0: (np.ones(w * ny), np.zeros(w * ny), np.full(w * ny, uy))},
+                sopen=[("xlo", 0, ny - 1, "inlet", "dirichlet", 1.0, 0.0), xhi])
+
+
+@pytest.mark.parametrize("q", [4, 9])
+@pytest.mark.parametrize("nx,ny", [(13, 8), (77, 45)])
+def test_adiabatic_wall_is_a_mirror_plane_fp64(q, nx, ny):
+    """The adiabatic opening (g3 = g1 on xhi, each unknown copies its
+    mirror) on the GPU: every solute population equals the oracle's, and
+    the strip equals the oracle's mirrored strip of 2 nx - 1 nodes with
+    dirichlet walls on both sides (the pin of the oracle's adiabatic rule)."""
+    case = _mirror_case(nx, ny, q)
+    o, g = build_oracle(case), build_gpu(case, "f64")
+    wide = build_oracle(_mirror_case(nx, ny, q, width=2 * nx - 1))
+    for side in (o, g, wide):
+        side.iteration(60)
+    np.testing.assert_allclose(g.get_populations(-1), o.get_g(), rtol=0, atol=1e-14)
+    Cg, _ = g.solute_state()
+    Cw, _ = wide.solute_state()
+    np.testing.assert_allclose(Cg.reshape(ny, nx), Cw.reshape(ny, 2 * nx - 1)[:, :nx], rtol=1e-12)
+
+
+def test_adiabatic_wall_fp32():
+    case = _mirror_case(77, 45, 9)
+    o, g = build_oracle(case), build_gpu(case, "f32")
+    o.iteration(300)
+    g.iteration(300)
+    _cmp(g, o, 1e-5)

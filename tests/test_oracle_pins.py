@@ -896,6 +896,60 @@ def test_solute_openings_on_y_walls_and_closed_wall_parts(q):
     assert b["solute"] - b["inflow"] + b["outflow"] == pytest.approx(b0["solute"], rel=1e-12)
 
 
+
+@pytest.mark.parametrize("q", [4, 9])
+def test_adiabatic_walls_keep_tangential_equilibrium(q):
+    """Adiabatic openings on both x walls (inlet_solute / outlet_solute,
+    zero normal flux: g3 = g1 on xhi) under a uniform flow along the walls:
+    a uniform concentration is an exact steady state, so every population of
+    every node, wall nodes included, stays at g_eq(C, u) = w_i C (1 + e.u/c_s^2)."""
+    nx, ny, C0, uy = 9, 7, 0.37, 0.02
+    o = Oracle(nx, ny)
+    o.fluids(1, 1.0)
+    o.solute(0.8, q)
+    o.solute_opening_range("xlo", 0, ny - 1, "inlet", "adiabatic")
+    o.solute_opening_range("xhi", 0, ny - 1, "outlet", "adiabatic")
+    o.set_fields(0, 1.0, 0.0, uy)
+    o.set_concentration(C0, 0.0, uy)
+    o.iteration(100)
+    g = o.get_g()
+    w = [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4 if q == 9 else [0] + [0.25] * 4 + [0] * 4
+    ics2 = 3.0 if q == 9 else 2.0
+    for i in range(9):
+        np.testing.assert_allclose(g[i], w[i] * C0 * (1 + ics2 * EY[i] * uy), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("q", [4, 9])
+def test_adiabatic_wall_is_a_mirror_plane(q):
+    """An adiabatic wall node is a symmetry plane of the solute (the unknown
+    populations copy their mirror images): a strip of nx nodes with a
+    dirichlet xlo and an adiabatic xhi evolves exactly as the first nx
+    columns of a strip of 2 nx - 1 nodes with dirichlet walls on both
+    sides and the mirrored initial concentration, here under a flow along
+    the walls and a concentration that varies along them."""
+    nx, ny, uy, Cbar = 13, 8, 0.03, 1.0
+    rng = np.random.default_rng(44)
+    C = 0.2 + 0.5 * rng.uniform(0, 1, (ny, nx))
+    wide = 2 * nx - 1
+    Cw = np.concatenate([C, C[:, -2::-1]], axis=1)
+
+    def run(width, xhi_style, C0):
+        o = Oracle(width, ny)
+        o.fluids(1, 1.0)
+        o.solute(0.7, q)
+        o.solute_opening_range("xlo", 0, ny - 1, "inlet", "dirichlet", Cbar)
+        o.solute_opening_range("xhi", 0, ny - 1, "outlet", xhi_style, Cbar)
+        o.set_fields(0, 1.0, 0.0, uy)
+        o.set_concentration(C0.ravel(), 0.0, uy)
+        o.iteration(60)
+        return o.solute_state()[0]
+
+    half = run(nx, "adiabatic", C)
+    full = run(wide, "dirichlet", Cw)
+    np.testing.assert_allclose(full[:, nx - 1:], full[:, nx - 1::-1], rtol=1e-12)  # the wide run stays symmetric
+    np.testing.assert_allclose(half, full[:, :nx], rtol=1e-12)
+    assert np.ptp(half[:, -1]) > 1e-4    # the wall column still varies along the wall
+
 def test_solute_budget_closes_with_openings_on_every_wall():
     """Openings of all three styles on all four walls, reactive walls and
     growth: solute + deposit + consumed deposit + removed solute - b0 per
