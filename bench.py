@@ -347,17 +347,34 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
         for L in lats:
             L.iteration(k)
     ms_seq = time_steps(torch, stream, seq, seq_steps)
+    nfl = sum(L.budgets()["fluid_nodes"] for L in lats)
     B = lb2d.Batch(0)
     for L in lats:
         B.add(L)
     B.finalize(stream=stream)
     B.iteration(GRAPH_WARMUP)
     ms_b = time_steps(torch, stream, B.iteration, steps)
+    # algorithmic bytes of one batched step (one launch): 18 values per
+    # fluid node of every lattice and the 1-byte mask of every node
+    byt = nfl * 18 * STORE_BYTES[storage] + ntot
+    per = ms_b / steps
+    trials = B.trials()
+    spread = {}
+    for t in trials:
+        k = f"{t['tile_w']}x{t['tile_h']}"
+        spread[k] = min(spread.get(k, 1e30), t["ms"])
     out = {"workload": f"{count} porous lattices, sides log-uniform 256..1536, {ntot} nodes, {storage}"
                        + ("" if rounding == "nearest" else f", {rounding} rounding"),
            "batched_mlups": ntot * steps / (ms_b * 1e-3) / 1e6,
            "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6,
-           "tuned": B.config(), "steps": steps, "sequential_steps": seq_steps}
+           "tuned": B.config(), "autotuner_trials": len(trials),
+           "best_ms_per_tile_shape": {k: round(v, 4) for k, v in spread.items()},
+           "roofline": {"bound": "hbm", "achieved": round(byt / (per * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBPS,
+                        "unit": "GB/s", "frac": round(byt / (per * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                        "kernel": "k_batch", "bytes_per_launch": byt,
+                        "bytes_rule": f"{18 * STORE_BYTES[storage]} B per fluid node of every lattice "
+                                      "+ 1 B mask per node"},
+           "ms_per_step": per, "steps": steps, "sequential_steps": seq_steps}
     out["speedup"] = out["batched_mlups"] / out["sequential_mlups"]
     B.close()
     for L in lats:

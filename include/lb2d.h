@@ -331,8 +331,12 @@ int lb2d_step_count(lb2d_ctx *ctx, int64_t *t);
 
 /* A batch advances many bound one-fluid lattices (no solute, no Shan-Chen;
  * each with its own size, geometry, tau and forces, one storage format) in
- * one launch per time step.  Tile shape and the order of tiles are picked
- * by an autotuner at finalize (results never depend on them). */
+ * one launch per time step: 256-thread blocks walk a table of tiles of all
+ * the lattices.  The tile shape (one, two or four brick rows: 64x4, 32x8 or
+ * 16x16 nodes for FP32/FP64, 32x8, 16x16 or 8x32 for 16-bit storage), the
+ * order of the tiles in the table and the grid (one block per tile or
+ * persistent blocks) are picked by an autotuner at finalize; results never
+ * depend on them. */
 int lb2d_batch_create(lb2d_batch **out, int hip_device);
 /* Waits for the batch's queued work, then frees the batch (not its
  * lattices, nor the caller's device memory). */
@@ -356,10 +360,19 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes,
                         void *hip_stream, const char *tune_cache_json);
 /* Advances every lattice by nsteps (asynchronous, graph-launched). */
 int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps);
-/* The tuned launch shape: tile width, tile height, schedule id, blocks per
- * CU (0 = one block per tile). */
+/* The tuned launch shape: tile width, tile height, schedule id (0 lattice
+ * by lattice, 1 largest lattices first, 2 tiles of all lattices interleaved
+ * round-robin), blocks per CU (0 = one block per tile). */
 int lb2d_batch_config(lb2d_batch *b, int *tile_w, int *tile_h, int *schedule,
                       int *blocks_per_cu);
+/* The autotuner's trials at finalize: *count receives their number (0 when
+ * the choice came from the tune cache); the first min(max, count) are
+ * written to the caller's arrays of max entries: tile width and height,
+ * schedule id, blocks per CU and the measured milliseconds per step.
+ * max = 0 only queries the count. */
+int lb2d_batch_trials(lb2d_batch *b, int max, int *tile_w, int *tile_h,
+                      int *schedule, int *blocks_per_cu, double *ms,
+                      int *count);
 
 /* -------------------------------------------------------- measurement */
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -156,6 +157,9 @@ struct lb2d_batch {
     unsigned long long *d_step = nullptr;  // device step count shared by the lattices (stochastic rounding)
     hipGraphExec_t graph = nullptr;
     int64_t t = 0;
+    // the autotuner's trials: tile width, height, schedule, blocks per CU
+    // and milliseconds per step (empty when the choice came from a cache)
+    std::vector<std::array<double, 5>> trials;
     int fail(int code, const char *fmt, ...) {
         char buf[512];
         va_list ap;
@@ -1394,11 +1398,21 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
-// The tile of one block is fixed by the brick layout of the storage format.
+// Largest tile table over the tile shapes of the storage format.
 static size_t max_tiles_for(const lb2d_batch *b) {
-    int tw, th;
-    plain_tile(b->storage, &tw, &th);
-    return tiles_for(b, tw, th);
+    int tw[4], th[4];
+    const int ns = batch_shapes(b->storage, tw, th, 4);
+    size_t m = 0;
+    for (int k = 0; k < ns; ++k) m = std::max(m, tiles_for(b, tw[k], th[k]));
+    return m;
+}
+
+static bool is_batch_shape(int st, int w, int h) {
+    int tw[4], th[4];
+    const int ns = batch_shapes(st, tw, th, 4);
+    for (int k = 0; k < ns; ++k)
+        if (tw[k] == w && th[k] == h) return true;
+    return false;
 }
 
 int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
@@ -1470,7 +1484,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             if (std::fscanf(fh, "{\"key\": \"%63[0-9a-f]\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
                                 "\"blocks_per_cu\": %d}",
                             k, &w, &h, &s, &p) == 5 &&
-                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 && w == b->tile_w && h == b->tile_h) {
+                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 && is_batch_shape(b->storage, w, h)) {
                 b->tile_w = w;
                 b->tile_h = h;
                 b->schedule = s;
@@ -1482,13 +1496,17 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     }
     if (!have) {
         // timed trial steps: each writes the lattices' next buffers from the
-        // current ones without advancing, so the state is unchanged
-        // schedules (lattice by lattice, largest first, interleaved) x grid
-        // (one block per tile, or persistent blocks per CU)
-        const int tw = b->tile_w, th = b->tile_h;
-        const TuneCand cands[] = {{tw, th, 0, 0},  {tw, th, 1, 0},  {tw, th, 2, 0},  {tw, th, 0, 8},
-                                  {tw, th, 1, 8},  {tw, th, 2, 8},  {tw, th, 0, 16}, {tw, th, 1, 16},
-                                  {tw, th, 2, 16}, {tw, th, 1, 32}};
+        // current ones without advancing, so the state is unchanged.
+        // Candidates: tile shape (one, two or four brick rows) x schedule
+        // (lattice by lattice, largest first, interleaved) x grid (one block
+        // per tile, or 8 or 16 persistent blocks per CU)
+        int tws[4], ths[4];
+        const int ns = batch_shapes(b->storage, tws, ths, 4);
+        std::vector<TuneCand> cands;
+        for (int k = 0; k < ns; ++k)
+            for (int bpc : {0, 8, 16})
+                for (int sched = 0; sched < 3; ++sched) cands.push_back({tws[k], ths[k], sched, bpc});
+        b->trials.clear();
         hipEvent_t e0, e1;
         HIPCHK(b, hipEventCreate(&e0));
         HIPCHK(b, hipEventCreate(&e1));
@@ -1498,16 +1516,17 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane, b->nt,
-                                   b->sr, 0, b->d_step, b->stream));
+            HIPCHK(b, launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
+                                   b->nt, b->sr, 0, b->d_step, b->stream));
             HIPCHK(b, hipEventRecord(e0, b->stream));
             for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
-                                       b->nt, b->sr, 0, b->d_step, b->stream));
+                HIPCHK(b, launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
+                                       b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream));
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+            b->trials.push_back({(double)cd.w, (double)cd.h, (double)cd.sched, (double)cd.bpc, ms / 3.0});
             if (ms < best) {
                 best = ms;
                 bc = cd;
@@ -1540,8 +1559,8 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 // One batched step at offset k of its launch group; tick: steps to add to
 // the lattices' step counters after it (stochastic rounding only).
 static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
-    hipError_t e = launch_batch(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid, b->max_plane, b->nt,
-                                b->sr, k, b->d_step, s);
+    hipError_t e = launch_batch(b->storage, b->tile_w, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid,
+                                b->max_plane, b->nt, b->sr, k, b->d_step, s);
     if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
@@ -1591,6 +1610,23 @@ int lb2d_batch_config(lb2d_batch *b, int *w, int *h, int *s, int *p) {
     *h = b->tile_h;
     *s = b->schedule;
     *p = b->bpc;
+    return LB2D_OK;
+}
+
+int lb2d_batch_trials(lb2d_batch *b, int max, int *tile_w, int *tile_h, int *schedule, int *blocks_per_cu,
+                      double *ms, int *count) {
+    if (!b || !count || max < 0) return LB2D_E_INVAL;
+    if (!b->final_) return b->fail(LB2D_E_STATE, "not finalized");
+    const int n = (int)b->trials.size();
+    *count = n;
+    if (max > 0 && (!tile_w || !tile_h || !schedule || !blocks_per_cu || !ms)) return LB2D_E_INVAL;
+    for (int k = 0; k < n && k < max; ++k) {
+        tile_w[k] = (int)b->trials[k][0];
+        tile_h[k] = (int)b->trials[k][1];
+        schedule[k] = (int)b->trials[k][2];
+        blocks_per_cu[k] = (int)b->trials[k][3];
+        ms[k] = b->trials[k][4];
+    }
     return LB2D_OK;
 }
 

@@ -407,15 +407,25 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     }
 }
 
-// Thread t of a 256-thread block -> node of a brick-aligned tile of
-// (256 / (BW*BH)) bricks side by side: BW*BH (16 to 32) consecutive lanes
-// cover one brick, so each store of a wavefront writes whole bricks.
+// Node of a TX-wide tile handled by thread t: BW x BH consecutive threads
+// cover one brick, the tile's bricks in row-major order, so a wavefront's
+// loads and stores of one plane touch whole bricks (four 64-byte FP32
+// bricks, two 64-byte 16-bit bricks, two 256-byte FP64 bricks).
+template <int TX, int BW, int BH>
+__device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
+    constexpr int BPR = TX / BW;
+    const int b = t / (BW * BH), k = t % (BW * BH);
+    lx = (b % BPR) * BW + k % BW;
+    ly = (b / BPR) * BH + k / BW;
+}
+
+// Thread t of a 256-thread block of the one-fluid step -> node of a tile of
+// (256 / (BW*BH)) bricks side by side (64x4 nodes for 4-byte values, 32x8
+// for 2-byte values, 64x4 for 8-byte values).
 template <typename S>
 __device__ __forceinline__ void brick_thread(int t, int &lx, int &ly) {
     constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
-    const int b = t / (W * H), k = t % (W * H);
-    lx = b * W + k % W;
-    ly = k / W;
+    tile_thread<256 / (W * H) * W, W, H>(t, lx, ly);
 }
 
 // k: offset of this step in its launch group (the step computed is the
@@ -434,18 +444,21 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many
-// independent lattices; `persistent` grids stride over the table.  With
-// stochastic rounding each lattice draws the random words it would draw
-// stepped alone (its seed and node numbering, and the step count, which
-// all lattices of a batch share: `bstep`, read once per block); k is the
-// step's offset in its launch group, as in k_plain.
-template <typename S, typename O, bool SR, bool NT>
+// independent lattices; `persistent` grids stride over the table.  A tile
+// is TX nodes wide and 256 / TX nodes high (whole bricks; the autotuner
+// picks TX).  With stochastic rounding each lattice draws the random words
+// it would draw stepped alone (its seed and node numbering, and the step
+// count, which all lattices of a batch share: `bstep`, read once per
+// block); k is the step's offset in its launch group, as in k_plain.
+template <typename S, typename O, bool SR, bool NT, int TX>
 __global__ void __launch_bounds__(256) k_batch(const PlainLattice *__restrict__ lat,
                                               const Tile *__restrict__ tiles, int ntiles,
                                               int parity, int k,
                                               const unsigned long long *__restrict__ bstep) {
+    constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
+    static_assert(TX % W == 0 && (256 / (W * H)) % (TX / W) == 0, "tile of whole bricks");
     int lx, ly;
-    brick_thread<S>(threadIdx.x, lx, ly);
+    tile_thread<TX, W, H>(threadIdx.x, lx, ly);
     unsigned long long step = 0ull;
     if constexpr (SR) step = *bstep + (unsigned long long)k + 1ull;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -511,17 +524,6 @@ __device__ __forceinline__ int xcd_band(int b, int nblk) {
     return (k < len) ? start + k : -1;
 }
 
-// Node of a TX x TY tile handled by thread t: BW x BH consecutive threads
-// cover one brick, the tile's bricks in row-major order, so a wavefront's
-// loads and stores of one plane touch whole bricks (four 64-byte FP32
-// bricks, two 64-byte 16-bit bricks, two 256-byte FP64 bricks).
-template <int TX, int BW, int BH>
-__device__ __forceinline__ void tile_thread(int t, int &lx, int &ly) {
-    constexpr int BPR = TX / BW;
-    const int b = t / (BW * BH), k = t % (BW * BH);
-    lx = (b % BPR) * BW + k % BW;
-    ly = (b / BPR) * BH + k / BW;
-}
 
 // psi(rho) = psi0 exp(-rho0 / rho) of the one-component interforce and
 // adhesiveforce commands.
@@ -1881,30 +1883,55 @@ hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool NT>
-static void batch_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                           size_t max_plane, bool sr, int k, const unsigned long long *bstep, hipStream_t stream) {
-    dim3 blk(256);
-    // stochastic rounding: every lattice's arrays are below 4 GiB (checked at bind)
-    if (sr && st == kF16)
-        hipLaunchKernelGGL((k_batch<_Float16, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                           parity, k, bstep);
-    else if (sr && st == kBF16)
-        hipLaunchKernelGGL((k_batch<bf16s, uint32_t, true, NT>), dim3(grid), blk, 0, stream, lat, tiles, ntiles,
-                           parity, k, bstep);
-    else if (fits32(max_plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, uint32_t, false, NT>), dim3(grid), blk, 0, stream, lat,
-                                             tiles, ntiles, parity, k, bstep));
-    else
-        LB2D_DISPATCH(st, hipLaunchKernelGGL((k_batch<S, size_t, false, NT>), dim3(grid), blk, 0, stream, lat,
-                                             tiles, ntiles, parity, k, bstep));
+// Tile widths of the batched step for a storage format: tiles of 1, 2 or 4
+// brick rows (64x4, 32x8, 16x16 nodes for 4- and 8-byte values; 32x8,
+// 16x16, 8x32 for 2-byte values).
+int batch_shapes(int st, int *tw, int *th, int max) {
+    const int vb = (int)storage_bytes(st);
+    const int W = brick_w_for(vb), H = brick_h_for(vb), bricks = 256 / (W * H);
+    int n = 0;
+    for (int rows = 1; rows <= 4 && n < max; rows *= 2) {
+        tw[n] = bricks / rows * W;
+        th[n] = rows * H;
+        ++n;
+    }
+    return n;
 }
 
-hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+template <typename S, typename O, bool SR, bool NT>
+static void batch_shape(int tw, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid, int k,
+                        const unsigned long long *bstep, hipStream_t stream) {
+    constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S)), B = 256 / (W * H);
+#define LB2D_BATCH(TX_) \
+    hipLaunchKernelGGL((k_batch<S, O, SR, NT, TX_>), dim3(grid), dim3(256), 0, stream, lat, tiles, ntiles, parity, k, bstep)
+    if (tw == B * W) LB2D_BATCH(B * W);
+    else if (tw == B / 2 * W) LB2D_BATCH(B / 2 * W);
+    else LB2D_BATCH(B / 4 * W);
+#undef LB2D_BATCH
+}
+
+template <bool NT>
+static void batch_dispatch(int st, int tw, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity,
+                           int grid, size_t max_plane, bool sr, int k, const unsigned long long *bstep,
+                           hipStream_t stream) {
+    // stochastic rounding: every lattice's arrays are below 4 GiB (checked at bind)
+    if (sr && st == kF16)
+        batch_shape<_Float16, uint32_t, true, NT>(tw, lat, tiles, ntiles, parity, grid, k, bstep, stream);
+    else if (sr && st == kBF16)
+        batch_shape<bf16s, uint32_t, true, NT>(tw, lat, tiles, ntiles, parity, grid, k, bstep, stream);
+    else if (fits32(max_plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, (batch_shape<S, uint32_t, false, NT>(tw, lat, tiles, ntiles, parity, grid, k, bstep,
+                                                                stream)));
+    else
+        LB2D_DISPATCH(st, (batch_shape<S, size_t, false, NT>(tw, lat, tiles, ntiles, parity, grid, k, bstep,
+                                                              stream)));
+}
+
+hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity,
+                        int grid, size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
                         hipStream_t stream) {
-    if (nt) batch_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
-    else batch_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    if (nt) batch_dispatch<true>(st, tile_w, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    else batch_dispatch<false>(st, tile_w, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
     return hipGetLastError();
 }
 

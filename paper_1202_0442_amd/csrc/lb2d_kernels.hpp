@@ -20,11 +20,16 @@ void plain_tile(int st, int *tw, int *th);
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
 // Adds n to the device step counter.
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
-// max_plane: largest population plane (elements) of the batch's lattices;
-// sr, nt, k as for launch_plain; bstep: the batch's device step counter
-// (equal to every lattice's; read only with sr).
-hipError_t launch_batch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                        size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep, hipStream_t s);
+// Tile shapes (width, height in nodes) of the batched step for a storage
+// format, widest first; returns their number (at most max).
+int batch_shapes(int st, int *tw, int *th, int max);
+// tile_w: one of the widths of batch_shapes; max_plane: largest population
+// plane (elements) of the batch's lattices; sr, nt, k as for launch_plain;
+// bstep: the batch's device step counter (equal to every lattice's; read
+// only with sr).
+hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity,
+                        int grid, size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+                        hipStream_t s);
 // Adds n to the batch's step counter and to that of each of its nlat lattices.
 hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, unsigned long long *bstep, hipStream_t s);
 // Streaming stores pay off once the populations (all buffers) no longer

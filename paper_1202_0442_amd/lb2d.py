@@ -90,6 +90,8 @@ _SIGS = {
     "lb2d_batch_iteration": [_P, _I64],
     "lb2d_batch_config": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                           ctypes.POINTER(_I)],
+    "lb2d_batch_trials": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                          ctypes.POINTER(_I), _DP, ctypes.POINTER(_I)],
     "lb2d_copy_bench": [_P, _P, _SZ, _I, _P, _DP],
 }
 for _name, _args in _SIGS.items():
@@ -375,6 +377,21 @@ class Batch:
         self._chk(_lib.lb2d_batch_config(self._h, *[ctypes.byref(x) for x in v]))
         return dict(tile_w=v[0].value, tile_h=v[1].value, schedule=v[2].value,
                     blocks_per_cu=v[3].value)
+
+    def trials(self):
+        """The autotuner's trials: list of dicts (tile_w, tile_h, schedule,
+        blocks_per_cu, ms per step); empty when a tune cache gave the
+        choice."""
+        cnt = _I(0)
+        self._chk(_lib.lb2d_batch_trials(self._h, 0, None, None, None, None, None, ctypes.byref(cnt)))
+        n = cnt.value
+        if n == 0:
+            return []
+        ints = [(_I * n)() for _ in range(4)]
+        ms = (_D * n)()
+        self._chk(_lib.lb2d_batch_trials(self._h, n, *ints, ms, ctypes.byref(cnt)))
+        return [dict(tile_w=ints[0][k], tile_h=ints[1][k], schedule=ints[2][k], blocks_per_cu=ints[3][k],
+                     ms=ms[k]) for k in range(n)]
 
 
 def copy_bench(nbytes: int, reps: int = 20, stream=None):

@@ -90,3 +90,37 @@ def test_toy_batch_matches_oracle_and_single_lattices(storage):
         o.iteration(75)
         eu, er = _errors(m, o)
         assert eu <= tol_u and er <= tol_r, (eu, er)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_every_tuned_shape_equals_single_lattices(storage, tmp_path):
+    """Every tile shape, schedule and grid the autotuner tries gives the
+    lattices' own results bit for bit: each configuration is forced through
+    the tune cache and run for 75 steps against the lattices stepped alone."""
+    import json
+    cases = [porous_case(nx, ny, 30 + k, tau=0.6 + 0.15 * k) for k, (nx, ny) in
+             enumerate([(70, 41), (131, 77), (33, 200), (256, 9)])]
+    singles = [build_gpu(c, storage) for c in cases]
+    for s in singles:
+        s.iteration(75)
+    want = [s.get_populations(0) for s in singles]
+    cache = str(tmp_path / "tune.json")
+    first = _batch([build_gpu(c, storage) for c in cases], tune_cache=cache)
+    trials = first.trials()
+    shapes = sorted({(t["tile_w"], t["tile_h"]) for t in trials})
+    print(storage, "shapes", shapes, "chosen", first.config())
+    assert len(shapes) == 3 and len(trials) == 27
+    key = json.load(open(cache))["key"]
+    for t in trials:
+        with open(cache, "w") as fh:
+            json.dump(dict(key=key, tile_w=t["tile_w"], tile_h=t["tile_h"], schedule=t["schedule"],
+                           blocks_per_cu=t["blocks_per_cu"]), fh)
+        members = [build_gpu(c, storage) for c in cases]
+        b = _batch(members, tune_cache=cache)
+        cfg = b.config()
+        assert (cfg["tile_w"], cfg["tile_h"], cfg["schedule"], cfg["blocks_per_cu"]) == \
+            (t["tile_w"], t["tile_h"], t["schedule"], t["blocks_per_cu"]) and b.trials() == []
+        b.iteration(75)
+        for w, m in zip(want, members):
+            assert np.array_equal(w, m.get_populations(0)), cfg
+        b.close()
