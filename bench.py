@@ -36,13 +36,13 @@ def log(msg):
 
 def source_hash():
     """Hash of the code the one-fluid step kernel is built from: the shared
-    parameter header and the kernel file up to the general step."""
+    parameter header and the device code up to the general step."""
     csrc = os.path.join(ROOT, "paper_1202_0442_amd", "csrc")
     h = hashlib.sha256()
     with open(os.path.join(csrc, "lb2d_common.hpp"), "rb") as fh:
         hdr = fh.read()
     h.update(hdr[hdr.index(b"struct PlainLattice"):hdr.index(b"struct FullParams")])
-    with open(os.path.join(csrc, "lb2d_kernels.hip"), "rb") as fh:
+    with open(os.path.join(csrc, "lb2d_device.hpp"), "rb") as fh:
         src = fh.read()
     h.update(src[:src.index(b"// --------------------------------------------------------- general step")])
     return h.hexdigest()[:16]

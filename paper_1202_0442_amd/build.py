@@ -9,7 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblb2d_hip.so")
-SOURCES = ["lb2d_kernels.hip", "lb2d_api.cpp"]
+# the general step's instantiations are split over one unit per storage
+# format and feature set, so the units compile in parallel
+SOURCES = ["lb2d_kernels.hip", "lb2d_api.cpp"] + [
+    f"lb2d_full_{st}{ext}.hip" for st in ("f64", "f32", "f16", "bf16") for ext in ("", "_ext")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -19,19 +22,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def _compile(src: str, build_dir: str, verbose: bool) -> str:
+    obj = os.path.join(build_dir, src + ".o")
+    lang = [] if src.endswith(".hip") else ["-x", "hip"]
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang,
+           "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src + ".o")
-        lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang,
-               "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, build_dir, verbose), SOURCES))
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -324,15 +324,16 @@ FullParams full_params(const lb2d_ctx *c) {
     p.nopen = (int)c->opens.size();
     for (int k = 0; k < p.nopen; ++k) p.open[k] = c->opens[k];
     // per-link rate k_i = kr w_i / W (W = 1/6 for D2Q9, 1/4 for D2Q4: the
-    // links of a flat wall add up to kr) and the denominator of the link
-    // concentration; D2Q4 has no diagonal links
+    // links of a flat wall add up to kr); a link's deposit is
+    // 2 k_i / (2 w_i + k_i) (g_out - w_i Cs).  D2Q4 has no diagonal links.
     p.sq = c->q;
     const double wa = c->q == 4 ? 0.25 : 1.0 / 9.0, wd = 1.0 / 36.0;
     const double iW = c->q == 4 ? 4.0 : 6.0;
-    k8.klink[0] = c->kr * wa * iW;
-    k8.klink[1] = c->kr * wd * iW;
-    k8.klink_inv[0] = 1.0 / (2.0 * wa + k8.klink[0]);
-    k8.klink_inv[1] = 1.0 / (2.0 * wd + k8.klink[1]);
+    const double ka = c->kr * wa * iW, kd = c->kr * wd * iW;
+    k8.rlink[0] = 2.0 * ka / (2.0 * wa + ka);
+    k8.rlink[1] = 2.0 * kd / (2.0 * wd + kd);
+    k8.rlink_cs[0] = k8.rlink[0] * wa * c->Cs;
+    k8.rlink_cs[1] = k8.rlink[1] * wd * c->Cs;
     // FP32 copy (each value rounded once)
     StepCoef<float> &k4 = p.cf;
     for (int k = 0; k < 2; ++k) {
@@ -346,8 +347,8 @@ FullParams full_params(const lb2d_ctx *c) {
             k4.accel[k][d] = (float)k8.accel[k][d];
         }
         k4.Gads[k] = (float)k8.Gads[k];
-        k4.klink[k] = (float)k8.klink[k];
-        k4.klink_inv[k] = (float)k8.klink_inv[k];
+        k4.rlink[k] = (float)k8.rlink[k];
+        k4.rlink_cs[k] = (float)k8.rlink_cs[k];
     }
     k4.G = (float)k8.G;
     k4.Dsol = (float)k8.Dsol;

@@ -64,8 +64,8 @@ struct StepCoef {
     R omega_s;             // 1 / tau_s
     R Dsol;                // solute diffusivity c_s^2 (tau_s - 1/2)
     R Cs;                  // saturation concentration
-    R klink[2];            // per-link reaction rate k_i: axial, diagonal links
-    R klink_inv[2];        // 1 / (2 w_i + k_i): axial, diagonal links
+    R rlink[2];            // reactive links: 2 k_i / (2 w_i + k_i), axial and diagonal
+    R rlink_cs[2];         // the same times w_i Cs
 };
 
 // One momentum opening (inlet/outlet + inlet_momentum/outlet_momentum

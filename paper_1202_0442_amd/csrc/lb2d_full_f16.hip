@@ -1,0 +1,8 @@
+// General fused step, f16 storage, lattices without the extended features.
+#include "lb2d_full.hpp"
+
+namespace lb2d {
+hipError_t launch_full_f16(const FullParams &p, int parity, bool sc, bool react, hipStream_t s) {
+    return full_dispatch<_Float16, false>(p, parity, sc, react, s);
+}
+}  // namespace lb2d

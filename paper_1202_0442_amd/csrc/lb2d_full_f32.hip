@@ -1,0 +1,8 @@
+// General fused step, f32 storage, lattices without the extended features.
+#include "lb2d_full.hpp"
+
+namespace lb2d {
+hipError_t launch_full_f32(const FullParams &p, int parity, bool sc, bool react, hipStream_t s) {
+    return full_dispatch<float, false>(p, parity, sc, react, s);
+}
+}  // namespace lb2d

@@ -37,6 +37,17 @@ hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, unsigned 
 constexpr size_t kLastLevelCache = 256ull << 20;
 // General step; the solute lattice (none, D2Q9, D2Q4) is p.sq.
 hipError_t launch_full(int st, const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+// The general step per storage format, for lattices without (plain name)
+// and with (_ext) momentum openings, slip solids or intersolute; one
+// translation unit each (lb2d_full_*.hip).
+hipError_t launch_full_f64(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_f64_ext(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_f32(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_f32_ext(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_f16(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_f16_ext(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_bf16(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
+hipError_t launch_full_bf16_ext(const FullParams &p, int parity, bool sc, bool react, hipStream_t s);
 hipError_t launch_growth(int st, const FullParams &p, int parity_new, bool react, hipStream_t s);
 // Normal velocity (inward) of velocity opening o at coordinate k along its
 // wall (poiseuille profile or uniform; negative for outlets).
