@@ -308,6 +308,16 @@ int lb2d_solute_state(lb2d_ctx *ctx, double *C, double *b);
 int lb2d_mask(lb2d_ctx *ctx, uint8_t *m);
 /* thermo command: FP64 budgets, out[LB2D_NBUDGET] (see LB2D_B_*). */
 int lb2d_budgets(lb2d_ctx *ctx, double *out);
+/* lb2d_budgets for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same kernels and results, bit for bit, but the reduction's scratch (per-row
+ * partials, sums, tally totals) lives in a 4 MiB device array of the library
+ * instead of the bound workspace; the call allocates nothing.  Lattices of
+ * more than 65533 rows return LB2D_E_SIZE.  Every call on one GPU shares that
+ * GPU's array (each value read is written in the same call, so nothing
+ * carries over), so calls that overlap on one GPU, from several threads or
+ * streams, race. */
+int lb2d_budgets_noalloc(lb2d_ctx *ctx, double *out);
 
 /* Raw state, decoded to FP64 f_i (comp 0/1) or g_i (comp -1): 9*nx*ny
  * doubles [9][ny][nx] of the post-collision state (for checkpoints and

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -504,6 +505,35 @@ std::string batch_key(const lb2d_batch *b) {
     return buf;
 }
 
+}  // namespace
+
+// Scratch of lb2d_budgets_noalloc (for callers that cannot allocate device
+// memory): the per-row partials, the eight sums and the tally totals of one
+// budget reduction, in a file-scope device array of 4 MiB that every GPU the
+// library runs on holds until the process ends (lattices of up to 65533
+// rows).  Host code uses the array only through the device address that
+// hipGetSymbolAddress returns, once per device, with that device current.
+namespace {
+constexpr size_t kBudgetScratchDoubles = (size_t)1 << 19;
+static __device__ __align__(256) double scratch[kBudgetScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the context's (current) device.
+int budget_scratch(lb2d_ctx *c, double **out) {
+    if (c->device >= kMaxDevices) return c->fail(LB2D_E_INVAL, "device %d beyond %d", c->device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[c->device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return c->fail(LB2D_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch[c->device] = (double *)ptr;
+    }
+    *out = g_scratch[c->device];
+    return LB2D_OK;
+}
 }  // namespace
 
 // ======================================================================
@@ -1189,19 +1219,21 @@ int lb2d_mask(lb2d_ctx *c, uint8_t *m) {
     return LB2D_OK;
 }
 
-int lb2d_budgets(lb2d_ctx *c, double *out) {
-    if (!c || !out) return LB2D_E_INVAL;
-    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
-    HIPCHK(c, hipSetDevice(c->device));
-    const FullParams p = full_params(c);
-    double *part = c->staging;
-    double *out8 = c->staging + (size_t)c->ny * 8;
+// Budgets of a bound lattice with the reduction's scratch (per-row
+// partials, the eight sums, the fixed-order tally totals) at part / out8 /
+// totals: the workspace's staging area for lb2d_budgets, the library's
+// static array for lb2d_budgets_noalloc.
+static int budgets_with(lb2d_ctx *c, double *out, double *part, double *out8, double *totals) {
+    FullParams p = full_params(c);
+    p.totals = totals;
     HIPCHK(c, launch_budgets(c->storage, p, (int)(c->t & 1), c->q ? 1 : 0, c->reaction ? 1 : 0, part, out8,
                              c->stream));
     if (c->q) HIPCHK(c, launch_tally_final(p, c->stream));
     double v8[8], tot[16];
+    for (int k = 0; k < 16; ++k) tot[k] = 0.0;
     HIPCHK(c, hipMemcpyAsync(v8, out8, sizeof(v8), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(tot, c->totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+    // without a solute nothing is tallied: the totals stay zero
+    if (c->q) HIPCHK(c, hipMemcpyAsync(tot, totals, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int k = 0; k < LB2D_NBUDGET; ++k) out[k] = 0.0;
     out[LB2D_B_MASS0] = v8[0];
@@ -1220,6 +1252,27 @@ int lb2d_budgets(lb2d_ctx *c, double *out) {
     out[LB2D_B_CONSUMED] = tot[14];
     out[LB2D_B_STEPS] = (double)c->t;
     return LB2D_OK;
+}
+
+int lb2d_budgets(lb2d_ctx *c, double *out) {
+    if (!c || !out) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    HIPCHK(c, hipSetDevice(c->device));
+    return budgets_with(c, out, c->staging, c->staging + (size_t)c->ny * 8, c->totals);
+}
+
+int lb2d_budgets_noalloc(lb2d_ctx *c, double *out) {
+    if (!c || !out) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    const size_t need = (size_t)c->ny * 8 + 8 + 16;
+    if (need > kBudgetScratchDoubles)
+        return c->fail(LB2D_E_SIZE, "lb2d_budgets_noalloc: %d rows exceed its limit of %d rows", c->ny,
+                       (int)((kBudgetScratchDoubles - 24) / 8));
+    HIPCHK(c, hipSetDevice(c->device));
+    double *scr = nullptr;
+    const int rc = budget_scratch(c, &scr);
+    if (rc) return rc;
+    return budgets_with(c, out, scr, scr + (size_t)c->ny * 8, scr + (size_t)c->ny * 8 + 8);
 }
 
 static int pop_target(lb2d_ctx *c, int comp, void **buf, double *ref) {

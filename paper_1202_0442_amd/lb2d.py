@@ -74,6 +74,7 @@ _SIGS = {
     "lb2d_solute_state": [_P, _DP, _DP],
     "lb2d_mask": [_P, _U8P],
     "lb2d_budgets": [_P, _DP],
+    "lb2d_budgets_noalloc": [_P, _DP],
     "lb2d_get_populations": [_P, _I, _DP],
     "lb2d_set_populations": [_P, _I, _DP],
     "lb2d_get_deposit": [_P, _DP],
@@ -289,6 +290,13 @@ class Lattice:
     def budgets(self):
         out = np.zeros(NBUDGET)
         self._chk(_lib.lb2d_budgets(self._h, _dp(out)))
+        return dict(zip(BUDGET_NAMES, out.tolist()))
+
+    def budgets_noalloc(self):
+        """lb2d_budgets_noalloc: the budgets with the library's static
+        scratch instead of the workspace's."""
+        out = np.zeros(NBUDGET)
+        self._chk(_lib.lb2d_budgets_noalloc(self._h, _dp(out)))
         return dict(zip(BUDGET_NAMES, out.tolist()))
 
     def get_populations(self, comp=0):
