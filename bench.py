@@ -368,14 +368,16 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
     # one lattice at a time with the one-fluid kernel: each lattice runs its
     # k steps (graph-launched: k is a multiple of the 32-step graph, built in
     # the warm-up) before the next one starts
-    assert seq_steps % 32 == 0
-    for L in lats:
-        L.iteration(GRAPH_WARMUP)
-
-    def seq(k):
+    ms_seq = None
+    if seq_steps:
+        assert seq_steps % 32 == 0
         for L in lats:
-            L.iteration(k)
-    ms_seq = time_steps(torch, stream, seq, seq_steps)
+            L.iteration(GRAPH_WARMUP)
+
+        def seq(k):
+            for L in lats:
+                L.iteration(k)
+        ms_seq = time_steps(torch, stream, seq, seq_steps)
     nfl = sum(L.budgets()["fluid_nodes"] for L in lats)
     B = lb2d.Batch(0)
     for L in lats:
@@ -395,7 +397,7 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
     out = {"workload": f"{count} porous lattices, sides log-uniform 256..1536, {ntot} nodes, {storage}"
                        + ("" if rounding == "nearest" else f", {rounding} rounding"),
            "batched_mlups": ntot * steps / (ms_b * 1e-3) / 1e6,
-           "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6,
+           "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6 if seq_steps else None,
            "tuned": B.config(), "autotuner_trials": len(trials),
            "best_ms_per_tile_shape": {k: round(v, 4) for k, v in spread.items()},
            "roofline": {"bound": "hbm", "achieved": round(byt / (per * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBPS,
@@ -404,7 +406,7 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
                         "bytes_rule": f"{18 * STORE_BYTES[storage]} B per fluid node of every lattice "
                                       "+ 1 B mask per node"},
            "ms_per_step": per, "steps": steps, "sequential_steps": seq_steps}
-    out["speedup"] = out["batched_mlups"] / out["sequential_mlups"]
+    out["speedup"] = out["batched_mlups"] / out["sequential_mlups"] if seq_steps else None
     B.close()
     for L in lats:
         L.close()
@@ -483,6 +485,8 @@ def main():
     ap.add_argument("--sc-steps", type=int, default=20000,
                     help="steps of the two-component, phase and ensemble variants run with --no-main; "
                          "the two-component variant's configuration runs 20000")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with --no-main: the ensemble without its one-at-a-time baseline")
     ap.add_argument("--no-main", action="store_true",
                     help="profiling aid: run only the selected variants (no headline line)")
     ap.add_argument("--precision", action="store_true",
@@ -513,7 +517,8 @@ def main():
         if "growth" in want:
             res["growth"] = run_growth_sweep(lb2d, torch, stream)
         if "batch" in want:
-            res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 64, stream)
+            res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 0 if args.no_sequential else 64,
+                                           stream, storage=args.storage)
         if "channel" in want:
             res["channel"] = run_channel(lb2d, torch, stream)
         if "droplet" in want:
