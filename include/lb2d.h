@@ -290,8 +290,14 @@ int lb2d_bind(lb2d_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
 /* iteration command: advances nsteps >= 0 time steps (stream with
  * bounce-back, moments, forces, collision; then solute stream, reactive and
  * opening rules, collision, deposit, growth).  Asynchronous on the stream;
- * launches captured HIP graphs. */
+ * launches captured HIP graphs: a single step when the step count is odd,
+ * graphs of 32 steps, then one graph of the remaining steps.  A graph is
+ * captured the first time its length is needed and kept. */
 int lb2d_iteration(lb2d_ctx *ctx, int64_t nsteps);
+/* Captures, without running any step, the graphs that
+ * lb2d_iteration(ctx, nsteps) will launch from the current step count, so
+ * that the call itself launches without capture cost (for timed regions). */
+int lb2d_prepare(lb2d_ctx *ctx, int64_t nsteps);
 
 /* ------------------------------------------------------------ output */
 
@@ -336,6 +342,22 @@ int lb2d_set_deposit(lb2d_ctx *ctx, const double *b);
 int lb2d_set_mask(lb2d_ctx *ctx, const uint8_t *m);
 /* Steps completed since bind. */
 int lb2d_step_count(lb2d_ctx *ctx, int64_t *t);
+
+/* Checkpoint and restart (the binary counterpart of the paper's
+ * write_restart / read_data commands).  lb2d_checkpoint_bytes gives the
+ * size; lb2d_checkpoint_save copies the lattice's whole device state
+ * (populations, mask, link words, deposits, growth triggers, running
+ * tallies, step counters) and its step count into the caller's host buffer
+ * (waits for the bound stream); lb2d_checkpoint_load restores such a buffer
+ * into a lattice bound after the same commands with the same storage and
+ * rounding (LB2D_E_INVAL if the saved lattice's sizes, components, solute,
+ * storage, rounding, population shift or workspace layout differ; the
+ * other parameters are the caller's to match; LB2D_E_SIZE if the data is
+ * truncated).  Continuing after a load gives the run that was saved, bit
+ * for bit. */
+int lb2d_checkpoint_bytes(lb2d_ctx *ctx, size_t *bytes);
+int lb2d_checkpoint_save(lb2d_ctx *ctx, void *host, size_t bytes);
+int lb2d_checkpoint_load(lb2d_ctx *ctx, const void *host, size_t bytes);
 
 /* ------------------------------------------------------- batched lattices */
 

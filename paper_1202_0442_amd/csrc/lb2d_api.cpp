@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -94,7 +95,8 @@ struct lb2d_ctx {
     size_t staging_doubles = 0;
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;            // kGraphSteps steps
+    std::map<int, hipGraphExec_t> tail_graphs;  // fewer steps, by count
     // population plane geometry: brick layout, padded to whole bricks
     unsigned pnx = 0;
     size_t pplane = 0;
@@ -416,20 +418,42 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
     return e;
 }
 
-int build_graph(lb2d_ctx *c) {
-    if (c->graph) return LB2D_OK;
+// The launch graph of `len` steps starting at an even step (len <=
+// kGraphSteps; captured once per length and kept until lb2d_destroy).
+int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
+    hipGraphExec_t &g = len == kGraphSteps ? c->graph : c->tail_graphs[len];
+    if (g) {
+        *out = g;
+        return LB2D_OK;
+    }
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t gr = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
-        e = enqueue_step(c, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, c->cap_stream);
+    for (int k = 0; k < len && e == hipSuccess; ++k)
+        e = enqueue_step(c, k & 1, k, k == len - 1 ? len : 0, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
     if (e != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));
-    HIPCHK(c, hipGraphInstantiate(&c->graph, gr, nullptr, nullptr, 0));
+    HIPCHK(c, hipGraphInstantiate(&g, gr, nullptr, nullptr, 0));
     HIPCHK(c, hipGraphDestroy(gr));
+    *out = g;
     return LB2D_OK;
+}
+
+// How lb2d_iteration splits nsteps from step t: a single step if t is odd
+// (graphs start at even steps), whole graphs of kGraphSteps, then one graph
+// of the remaining steps (a single launch for one step).
+struct StepPlan {
+    int64_t first, graphs, tail;
+};
+StepPlan step_plan(int64_t t, int64_t nsteps) {
+    StepPlan q{};
+    q.first = ((t & 1) && nsteps > 0) ? 1 : 0;
+    const int64_t left = nsteps - q.first;
+    q.graphs = left / kGraphSteps;
+    q.tail = left % kGraphSteps;
+    return q;
 }
 
 int upload(lb2d_ctx *c, double *dst, const std::vector<double> &src, double fill) {
@@ -558,9 +582,11 @@ int lb2d_destroy(lb2d_ctx *c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
     }
-    if (c->graph || c->cap_stream || c->ev0) {
+    if (c->graph || c->cap_stream || c->ev0 || !c->tail_graphs.empty()) {
         (void)hipSetDevice(c->device);
         if (c->graph) (void)hipGraphExecDestroy(c->graph);
+        for (auto &kv : c->tail_graphs)
+            if (kv.second) (void)hipGraphExecDestroy(kv.second);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->ev0) (void)hipEventDestroy(c->ev0);
         if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1158,25 +1184,43 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
         }
         return LB2D_OK;
     }
-    if ((c->t & 1) && left > 0) {
+    const StepPlan q = step_plan(c->t, left);
+    if (q.first) {
         HIPCHK(c, enqueue_step(c, 1, 0, 1, c->stream));
         c->t += 1;
-        --left;
     }
-    if (left >= kGraphSteps) {
-        int rc = build_graph(c);
+    hipGraphExec_t g = nullptr;
+    if (q.graphs) {
+        int rc = build_graph(c, kGraphSteps, &g);
         if (rc) return rc;
-        while (left >= kGraphSteps) {
-            HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+        for (int64_t k = 0; k < q.graphs; ++k) {
+            HIPCHK(c, hipGraphLaunch(g, c->stream));
             c->t += kGraphSteps;
-            left -= kGraphSteps;
         }
     }
-    for (; left > 0; --left) {
+    if (q.tail == 1) {
         HIPCHK(c, enqueue_step(c, (int)(c->t & 1), 0, 1, c->stream));
         c->t += 1;
+    } else if (q.tail > 1) {
+        int rc = build_graph(c, (int)q.tail, &g);
+        if (rc) return rc;
+        HIPCHK(c, hipGraphLaunch(g, c->stream));
+        c->t += q.tail;
     }
     return LB2D_OK;
+}
+
+int lb2d_prepare(lb2d_ctx *c, int64_t nsteps) {
+    if (!c) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "bind the lattice before preparing its steps");
+    if (nsteps < 0) return c->fail(LB2D_E_INVAL, "nsteps must be >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    const StepPlan q = step_plan(c->t, nsteps);
+    hipGraphExec_t g = nullptr;
+    int rc = LB2D_OK;
+    if (q.graphs) rc = build_graph(c, kGraphSteps, &g);
+    if (!rc && q.tail > 1) rc = build_graph(c, (int)q.tail, &g);
+    return rc;
 }
 
 int lb2d_moments(lb2d_ctx *c, int comp, double *rho, double *ux, double *uy) {
@@ -1377,6 +1421,88 @@ int lb2d_set_mask(lb2d_ctx *c, const uint8_t *m) {
 int lb2d_step_count(lb2d_ctx *c, int64_t *t) {
     if (!c || !t) return LB2D_E_INVAL;
     *t = c->t;
+    return LB2D_OK;
+}
+
+// Checkpoints: a header that identifies the lattice (sizes, components,
+// solute, storage, rounding, the population shift, the workspace layout)
+// and its step count, followed by the whole bound workspace, byte for byte.
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, nx, ny, ncomp, q, storage, sr, pad;
+    int64_t t;
+    uint64_t ws_bytes, layout;
+    double rho_ref[2];
+};
+
+uint64_t layout_fingerprint(const lb2d_ctx *c) {
+    const Layout L = make_layout(c, c->storage);
+    const unsigned char *p = (const unsigned char *)&L;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t k = 0; k < sizeof(L); ++k) h = (h ^ p[k]) * 1099511628211ull;
+    return h;
+}
+
+CkptHeader ckpt_header(const lb2d_ctx *c) {
+    CkptHeader h{};
+    std::memcpy(h.magic, "LB2DCKPT", 8);
+    h.version = 1;
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.ncomp = c->ncomp;
+    h.q = c->q;
+    h.storage = c->storage;
+    h.sr = c->sr ? 1 : 0;
+    h.t = c->t;
+    h.ws_bytes = make_layout(c, c->storage).total;
+    h.layout = layout_fingerprint(c);
+    h.rho_ref[0] = c->rho_ref[0];
+    h.rho_ref[1] = c->rho_ref[1];
+    return h;
+}
+}  // namespace
+
+int lb2d_checkpoint_bytes(lb2d_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    *bytes = sizeof(CkptHeader) + make_layout(c, c->storage).total;
+    return LB2D_OK;
+}
+
+int lb2d_checkpoint_save(lb2d_ctx *c, void *host, size_t bytes) {
+    if (!c || !host) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    const CkptHeader h = ckpt_header(c);
+    if (bytes < sizeof(h) + h.ws_bytes)
+        return c->fail(LB2D_E_SIZE, "checkpoint needs %zu bytes", (size_t)(sizeof(h) + h.ws_bytes));
+    HIPCHK(c, hipSetDevice(c->device));
+    std::memcpy(host, &h, sizeof(h));
+    HIPCHK(c, hipMemcpyAsync((char *)host + sizeof(h), c->ws, h.ws_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LB2D_OK;
+}
+
+int lb2d_checkpoint_load(lb2d_ctx *c, const void *host, size_t bytes) {
+    if (!c || !host) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    CkptHeader h;
+    if (bytes < sizeof(h)) return c->fail(LB2D_E_INVAL, "not a checkpoint");
+    std::memcpy(&h, host, sizeof(h));
+    const CkptHeader mine = ckpt_header(c);
+    if (std::memcmp(h.magic, mine.magic, 8) != 0 || h.version != mine.version)
+        return c->fail(LB2D_E_INVAL, "not a checkpoint of this library");
+    if (h.nx != mine.nx || h.ny != mine.ny || h.ncomp != mine.ncomp || h.q != mine.q || h.storage != mine.storage ||
+        h.sr != mine.sr || h.ws_bytes != mine.ws_bytes || h.layout != mine.layout ||
+        std::memcmp(h.rho_ref, mine.rho_ref, sizeof(h.rho_ref)) != 0)
+        return c->fail(LB2D_E_INVAL, "checkpoint of a lattice set up differently");
+    if (bytes < sizeof(h) + h.ws_bytes) return c->fail(LB2D_E_SIZE, "checkpoint truncated");
+    if (h.t < 0) return c->fail(LB2D_E_INVAL, "bad step count");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws, (const char *)host + sizeof(h), h.ws_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->t = h.t;
     return LB2D_OK;
 }
 

@@ -70,6 +70,7 @@ _SIGS = {
     "lb2d_workspace_bytes": [_P, _I, ctypes.POINTER(_SZ)],
     "lb2d_bind": [_P, _P, _SZ, _P],
     "lb2d_iteration": [_P, _I64],
+    "lb2d_prepare": [_P, _I64],
     "lb2d_moments": [_P, _I, _DP, _DP, _DP],
     "lb2d_solute_state": [_P, _DP, _DP],
     "lb2d_mask": [_P, _U8P],
@@ -81,6 +82,9 @@ _SIGS = {
     "lb2d_set_deposit": [_P, _DP],
     "lb2d_set_mask": [_P, _U8P],
     "lb2d_step_count": [_P, ctypes.POINTER(_I64)],
+    "lb2d_checkpoint_bytes": [_P, ctypes.POINTER(_SZ)],
+    "lb2d_checkpoint_save": [_P, _P, _SZ],
+    "lb2d_checkpoint_load": [_P, _P, _SZ],
     "lb2d_set_timing": [_P, _I],
     "lb2d_kernel_time": [_P, _DP, ctypes.POINTER(_I64)],
     "lb2d_batch_create": [ctypes.POINTER(_P), _I],
@@ -268,6 +272,10 @@ class Lattice:
     def iteration(self, nsteps):
         self._chk(_lib.lb2d_iteration(self._h, int(nsteps)))
 
+    def prepare(self, nsteps):
+        """Captures the launch graphs of a later iteration(nsteps)."""
+        self._chk(_lib.lb2d_prepare(self._h, int(nsteps)))
+
     # output
     def moments(self, comp=0):
         n = self.nx * self.ny
@@ -325,6 +333,19 @@ class Lattice:
         t = _I64(0)
         self._chk(_lib.lb2d_step_count(self._h, ctypes.byref(t)))
         return t.value
+
+    def checkpoint(self):
+        """The lattice's device state and step count as bytes."""
+        n = _SZ(0)
+        self._chk(_lib.lb2d_checkpoint_bytes(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._chk(_lib.lb2d_checkpoint_save(self._h, buf, n.value))
+        return buf.raw
+
+    def restore(self, data: bytes):
+        """Loads a checkpoint() of a lattice set up the same way."""
+        buf = ctypes.create_string_buffer(data, len(data))
+        self._chk(_lib.lb2d_checkpoint_load(self._h, buf, len(data)))
 
     def set_timing(self, on=True):
         self._chk(_lib.lb2d_set_timing(self._h, 1 if on else 0))

@@ -188,6 +188,35 @@ def test_graph_launch_equals_single_launches(kind):
     assert np.array_equal(a.mask(), b.mask())
 
 
+@pytest.mark.parametrize("kind,storage", [("plain", "f32"), ("plain", "f16sr"), ("full", "f32"), ("full", "f16sr")])
+def test_graphs_of_every_length_equal_single_launches(kind, storage):
+    """lb2d_iteration launches a single step at an odd step count, graphs of
+    32 steps and one graph of the remaining steps (captured ahead by
+    lb2d_prepare or on first use): calls of 1, 2, 5, 33, 63 and 7 steps
+    (odd and even starts) equal the same steps launched one by one, also
+    with stochastic rounding, whose random stream is keyed on the step."""
+    case = porous_case(150, 90, 17) if kind == "plain" else sc_solute_case(96, 64, 17)
+    st = storage[:3]
+
+    def lattice():
+        g = build_gpu(case, st, bind=False)
+        if storage.endswith("sr"):
+            g.rounding("stochastic", 5)
+        g.bind(st)
+        return g
+    a, b = lattice(), lattice()
+    b.set_timing(True)
+    for n in (1, 2, 5, 33, 63, 7):
+        a.prepare(n)
+        a.iteration(n)
+        b.iteration(n)
+        assert a.step_count() == b.step_count()
+        assert np.array_equal(a.get_populations(0), b.get_populations(0)), n
+    if kind == "full":
+        assert np.array_equal(a.get_populations(-1), b.get_populations(-1))
+        assert np.array_equal(a.mask(), b.mask())
+
+
 def test_minimum_lattice_and_zero_steps():
     case = dict(nx=3, ny=3, tau=0.9, accel=[(5, 1e-4, 0)],
                 fields={0: (np.linspace(0.9, 1.1, 9), None, None)})
