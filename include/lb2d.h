@@ -6,9 +6,9 @@
  * Conventions (every entry point):
  *  - Returns an int status: LB2D_OK (0) or one of the negative LB2D_E_*
  *    codes below; lb2d_last_error() gives a message.  Nothing aborts: where
- *    the paper says that a wrong command order "interrupts the simulation
- *    with an error message", the call returns LB2D_E_ORDER and leaves the
- *    context unchanged.
+ *    the paper stops a simulation with an error message on a wrong command
+ *    order, the call returns LB2D_E_ORDER and leaves the context
+ *    unchanged.
  *  - Sizes are NODE COUNTS nx, ny (x fastest).  The paper's
  *    lattice(d2q9, Nx, Ny, tau) numbers its sites 0..Nx, 0..Ny, i.e. it has
  *    Nx+1 by Ny+1 nodes; callers that follow the paper pass Nx+1, Ny+1.

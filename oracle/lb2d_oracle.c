@@ -1189,8 +1189,8 @@ int orc_step(orc *o, long nsteps) {
 
 /* ---------------------------------------------------------------- readout */
 
-/* Output command: density and velocity "including the contributions from
- * the applied forces", after collision.  From the stored post-collision
+/* Output command: density and velocity after collision, the velocity with
+ * the applied forces taken into account (output command).  From the stored post-collision
  * state the velocity is (j_post - F/2)/rho, which equals the half-force
  * velocity (j + F/2)/rho of the streamed state for one fluid, and for the
  * mixture (comp = -1) equals Eq. (u_solvent).  Solid nodes read rho = -11
