@@ -118,15 +118,84 @@ def _oracle_rate(n, threads, target_seconds):
     return w.nx * w.ny * steps / dt / 1e6, used, sample
 
 
+def _oracle_timed(o, nodes, target_seconds):
+    """MLUPS of an oracle lattice over about target_seconds (after 2 steps)."""
+    o.iteration(2)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < target_seconds:
+        o.iteration(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return nodes * steps / dt / 1e6, steps, dt
+
+
+def _oracle_configs(target_seconds):
+    """The FP64 oracle on one thread on the other configurations (or samples
+    of them): the 128x64 FP64 channel, the two-component + solute + reaction
+    workload on a 256x256 sample of its generator, and one lattice of the
+    ensemble."""
+    import numpy as np
+    from oracle import Oracle
+    from oracle.oracle import set_threads
+    from paper_1202_0442_amd import inputs
+    set_threads(1)
+    out = {}
+    w = inputs.poiseuille()
+    o = Oracle(w.nx, w.ny)
+    o.fluids(1, w.tau)
+    for r in w.rects:
+        o.obstacle_rect(*r)
+    o.aveacceleration(1, w.accel_x)
+    o.set_fields(0, 1.0)
+    v, n, dt = _oracle_timed(o, w.nx * w.ny, target_seconds)
+    out["channel"] = {"value": v, "unit": "MLUPS", "sample": f"channel {w.nx}x{w.ny} (the full configuration), "
+                                                             f"{n} steps, {dt:.1f} s, 1 thread"}
+    w = inputs.sc_solute(n=256)
+    e = w.extra
+    ra, rb = inputs.sc_initial_fields(w)
+    o = Oracle(w.nx, w.ny)
+    o.fluids(2, w.tau, e["tau2"])
+    o.interforce(e["G"])
+    o.adhesiveforce(e["Gads"][0], 0)
+    o.adhesiveforce(e["Gads"][1], 1)
+    for d in w.discs:
+        o.obstacle_circle(*d)
+    o.set_fields(0, ra.ravel())
+    o.set_fields(1, rb.ravel())
+    o.solute(e["tau_s"], 9)
+    o.solute_opening("xlo", "dirichlet", e["C_in"])
+    o.solute_opening("xhi", "adiabatic", 0.0)
+    o.surface_reaction(e["kr"], e["Cs"], e["b0"], e["bmax"], e["rng_seed"])
+    o.set_concentration(np.zeros(w.nx * w.ny))
+    v, n, dt = _oracle_timed(o, w.nx * w.ny, target_seconds)
+    out["sc_solute"] = {"value": v, "unit": "MLUPS",
+                        "sample": f"two-component + D2Q9 solute + reaction, {w.nx}x{w.ny} sample of the 2048x2048 "
+                                  f"generator, {n} steps, {dt:.1f} s, 1 thread"}
+    w = next(x for x in inputs.ensemble() if max(x.nx, x.ny) <= 512)
+    o = Oracle(w.nx, w.ny)
+    o.fluids(1, w.tau)
+    for d in w.discs:
+        o.obstacle_circle(*d)
+    o.aveacceleration(1, w.accel_x)
+    o.set_fields(0, 1.0)
+    v, n, dt = _oracle_timed(o, w.nx * w.ny, target_seconds)
+    out["ensemble_lattice"] = {"value": v, "unit": "MLUPS",
+                               "sample": f"one ensemble lattice, {w.nx}x{w.ny}, {n} steps, {dt:.1f} s, 1 thread"}
+    return out
+
+
 def cpu_baseline(target_seconds=15.0):
-    """The FP64 oracle on one host thread (the reported baseline), and the
-    same oracle with its OpenMP rows over the host threads this process may
-    use, on a larger sample."""
+    """The FP64 oracle on one host thread (the reported baseline), the same
+    oracle with its OpenMP rows over the host threads this process may use
+    on a larger sample, and the oracle on one thread on the other
+    configurations."""
     v1, _, s1 = _oracle_rate(512, 1, target_seconds)
     nthr = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     vn, used, sn = _oracle_rate(1024, nthr, 8.0)
     return {"value": v1, "unit": "MLUPS", "cores": 1, "kind": "oracle", "sample": s1,
-            "all_threads": {"value": vn, "unit": "MLUPS", "cores": used, "sample": sn}}
+            "all_threads": {"value": vn, "unit": "MLUPS", "cores": used, "sample": sn},
+            "per_configuration": _oracle_configs(4.0)}
 
 
 def steady_k(L, accel, tau, chunk=1000, rel=1e-6, max_steps=100000):
@@ -478,7 +547,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--n", type=int, default=4096, help="porous lattice side")
+    ap.add_argument("--n", type=int, default=4096, help="lattice side")
+    ap.add_argument("--workload", default="porous", choices=("porous", "channel"),
+                    help="porous: discs r 8..24 to porosity 0.6; channel: walls at rows 0 and n-1, a_x 1e-6, tau 1")
+    ap.add_argument("--seed", type=int, default=2, help="seed of the porous geometry")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--variants", default="all",
                     help="all | none | comma list of f16,bf16,sc,phase,growth,batch,channel,droplet")
@@ -533,8 +605,15 @@ def main():
         print(json.dumps(res), flush=True)
         lb2d.copy_bench(1 << 30, reps=3, stream=stream)
         return
-    log("generating porous workload")
-    w = inputs.porous(n=args.n, seed=2)
+    log(f"generating {args.workload} workload")
+    if args.workload == "porous":
+        w = inputs.porous(n=args.n, seed=args.seed)
+        wname = f"porous {w.nx}x{w.ny}, non-overlapping discs r 8..24, porosity 0.6, periodic, tau 0.8, accel 1e-5 (e1)"
+        pname = f"porous{args.n}" + ("" if args.seed == 2 else f"_seed{args.seed}")
+    else:
+        w = inputs.poiseuille(nx=args.n, ny=args.n, accel=1e-6, tau=1.0)
+        wname = f"channel {w.nx}x{w.ny}, walls at rows 0 and {w.ny - 1}, periodic x, tau 1, accel 1e-6 (e1)"
+        pname = f"channel{args.n}"
     L = make_porous_lattice(lb2d, w, args.storage, stream)
     n = w.nx * w.ny
     bud = L.budgets()
@@ -552,14 +631,13 @@ def main():
     # stream the kernel runs on)
     bytes_launch = nfl * 18 * STORE_BYTES[args.storage] + n
     achieved = bytes_launch / (per * 1e-3) / 1e9
-    traffic = measured_traffic(f"k_plain_{args.storage}_porous{args.n}.md")
+    traffic = measured_traffic(f"k_plain_{args.storage}_{pname}.md")
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": per,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
-        "config": {"workload": f"porous {w.nx}x{w.ny}, non-overlapping discs r 8..24, porosity 0.6, "
-                               f"periodic, tau 0.8, accel 1e-5 (e1), {args.storage} shifted storage",
+        "config": {"workload": f"{wname}, {args.storage} shifted storage",
                    "nx": w.nx, "ny": w.ny, "discs": len(w.discs), "fluid_fraction": nfl / n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
@@ -583,7 +661,7 @@ def main():
         b1 = L.budgets()
         mass_drift = (b1["mass0"] - bud["mass0"]) / bud["mass0"]
         out["mass_drift"] = mass_drift
-        if not args.no_permeability:
+        if not args.no_permeability and args.workload == "porous":
             log("permeability: continuing to steady state, then at twice the forcing")
             out["permeability"] = permeability(lb2d, w, L, stream)
     L.close()
