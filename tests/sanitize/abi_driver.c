@@ -47,6 +47,7 @@ int main(void) {
     EXPECT(lb2d_obstacle_circle(c, 5, 5, 2.0), LB2D_E_ORDER);
     EXPECT(lb2d_solute_opening(c, "xlo", "dirichlet", 1.0), LB2D_E_ORDER);
     EXPECT(lb2d_iteration(c, 5), LB2D_E_STATE);
+    EXPECT(lb2d_prepare(c, 5), LB2D_E_STATE);
     EXPECT(lb2d_moments(c, 0, field, field, field), LB2D_E_STATE);
     EXPECT(lb2d_budgets(c, out), LB2D_E_STATE);
     EXPECT(lb2d_budgets_noalloc(c, out), LB2D_E_STATE);

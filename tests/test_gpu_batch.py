@@ -124,3 +124,30 @@ def test_every_tuned_shape_equals_single_lattices(storage, tmp_path):
         for w, m in zip(want, members):
             assert np.array_equal(w, m.get_populations(0)), cfg
         b.close()
+
+
+def test_ensemble_lattices_full_length_fp64():
+    """The same eight lattices for the ensemble's full 5000 steps, batched in
+    FP64 storage, each against its oracle run.  The two sides round in a
+    different order: each step's values may differ by a unit of 2^-53 of the
+    populations (at most 4/9 of the largest density), and such differences
+    add up at most linearly over the steps; a velocity sums six populations,
+    so its error stays below steps * 6 * 2^-53 * (4/9) max rho, taken
+    relative to the lattice's largest velocity.  (FP32 storage accumulates
+    rounding over such runs to about the 1e-5 bar; the shorter FP32 test
+    above holds that bar.)"""
+    cases = ensemble_cases()
+    members = [build_gpu(c, "f64") for c in cases]
+    batch = _batch(members)
+    steps = 5000
+    batch.iteration(steps)
+    for c, m in zip(cases, members):
+        o = build_oracle(c)
+        o.iteration(steps)
+        eu, er = _errors(m, o)
+        orr, ox, oy = o.moments(0)
+        fluid = orr != -11.0
+        umax = max(np.abs(ox).max(), np.abs(oy).max())
+        bound = steps * 6 * 2.0 ** -53 * (4 / 9) * orr[fluid].max() / umax
+        print(f"{c['nx']}x{c['ny']}: rel u err {eu:.2e} (bound {bound:.1e}), rel rho err {er:.2e}")
+        assert eu <= bound and er <= 1e-12, (c["nx"], c["ny"], eu, er)
