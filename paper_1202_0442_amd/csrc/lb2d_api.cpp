@@ -418,6 +418,30 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
     return e;
 }
 
+// The launches of `len` steps from an even step.  The one-fluid step on a
+// lattice of at least one tile of the two-step kernel runs as pairs of
+// two-step launches (four steps, ending in the buffer they started from),
+// then single steps; the device step counter (read only by stochastic
+// rounding) advances once, after the last of them.
+hipError_t enqueue_group(lb2d_ctx *c, int len, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!c->plain()) {
+        for (int k = 0; k < len && e == hipSuccess; ++k) e = enqueue_step(c, k & 1, k, 0, s);
+        return e;
+    }
+    const PlainLattice L = plain_lattice(c);
+    const bool nt = stream_stores(c);
+    int k = 0;
+    if (plain2_fits(c->storage, c->nx, c->ny))
+        for (; k + 4 <= len && e == hipSuccess; k += 4) {
+            e = launch_plain2(c->storage, L, 0, c->sr, nt, k, s);
+            if (e == hipSuccess) e = launch_plain2(c->storage, L, 1, c->sr, nt, k + 2, s);
+        }
+    for (; k < len && e == hipSuccess; ++k) e = launch_plain(c->storage, L, k & 1, c->sr, nt, k, s);
+    if (e == hipSuccess && c->sr && len > 0) e = launch_tick((unsigned long long *)c->dstep, len, s);
+    return e;
+}
+
 // The launch graph of `len` steps starting at an even step (len <=
 // kGraphSteps; captured once per length and kept until lb2d_destroy).
 int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
@@ -429,9 +453,7 @@ int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t gr = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < len && e == hipSuccess; ++k)
-        e = enqueue_step(c, k & 1, k, k == len - 1 ? len : 0, c->cap_stream);
+    const hipError_t e = enqueue_group(c, len, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
     if (e != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));

@@ -330,12 +330,106 @@ __device__ __forceinline__ PlainArgs<S> uniform_args(PlainArgs<S> a) {
     return a;
 }
 
+// Multiply-add with one rounding, in the arithmetic type.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Pull of one fluid node (x, y) with link word lk: d_i from x - e_i in the
+// input buffer, or the node's own opposite population where x - e_i is
+// solid (noslip bounce-back).
+template <typename S, typename O>
+__device__ __forceinline__ void plain_pull(const PlainArgs<S> &L, unsigned xx, unsigned yy, unsigned lk,
+                                           typename Codec<S>::R (&d)[9]) {
+    using C = Codec<S>;
+    const unsigned nx = L.nx, ny = L.ny, pnx = L.pnx;
+    const O pl = (O)L.plane * (O)sizeof(S);  // bytes per plane
+    const LB2D_GLOBAL char *__restrict__ fin = (const LB2D_GLOBAL char *)gbl(L.fin);
+    const O s = brick_off<S, O>(xx, yy, pnx);
+    const unsigned xm = (xx == 0) ? nx - 1 : xx - 1;
+    const unsigned xp = (xx == nx - 1) ? 0 : xx + 1;
+    const unsigned ym = (yy == 0) ? ny - 1 : yy - 1;
+    const unsigned yp = (yy == ny - 1) ? 0 : yy + 1;
+    // node - e_i for each direction
+    const O src[9] = {s,
+                      brick_off<S, O>(xm, yy, pnx), brick_off<S, O>(xx, ym, pnx),
+                      brick_off<S, O>(xp, yy, pnx), brick_off<S, O>(xx, yp, pnx),
+                      brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
+                      brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
+    d[0] = C::dec(*(const LB2D_GLOBAL S *)(fin + s), 0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        // node - e_i is node + e_opp(i): solid -> bounce-back
+        const bool wall = (lk >> opp(i)) & 1u;
+        const O a = wall ? (O)opp(i) * pl + s : (O)i * pl + src[i];
+        d[i] = C::dec(*(const LB2D_GLOBAL S *)(fin + a), i);
+    }
+}
+
+// Collision of one node from its pulled deviations: moments, velocity-shift
+// forcing, Eq. (eq), BGK relaxation; d receives the post-collision
+// deviations (zero at solid nodes).  Every multiply-add is written out and
+// implicit contraction is off, so the rounding is the same in every kernel
+// this is inlined into (the one-step, batched and two-step kernels give the
+// same bits).  The order of operations and the fused products are those the
+// compiler chose for the FP32 and FP64 one-step kernels with contraction
+// on: the diagonal projections e.u fuse the product of 1/rho with the x
+// momentum, and the u.u term enters the bracket as one multiply-add.
+template <typename S, typename R>
+__device__ __forceinline__ void plain_relax(const PlainArgs<S> &L, R (&d)[9], bool fluid) {
+#pragma clang fp contract(off)
+    R drho = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) drho = drho + d[i];
+    const R jx = ((((R(0) + d[1]) - d[3]) + d[5]) - d[6] - d[7]) + d[8];
+    const R jy = ((((R(0) + d[2]) - d[4]) + d[5]) + d[6] - d[7]) - d[8];
+    const R rho = drho + R(L.rho_ref);
+    const R tau = R(L.tau), omega = R(L.omega);
+    const R Fx = fmar(rho, R(L.ax), R(L.Fx));
+    const R Fy = fmar(rho, R(L.ay), R(L.Fy));
+    const R mx = fmar(Fx, tau, jx);  // j + tau F
+    const R my = fmar(Fy, tau, jy);
+    const R inv = rcp(rho);
+    const R ux = inv * mx, uy = inv * my;
+    const R u2 = fmar(ux, ux, uy * uy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        R eu;
+        if (i == 0) eu = R(0);
+        else if (i == 1) eu = ux;
+        else if (i == 2) eu = uy;
+        else if (i == 3) eu = -ux;
+        else if (i == 4) eu = -uy;
+        else eu = fmar(ex(i) > 0 ? inv : -inv, mx, ey(i) > 0 ? uy : -uy);
+        // 3 e.u + 9/2 (e.u)^2 - 3/2 u.u, then f_eq - w_i rho_ref - d_i
+        R t = (R(4.5) * eu) * eu;
+        t = fmar(R(3), eu, t);
+        t = fmar(R(-1.5), u2, t);
+        const R dd = fmar(fmar(rho, t, drho), wgt<R>(i), -d[i]);
+        d[i] = fluid ? fmar(dd, omega, d[i]) : R(0);
+    }
+}
+
+// Random words of node (x, y) for stochastic rounding under step key tkey.
+__device__ __forceinline__ void sr_words(unsigned node, unsigned tkey, unsigned (&w)[5]) {
+    w[0] = lowbias32(node ^ tkey);
+#pragma unroll
+    for (int k = 1; k < 5; ++k) w[k] = xorshift32(w[k - 1]);
+}
+
+// Population i of a node in the storage format (rounded stochastically with
+// the node's words when SR).
+template <typename S, bool SR>
+__device__ __forceinline__ S plain_enc(typename Codec<S>::R v, int i, const unsigned (&w)[5]) {
+    if constexpr (SR) return Codec<S>::enc_sr(v, i, (i & 1) ? (w[i >> 1] << 16) : w[i >> 1]);
+    else return Codec<S>::enc(v, i);
+}
+
 template <typename S, typename O, bool SR, bool NT>
 __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, bool inside, unsigned tkey) {
     using C = Codec<S>;
     using R = typename C::R;
     constexpr unsigned kGroup = brick_w_for(sizeof(S)) * brick_h_for(sizeof(S));  // lanes per brick
-    const unsigned nx = L.nx, ny = L.ny, pnx = L.pnx;
+    const unsigned nx = L.nx, pnx = L.pnx;
     const unsigned s_row = inside ? (unsigned)y * nx + (unsigned)x : 0u;
     const unsigned lk = inside ? (unsigned)gbl(L.links)[s_row] : 1u;
     const bool fluid = (lk & 1u) == 0u;
@@ -346,70 +440,25 @@ __device__ __forceinline__ void plain_node(const PlainArgs<S> &L, int x, int y, 
     const unsigned lane = __lane_id();
     const unsigned long long gmask =
         (kGroup >= 64) ? ~0ull : (((1ull << (kGroup & 63)) - 1ull) << ((lane / kGroup) * kGroup));
-    const bool store = (bal & gmask) != 0ull;
-    const O pl = (O)L.plane * (O)sizeof(S);  // bytes per plane
-    const LB2D_GLOBAL char *__restrict__ fin = (const LB2D_GLOBAL char *)gbl(L.fin);
-    LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(L.fout);
-    const O s = brick_off<S, O>((unsigned)x, (unsigned)y, pnx);
-
+    if ((bal & gmask) == 0ull) return;
     R d[9];
     if (fluid) {
-        const unsigned xx = (unsigned)x, yy = (unsigned)y;
-        const unsigned xm = (xx == 0) ? nx - 1 : xx - 1;
-        const unsigned xp = (xx == nx - 1) ? 0 : xx + 1;
-        const unsigned ym = (yy == 0) ? ny - 1 : yy - 1;
-        const unsigned yp = (yy == ny - 1) ? 0 : yy + 1;
-        // node - e_i for each direction
-        const O src[9] = {s,
-                          brick_off<S, O>(xm, yy, pnx), brick_off<S, O>(xx, ym, pnx),
-                          brick_off<S, O>(xp, yy, pnx), brick_off<S, O>(xx, yp, pnx),
-                          brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
-                          brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
-        d[0] = C::dec(*(const LB2D_GLOBAL S *)(fin + s), 0);
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            // node - e_i is node + e_opp(i): solid -> bounce-back
-            const bool wall = (lk >> opp(i)) & 1u;
-            const O a = wall ? (O)opp(i) * pl + s : (O)i * pl + src[i];
-            d[i] = C::dec(*(const LB2D_GLOBAL S *)(fin + a), i);
-        }
+        plain_pull<S, O>(L, (unsigned)x, (unsigned)y, lk, d);
     } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] = R(0);
     }
-    R drho = 0, jx = 0, jy = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        drho += d[i];
-        if (ex(i)) jx += ex(i) > 0 ? d[i] : -d[i];
-        if (ey(i)) jy += ey(i) > 0 ? d[i] : -d[i];
-    }
-    const R rho = R(L.rho_ref) + drho;
-    const R tau = R(L.tau), omega = R(L.omega);
-    const R Fx = R(L.Fx) + rho * R(L.ax);
-    const R Fy = R(L.Fy) + rho * R(L.ay);
-    const R inv = rcp(rho);
-    const R ux = (jx + tau * Fx) * inv;
-    const R uy = (jy + tau * Fy) * inv;
-    const R usq = R(1.5) * (ux * ux + uy * uy);
+    plain_relax(L, d, fluid);
     unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
-    if constexpr (SR) {
-        w[0] = lowbias32((unsigned)(y * (int)nx + x) ^ tkey);
-#pragma unroll
-        for (int k = 1; k < 5; ++k) w[k] = xorshift32(w[k - 1]);
-    }
+    if constexpr (SR) sr_words((unsigned)(y * (int)nx + x), tkey, w);
+    const O pl = (O)L.plane * (O)sizeof(S);
+    LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(L.fout);
+    const O s = brick_off<S, O>((unsigned)x, (unsigned)y, pnx);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const R eu = R(ex(i)) * ux + R(ey(i)) * uy;
-        const R deq = wgt<R>(i) * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - usq));
-        const R v = fluid ? d[i] + omega * (deq - d[i]) : R(0);
-        if (store) {
-            S e;
-            if constexpr (SR) e = C::enc_sr(v, i, (i & 1) ? (w[i >> 1] << 16) : w[i >> 1]);
-            else e = C::enc(v, i);
-            if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
-            else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
-        }
+        const S e = plain_enc<S, SR>(d[i], i, w);
+        if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
+        else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
     }
 }
 
@@ -447,6 +496,121 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
     unsigned tkey = 0u;
     if constexpr (SR) tkey = lowbias32((unsigned)(*L.step + (unsigned long long)k + 1ull) ^ L.seed);
     plain_node<S, O, SR, NT>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
+}
+
+// Two steps in one pass (temporal blocking).  A block of TW x TH threads
+// owns a tile of whole bricks.  Step one is computed for the tile and for a
+// one-node ring around it, pulled from the input buffer as in the one-step
+// kernel, and kept in LDS in the storage format (rounded exactly as it would
+// be stored); after a barrier, step two pulls the tile's nodes from LDS and
+// writes whole bricks of the output buffer.  So the populations cross HBM
+// once per two steps, and the results are those of two one-step launches
+// bit for bit.  The host launches these in pairs (buffer p -> p^1 -> p), so
+// that after every pair the state lies in the buffer the step count names.
+// Ring nodes wrap periodically with one conditional add or subtract, which
+// needs nx >= TW and ny >= TH.  k: offset of the first of the two steps in
+// its launch group, as in k_plain.
+constexpr int kPlain2TW = 64;  // tile of the two-step kernel (FP64: 32 x 16)
+constexpr int kPlain2TH = 16;
+
+// Step one of node (x, y) into LDS slot `slot` (planes of PL elements);
+// returns the node's link word.
+template <typename S, typename O, bool SR, int PL>
+__device__ __forceinline__ unsigned plain_stage(const PlainArgs<S> &L, unsigned x, unsigned y, int slot, S *sf,
+                                                unsigned tkey) {
+    using R = typename Codec<S>::R;
+    const unsigned lk = (unsigned)gbl(L.links)[y * L.nx + x];
+    const bool fluid = (lk & 1u) == 0u;
+    if (__ballot(fluid) == 0ull || !fluid) return lk;
+    R d[9];
+    plain_pull<S, O>(L, x, y, lk, d);
+    plain_relax(L, d, true);
+    unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
+    if constexpr (SR) sr_words(y * L.nx + x, tkey, w);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sf[i * PL + slot] = plain_enc<S, SR>(d[i], i, w);
+    return lk;
+}
+
+template <typename S, typename O, bool SR, bool NT, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_plain2(PlainLattice L, int parity, int k) {
+    using C = Codec<S>;
+    using R = typename C::R;
+    constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S)), G = W * H;
+    // LDS tile: (TW + 2) x (TH + 2) slots per plane, rows padded to 8 slots
+    constexpr int SW = TW + 2, SH = TH + 2, PITCH = (SW + 7) / 8 * 8, PL = SH * PITCH;
+    constexpr int NR = 2 * SW + 2 * TH;  // ring slots
+    static_assert(TW % W == 0 && TH % H == 0 && NR <= TW * TH, "tile of whole bricks");
+    __shared__ S sf[9 * PL];
+    const PlainArgs<S> a = plain_args<S>(L, parity);
+    const int nx = L.nx, ny = L.ny;
+    const int t = threadIdx.x;
+    int lx, ly;
+    tile_thread<TW, W, H>(t, lx, ly);
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+    unsigned key1 = 0u, key2 = 0u;
+    if constexpr (SR) {
+        const unsigned long long st = *L.step + (unsigned long long)k;
+        key1 = lowbias32((unsigned)(st + 1ull) ^ L.seed);
+        key2 = lowbias32((unsigned)(st + 2ull) ^ L.seed);
+    }
+    // step one: the thread's own node (wrapped when the tile overhangs the
+    // lattice: such slots are the ring of the last real nodes) ...
+    const int gx = x0 + lx, gy = y0 + ly;
+    const unsigned lk = plain_stage<S, O, SR, PL>(a, (unsigned)(gx < nx ? gx : gx - nx),
+                                                  (unsigned)(gy < ny ? gy : gy - ny),
+                                                  (ly + 1) * PITCH + lx + 1, sf, key1);
+    // ... and one ring slot for the first NR threads: the row y0 - 1, the
+    // row y0 + TH, the column x0 - 1, the column x0 + TW
+    if (t < NR) {
+        int sx, sy;
+        if (t < SW) {
+            sx = t;
+            sy = 0;
+        } else if (t < 2 * SW) {
+            sx = t - SW;
+            sy = SH - 1;
+        } else if (t < 2 * SW + TH) {
+            sx = 0;
+            sy = 1 + t - 2 * SW;
+        } else {
+            sx = SW - 1;
+            sy = 1 + t - 2 * SW - TH;
+        }
+        int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
+        rx = rx < 0 ? rx + nx : (rx >= nx ? rx - nx : rx);
+        ry = ry < 0 ? ry + ny : (ry >= ny ? ry - ny : ry);
+        plain_stage<S, O, SR, PL>(a, (unsigned)rx, (unsigned)ry, sy * PITCH + sx, sf, key1);
+    }
+    __syncthreads();
+    // step two: the tile's nodes from LDS
+    const bool inside = gx < nx && gy < ny;
+    const bool fluid = inside && (lk & 1u) == 0u;
+    const unsigned long long bal = __ballot(fluid);
+    if (bal == 0ull || !inside) return;
+    const unsigned lane = __lane_id();
+    const unsigned long long gmask = (G >= 64) ? ~0ull : (((1ull << (G & 63)) - 1ull) << ((lane / G) * G));
+    if ((bal & gmask) == 0ull) return;
+    const int c = (ly + 1) * PITCH + lx + 1;
+    R d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool wall = (lk >> opp(i)) & 1u;
+        const int src = wall ? opp(i) * PL + c : i * PL + c - ey(i) * PITCH - ex(i);
+        d[i] = fluid ? C::dec(sf[src], i) : R(0);
+    }
+    plain_relax(a, d, fluid);
+    unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
+    if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key2, w);
+    const O pl = (O)a.plane * (O)sizeof(S);
+    LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(a.fout);
+    const O s = brick_off<S, O>((unsigned)gx, (unsigned)gy, a.pnx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const S e = plain_enc<S, SR>(d[i], i, w);
+        if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
+        else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+    }
 }
 
 // Batched step: blocks walk a table of tiles (lattice, x0, y0) of many

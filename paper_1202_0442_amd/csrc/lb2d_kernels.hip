@@ -41,6 +41,45 @@ hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool
     return hipGetLastError();
 }
 
+// Tile of the two-step kernel: 64 x 16 nodes (1024 threads), 32 x 16 for
+// 8-byte values (whose LDS tile would otherwise take 85 KB).
+void plain2_tile(int st, int *tw, int *th) {
+    *tw = st == kF64 ? kPlain2TW / 2 : kPlain2TW;
+    *th = kPlain2TH;
+}
+
+bool plain2_fits(int st, int nx, int ny) {
+    int tw, th;
+    plain2_tile(st, &tw, &th);
+    return nx >= tw && ny >= th;
+}
+
+template <typename S, typename O, bool SR, bool NT>
+static void plain2_launch(const PlainLattice &L, int parity, int k, hipStream_t stream) {
+    constexpr int TW = sizeof(S) == 8 ? kPlain2TW / 2 : kPlain2TW, TH = kPlain2TH;
+    const dim3 blk(TW * TH), grd((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
+    hipLaunchKernelGGL((k_plain2<S, O, SR, NT, TW, TH>), grd, blk, 0, stream, L, parity, k);
+}
+
+template <bool NT>
+static void plain2_dispatch(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
+    if (sr && st == kF16)
+        plain2_launch<_Float16, uint32_t, true, NT>(L, parity, k, stream);
+    else if (sr && st == kBF16)
+        plain2_launch<bf16s, uint32_t, true, NT>(L, parity, k, stream);
+    else if (fits32(L.plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, (plain2_launch<S, uint32_t, false, NT>(L, parity, k, stream)));
+    else
+        LB2D_DISPATCH(st, (plain2_launch<S, size_t, false, NT>(L, parity, k, stream)));
+}
+
+hipError_t launch_plain2(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t stream) {
+    if (!plain2_fits(st, L.nx, L.ny)) return hipErrorInvalidValue;
+    if (nt) plain2_dispatch<true>(st, L, parity, sr, k, stream);
+    else plain2_dispatch<false>(st, L, parity, sr, k, stream);
+    return hipGetLastError();
+}
+
 __global__ void k_tick(unsigned long long *step, int n) { *step += (unsigned long long)n; }
 
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s) {

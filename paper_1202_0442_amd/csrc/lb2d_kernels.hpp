@@ -18,6 +18,12 @@ void plain_tile(int st, int *tw, int *th);
 // One-fluid step; sr: stochastic rounding (16-bit storage, 32-bit offsets),
 // nt: streaming stores, k: offset of the step in its launch group.
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
+// Two steps in one launch (buffer parity -> parity^1), for lattices of at
+// least one tile (plain2_fits); the host launches them in pairs.  Arguments
+// as for launch_plain (k: offset of the first of the two steps).
+void plain2_tile(int st, int *tw, int *th);
+bool plain2_fits(int st, int nx, int ny);
+hipError_t launch_plain2(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
 // Adds n to the device step counter.
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
 // Tile shapes (width, height in nodes) of the batched step for a storage
