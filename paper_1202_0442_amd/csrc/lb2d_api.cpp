@@ -26,7 +26,8 @@ using namespace lb2d;
 
 namespace {
 
-constexpr int kGraphSteps = 32;  // steps per captured graph (even)
+constexpr int kGraphSteps = 32;  // steps per captured graph (a multiple of 4: pairs of two-step launches)
+static_assert(kGraphSteps % 4 == 0, "graphs hold whole pairs of two-step launches");
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -154,6 +155,11 @@ struct lb2d_batch {
     size_t max_tiles = 0;
     int ntiles = 0;
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
+    bool two = false;      // the chosen tiles are the two-step kernel's (run in pairs)
+    // one-step tiles of the storage's default shape, lattice by lattice, for
+    // the odd and leftover steps when the two-step kernel was chosen
+    Tile *d_tiles1 = nullptr;
+    int ntiles1 = 0, tile_w1 = 64, tile_h1 = 4;
     size_t max_plane = 0;  // largest population plane of the lattices
     bool nt = false;       // streaming stores: the lattices' populations exceed the last-level cache
     bool sr = false;       // stochastic rounding (every lattice of the batch asked for it)
@@ -387,6 +393,13 @@ PlainLattice plain_lattice(const lb2d_ctx *c) {
     L.ax = c->accel[0][0];
     L.ay = c->accel[0][1];
     L.rho_ref = c->rho_ref[0];
+    L.omega_f = (float)L.omega;
+    L.tau_f = (float)L.tau;
+    L.Fx_f = (float)L.Fx;
+    L.Fy_f = (float)L.Fy;
+    L.ax_f = (float)L.ax;
+    L.ay_f = (float)L.ay;
+    L.rho_ref_f = (float)L.rho_ref;
     L.step = (const unsigned long long *)c->dstep;
     L.seed = c->sr_seed;
     return L;
@@ -1600,18 +1613,42 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
-// Largest tile table over the tile shapes of the storage format.
+// The two-step kernel serves a batch whose every lattice holds one of its tiles.
+static bool batch2_ok(const lb2d_batch *b) {
+    for (auto *c : b->lat)
+        if (!plain2_fits(b->storage, c->nx, c->ny)) return false;
+    return !b->lat.empty();
+}
+
+// Tile shapes the autotuner may choose: the one-step shapes of the storage
+// format, then the two-step kernel's tile when the batch allows it.
+static int candidate_shapes(const lb2d_batch *b, int *tw, int *th) {
+    int n = batch_shapes(b->storage, tw, th, 4);
+    if (batch2_ok(b)) {
+        plain2_tile(b->storage, &tw[n], &th[n]);
+        ++n;
+    }
+    return n;
+}
+
+static bool is_two_step_shape(const lb2d_batch *b, int w, int h) {
+    int tw, th;
+    plain2_tile(b->storage, &tw, &th);
+    return w == tw && h == th && batch2_ok(b);
+}
+
+// Largest tile table over the candidate shapes.
 static size_t max_tiles_for(const lb2d_batch *b) {
-    int tw[4], th[4];
-    const int ns = batch_shapes(b->storage, tw, th, 4);
+    int tw[5], th[5];
+    const int ns = candidate_shapes(b, tw, th);
     size_t m = 0;
     for (int k = 0; k < ns; ++k) m = std::max(m, tiles_for(b, tw[k], th[k]));
     return m;
 }
 
-static bool is_batch_shape(int st, int w, int h) {
-    int tw[4], th[4];
-    const int ns = batch_shapes(st, tw, th, 4);
+static bool is_batch_shape(const lb2d_batch *b, int w, int h) {
+    int tw[5], th[5];
+    const int ns = candidate_shapes(b, tw, th);
     for (int k = 0; k < ns; ++k)
         if (tw[k] == w && th[k] == h) return true;
     return false;
@@ -1621,7 +1658,10 @@ int lb2d_batch_workspace_bytes(lb2d_batch *b, size_t *bytes) {
     if (!b || !bytes) return LB2D_E_INVAL;
     if (b->lat.empty()) return b->fail(LB2D_E_STATE, "empty batch");
     const size_t tiles = max_tiles_for(b);
-    *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile)) + align_up(8);
+    int w1, h1;
+    plain_tile(b->storage, &w1, &h1);
+    *bytes = align_up(b->lat.size() * sizeof(PlainLattice)) + align_up(tiles * sizeof(Tile)) +
+             align_up(tiles_for(b, w1, h1) * sizeof(Tile)) + align_up(8);
     return LB2D_OK;
 }
 
@@ -1650,7 +1690,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     b->d_lat = (PlainLattice *)b->ws;
     b->d_tiles = (Tile *)(b->ws + align_up(b->lat.size() * sizeof(PlainLattice)));
     b->max_tiles = max_tiles_for(b);
-    b->d_step = (unsigned long long *)((char *)b->d_tiles + align_up(b->max_tiles * sizeof(Tile)));
+    plain_tile(b->storage, &b->tile_w1, &b->tile_h1);
+    b->d_tiles1 = (Tile *)((char *)b->d_tiles + align_up(b->max_tiles * sizeof(Tile)));
+    b->d_step = (unsigned long long *)((char *)b->d_tiles1 +
+                                       align_up(tiles_for(b, b->tile_w1, b->tile_h1) * sizeof(Tile)));
     {
         // every lattice of a batch is at the same step, and a lattice that
         // rounds stochastically has its device counter at that step
@@ -1669,6 +1712,12 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     }
     b->nt = pop_bytes > kLastLevelCache;
     HIPCHK(b, hipMemcpyAsync(b->d_lat, L.data(), L.size() * sizeof(PlainLattice), hipMemcpyHostToDevice, b->stream));
+    {
+        const std::vector<Tile> t1 = make_tiles(b, b->tile_w1, b->tile_h1, 0);
+        HIPCHK(b, hipMemcpyAsync(b->d_tiles1, t1.data(), t1.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                 b->stream));
+        b->ntiles1 = (int)t1.size();
+    }
     HIPCHK(b, hipStreamSynchronize(b->stream));
     int cus = 256;
     {
@@ -1686,7 +1735,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             if (std::fscanf(fh, "{\"key\": \"%63[0-9a-f]\", \"tile_w\": %d, \"tile_h\": %d, \"schedule\": %d, "
                                 "\"blocks_per_cu\": %d}",
                             k, &w, &h, &s, &p) == 5 &&
-                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 && is_batch_shape(b->storage, w, h)) {
+                key == k && s >= 0 && s <= 2 && p >= 0 && p <= 64 && is_batch_shape(b, w, h)) {
                 b->tile_w = w;
                 b->tile_h = h;
                 b->schedule = s;
@@ -1697,17 +1746,21 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         }
     }
     if (!have) {
-        // timed trial steps: each writes the lattices' next buffers from the
-        // current ones without advancing, so the state is unchanged.
-        // Candidates: tile shape (one, two or four brick rows) x schedule
+        // timed trial launches: each writes the lattices' next buffers from
+        // the current ones without advancing, so the state is unchanged.
+        // Candidates: tile shape (one, two or four brick rows of the
+        // one-step kernel, and the two-step kernel's tile) x schedule
         // (lattice by lattice, largest first, interleaved) x grid (one block
-        // per tile, or 8 or 16 persistent blocks per CU)
-        int tws[4], ths[4];
-        const int ns = batch_shapes(b->storage, tws, ths, 4);
+        // per tile, or persistent blocks: 8 or 16 per CU of 256 threads, 1
+        // or 2 per CU of the two-step kernel's 1024 or 512)
+        int tws[5], ths[5];
+        const int ns = candidate_shapes(b, tws, ths);
         std::vector<TuneCand> cands;
-        for (int k = 0; k < ns; ++k)
-            for (int bpc : {0, 8, 16})
+        for (int k = 0; k < ns; ++k) {
+            const bool two = is_two_step_shape(b, tws[k], ths[k]);
+            for (int bpc : {0, two ? 1 : 8, two ? 2 : 16})
                 for (int sched = 0; sched < 3; ++sched) cands.push_back({tws[k], ths[k], sched, bpc});
+        }
         b->trials.clear();
         hipEvent_t e0, e1;
         HIPCHK(b, hipEventCreate(&e0));
@@ -1718,16 +1771,21 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            HIPCHK(b, launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
-                                   b->nt, b->sr, 0, b->d_step, b->stream));
+            const bool two = is_two_step_shape(b, cd.w, cd.h);
+            auto launch = [&]() {
+                return two ? launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
+                                           b->nt, b->sr, 0, b->d_step, b->stream)
+                           : launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
+                                          b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream);
+            };
+            HIPCHK(b, launch());
             HIPCHK(b, hipEventRecord(e0, b->stream));
-            for (int r = 0; r < 3; ++r)
-                HIPCHK(b, launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
-                                       b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream));
+            for (int r = 0; r < 3; ++r) HIPCHK(b, launch());
             HIPCHK(b, hipEventRecord(e1, b->stream));
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+            ms /= two ? 2.0f : 1.0f;  // per step
             b->trials.push_back({(double)cd.w, (double)cd.h, (double)cd.sched, (double)cd.bpc, ms / 3.0});
             if (ms < best) {
                 best = ms;
@@ -1743,6 +1801,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     }
     if ((rc = batch_upload_tiles(b, b->tile_w, b->tile_h, b->schedule))) return rc;
     b->grid = batch_grid(b->ntiles, b->bpc, cus);
+    b->two = is_two_step_shape(b, b->tile_w, b->tile_h);
     if (cache) {
         FILE *fh = std::fopen(cache, "w");
         if (fh) {
@@ -1758,11 +1817,26 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     return LB2D_OK;
 }
 
-// One batched step at offset k of its launch group; tick: steps to add to
-// the lattices' step counters after it (stochastic rounding only).
+// One batched step at offset k of its launch group (with the one-step
+// tiles when the two-step kernel was chosen); tick: steps to add to the
+// lattices' step counters after it (stochastic rounding only).
 static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
-    hipError_t e = launch_batch(b->storage, b->tile_w, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid,
-                                b->max_plane, b->nt, b->sr, k, b->d_step, s);
+    hipError_t e = b->two ? launch_batch(b->storage, b->tile_w1, b->d_lat, b->d_tiles1, b->ntiles1, parity,
+                                         b->ntiles1, b->max_plane, b->nt, b->sr, k, b->d_step, s)
+                          : launch_batch(b->storage, b->tile_w, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid,
+                                         b->max_plane, b->nt, b->sr, k, b->d_step, s);
+    if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
+    return e;
+}
+
+// Four batched steps from an even step as two two-step launches (p -> p^1
+// -> p), at offset k of their launch group; tick as for batch_step.
+static hipError_t batch_quad(lb2d_batch *b, int k, int tick, hipStream_t s) {
+    hipError_t e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, 0, b->grid, b->max_plane, b->nt,
+                                 b->sr, k, b->d_step, s);
+    if (e == hipSuccess)
+        e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, 1, b->grid, b->max_plane, b->nt, b->sr,
+                          k + 2, b->d_step, s);
     if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
@@ -1785,8 +1859,12 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         hipGraph_t gr = nullptr;
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
-            e = batch_step(b, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
+        if (b->two)
+            for (int k = 0; k < kGraphSteps && e == hipSuccess; k += 4)
+                e = batch_quad(b, k, k == kGraphSteps - 4 ? kGraphSteps : 0, b->cap_stream);
+        else
+            for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+                e = batch_step(b, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess) return b->fail(LB2D_E_HIP, "batch graph capture failed");
         HIPCHK(b, hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0));
@@ -1796,6 +1874,10 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         HIPCHK(b, hipGraphLaunch(b->graph, b->stream));
         b->t += kGraphSteps;
         left -= kGraphSteps;
+    }
+    for (; b->two && left >= 4; left -= 4) {
+        HIPCHK(b, batch_quad(b, 0, 4, b->stream));
+        b->t += 4;
     }
     for (; left > 0; --left) {
         HIPCHK(b, batch_step(b, (int)(b->t & 1), 0, 1, b->stream));

@@ -37,6 +37,9 @@ struct PlainLattice {
     double Fx, Fy;        // aveforce (summed vector)
     double ax, ay;        // aveacceleration (summed vector)
     double rho_ref;       // shift of the stored populations
+    // the same seven coefficients rounded to FP32, for the formats whose
+    // collision runs in FP32 (FP32 and the 16-bit formats)
+    float omega_f, tau_f, Fx_f, Fy_f, ax_f, ay_f, rho_ref_f;
     const unsigned long long *step;  // completed steps (device; read only by
                                      // the stochastically rounded step)
     unsigned seed;        // key of the stochastic-rounding stream

@@ -270,15 +270,17 @@ __device__ __forceinline__ void st_stream(LB2D_GLOBAL S *p, S v) {
     }
 }
 
-// Wavefront-uniform copy of one step's lattice parameters (scalar registers).
+// Wavefront-uniform copy of one step's lattice parameters (scalar
+// registers); the collision coefficients in the arithmetic type.
 template <typename S>
 struct PlainArgs {
+    using R = typename Codec<S>::R;
     const S *fin;
     S *fout;
     const uint16_t *links;
     unsigned nx, ny, pnx;
     size_t plane;
-    double omega, tau, Fx, Fy, ax, ay, rho_ref;
+    R omega, tau, Fx, Fy, ax, ay, rho_ref;
 };
 
 __device__ __forceinline__ unsigned ufl(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -286,6 +288,7 @@ __device__ __forceinline__ unsigned long long ufl64(unsigned long long v) {
     return ((unsigned long long)ufl((unsigned)(v >> 32)) << 32) | ufl((unsigned)v);
 }
 __device__ __forceinline__ double ufld(double v) { return __longlong_as_double((long long)ufl64((unsigned long long)__double_as_longlong(v))); }
+__device__ __forceinline__ float ufld(float v) { return __uint_as_float(ufl(__float_as_uint(v))); }
 template <typename T>
 __device__ __forceinline__ T *uflp(T *p) { return (T *)ufl64((unsigned long long)p); }
 
@@ -301,13 +304,23 @@ __device__ __forceinline__ PlainArgs<S> plain_args(const PlainLattice &L, int pa
     a.ny = (unsigned)L.ny;
     a.pnx = L.pnx;
     a.plane = L.plane;
-    a.omega = L.omega;
-    a.tau = L.tau;
-    a.Fx = L.Fx;
-    a.Fy = L.Fy;
-    a.ax = L.ax;
-    a.ay = L.ay;
-    a.rho_ref = L.rho_ref;
+    if constexpr (sizeof(typename PlainArgs<S>::R) == 4) {
+        a.omega = L.omega_f;
+        a.tau = L.tau_f;
+        a.Fx = L.Fx_f;
+        a.Fy = L.Fy_f;
+        a.ax = L.ax_f;
+        a.ay = L.ay_f;
+        a.rho_ref = L.rho_ref_f;
+    } else {
+        a.omega = L.omega;
+        a.tau = L.tau;
+        a.Fx = L.Fx;
+        a.Fy = L.Fy;
+        a.ax = L.ax;
+        a.ay = L.ay;
+        a.rho_ref = L.rho_ref;
+    }
     return a;
 }
 
@@ -382,10 +395,10 @@ __device__ __forceinline__ void plain_relax(const PlainArgs<S> &L, R (&d)[9], bo
     for (int i = 0; i < 9; ++i) drho = drho + d[i];
     const R jx = ((((R(0) + d[1]) - d[3]) + d[5]) - d[6] - d[7]) + d[8];
     const R jy = ((((R(0) + d[2]) - d[4]) + d[5]) + d[6] - d[7]) - d[8];
-    const R rho = drho + R(L.rho_ref);
-    const R tau = R(L.tau), omega = R(L.omega);
-    const R Fx = fmar(rho, R(L.ax), R(L.Fx));
-    const R Fy = fmar(rho, R(L.ay), R(L.Fy));
+    const R rho = drho + L.rho_ref;
+    const R tau = L.tau, omega = L.omega;
+    const R Fx = fmar(rho, L.ax, L.Fx);
+    const R Fy = fmar(rho, L.ay, L.Fy);
     const R mx = fmar(Fx, tau, jx);  // j + tau F
     const R my = fmar(Fy, tau, jy);
     const R inv = rcp(rho);
@@ -532,28 +545,30 @@ __device__ __forceinline__ unsigned plain_stage(const PlainArgs<S> &L, unsigned 
     return lk;
 }
 
+// LDS planes of the two-step kernel for a TW x TH tile: (TW + 2) x (TH + 2)
+// slots, rows padded to 8 slots.
+template <int TW, int TH>
+struct Plain2Tile {
+    static constexpr int SW = TW + 2, SH = TH + 2, PITCH = (SW + 7) / 8 * 8, PL = SH * PITCH;
+    static constexpr int NR = 2 * SW + 2 * TH;  // ring slots
+};
+
+// The two steps of the tile at (x0, y0) by a block of TW x TH threads; sf:
+// the block's LDS tile (9 planes).  No thread leaves early, so a block may
+// run several tiles in a row (the caller separates them by a barrier).
 template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_plain2(PlainLattice L, int parity, int k) {
+__device__ __forceinline__ void plain2_tile(const PlainArgs<S> &a, int x0, int y0, unsigned key1, unsigned key2,
+                                            S *sf) {
     using C = Codec<S>;
     using R = typename C::R;
+    using T = Plain2Tile<TW, TH>;
     constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S)), G = W * H;
-    // LDS tile: (TW + 2) x (TH + 2) slots per plane, rows padded to 8 slots
-    constexpr int SW = TW + 2, SH = TH + 2, PITCH = (SW + 7) / 8 * 8, PL = SH * PITCH;
-    constexpr int NR = 2 * SW + 2 * TH;  // ring slots
+    constexpr int SW = T::SW, SH = T::SH, PITCH = T::PITCH, PL = T::PL, NR = T::NR;
     static_assert(TW % W == 0 && TH % H == 0 && NR <= TW * TH, "tile of whole bricks");
-    __shared__ S sf[9 * PL];
-    const PlainArgs<S> a = plain_args<S>(L, parity);
-    const int nx = L.nx, ny = L.ny;
+    const int nx = (int)a.nx, ny = (int)a.ny;
     const int t = threadIdx.x;
     int lx, ly;
     tile_thread<TW, W, H>(t, lx, ly);
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-    unsigned key1 = 0u, key2 = 0u;
-    if constexpr (SR) {
-        const unsigned long long st = *L.step + (unsigned long long)k;
-        key1 = lowbias32((unsigned)(st + 1ull) ^ L.seed);
-        key2 = lowbias32((unsigned)(st + 2ull) ^ L.seed);
-    }
     // step one: the thread's own node (wrapped when the tile overhangs the
     // lattice: such slots are the ring of the last real nodes) ...
     const int gx = x0 + lx, gy = y0 + ly;
@@ -583,33 +598,69 @@ __global__ void __launch_bounds__(TW *TH) k_plain2(PlainLattice L, int parity, i
         plain_stage<S, O, SR, PL>(a, (unsigned)rx, (unsigned)ry, sy * PITCH + sx, sf, key1);
     }
     __syncthreads();
-    // step two: the tile's nodes from LDS
+    // step two: the tile's nodes from LDS; a brick is written iff it holds a
+    // fluid node
     const bool inside = gx < nx && gy < ny;
     const bool fluid = inside && (lk & 1u) == 0u;
     const unsigned long long bal = __ballot(fluid);
-    if (bal == 0ull || !inside) return;
     const unsigned lane = __lane_id();
     const unsigned long long gmask = (G >= 64) ? ~0ull : (((1ull << (G & 63)) - 1ull) << ((lane / G) * G));
-    if ((bal & gmask) == 0ull) return;
-    const int c = (ly + 1) * PITCH + lx + 1;
-    R d[9];
+    if (inside && (bal & gmask) != 0ull) {
+        const int c = (ly + 1) * PITCH + lx + 1;
+        R d[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const bool wall = (lk >> opp(i)) & 1u;
-        const int src = wall ? opp(i) * PL + c : i * PL + c - ey(i) * PITCH - ex(i);
-        d[i] = fluid ? C::dec(sf[src], i) : R(0);
+        for (int i = 0; i < 9; ++i) {
+            const bool wall = (lk >> opp(i)) & 1u;
+            const int src = wall ? opp(i) * PL + c : i * PL + c - ey(i) * PITCH - ex(i);
+            d[i] = fluid ? C::dec(sf[src], i) : R(0);
+        }
+        plain_relax(a, d, fluid);
+        unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
+        if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key2, w);
+        const O pl = (O)a.plane * (O)sizeof(S);
+        LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(a.fout);
+        const O s = brick_off<S, O>((unsigned)gx, (unsigned)gy, a.pnx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const S e = plain_enc<S, SR>(d[i], i, w);
+            if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
+            else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+        }
     }
-    plain_relax(a, d, fluid);
-    unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
-    if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key2, w);
-    const O pl = (O)a.plane * (O)sizeof(S);
-    LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(a.fout);
-    const O s = brick_off<S, O>((unsigned)gx, (unsigned)gy, a.pnx);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const S e = plain_enc<S, SR>(d[i], i, w);
-        if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
-        else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+}
+
+// Keys of the stochastic rounding of steps st + 1 and st + 2.
+__device__ __forceinline__ void sr_keys2(unsigned long long st, unsigned seed, unsigned &key1, unsigned &key2) {
+    key1 = lowbias32((unsigned)(st + 1ull) ^ seed);
+    key2 = lowbias32((unsigned)(st + 2ull) ^ seed);
+}
+
+template <typename S, typename O, bool SR, bool NT, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_plain2(PlainLattice L, int parity, int k) {
+    __shared__ S sf[9 * Plain2Tile<TW, TH>::PL];
+    unsigned key1 = 0u, key2 = 0u;
+    if constexpr (SR) sr_keys2(*L.step + (unsigned long long)k, L.seed, key1, key2);
+    plain2_tile<S, O, SR, NT, TW, TH>(plain_args<S>(L, parity), blockIdx.x * TW, blockIdx.y * TH, key1, key2, sf);
+}
+
+// Batched two-step kernel: blocks walk a table of TW x TH tiles of many
+// lattices, as k_batch does, each tile as in k_plain2 (every lattice of
+// the batch has at least one tile's extent).
+template <typename S, typename O, bool SR, bool NT, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_batch2(const PlainLattice *__restrict__ lat,
+                                                  const Tile *__restrict__ tiles, int ntiles, int parity, int k,
+                                                  const unsigned long long *__restrict__ bstep) {
+    __shared__ S sf[9 * Plain2Tile<TW, TH>::PL];
+    unsigned long long step = 0ull;
+    if constexpr (SR) step = *bstep + (unsigned long long)k;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int li = (int)ufl((unsigned)tiles[t].lattice);
+        const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
+        const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
+        unsigned key1 = 0u, key2 = 0u;
+        if constexpr (SR) sr_keys2(step, lat[li].seed, key1, key2);
+        if (t != (int)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
+        plain2_tile<S, O, SR, NT, TW, TH>(a, x0, y0, ufl(key1), ufl(key2), sf);
     }
 }
 

@@ -139,6 +139,35 @@ hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile 
     return hipGetLastError();
 }
 
+template <typename S, typename O, bool SR, bool NT>
+static void batch2_launch(const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid, int k,
+                          const unsigned long long *bstep, hipStream_t stream) {
+    constexpr int TW = sizeof(S) == 8 ? kPlain2TW / 2 : kPlain2TW, TH = kPlain2TH;
+    hipLaunchKernelGGL((k_batch2<S, O, SR, NT, TW, TH>), dim3(grid), dim3(TW * TH), 0, stream, lat, tiles, ntiles,
+                       parity, k, bstep);
+}
+
+template <bool NT>
+static void batch2_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                            size_t max_plane, bool sr, int k, const unsigned long long *bstep, hipStream_t stream) {
+    if (sr && st == kF16)
+        batch2_launch<_Float16, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
+    else if (sr && st == kBF16)
+        batch2_launch<bf16s, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
+    else if (fits32(max_plane, storage_bytes(st)))
+        LB2D_DISPATCH(st, (batch2_launch<S, uint32_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
+    else
+        LB2D_DISPATCH(st, (batch2_launch<S, size_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
+}
+
+hipError_t launch_batch2(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                         size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+                         hipStream_t stream) {
+    if (nt) batch2_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    else batch2_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    return hipGetLastError();
+}
+
 // Advances the batch's step counter and that of every lattice of the batch
 // (which each lattice reads when stepped alone) by n.
 __global__ void k_tick_batch(const PlainLattice *__restrict__ lat, int nlat, int n, unsigned long long *bstep) {

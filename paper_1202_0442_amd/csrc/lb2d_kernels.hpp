@@ -36,6 +36,12 @@ int batch_shapes(int st, int *tw, int *th, int max);
 hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity,
                         int grid, size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
                         hipStream_t s);
+// Batched two-step kernel over a table of plain2_tile-sized tiles of
+// lattices that each hold at least one such tile; arguments as for
+// launch_batch (k: offset of the first of the two steps).
+hipError_t launch_batch2(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                         size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+                         hipStream_t s);
 // Adds n to the batch's step counter and to that of each of its nlat lattices.
 hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, unsigned long long *bstep, hipStream_t s);
 // Streaming stores pay off once the populations (all buffers) no longer

@@ -92,36 +92,56 @@ def test_toy_batch_matches_oracle_and_single_lattices(storage):
         assert eu <= tol_u and er <= tol_r, (eu, er)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
-def test_every_tuned_shape_equals_single_lattices(storage, tmp_path):
+# Lattice sets of the tuned-shape test: "ragged" holds lattices narrower
+# or lower than the two-step kernel's tile (64 x 16, 32 x 16 for FP64), so
+# the autotuner tries the three one-step shapes only; "tiles" holds
+# lattices of at least that tile, so it also tries the two-step kernel.
+SETS = {"ragged": [(70, 41), (131, 77), (33, 200), (256, 9)],
+        "tiles": [(70, 41), (131, 77), (64, 200), (256, 17)]}
+
+
+def _member(case, storage, rounding, seed):
+    g = build_gpu(case, storage, bind=False)
+    if rounding == "stochastic":
+        g.rounding("stochastic", seed)
+    g.bind(storage)
+    return g
+
+
+@pytest.mark.parametrize("lattices", ["ragged", "tiles"])
+@pytest.mark.parametrize("storage,rounding", [("f32", "nearest"), ("f16", "nearest"), ("f64", "nearest"),
+                                              ("bf16", "stochastic")])
+def test_every_tuned_shape_equals_single_lattices(storage, rounding, lattices, tmp_path):
     """Every tile shape, schedule and grid the autotuner tries gives the
     lattices' own results bit for bit: each configuration is forced through
-    the tune cache and run for 75 steps against the lattices stepped alone."""
+    the tune cache and run for 75 steps (two 32-step graphs, then pairs of
+    two-step launches or single steps) against the lattices stepped alone."""
     import json
-    cases = [porous_case(nx, ny, 30 + k, tau=0.6 + 0.15 * k) for k, (nx, ny) in
-             enumerate([(70, 41), (131, 77), (33, 200), (256, 9)])]
-    singles = [build_gpu(c, storage) for c in cases]
+    cases = [porous_case(nx, ny, 30 + k, tau=0.6 + 0.15 * k) for k, (nx, ny) in enumerate(SETS[lattices])]
+    singles = [_member(c, storage, rounding, 7 + k) for k, c in enumerate(cases)]
     for s in singles:
         s.iteration(75)
     want = [s.get_populations(0) for s in singles]
     cache = str(tmp_path / "tune.json")
-    first = _batch([build_gpu(c, storage) for c in cases], tune_cache=cache)
+    first = _batch([_member(c, storage, rounding, 7 + k) for k, c in enumerate(cases)], tune_cache=cache)
     trials = first.trials()
     shapes = sorted({(t["tile_w"], t["tile_h"]) for t in trials})
-    print(storage, "shapes", shapes, "chosen", first.config())
-    assert len(shapes) == 3 and len(trials) == 27
+    print(storage, rounding, lattices, "shapes", shapes, "chosen", first.config())
+    nshape = 3 if lattices == "ragged" else 4
+    assert len(shapes) == nshape and len(trials) == 9 * nshape
     key = json.load(open(cache))["key"]
     for t in trials:
         with open(cache, "w") as fh:
             json.dump(dict(key=key, tile_w=t["tile_w"], tile_h=t["tile_h"], schedule=t["schedule"],
                            blocks_per_cu=t["blocks_per_cu"]), fh)
-        members = [build_gpu(c, storage) for c in cases]
+        members = [_member(c, storage, rounding, 7 + k) for k, c in enumerate(cases)]
         b = _batch(members, tune_cache=cache)
         cfg = b.config()
         assert (cfg["tile_w"], cfg["tile_h"], cfg["schedule"], cfg["blocks_per_cu"]) == \
             (t["tile_w"], t["tile_h"], t["schedule"], t["blocks_per_cu"]) and b.trials() == []
         b.iteration(75)
         for w, m in zip(want, members):
+            assert m.step_count() == 75
             assert np.array_equal(w, m.get_populations(0)), cfg
         b.close()
 
