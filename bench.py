@@ -3,10 +3,13 @@
 Default workload: one-fluid flow through a seeded porous medium of
 4096 x 4096 nodes (non-overlapping discs, radius 8..24, porosity 0.6,
 periodic, tau = 0.8, acceleration 1e-5 along e1), FP32 shifted storage.
-A step is one fused stream + bounce-back + collide pass over the lattice.
+A step is one time step (stream + bounce-back + collide) over the whole
+lattice; the step kernel fuses two of them per launch (the first kept in
+LDS), so each launch advances two steps.
 
 Prints ONE JSON line with MLUPS (all nodes), the HBM roofline of the step
-kernel (algorithmic bytes per launch / measured launch time), the FP64 CPU
+kernel (algorithmic bytes of the steps one launch advances / measured launch
+time, beside the bytes the launch must move at least), the FP64 CPU
 oracle timed on a bounded sample of the same workload, and variants:
 16-bit storage, the two-component Shan-Chen + solute + growth step, and the
 batched ensemble of uneven lattices against running them one at a time.
@@ -460,10 +463,14 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
     B.finalize(stream=stream)
     B.iteration(GRAPH_WARMUP)
     ms_b = time_steps(torch, stream, B.iteration, steps)
-    # algorithmic bytes of one batched step (one launch): 18 values per
-    # fluid node of every lattice and the 1-byte mask of every node
-    byt = nfl * 18 * STORE_BYTES[storage] + ntot
+    # algorithmic bytes of one batched step: 18 values per fluid node of
+    # every lattice and the 1-byte mask of every node; a launch advances
+    # `spl` steps (2 for the two-step tile)
+    spl = B.steps_per_launch()
+    step_bytes = nfl * 18 * STORE_BYTES[storage] + ntot
+    byt = spl * step_bytes
     per = ms_b / steps
+    launch_ms = per * spl
     trials = B.trials()
     spread = {}
     for t in trials:
@@ -475,12 +482,18 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
            "sequential_mlups": ntot * seq_steps / (ms_seq * 1e-3) / 1e6 if seq_steps else None,
            "tuned": B.config(), "autotuner_trials": len(trials),
            "best_ms_per_tile_shape": {k: round(v, 4) for k, v in spread.items()},
-           "roofline": {"bound": "hbm", "achieved": round(byt / (per * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBPS,
-                        "unit": "GB/s", "frac": round(byt / (per * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
-                        "kernel": "k_batch", "bytes_per_launch": byt,
-                        "bytes_rule": f"{18 * STORE_BYTES[storage]} B per fluid node of every lattice "
-                                      "+ 1 B mask per node"},
+           "roofline": {"bound": "hbm", "achieved": round(byt / (launch_ms * 1e-3) / 1e9, 1),
+                        "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                        "frac": round(byt / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                        "kernel": "k_batch2" if spl == 2 else "k_batch", "steps_per_launch": spl,
+                        "bytes_per_launch": byt, "launch_ms": launch_ms,
+                        "bytes_rule": f"{18 * STORE_BYTES[storage]} B per fluid node of every lattice and step "
+                                      f"+ 1 B mask per node and step, times the {spl} step(s) one launch "
+                                      "advances"},
            "ms_per_step": per, "steps": steps, "sequential_steps": seq_steps}
+    if spl > 1:
+        out["roofline"]["launch_io_bytes"] = step_bytes
+        out["roofline"]["launch_io_GBps"] = round(step_bytes / (launch_ms * 1e-3) / 1e9, 1)
     out["speedup"] = out["batched_mlups"] / out["sequential_mlups"] if seq_steps else None
     B.close()
     for L in lats:
@@ -627,11 +640,16 @@ def main():
     per = ms / args.steps
     mlups = n * args.steps / (ms * 1e-3) / 1e6
     log(f"{mlups:.0f} MLUPS, {per * 1e3:.1f} us/step")
-    # one kernel launch per step: launch time = step time (HIP events on the
-    # stream the kernel runs on)
-    bytes_launch = nfl * 18 * STORE_BYTES[args.storage] + n
-    achieved = bytes_launch / (per * 1e-3) / 1e9
-    traffic = measured_traffic(f"k_plain_{args.storage}_{pname}.md")
+    # the dominant kernel advances `spl` steps per launch (the two-step
+    # kernel: 2), launched back to back inside the graphs: launch time =
+    # spl x step time (HIP events on the stream the kernel runs on)
+    spl = L.steps_per_launch()
+    kernel = "k_plain2" if spl == 2 else "k_plain"
+    launch_ms = per * spl
+    step_bytes = nfl * 18 * STORE_BYTES[args.storage] + n
+    bytes_launch = spl * step_bytes
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(f"{kernel}_{args.storage}_{pname}.md")
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": per,
@@ -641,8 +659,11 @@ def main():
                    "nx": w.nx, "ny": w.ny, "discs": len(w.discs), "fluid_fraction": nfl / n},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic,
-                     "kernel": "k_plain", "bytes_per_launch": bytes_launch,
-                     "bytes_rule": "72 B per fluid node (9 loads + 9 stores of 4 B) + 1 B mask per node"},
+                     "kernel": kernel, "steps_per_launch": spl, "bytes_per_launch": bytes_launch,
+                     "launch_ms": launch_ms,
+                     "bytes_rule": f"{18 * STORE_BYTES[args.storage]} B per fluid node and step (9 loads + 9 stores "
+                                   f"of {STORE_BYTES[args.storage]} B) + 1 B mask per node and step, times the "
+                                   f"{spl} step(s) one launch advances"},
         "mflups": round(nfl * args.steps / (ms * 1e-3) / 1e6, 1),
     }
     # dense accounting (every node, solids included, moves 18 values + mask):
@@ -651,11 +672,18 @@ def main():
     dense = n * (18 * STORE_BYTES[args.storage] + 1) / (per * 1e-3) / 1e9
     out["roofline"]["dense_equiv_GBps"] = round(dense, 1)
     out["roofline"]["dense_equiv_frac"] = round(dense / PEAK_HBM_GBPS, 4)
+    if spl > 1:
+        # what a two-step launch must move at least: every fluid population
+        # read once and written once, and the mask (the first step's values
+        # stay in LDS), at the launch's duration
+        out["roofline"]["launch_io_bytes"] = step_bytes
+        out["roofline"]["launch_io_GBps"] = round(step_bytes / (launch_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["launch_io_frac"] = round(step_bytes / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)
     if traffic is not None:
         # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
         # scaled by a copy kernel of known size) at this launch's duration
-        out["roofline"]["traffic_GBps"] = round(traffic / (per * 1e-3) / 1e9, 1)
-        out["roofline"]["traffic_frac"] = round(traffic / (per * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)
+        out["roofline"]["traffic_GBps"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(traffic / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)
     mass_drift = None
     if not args.no_readout:
         b1 = L.budgets()
@@ -672,6 +700,9 @@ def main():
     cms = lb2d.copy_bench(cb, reps=20, stream=stream)
     out["copy_ceiling_GBps"] = round(2 * cb / (cms * 1e-3) / 1e9, 1)
     out["roofline"]["frac_of_copy"] = round(achieved / out["copy_ceiling_GBps"], 4)
+    if spl > 1:
+        out["roofline"]["launch_io_frac_of_copy"] = round(out["roofline"]["launch_io_GBps"]
+                                                          / out["copy_ceiling_GBps"], 4)
 
     want = set() if args.variants == "none" else (
         {"f16", "bf16", "sc", "phase", "growth", "batch", "channel", "droplet"} if args.variants == "all"

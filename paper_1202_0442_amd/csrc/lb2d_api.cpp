@@ -96,8 +96,8 @@ struct lb2d_ctx {
     size_t staging_doubles = 0;
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
-    hipGraphExec_t graph = nullptr;            // kGraphSteps steps
-    std::map<int, hipGraphExec_t> tail_graphs;  // fewer steps, by count
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // kGraphSteps steps, by the parity they start at
+    std::map<int, hipGraphExec_t> tail_graphs;      // fewer steps, by 2 x count + start parity
     // population plane geometry: brick layout, padded to whole bricks
     unsigned pnx = 0;
     size_t pplane = 0;
@@ -157,14 +157,14 @@ struct lb2d_batch {
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
     bool two = false;      // the chosen tiles are the two-step kernel's (run in pairs)
     // one-step tiles of the storage's default shape, lattice by lattice, for
-    // the odd and leftover steps when the two-step kernel was chosen
+    // the leftover steps (fewer than four) when the two-step kernel was chosen
     Tile *d_tiles1 = nullptr;
     int ntiles1 = 0, tile_w1 = 64, tile_h1 = 4;
     size_t max_plane = 0;  // largest population plane of the lattices
     bool nt = false;       // streaming stores: the lattices' populations exceed the last-level cache
     bool sr = false;       // stochastic rounding (every lattice of the batch asked for it)
     unsigned long long *d_step = nullptr;  // device step count shared by the lattices (stochastic rounding)
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // kGraphSteps steps, by start parity
     int64_t t = 0;
     // the autotuner's trials: tile width, height, schedule, blocks per CU
     // and milliseconds per step (empty when the choice came from a cache)
@@ -431,15 +431,16 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
     return e;
 }
 
-// The launches of `len` steps from an even step.  The one-fluid step on a
-// lattice of at least one tile of the two-step kernel runs as pairs of
-// two-step launches (four steps, ending in the buffer they started from),
-// then single steps; the device step counter (read only by stochastic
-// rounding) advances once, after the last of them.
-hipError_t enqueue_group(lb2d_ctx *c, int len, hipStream_t s) {
+// The launches of `len` steps from a step of parity p0 (the state is in
+// buffer p0).  The one-fluid step on a lattice of at least one tile of the
+// two-step kernel runs as pairs of two-step launches (p0 -> p0^1 -> p0: four
+// steps, ending in the buffer they started from, at either parity), then
+// single steps; the device step counter (read only by stochastic rounding)
+// advances once, after the last of them.
+hipError_t enqueue_group(lb2d_ctx *c, int len, int p0, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!c->plain()) {
-        for (int k = 0; k < len && e == hipSuccess; ++k) e = enqueue_step(c, k & 1, k, 0, s);
+        for (int k = 0; k < len && e == hipSuccess; ++k) e = enqueue_step(c, (p0 + k) & 1, k, 0, s);
         return e;
     }
     const PlainLattice L = plain_lattice(c);
@@ -447,18 +448,19 @@ hipError_t enqueue_group(lb2d_ctx *c, int len, hipStream_t s) {
     int k = 0;
     if (plain2_fits(c->storage, c->nx, c->ny))
         for (; k + 4 <= len && e == hipSuccess; k += 4) {
-            e = launch_plain2(c->storage, L, 0, c->sr, nt, k, s);
-            if (e == hipSuccess) e = launch_plain2(c->storage, L, 1, c->sr, nt, k + 2, s);
+            e = launch_plain2(c->storage, L, p0, c->sr, nt, k, s);
+            if (e == hipSuccess) e = launch_plain2(c->storage, L, p0 ^ 1, c->sr, nt, k + 2, s);
         }
-    for (; k < len && e == hipSuccess; ++k) e = launch_plain(c->storage, L, k & 1, c->sr, nt, k, s);
+    for (; k < len && e == hipSuccess; ++k) e = launch_plain(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
     if (e == hipSuccess && c->sr && len > 0) e = launch_tick((unsigned long long *)c->dstep, len, s);
     return e;
 }
 
-// The launch graph of `len` steps starting at an even step (len <=
-// kGraphSteps; captured once per length and kept until lb2d_destroy).
-int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
-    hipGraphExec_t &g = len == kGraphSteps ? c->graph : c->tail_graphs[len];
+// The launch graph of `len` steps starting at a step of parity p0 (len <=
+// kGraphSteps; captured once per length and parity and kept until
+// lb2d_destroy).
+int build_graph(lb2d_ctx *c, int len, int p0, hipGraphExec_t *out) {
+    hipGraphExec_t &g = len == kGraphSteps ? c->graph[p0] : c->tail_graphs[2 * len + p0];
     if (g) {
         *out = g;
         return LB2D_OK;
@@ -466,7 +468,7 @@ int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t gr = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = enqueue_group(c, len, c->cap_stream);
+    const hipError_t e = enqueue_group(c, len, p0, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
     if (e != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));
@@ -476,18 +478,19 @@ int build_graph(lb2d_ctx *c, int len, hipGraphExec_t *out) {
     return LB2D_OK;
 }
 
-// How lb2d_iteration splits nsteps from step t: a single step if t is odd
-// (graphs start at even steps), whole graphs of kGraphSteps, then one graph
-// of the remaining steps (a single launch for one step).
+// How lb2d_iteration splits nsteps from step t: whole graphs of
+// kGraphSteps, then one graph of the remaining steps (a single launch for
+// one step); every graph of the call starts at the parity of t, since
+// kGraphSteps is even.
 struct StepPlan {
-    int64_t first, graphs, tail;
+    int64_t graphs, tail;
+    int p0;
 };
 StepPlan step_plan(int64_t t, int64_t nsteps) {
     StepPlan q{};
-    q.first = ((t & 1) && nsteps > 0) ? 1 : 0;
-    const int64_t left = nsteps - q.first;
-    q.graphs = left / kGraphSteps;
-    q.tail = left % kGraphSteps;
+    q.graphs = nsteps / kGraphSteps;
+    q.tail = nsteps % kGraphSteps;
+    q.p0 = (int)(t & 1);
     return q;
 }
 
@@ -617,9 +620,10 @@ int lb2d_destroy(lb2d_ctx *c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
     }
-    if (c->graph || c->cap_stream || c->ev0 || !c->tail_graphs.empty()) {
+    if (c->graph[0] || c->graph[1] || c->cap_stream || c->ev0 || !c->tail_graphs.empty()) {
         (void)hipSetDevice(c->device);
-        if (c->graph) (void)hipGraphExecDestroy(c->graph);
+        for (hipGraphExec_t g : c->graph)
+            if (g) (void)hipGraphExecDestroy(g);
         for (auto &kv : c->tail_graphs)
             if (kv.second) (void)hipGraphExecDestroy(kv.second);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1220,13 +1224,9 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
         return LB2D_OK;
     }
     const StepPlan q = step_plan(c->t, left);
-    if (q.first) {
-        HIPCHK(c, enqueue_step(c, 1, 0, 1, c->stream));
-        c->t += 1;
-    }
     hipGraphExec_t g = nullptr;
     if (q.graphs) {
-        int rc = build_graph(c, kGraphSteps, &g);
+        int rc = build_graph(c, kGraphSteps, q.p0, &g);
         if (rc) return rc;
         for (int64_t k = 0; k < q.graphs; ++k) {
             HIPCHK(c, hipGraphLaunch(g, c->stream));
@@ -1234,14 +1234,21 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
         }
     }
     if (q.tail == 1) {
-        HIPCHK(c, enqueue_step(c, (int)(c->t & 1), 0, 1, c->stream));
+        HIPCHK(c, enqueue_step(c, q.p0, 0, 1, c->stream));
         c->t += 1;
     } else if (q.tail > 1) {
-        int rc = build_graph(c, (int)q.tail, &g);
+        int rc = build_graph(c, (int)q.tail, q.p0, &g);
         if (rc) return rc;
         HIPCHK(c, hipGraphLaunch(g, c->stream));
         c->t += q.tail;
     }
+    return LB2D_OK;
+}
+
+int lb2d_steps_per_launch(lb2d_ctx *c, int *steps) {
+    if (!c || !steps) return LB2D_E_INVAL;
+    if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
+    *steps = c->plain() && plain2_fits(c->storage, c->nx, c->ny) ? 2 : 1;
     return LB2D_OK;
 }
 
@@ -1253,8 +1260,8 @@ int lb2d_prepare(lb2d_ctx *c, int64_t nsteps) {
     const StepPlan q = step_plan(c->t, nsteps);
     hipGraphExec_t g = nullptr;
     int rc = LB2D_OK;
-    if (q.graphs) rc = build_graph(c, kGraphSteps, &g);
-    if (!rc && q.tail > 1) rc = build_graph(c, (int)q.tail, &g);
+    if (q.graphs) rc = build_graph(c, kGraphSteps, q.p0, &g);
+    if (!rc && q.tail > 1) rc = build_graph(c, (int)q.tail, q.p0, &g);
     return rc;
 }
 
@@ -1577,9 +1584,10 @@ int lb2d_batch_destroy(lb2d_batch *b) {
         (void)hipSetDevice(b->device);
         (void)hipStreamSynchronize(b->stream);
     }
-    if (b->graph || b->cap_stream) {
+    if (b->graph[0] || b->graph[1] || b->cap_stream) {
         (void)hipSetDevice(b->device);
-        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        for (hipGraphExec_t g : b->graph)
+            if (g) (void)hipGraphExecDestroy(g);
         if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     }
     delete b;
@@ -1829,14 +1837,15 @@ static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStre
     return e;
 }
 
-// Four batched steps from an even step as two two-step launches (p -> p^1
-// -> p), at offset k of their launch group; tick as for batch_step.
-static hipError_t batch_quad(lb2d_batch *b, int k, int tick, hipStream_t s) {
-    hipError_t e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, 0, b->grid, b->max_plane, b->nt,
+// Four batched steps from a step of parity p0 as two two-step launches
+// (p0 -> p0^1 -> p0), at offset k of their launch group; tick as for
+// batch_step.
+static hipError_t batch_quad(lb2d_batch *b, int p0, int k, int tick, hipStream_t s) {
+    hipError_t e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, p0, b->grid, b->max_plane, b->nt,
                                  b->sr, k, b->d_step, s);
     if (e == hipSuccess)
-        e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, 1, b->grid, b->max_plane, b->nt, b->sr,
-                          k + 2, b->d_step, s);
+        e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, p0 ^ 1, b->grid, b->max_plane, b->nt,
+                          b->sr, k + 2, b->d_step, s);
     if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
@@ -1849,34 +1858,31 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         if (c->t != b->t) return b->fail(LB2D_E_STATE, "a lattice of the batch was advanced on its own");
     HIPCHK(b, hipSetDevice(b->device));
     int64_t left = nsteps;
-    if ((b->t & 1) && left > 0) {
-        HIPCHK(b, batch_step(b, 1, 0, 1, b->stream));
-        b->t += 1;
-        --left;
-    }
-    if (left >= kGraphSteps && !b->graph) {
+    // graphs of kGraphSteps (even) steps, captured once per start parity
+    const int p0 = (int)(b->t & 1);
+    if (left >= kGraphSteps && !b->graph[p0]) {
         if (!b->cap_stream) HIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         if (b->two)
             for (int k = 0; k < kGraphSteps && e == hipSuccess; k += 4)
-                e = batch_quad(b, k, k == kGraphSteps - 4 ? kGraphSteps : 0, b->cap_stream);
+                e = batch_quad(b, p0, k, k == kGraphSteps - 4 ? kGraphSteps : 0, b->cap_stream);
         else
             for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
-                e = batch_step(b, k & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
+                e = batch_step(b, (p0 + k) & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
         hipError_t e2 = hipStreamEndCapture(b->cap_stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess) return b->fail(LB2D_E_HIP, "batch graph capture failed");
-        HIPCHK(b, hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0));
+        HIPCHK(b, hipGraphInstantiate(&b->graph[p0], gr, nullptr, nullptr, 0));
         HIPCHK(b, hipGraphDestroy(gr));
     }
     while (left >= kGraphSteps) {
-        HIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+        HIPCHK(b, hipGraphLaunch(b->graph[p0], b->stream));
         b->t += kGraphSteps;
         left -= kGraphSteps;
     }
     for (; b->two && left >= 4; left -= 4) {
-        HIPCHK(b, batch_quad(b, 0, 4, b->stream));
+        HIPCHK(b, batch_quad(b, p0, 0, 4, b->stream));
         b->t += 4;
     }
     for (; left > 0; --left) {
@@ -1894,6 +1900,13 @@ int lb2d_batch_config(lb2d_batch *b, int *w, int *h, int *s, int *p) {
     *h = b->tile_h;
     *s = b->schedule;
     *p = b->bpc;
+    return LB2D_OK;
+}
+
+int lb2d_batch_steps_per_launch(lb2d_batch *b, int *steps) {
+    if (!b || !steps) return LB2D_E_INVAL;
+    if (!b->final_) return b->fail(LB2D_E_STATE, "not finalized");
+    *steps = b->two ? 2 : 1;
     return LB2D_OK;
 }
 

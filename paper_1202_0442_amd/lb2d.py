@@ -71,6 +71,8 @@ _SIGS = {
     "lb2d_bind": [_P, _P, _SZ, _P],
     "lb2d_iteration": [_P, _I64],
     "lb2d_prepare": [_P, _I64],
+    "lb2d_steps_per_launch": [_P, ctypes.POINTER(_I)],
+    "lb2d_batch_steps_per_launch": [_P, ctypes.POINTER(_I)],
     "lb2d_moments": [_P, _I, _DP, _DP, _DP],
     "lb2d_solute_state": [_P, _DP, _DP],
     "lb2d_mask": [_P, _U8P],
@@ -276,6 +278,12 @@ class Lattice:
         """Captures the launch graphs of a later iteration(nsteps)."""
         self._chk(_lib.lb2d_prepare(self._h, int(nsteps)))
 
+    def steps_per_launch(self):
+        """lb2d_steps_per_launch: 2 where the graphs run the two-step kernel."""
+        v = _I(0)
+        self._chk(_lib.lb2d_steps_per_launch(self._h, ctypes.byref(v)))
+        return v.value
+
     # output
     def moments(self, comp=0):
         n = self.nx * self.ny
@@ -406,6 +414,12 @@ class Batch:
         self._chk(_lib.lb2d_batch_config(self._h, *[ctypes.byref(x) for x in v]))
         return dict(tile_w=v[0].value, tile_h=v[1].value, schedule=v[2].value,
                     blocks_per_cu=v[3].value)
+
+    def steps_per_launch(self):
+        """lb2d_batch_steps_per_launch: 2 when the two-step tile was chosen."""
+        v = _I(0)
+        self._chk(_lib.lb2d_batch_steps_per_launch(self._h, ctypes.byref(v)))
+        return v.value
 
     def trials(self):
         """The autotuner's trials: list of dicts (tile_w, tile_h, schedule,

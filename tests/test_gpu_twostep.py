@@ -39,8 +39,9 @@ def _pair(case, storage, rounding):
                                               ("bf16", "stochastic")])
 @pytest.mark.parametrize("nx,ny", SHAPES)
 def test_two_step_launches_equal_single_steps(nx, ny, storage, rounding):
-    """101 steps (one odd start-up step, three 32-step graphs, a 4-step tail)
-    through graphs equal 101 single launches, bit for bit."""
+    """101 steps (one step, then from the odd step count three 32-step
+    graphs and a 4-step tail) through graphs equal 101 single launches, bit
+    for bit."""
     case = porous_case(nx, ny, 40 + nx + ny, tau=0.7)
     a, b = _pair(case, storage, rounding)
     a.iteration(1)
