@@ -128,7 +128,9 @@ typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 template <>
 struct Codec<_Float16> {
     using R = float;
-    __device__ static float dec(_Float16 v, int i) { return (float)v * iscale16(i); }
+    // one mixed-precision multiply-add (v_fma_mix_f32) instead of a convert
+    // and a multiply; exact, the scale being a power of two
+    __device__ static float dec(_Float16 v, int i) { return __builtin_fmaf((float)v, iscale16(i), 0.0f); }
     __device__ static _Float16 enc(float d, int i) { return (_Float16)(d * scale16(i)); }
     __device__ static _Float16 enc_sr(float d, int i, unsigned r) {
         half2_t h = {};
@@ -193,6 +195,37 @@ template <typename S, typename O>
 __device__ __forceinline__ O brick_off(unsigned x, unsigned y, unsigned pnx) {
     constexpr unsigned W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
     return (((O)(y / H) * (O)(pnx / W) + (O)(x / W)) * (O)(W * H) + (O)((y % H) * W + (x % W))) * (O)sizeof(S);
+}
+
+// The same offset split into a row part and a column part (their sum), so
+// that the eight neighbours of a node cost one add each.
+template <typename S, typename O>
+__device__ __forceinline__ O brick_row(unsigned y, unsigned pnx) {
+    constexpr unsigned W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
+    return ((O)(y / H) * (O)(pnx / W) * (O)(W * H) + (O)((y % H) * W)) * (O)sizeof(S);
+}
+template <typename S, typename O>
+__device__ __forceinline__ O brick_col(unsigned x) {
+    constexpr unsigned W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S));
+    return ((O)(x / W) * (O)(W * H) + (O)(x % W)) * (O)sizeof(S);
+}
+
+// Offsets of node (x, y) (src[0]) and of node - e_i for each direction,
+// given the periodic neighbour coordinates xm = x - 1, xp = x + 1, ym, yp.
+template <typename S, typename O>
+__device__ __forceinline__ void brick_pulls(unsigned x, unsigned y, unsigned xm, unsigned xp, unsigned ym,
+                                            unsigned yp, unsigned pnx, O (&src)[9]) {
+    const O r0 = brick_row<S, O>(y, pnx), rm = brick_row<S, O>(ym, pnx), rp = brick_row<S, O>(yp, pnx);
+    const O c0 = brick_col<S, O>(x), cm = brick_col<S, O>(xm), cp = brick_col<S, O>(xp);
+    src[0] = r0 + c0;
+    src[1] = r0 + cm;
+    src[2] = rm + c0;
+    src[3] = r0 + cp;
+    src[4] = rp + c0;
+    src[5] = rm + cm;
+    src[6] = rm + cp;
+    src[7] = rp + cp;
+    src[8] = rp + cm;
 }
 
 // Deterministic block sum of K doubles per thread into out[0..K) (valid in
@@ -357,17 +390,13 @@ __device__ __forceinline__ void plain_pull(const PlainArgs<S> &L, unsigned xx, u
     const unsigned nx = L.nx, ny = L.ny, pnx = L.pnx;
     const O pl = (O)L.plane * (O)sizeof(S);  // bytes per plane
     const LB2D_GLOBAL char *__restrict__ fin = (const LB2D_GLOBAL char *)gbl(L.fin);
-    const O s = brick_off<S, O>(xx, yy, pnx);
     const unsigned xm = (xx == 0) ? nx - 1 : xx - 1;
     const unsigned xp = (xx == nx - 1) ? 0 : xx + 1;
     const unsigned ym = (yy == 0) ? ny - 1 : yy - 1;
     const unsigned yp = (yy == ny - 1) ? 0 : yy + 1;
-    // node - e_i for each direction
-    const O src[9] = {s,
-                      brick_off<S, O>(xm, yy, pnx), brick_off<S, O>(xx, ym, pnx),
-                      brick_off<S, O>(xp, yy, pnx), brick_off<S, O>(xx, yp, pnx),
-                      brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
-                      brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
+    O src[9];  // the node, then node - e_i for each direction
+    brick_pulls<S, O>(xx, yy, xm, xp, ym, yp, pnx, src);
+    const O s = src[0];
     d[0] = C::dec(*(const LB2D_GLOBAL S *)(fin + s), 0);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -610,9 +639,14 @@ __device__ __forceinline__ void plain2_tile(const PlainArgs<S> &a, int x0, int y
         R d[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const bool wall = (lk >> opp(i)) & 1u;
-            const int src = wall ? opp(i) * PL + c : i * PL + c - ey(i) * PITCH - ex(i);
-            d[i] = fluid ? C::dec(sf[src], i) : R(0);
+            // slot of node - e_i in plane i, or (solid source) the node's own
+            // slot in plane opp(i): c + K + wall * (opposite - K), so that
+            // the constant part folds into the LDS instruction's offset.
+            // Solid lanes read one of the two slots too (inside the tile,
+            // whatever it holds): plain_relax zeroes their output.
+            const int K = i * PL - ey(i) * PITCH - ex(i);
+            const int wall = (int)((lk >> opp(i)) & 1u);
+            d[i] = C::dec(sf[c + wall * (opp(i) * PL - K) + K], i);
         }
         plain_relax(a, d, fluid);
         unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
@@ -1158,12 +1192,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
             if (hpull) {
                 const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
                 const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
-                const O hs = brick_off<S, O>(gx, gy, pnx);
-                const O hsrc[9] = {hs,
-                                   brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
-                                   brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
-                                   brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
-                                   brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
+                O hsrc[9];
+                brick_pulls<S, O>(gx, gy, gxm, gxp, gym, gyp, pnx, hsrc);
+                const O hs = hsrc[0];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const S *__restrict__ fin = (const S *)p.f[parity][c];
@@ -1189,12 +1220,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
     // byte offsets of the node and of node - e_i (periodic) in a plane
     const unsigned xm = (ux_ == 0) ? nx - 1 : ux_ - 1, xp = (ux_ + 1 >= (unsigned)nx) ? 0 : ux_ + 1;
     const unsigned ym = (uy_ == 0) ? ny - 1 : uy_ - 1, yp = (uy_ + 1 >= (unsigned)ny) ? 0 : uy_ + 1;
-    const O s = brick_off<S, O>(ux_, uy_, pnx);
-    const O src[9] = {s,
-                      brick_off<S, O>(xm, uy_, pnx), brick_off<S, O>(ux_, ym, pnx),
-                      brick_off<S, O>(xp, uy_, pnx), brick_off<S, O>(ux_, yp, pnx),
-                      brick_off<S, O>(xm, ym, pnx), brick_off<S, O>(xp, ym, pnx),
-                      brick_off<S, O>(xp, yp, pnx), brick_off<S, O>(xm, yp, pnx)};
+    O src[9];
+    brick_pulls<S, O>(ux_, uy_, xm, xp, ym, yp, pnx, src);
+    const O s = src[0];
 
     // 1. pull both components at the own node
     R d[NC][9];
@@ -1280,12 +1308,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                     if (!(hl & 1u)) {
                         const unsigned gxm = (gx == 0) ? nx - 1 : gx - 1, gxp = (gx + 1 == (unsigned)nx) ? 0 : gx + 1;
                         const unsigned gym = (gy == 0) ? ny - 1 : gy - 1, gyp = (gy + 1 == (unsigned)ny) ? 0 : gy + 1;
-                        const O hs = brick_off<S, O>(gx, gy, pnx);
-                        const O hsrc[9] = {hs,
-                                           brick_off<S, O>(gxm, gy, pnx), brick_off<S, O>(gx, gym, pnx),
-                                           brick_off<S, O>(gxp, gy, pnx), brick_off<S, O>(gx, gyp, pnx),
-                                           brick_off<S, O>(gxm, gym, pnx), brick_off<S, O>(gxp, gym, pnx),
-                                           brick_off<S, O>(gxp, gyp, pnx), brick_off<S, O>(gxm, gyp, pnx)};
+                        O hsrc[9];
+                        brick_pulls<S, O>(gx, gy, gxm, gxp, gym, gyp, pnx, hsrc);
+                        const O hs = hsrc[0];
                         R gh[9];
 #pragma unroll
                         for (int i = 0; i < 9; ++i) gh[i] = R(0);
