@@ -26,8 +26,8 @@ using namespace lb2d;
 
 namespace {
 
-constexpr int kGraphSteps = 32;  // steps per captured graph (a multiple of 4: pairs of two-step launches)
-static_assert(kGraphSteps % 4 == 0, "graphs hold whole pairs of two-step launches");
+constexpr int kGraphSteps = 48;  // steps per captured graph: whole three-step launches, even
+static_assert(kGraphSteps % 6 == 0, "graphs hold whole three-step launches and keep the parity");
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -155,9 +155,9 @@ struct lb2d_batch {
     size_t max_tiles = 0;
     int ntiles = 0;
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
-    bool two = false;      // the chosen tiles are the two-step kernel's (run in pairs)
+    bool multi = false;    // the chosen tiles are the three-step kernel's
     // one-step tiles of the storage's default shape, lattice by lattice, for
-    // the leftover steps (fewer than four) when the two-step kernel was chosen
+    // the leftover steps (fewer than three) when the three-step kernel was chosen
     Tile *d_tiles1 = nullptr;
     int ntiles1 = 0, tile_w1 = 64, tile_h1 = 4;
     size_t max_plane = 0;  // largest population plane of the lattices
@@ -432,9 +432,8 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
 }
 
 // The launches of `len` steps from a step of parity p0 (the state is in
-// buffer p0).  The one-fluid step on a lattice of at least one tile of the
-// two-step kernel runs as pairs of two-step launches (p0 -> p0^1 -> p0: four
-// steps, ending in the buffer they started from, at either parity), then
+// buffer p0).  The one-fluid step on a lattice that satisfies plain3_fits
+// runs as three-step launches (each p -> p^1, three steps ahead), then
 // single steps; the device step counter (read only by stochastic rounding)
 // advances once, after the last of them.
 hipError_t enqueue_group(lb2d_ctx *c, int len, int p0, hipStream_t s) {
@@ -446,11 +445,8 @@ hipError_t enqueue_group(lb2d_ctx *c, int len, int p0, hipStream_t s) {
     const PlainLattice L = plain_lattice(c);
     const bool nt = stream_stores(c);
     int k = 0;
-    if (plain2_fits(c->storage, c->nx, c->ny))
-        for (; k + 4 <= len && e == hipSuccess; k += 4) {
-            e = launch_plain2(c->storage, L, p0, c->sr, nt, k, s);
-            if (e == hipSuccess) e = launch_plain2(c->storage, L, p0 ^ 1, c->sr, nt, k + 2, s);
-        }
+    if (plain3_fits(c->storage, c->nx, c->ny))
+        for (; k + 3 <= len && e == hipSuccess; k += 3) e = launch_plain3(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
     for (; k < len && e == hipSuccess; ++k) e = launch_plain(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
     if (e == hipSuccess && c->sr && len > 0) e = launch_tick((unsigned long long *)c->dstep, len, s);
     return e;
@@ -1248,7 +1244,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
 int lb2d_steps_per_launch(lb2d_ctx *c, int *steps) {
     if (!c || !steps) return LB2D_E_INVAL;
     if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
-    *steps = c->plain() && plain2_fits(c->storage, c->nx, c->ny) ? 2 : 1;
+    *steps = c->plain() && plain3_fits(c->storage, c->nx, c->ny) ? 3 : 1;
     return LB2D_OK;
 }
 
@@ -1621,28 +1617,28 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
-// The two-step kernel serves a batch whose every lattice holds one of its tiles.
-static bool batch2_ok(const lb2d_batch *b) {
+// The three-step kernel serves a batch whose every lattice satisfies plain3_fits.
+static bool batch3_ok(const lb2d_batch *b) {
     for (auto *c : b->lat)
-        if (!plain2_fits(b->storage, c->nx, c->ny)) return false;
+        if (!plain3_fits(b->storage, c->nx, c->ny)) return false;
     return !b->lat.empty();
 }
 
 // Tile shapes the autotuner may choose: the one-step shapes of the storage
-// format, then the two-step kernel's tile when the batch allows it.
+// format, then the three-step kernel's tile when the batch allows it.
 static int candidate_shapes(const lb2d_batch *b, int *tw, int *th) {
     int n = batch_shapes(b->storage, tw, th, 4);
-    if (batch2_ok(b)) {
-        plain2_tile(b->storage, &tw[n], &th[n]);
+    if (batch3_ok(b)) {
+        plain3_tile(b->storage, &tw[n], &th[n]);
         ++n;
     }
     return n;
 }
 
-static bool is_two_step_shape(const lb2d_batch *b, int w, int h) {
+static bool is_multi_step_shape(const lb2d_batch *b, int w, int h) {
     int tw, th;
-    plain2_tile(b->storage, &tw, &th);
-    return w == tw && h == th && batch2_ok(b);
+    plain3_tile(b->storage, &tw, &th);
+    return w == tw && h == th && batch3_ok(b);
 }
 
 // Largest tile table over the candidate shapes.
@@ -1757,16 +1753,16 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         // timed trial launches: each writes the lattices' next buffers from
         // the current ones without advancing, so the state is unchanged.
         // Candidates: tile shape (one, two or four brick rows of the
-        // one-step kernel, and the two-step kernel's tile) x schedule
+        // one-step kernel, and the three-step kernel's tile) x schedule
         // (lattice by lattice, largest first, interleaved) x grid (one block
         // per tile, or persistent blocks: 8 or 16 per CU of 256 threads, 1
-        // or 2 per CU of the two-step kernel's 1024 or 512)
+        // or 2 per CU of the three-step kernel's 1024 or 512)
         int tws[5], ths[5];
         const int ns = candidate_shapes(b, tws, ths);
         std::vector<TuneCand> cands;
         for (int k = 0; k < ns; ++k) {
-            const bool two = is_two_step_shape(b, tws[k], ths[k]);
-            for (int bpc : {0, two ? 1 : 8, two ? 2 : 16})
+            const bool multi = is_multi_step_shape(b, tws[k], ths[k]);
+            for (int bpc : {0, multi ? 1 : 8, multi ? 2 : 16})
                 for (int sched = 0; sched < 3; ++sched) cands.push_back({tws[k], ths[k], sched, bpc});
         }
         b->trials.clear();
@@ -1779,12 +1775,12 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         for (const auto &cd : cands) {
             if ((rc = batch_upload_tiles(b, cd.w, cd.h, cd.sched))) return rc;
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
-            const bool two = is_two_step_shape(b, cd.w, cd.h);
+            const bool multi = is_multi_step_shape(b, cd.w, cd.h);
             auto launch = [&]() {
-                return two ? launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid, b->max_plane,
-                                           b->nt, b->sr, 0, b->d_step, b->stream)
-                           : launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
-                                          b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream);
+                return multi ? launch_batch3(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
+                                             b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream)
+                             : launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
+                                            b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream);
             };
             HIPCHK(b, launch());
             HIPCHK(b, hipEventRecord(e0, b->stream));
@@ -1793,7 +1789,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
-            ms /= two ? 2.0f : 1.0f;  // per step
+            ms /= multi ? 3.0f : 1.0f;  // per step
             b->trials.push_back({(double)cd.w, (double)cd.h, (double)cd.sched, (double)cd.bpc, ms / 3.0});
             if (ms < best) {
                 best = ms;
@@ -1809,7 +1805,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
     }
     if ((rc = batch_upload_tiles(b, b->tile_w, b->tile_h, b->schedule))) return rc;
     b->grid = batch_grid(b->ntiles, b->bpc, cus);
-    b->two = is_two_step_shape(b, b->tile_w, b->tile_h);
+    b->multi = is_multi_step_shape(b, b->tile_w, b->tile_h);
     if (cache) {
         FILE *fh = std::fopen(cache, "w");
         if (fh) {
@@ -1826,10 +1822,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 }
 
 // One batched step at offset k of its launch group (with the one-step
-// tiles when the two-step kernel was chosen); tick: steps to add to the
+// tiles when the three-step kernel was chosen); tick: steps to add to the
 // lattices' step counters after it (stochastic rounding only).
 static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
-    hipError_t e = b->two ? launch_batch(b->storage, b->tile_w1, b->d_lat, b->d_tiles1, b->ntiles1, parity,
+    hipError_t e = b->multi ? launch_batch(b->storage, b->tile_w1, b->d_lat, b->d_tiles1, b->ntiles1, parity,
                                          b->ntiles1, b->max_plane, b->nt, b->sr, k, b->d_step, s)
                           : launch_batch(b->storage, b->tile_w, b->d_lat, b->d_tiles, b->ntiles, parity, b->grid,
                                          b->max_plane, b->nt, b->sr, k, b->d_step, s);
@@ -1837,15 +1833,11 @@ static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStre
     return e;
 }
 
-// Four batched steps from a step of parity p0 as two two-step launches
-// (p0 -> p0^1 -> p0), at offset k of their launch group; tick as for
-// batch_step.
-static hipError_t batch_quad(lb2d_batch *b, int p0, int k, int tick, hipStream_t s) {
-    hipError_t e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, p0, b->grid, b->max_plane, b->nt,
+// Three batched steps from a step of parity p as one three-step launch (p
+// -> p^1), at offset k of its launch group; tick as for batch_step.
+static hipError_t batch_triple(lb2d_batch *b, int p, int k, int tick, hipStream_t s) {
+    hipError_t e = launch_batch3(b->storage, b->d_lat, b->d_tiles, b->ntiles, p, b->grid, b->max_plane, b->nt,
                                  b->sr, k, b->d_step, s);
-    if (e == hipSuccess)
-        e = launch_batch2(b->storage, b->d_lat, b->d_tiles, b->ntiles, p0 ^ 1, b->grid, b->max_plane, b->nt,
-                          b->sr, k + 2, b->d_step, s);
     if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
@@ -1865,9 +1857,9 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         hipGraph_t gr = nullptr;
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        if (b->two)
-            for (int k = 0; k < kGraphSteps && e == hipSuccess; k += 4)
-                e = batch_quad(b, p0, k, k == kGraphSteps - 4 ? kGraphSteps : 0, b->cap_stream);
+        if (b->multi)
+            for (int k = 0; k < kGraphSteps && e == hipSuccess; k += 3)
+                e = batch_triple(b, (p0 + k) & 1, k, k == kGraphSteps - 3 ? kGraphSteps : 0, b->cap_stream);
         else
             for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
                 e = batch_step(b, (p0 + k) & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
@@ -1881,9 +1873,9 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         b->t += kGraphSteps;
         left -= kGraphSteps;
     }
-    for (; b->two && left >= 4; left -= 4) {
-        HIPCHK(b, batch_quad(b, p0, 0, 4, b->stream));
-        b->t += 4;
+    for (; b->multi && left >= 3; left -= 3) {
+        HIPCHK(b, batch_triple(b, (int)(b->t & 1), 0, 3, b->stream));
+        b->t += 3;
     }
     for (; left > 0; --left) {
         HIPCHK(b, batch_step(b, (int)(b->t & 1), 0, 1, b->stream));
@@ -1906,7 +1898,7 @@ int lb2d_batch_config(lb2d_batch *b, int *w, int *h, int *s, int *p) {
 int lb2d_batch_steps_per_launch(lb2d_batch *b, int *steps) {
     if (!b || !steps) return LB2D_E_INVAL;
     if (!b->final_) return b->fail(LB2D_E_STATE, "not finalized");
-    *steps = b->two ? 2 : 1;
+    *steps = b->multi ? 3 : 1;
     return LB2D_OK;
 }
 

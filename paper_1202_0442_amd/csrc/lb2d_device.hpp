@@ -540,23 +540,28 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
     plain_node<S, O, SR, NT>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
 }
 
-// Two steps in one pass (temporal blocking).  A block of TW x TH threads
-// owns a tile of whole bricks.  Step one is computed for the tile and for a
-// one-node ring around it, pulled from the input buffer as in the one-step
-// kernel, and kept in LDS in the storage format (rounded exactly as it would
-// be stored); after a barrier, step two pulls the tile's nodes from LDS and
-// writes whole bricks of the output buffer.  So the populations cross HBM
-// once per two steps, and the results are those of two one-step launches
-// bit for bit.  The host launches these in pairs (buffer p -> p^1 -> p), so
-// that after every pair the state lies in the buffer the step count names.
-// Ring nodes wrap periodically with one conditional add or subtract, which
-// needs nx >= TW and ny >= TH.  k: offset of the first of the two steps in
-// its launch group, as in k_plain.
-constexpr int kPlain2TW = 64;  // tile of the two-step kernel (FP64: 32 x 16)
-constexpr int kPlain2TH = 16;
+// Three steps in one pass (temporal blocking).  A block of TW x TH threads
+// owns a tile of whole bricks; one LDS region holds the tile and two rings
+// of nodes around it, in the storage format (every value rounded exactly as
+// a store would round it):
+//  1. step one for the tile and both rings, pulled from the input buffer as
+//     in the one-step kernel, into LDS;
+//  2. step two for the tile and the inner ring, pulled from LDS into
+//     registers and, after a barrier, written back to the same slots;
+//  3. step three for the tile, pulled from LDS and written to the output
+//     buffer as whole bricks.
+// So the populations cross HBM once per three steps, and the results are
+// those of three one-step launches bit for bit.  A launch reads buffer p and
+// writes p^1, an odd number of steps ahead, so after every launch the state
+// lies in the buffer its step count names.  Ring nodes wrap periodically
+// with one conditional add or subtract, which needs nx >= TW + 2 and
+// ny >= TH + 2.  k: offset of the first of the three steps in its launch
+// group, as in k_plain.
+constexpr int kPlain3TW = 64;  // tile of the three-step kernel (FP64: 32 x 16)
+constexpr int kPlain3TH = 16;
 
-// Step one of node (x, y) into LDS slot `slot` (planes of PL elements);
-// returns the node's link word.
+// The first step of node (x, y) into LDS slot `slot` (planes of PL
+// elements); returns the node's link word.
 template <typename S, typename O, bool SR, int PL>
 __device__ __forceinline__ unsigned plain_stage(const PlainArgs<S> &L, unsigned x, unsigned y, int slot, S *sf,
                                                 unsigned tkey) {
@@ -574,127 +579,175 @@ __device__ __forceinline__ unsigned plain_stage(const PlainArgs<S> &L, unsigned 
     return lk;
 }
 
-// LDS planes of the two-step kernel for a TW x TH tile: (TW + 2) x (TH + 2)
-// slots, rows padded to 8 slots.
+// LDS region of the three-step kernel for a TW x TH tile: (TW + 4) x (TH + 4)
+// slots per plane, rows padded to 8 slots; the tile sits at offset (2, 2).
 template <int TW, int TH>
-struct Plain2Tile {
-    static constexpr int SW = TW + 2, SH = TH + 2, PITCH = (SW + 7) / 8 * 8, PL = SH * PITCH;
-    static constexpr int NR = 2 * SW + 2 * TH;  // ring slots
+struct Plain3Tile {
+    static constexpr int AW = TW + 4, AH = TH + 4, PITCH = (AW + 7) / 8 * 8, PL = AH * PITCH;
+    static constexpr int NR1 = 2 * (TW + 2) + 2 * TH;        // inner ring slots
+    static constexpr int NR2 = 2 * (TW + 4) + 2 * (TH + 2);  // outer ring slots
 };
 
-// The two steps of the tile at (x0, y0) by a block of TW x TH threads; sf:
-// the block's LDS tile (9 planes).  No thread leaves early, so a block may
-// run several tiles in a row (the caller separates them by a barrier).
+// Slot s of the ring at distance r (1 or 2) around the tile, in region
+// coordinates: the ring's first row, its last row, then its first and last
+// columns without their corners.
+template <int TW, int TH>
+__device__ __forceinline__ void ring_slot(int s, int r, int &ax, int &ay) {
+    const int w = TW + 2 * r, h = TH + 2 * r, o = 2 - r;
+    if (s < w) {
+        ax = o + s;
+        ay = o;
+    } else if (s < 2 * w) {
+        ax = o + s - w;
+        ay = o + h - 1;
+    } else if (s < 2 * w + h - 2) {
+        ax = o;
+        ay = o + 1 + s - 2 * w;
+    } else {
+        ax = o + w - 1;
+        ay = o + 1 + s - 2 * w - (h - 2);
+    }
+}
+
+// Pull of a node whose populations sit in LDS (slot c; rows of P slots,
+// planes of PL), then its collision; d receives the post-collision
+// deviations.  The slot of node - e_i in plane i, or (solid source) the
+// node's own slot in plane opp(i), is c + K + wall * (opposite - K), so that
+// the constant part folds into the LDS instruction's offset.  Solid lanes
+// read one of the two slots too (inside the region, whatever it holds):
+// plain_relax zeroes their output.
+template <typename S, int P, int PL>
+__device__ __forceinline__ void lds_pull_relax(const PlainArgs<S> &a, const S *sf, int c, unsigned lk, bool fluid,
+                                               typename Codec<S>::R (&d)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int K = i * PL - ey(i) * P - ex(i);
+        const int wall = (int)((lk >> opp(i)) & 1u);
+        d[i] = Codec<S>::dec(sf[c + wall * (opp(i) * PL - K) + K], i);
+    }
+    plain_relax(a, d, fluid);
+}
+
+// The three steps of the tile at (x0, y0) by a block of TW x TH threads;
+// key: stochastic-rounding keys of the three steps; sf: the block's LDS
+// region (9 planes).  No thread leaves before the last barrier, so a block
+// may run several tiles in a row (the caller separates them by a barrier).
 template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__device__ __forceinline__ void plain2_tile(const PlainArgs<S> &a, int x0, int y0, unsigned key1, unsigned key2,
+__device__ __forceinline__ void plain3_tile(const PlainArgs<S> &a, int x0, int y0, const unsigned (&key)[3],
                                             S *sf) {
     using C = Codec<S>;
     using R = typename C::R;
-    using T = Plain2Tile<TW, TH>;
+    using T = Plain3Tile<TW, TH>;
     constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S)), G = W * H;
-    constexpr int SW = T::SW, SH = T::SH, PITCH = T::PITCH, PL = T::PL, NR = T::NR;
-    static_assert(TW % W == 0 && TH % H == 0 && NR <= TW * TH, "tile of whole bricks");
+    constexpr int P = T::PITCH, PL = T::PL, NR1 = T::NR1, NR2 = T::NR2;
+    static_assert(TW % W == 0 && TH % H == 0 && NR1 + NR2 <= TW * TH, "tile of whole bricks");
     const int nx = (int)a.nx, ny = (int)a.ny;
     const int t = threadIdx.x;
     int lx, ly;
     tile_thread<TW, W, H>(t, lx, ly);
-    // step one: the thread's own node (wrapped when the tile overhangs the
-    // lattice: such slots are the ring of the last real nodes) ...
+    // the thread's own node (wrapped when the tile overhangs the lattice:
+    // such slots hold the nodes past the lattice's last row or column)
     const int gx = x0 + lx, gy = y0 + ly;
-    const unsigned lk = plain_stage<S, O, SR, PL>(a, (unsigned)(gx < nx ? gx : gx - nx),
-                                                  (unsigned)(gy < ny ? gy : gy - ny),
-                                                  (ly + 1) * PITCH + lx + 1, sf, key1);
-    // ... and one ring slot for the first NR threads: the row y0 - 1, the
-    // row y0 + TH, the column x0 - 1, the column x0 + TW
-    if (t < NR) {
-        int sx, sy;
-        if (t < SW) {
-            sx = t;
-            sy = 0;
-        } else if (t < 2 * SW) {
-            sx = t - SW;
-            sy = SH - 1;
-        } else if (t < 2 * SW + TH) {
-            sx = 0;
-            sy = 1 + t - 2 * SW;
-        } else {
-            sx = SW - 1;
-            sy = 1 + t - 2 * SW - TH;
+    const unsigned ux = (unsigned)(gx < nx ? gx : gx - nx), uy = (unsigned)(gy < ny ? gy : gy - ny);
+    const int c = (ly + 2) * P + lx + 2;
+    // 1. step one: the own node, and one ring slot for the first NR1 + NR2
+    // threads (inner ring first)
+    const unsigned lk = plain_stage<S, O, SR, PL>(a, ux, uy, c, sf, key[0]);
+    int rc = -1;
+    unsigned rlk = 1u, rx = 0u, ry = 0u;
+    if (t < NR1 + NR2) {
+        int ax, ay;
+        if (t < NR1) ring_slot<TW, TH>(t, 1, ax, ay);
+        else ring_slot<TW, TH>(t - NR1, 2, ax, ay);
+        int qx = x0 - 2 + ax, qy = y0 - 2 + ay;
+        qx = qx < 0 ? qx + nx : (qx >= nx ? qx - nx : qx);
+        qy = qy < 0 ? qy + ny : (qy >= ny ? qy - ny : qy);
+        const unsigned l = plain_stage<S, O, SR, PL>(a, (unsigned)qx, (unsigned)qy, ay * P + ax, sf, key[0]);
+        if (t < NR1) {
+            rc = ay * P + ax;
+            rlk = l;
+            rx = (unsigned)qx;
+            ry = (unsigned)qy;
         }
-        int rx = x0 - 1 + sx, ry = y0 - 1 + sy;
-        rx = rx < 0 ? rx + nx : (rx >= nx ? rx - nx : rx);
-        ry = ry < 0 ? ry + ny : (ry >= ny ? ry - ny : ry);
-        plain_stage<S, O, SR, PL>(a, (unsigned)rx, (unsigned)ry, sy * PITCH + sx, sf, key1);
     }
     __syncthreads();
-    // step two: the tile's nodes from LDS; a brick is written iff it holds a
-    // fluid node
+    // 2. step two into registers: the own node, and the inner-ring node of
+    // the first NR1 threads; then, once every thread has read, back to LDS
+    const bool fl = (lk & 1u) == 0u, rfl = rc >= 0 && (rlk & 1u) == 0u;
+    R d[9], e[9];
+    if (fl) lds_pull_relax<S, P, PL>(a, sf, c, lk, true, d);
+    if (rfl) lds_pull_relax<S, P, PL>(a, sf, rc, rlk, true, e);
+    __syncthreads();
+    unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
+    if (fl) {
+        if constexpr (SR) sr_words(uy * a.nx + ux, key[1], w);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sf[i * PL + c] = plain_enc<S, SR>(d[i], i, w);
+    }
+    if (rfl) {
+        if constexpr (SR) sr_words(ry * a.nx + rx, key[1], w);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sf[i * PL + rc] = plain_enc<S, SR>(e[i], i, w);
+    }
+    __syncthreads();
+    // 3. step three: the tile's nodes from LDS; a brick is written iff it
+    // holds a fluid node
     const bool inside = gx < nx && gy < ny;
-    const bool fluid = inside && (lk & 1u) == 0u;
+    const bool fluid = inside && fl;
     const unsigned long long bal = __ballot(fluid);
     const unsigned lane = __lane_id();
     const unsigned long long gmask = (G >= 64) ? ~0ull : (((1ull << (G & 63)) - 1ull) << ((lane / G) * G));
     if (inside && (bal & gmask) != 0ull) {
-        const int c = (ly + 1) * PITCH + lx + 1;
-        R d[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            // slot of node - e_i in plane i, or (solid source) the node's own
-            // slot in plane opp(i): c + K + wall * (opposite - K), so that
-            // the constant part folds into the LDS instruction's offset.
-            // Solid lanes read one of the two slots too (inside the tile,
-            // whatever it holds): plain_relax zeroes their output.
-            const int K = i * PL - ey(i) * PITCH - ex(i);
-            const int wall = (int)((lk >> opp(i)) & 1u);
-            d[i] = C::dec(sf[c + wall * (opp(i) * PL - K) + K], i);
-        }
-        plain_relax(a, d, fluid);
-        unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
-        if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key2, w);
+        lds_pull_relax<S, P, PL>(a, sf, c, lk, fluid, d);
+        if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key[2], w);
         const O pl = (O)a.plane * (O)sizeof(S);
         LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(a.fout);
         const O s = brick_off<S, O>((unsigned)gx, (unsigned)gy, a.pnx);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const S e = plain_enc<S, SR>(d[i], i, w);
-            if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), e);
-            else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = e;
+            const S v = plain_enc<S, SR>(d[i], i, w);
+            if constexpr (NT) st_stream((LB2D_GLOBAL S *)(fout + (O)i * pl + s), v);
+            else *(LB2D_GLOBAL S *)(fout + (O)i * pl + s) = v;
         }
     }
 }
 
-// Keys of the stochastic rounding of steps st + 1 and st + 2.
-__device__ __forceinline__ void sr_keys2(unsigned long long st, unsigned seed, unsigned &key1, unsigned &key2) {
-    key1 = lowbias32((unsigned)(st + 1ull) ^ seed);
-    key2 = lowbias32((unsigned)(st + 2ull) ^ seed);
+// Keys of the stochastic rounding of steps st + 1, st + 2 and st + 3.
+__device__ __forceinline__ void sr_keys3(unsigned long long st, unsigned seed, unsigned (&key)[3]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) key[j] = lowbias32((unsigned)(st + 1ull + (unsigned long long)j) ^ seed);
 }
 
 template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_plain2(PlainLattice L, int parity, int k) {
-    __shared__ S sf[9 * Plain2Tile<TW, TH>::PL];
-    unsigned key1 = 0u, key2 = 0u;
-    if constexpr (SR) sr_keys2(*L.step + (unsigned long long)k, L.seed, key1, key2);
-    plain2_tile<S, O, SR, NT, TW, TH>(plain_args<S>(L, parity), blockIdx.x * TW, blockIdx.y * TH, key1, key2, sf);
+__global__ void __launch_bounds__(TW *TH) k_plain3(PlainLattice L, int parity, int k) {
+    __shared__ S sf[9 * Plain3Tile<TW, TH>::PL];
+    unsigned key[3] = {0u, 0u, 0u};
+    if constexpr (SR) sr_keys3(*L.step + (unsigned long long)k, L.seed, key);
+    plain3_tile<S, O, SR, NT, TW, TH>(plain_args<S>(L, parity), blockIdx.x * TW, blockIdx.y * TH, key, sf);
 }
 
-// Batched two-step kernel: blocks walk a table of TW x TH tiles of many
-// lattices, as k_batch does, each tile as in k_plain2 (every lattice of
-// the batch has at least one tile's extent).
+// Batched three-step kernel: blocks walk a table of TW x TH tiles of many
+// lattices, as k_batch does, each tile as in k_plain3 (every lattice of the
+// batch has at least the extent k_plain3 needs).
 template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_batch2(const PlainLattice *__restrict__ lat,
+__global__ void __launch_bounds__(TW *TH) k_batch3(const PlainLattice *__restrict__ lat,
                                                   const Tile *__restrict__ tiles, int ntiles, int parity, int k,
                                                   const unsigned long long *__restrict__ bstep) {
-    __shared__ S sf[9 * Plain2Tile<TW, TH>::PL];
+    __shared__ S sf[9 * Plain3Tile<TW, TH>::PL];
     unsigned long long step = 0ull;
     if constexpr (SR) step = *bstep + (unsigned long long)k;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int li = (int)ufl((unsigned)tiles[t].lattice);
         const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
-        unsigned key1 = 0u, key2 = 0u;
-        if constexpr (SR) sr_keys2(step, lat[li].seed, key1, key2);
+        unsigned key[3] = {0u, 0u, 0u};
+        if constexpr (SR) {
+            sr_keys3(step, lat[li].seed, key);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) key[j] = ufl(key[j]);
+        }
         if (t != (int)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
-        plain2_tile<S, O, SR, NT, TW, TH>(a, x0, y0, ufl(key1), ufl(key2), sf);
+        plain3_tile<S, O, SR, NT, TW, TH>(a, x0, y0, key, sf);
     }
 }
 
