@@ -4,8 +4,8 @@ Default workload: one-fluid flow through a seeded porous medium of
 4096 x 4096 nodes (non-overlapping discs, radius 8..24, porosity 0.6,
 periodic, tau = 0.8, acceleration 1e-5 along e1), FP32 shifted storage.
 A step is one time step (stream + bounce-back + collide) over the whole
-lattice; the step kernel fuses three of them per launch (the first two kept
-in LDS), so each launch advances three steps.
+lattice; the step kernel fuses five of them per launch (the first four kept
+in LDS), so each launch advances five steps.
 
 Prints ONE JSON line with MLUPS (all nodes), the HBM roofline of the step
 kernel (algorithmic bytes of the steps one launch advances / measured launch
@@ -79,9 +79,9 @@ def make_porous_lattice(lb2d, w, storage, stream, rounding="nearest", accel=None
     return L
 
 
-# warm-up steps before a timed region: two 48-step graphs, so that graph
+# warm-up steps before a timed region: two 60-step graphs, so that graph
 # capture and instantiation happen outside it
-GRAPH_WARMUP = 96
+GRAPH_WARMUP = 120
 
 
 def time_steps(torch, stream, fn, steps):
@@ -444,11 +444,11 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
     lats = [make_porous_lattice(lb2d, w, storage, stream, rounding) for w in ws]
     ntot = sum(w.nx * w.ny for w in ws)
     # one lattice at a time with the one-fluid kernel: each lattice runs its
-    # k steps (graph-launched: k is a multiple of the 48-step graph, built in
+    # k steps (graph-launched: k is a multiple of the 60-step graph, built in
     # the warm-up) before the next one starts
     ms_seq = None
     if seq_steps:
-        assert seq_steps % 48 == 0
+        assert seq_steps % 60 == 0
         for L in lats:
             L.iteration(GRAPH_WARMUP)
 
@@ -465,7 +465,7 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
     ms_b = time_steps(torch, stream, B.iteration, steps)
     # algorithmic bytes of one batched step: 18 values per fluid node of
     # every lattice and the 1-byte mask of every node; a launch advances
-    # `spl` steps (3 for the three-step tile)
+    # `spl` steps (5 for the multi-step tile)
     spl = B.steps_per_launch()
     step_bytes = nfl * 18 * STORE_BYTES[storage] + ntot
     byt = spl * step_bytes
@@ -485,7 +485,7 @@ def run_ensemble(lb2d, torch, count, steps, seq_steps, stream, storage="f32", ro
            "roofline": {"bound": "hbm", "achieved": round(byt / (launch_ms * 1e-3) / 1e9, 1),
                         "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                         "frac": round(byt / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
-                        "kernel": "k_batch3" if spl == 3 else "k_batch", "steps_per_launch": spl,
+                        "kernel": "k_batch_ms" if spl > 1 else "k_batch", "steps_per_launch": spl,
                         "bytes_per_launch": byt, "launch_ms": launch_ms,
                         "bytes_rule": f"{18 * STORE_BYTES[storage]} B per fluid node of every lattice and step "
                                       f"+ 1 B mask per node and step, times the {spl} step(s) one launch "
@@ -608,7 +608,7 @@ def main():
         if "growth" in want:
             res["growth"] = run_growth_sweep(lb2d, torch, stream)
         if "batch" in want:
-            res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 0 if args.no_sequential else 96,
+            res["ensemble"] = run_ensemble(lb2d, torch, 256, args.sc_steps, 0 if args.no_sequential else 120,
                                            stream, storage=args.storage)
         if "channel" in want:
             res["channel"] = run_channel(lb2d, torch, stream)
@@ -640,11 +640,11 @@ def main():
     per = ms / args.steps
     mlups = n * args.steps / (ms * 1e-3) / 1e6
     log(f"{mlups:.0f} MLUPS, {per * 1e3:.1f} us/step")
-    # the dominant kernel advances `spl` steps per launch (the three-step
+    # the dominant kernel advances `spl` steps per launch (the multi-step
     # kernel: 2), launched back to back inside the graphs: launch time =
     # spl x step time (HIP events on the stream the kernel runs on)
     spl = L.steps_per_launch()
-    kernel = "k_plain3" if spl == 3 else "k_plain"
+    kernel = "k_plain_ms" if spl > 1 else "k_plain"
     launch_ms = per * spl
     step_bytes = nfl * 18 * STORE_BYTES[args.storage] + n
     bytes_launch = spl * step_bytes
@@ -673,7 +673,7 @@ def main():
     out["roofline"]["dense_equiv_GBps"] = round(dense, 1)
     out["roofline"]["dense_equiv_frac"] = round(dense / PEAK_HBM_GBPS, 4)
     if spl > 1:
-        # what a three-step launch must move at least: every fluid population
+        # what a multi-step launch must move at least: every fluid population
         # read once and written once, and the mask (the first steps' values
         # stay in LDS), at the launch's duration
         out["roofline"]["launch_io_bytes"] = step_bytes
@@ -746,15 +746,15 @@ def main():
             variants[f"droplet_{st}"] = run_droplet(lb2d, torch, stream, st)
     if "batch" in want:
         log("variant batched ensemble")
-        variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 96, stream)
+        variants["ensemble"] = run_ensemble(lb2d, torch, 256, 500, 120, stream)
         torch.cuda.empty_cache()
         log("variant batched ensemble, FP16 storage")
-        variants["ensemble_f16"] = run_ensemble(lb2d, torch, 256, 500, 96, stream, storage="f16")
+        variants["ensemble_f16"] = run_ensemble(lb2d, torch, 256, 500, 120, stream, storage="f16")
         variants["ensemble_f16"]["speedup_vs_f32_batched"] = (variants["ensemble_f16"]["batched_mlups"]
                                                              / variants["ensemble"]["batched_mlups"])
         torch.cuda.empty_cache()
         log("variant batched ensemble, FP16 storage, stochastic rounding")
-        variants["ensemble_f16_sr"] = run_ensemble(lb2d, torch, 256, 500, 96, stream, storage="f16",
+        variants["ensemble_f16_sr"] = run_ensemble(lb2d, torch, 256, 500, 120, stream, storage="f16",
                                                    rounding="stochastic")
         variants["ensemble_f16_sr"]["speedup_vs_f32_batched"] = (variants["ensemble_f16_sr"]["batched_mlups"]
                                                                 / variants["ensemble"]["batched_mlups"])

@@ -290,17 +290,17 @@ int lb2d_bind(lb2d_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
 /* iteration command: advances nsteps >= 0 time steps (stream with
  * bounce-back, moments, forces, collision; then solute stream, reactive and
  * opening rules, collision, deposit, growth).  Asynchronous on the stream;
- * launches captured HIP graphs: graphs of 48 steps, then one graph of the
+ * launches captured HIP graphs: graphs of 60 steps, then one graph of the
  * remaining steps (a single launch for one step).  A graph is captured the
  * first time its length and starting parity (even or odd step count) are
  * needed and kept.  Inside the graphs, a one-fluid lattice (no solute, no
- * Shan-Chen, no openings or slip solids) of at least 66 x 18 nodes (34 x 18
- * in FP64) advances by a three-step kernel (the first two of each three
- * steps are kept in LDS and never reach memory), then single steps for the
- * remainder; the results equal single steps bit for bit. */
+ * Shan-Chen, no openings or slip solids) of at least 72 x 24 nodes (40 x 24
+ * in FP64) advances by a multi-step kernel, five steps per launch (the first
+ * four of each five are kept in LDS and never reach memory), then single
+ * steps for the remainder; the results equal single steps bit for bit. */
 int lb2d_iteration(lb2d_ctx *ctx, int64_t nsteps);
 /* Steps that one launch of the dominant step kernel advances inside the
- * graphs of lb2d_iteration: 3 for the three-step kernel, else 1. */
+ * graphs of lb2d_iteration: 5 for the multi-step kernel, else 1. */
 int lb2d_steps_per_launch(lb2d_ctx *ctx, int *steps);
 /* Captures, without running any step, the graphs that
  * lb2d_iteration(ctx, nsteps) will launch from the current step count, so
@@ -371,12 +371,12 @@ int lb2d_checkpoint_load(lb2d_ctx *ctx, const void *host, size_t bytes);
 
 /* A batch advances many bound one-fluid lattices (no solute, no Shan-Chen;
  * each with its own size, geometry, tau and forces, one storage format) in
- * one launch per time step, or per three steps: blocks walk a table of
+ * one launch per time step, or per five steps: blocks walk a table of
  * tiles of all the lattices.  The tile shape (one, two or four brick rows of
  * the one-step kernel's 256-thread blocks: 64x4, 32x8 or 16x16 nodes for
- * FP32/FP64, 32x8, 16x16 or 8x32 for 16-bit storage; or the three-step
+ * FP32/FP64, 32x8, 16x16 or 8x32 for 16-bit storage; or the multi-step
  * kernel's 64x16 tile, 32x16 for FP64, when every lattice has at least that
- * extent plus two nodes each way), the
+ * extent plus four nodes each way), the
  * order of the tiles in the table and the grid (one block per tile or
  * persistent blocks) are picked by an autotuner at finalize; results never
  * depend on them. */
@@ -408,8 +408,8 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps);
  * round-robin), blocks per CU (0 = one block per tile). */
 int lb2d_batch_config(lb2d_batch *b, int *tile_w, int *tile_h, int *schedule,
                       int *blocks_per_cu);
-/* Steps one launch of the batch's step kernel advances: 3 when the
- * autotuner chose the three-step kernel's tile, else 1. */
+/* Steps one launch of the batch's step kernel advances: 5 when the
+ * autotuner chose the multi-step kernel's tile, else 1. */
 int lb2d_batch_steps_per_launch(lb2d_batch *b, int *steps);
 /* The autotuner's trials at finalize: *count receives their number (0 when
  * the choice came from the tune cache); the first min(max, count) are

@@ -26,8 +26,9 @@ using namespace lb2d;
 
 namespace {
 
-constexpr int kGraphSteps = 48;  // steps per captured graph: whole three-step launches, even
-static_assert(kGraphSteps % 6 == 0, "graphs hold whole three-step launches and keep the parity");
+constexpr int kGraphSteps = 60;  // steps per captured graph
+static_assert(kGraphSteps % 2 == 0 && kGraphSteps % kMultiSteps == 0,
+              "graphs start and end at the same parity and hold whole multi-step launches");
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -155,9 +156,9 @@ struct lb2d_batch {
     size_t max_tiles = 0;
     int ntiles = 0;
     int tile_w = 64, tile_h = 4, schedule = 0, bpc = 0, grid = 0;
-    bool multi = false;    // the chosen tiles are the three-step kernel's
+    bool multi = false;    // the chosen tiles are the multi-step kernel's
     // one-step tiles of the storage's default shape, lattice by lattice, for
-    // the leftover steps (fewer than three) when the three-step kernel was chosen
+    // the leftover steps when the multi-step kernel was chosen
     Tile *d_tiles1 = nullptr;
     int ntiles1 = 0, tile_w1 = 64, tile_h1 = 4;
     size_t max_plane = 0;  // largest population plane of the lattices
@@ -432,10 +433,10 @@ hipError_t enqueue_step(lb2d_ctx *c, int parity, int k, int tick, hipStream_t s)
 }
 
 // The launches of `len` steps from a step of parity p0 (the state is in
-// buffer p0).  The one-fluid step on a lattice that satisfies plain3_fits
-// runs as three-step launches (each p -> p^1, three steps ahead), then
-// single steps; the device step counter (read only by stochastic rounding)
-// advances once, after the last of them.
+// buffer p0).  The one-fluid step on a lattice that satisfies multi_fits
+// runs as multi-step launches (each p -> p^1, multi_steps() steps ahead),
+// then single steps; the device step counter (read only by stochastic
+// rounding) advances once, after the last of them.
 hipError_t enqueue_group(lb2d_ctx *c, int len, int p0, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (!c->plain()) {
@@ -445,8 +446,10 @@ hipError_t enqueue_group(lb2d_ctx *c, int len, int p0, hipStream_t s) {
     const PlainLattice L = plain_lattice(c);
     const bool nt = stream_stores(c);
     int k = 0;
-    if (plain3_fits(c->storage, c->nx, c->ny))
-        for (; k + 3 <= len && e == hipSuccess; k += 3) e = launch_plain3(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
+    const int ms = multi_steps();
+    if (multi_fits(c->storage, c->nx, c->ny))
+        for (; k + ms <= len && e == hipSuccess; k += ms)
+            e = launch_plain_ms(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
     for (; k < len && e == hipSuccess; ++k) e = launch_plain(c->storage, L, (p0 + k) & 1, c->sr, nt, k, s);
     if (e == hipSuccess && c->sr && len > 0) e = launch_tick((unsigned long long *)c->dstep, len, s);
     return e;
@@ -1244,7 +1247,7 @@ int lb2d_iteration(lb2d_ctx *c, int64_t nsteps) {
 int lb2d_steps_per_launch(lb2d_ctx *c, int *steps) {
     if (!c || !steps) return LB2D_E_INVAL;
     if (!c->bound) return c->fail(LB2D_E_STATE, "not bound");
-    *steps = c->plain() && plain3_fits(c->storage, c->nx, c->ny) ? 3 : 1;
+    *steps = c->plain() && multi_fits(c->storage, c->nx, c->ny) ? multi_steps() : 1;
     return LB2D_OK;
 }
 
@@ -1617,19 +1620,19 @@ static size_t tiles_for(const lb2d_batch *b, int w, int h) {
     return n;
 }
 
-// The three-step kernel serves a batch whose every lattice satisfies plain3_fits.
-static bool batch3_ok(const lb2d_batch *b) {
+// The multi-step kernel serves a batch whose every lattice satisfies multi_fits.
+static bool batch_ms_ok(const lb2d_batch *b) {
     for (auto *c : b->lat)
-        if (!plain3_fits(b->storage, c->nx, c->ny)) return false;
+        if (!multi_fits(b->storage, c->nx, c->ny)) return false;
     return !b->lat.empty();
 }
 
 // Tile shapes the autotuner may choose: the one-step shapes of the storage
-// format, then the three-step kernel's tile when the batch allows it.
+// format, then the multi-step kernel's tile when the batch allows it.
 static int candidate_shapes(const lb2d_batch *b, int *tw, int *th) {
     int n = batch_shapes(b->storage, tw, th, 4);
-    if (batch3_ok(b)) {
-        plain3_tile(b->storage, &tw[n], &th[n]);
+    if (batch_ms_ok(b)) {
+        multi_tile_shape(b->storage, &tw[n], &th[n]);
         ++n;
     }
     return n;
@@ -1637,8 +1640,8 @@ static int candidate_shapes(const lb2d_batch *b, int *tw, int *th) {
 
 static bool is_multi_step_shape(const lb2d_batch *b, int w, int h) {
     int tw, th;
-    plain3_tile(b->storage, &tw, &th);
-    return w == tw && h == th && batch3_ok(b);
+    multi_tile_shape(b->storage, &tw, &th);
+    return w == tw && h == th && batch_ms_ok(b);
 }
 
 // Largest tile table over the candidate shapes.
@@ -1753,10 +1756,10 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
         // timed trial launches: each writes the lattices' next buffers from
         // the current ones without advancing, so the state is unchanged.
         // Candidates: tile shape (one, two or four brick rows of the
-        // one-step kernel, and the three-step kernel's tile) x schedule
+        // one-step kernel, and the multi-step kernel's tile) x schedule
         // (lattice by lattice, largest first, interleaved) x grid (one block
         // per tile, or persistent blocks: 8 or 16 per CU of 256 threads, 1
-        // or 2 per CU of the three-step kernel's 1024 or 512)
+        // or 2 per CU of the multi-step kernel's 1024 or 512)
         int tws[5], ths[5];
         const int ns = candidate_shapes(b, tws, ths);
         std::vector<TuneCand> cands;
@@ -1777,8 +1780,8 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             const int grid = batch_grid(b->ntiles, cd.bpc, cus);
             const bool multi = is_multi_step_shape(b, cd.w, cd.h);
             auto launch = [&]() {
-                return multi ? launch_batch3(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
-                                             b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream)
+                return multi ? launch_batch_ms(b->storage, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
+                                               b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream)
                              : launch_batch(b->storage, cd.w, b->d_lat, b->d_tiles, b->ntiles, parity, grid,
                                             b->max_plane, b->nt, b->sr, 0, b->d_step, b->stream);
             };
@@ -1789,7 +1792,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
             HIPCHK(b, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
-            ms /= multi ? 3.0f : 1.0f;  // per step
+            ms /= multi ? (float)multi_steps() : 1.0f;  // per step
             b->trials.push_back({(double)cd.w, (double)cd.h, (double)cd.sched, (double)cd.bpc, ms / 3.0});
             if (ms < best) {
                 best = ms;
@@ -1822,7 +1825,7 @@ int lb2d_batch_finalize(lb2d_batch *b, void *dev_ptr, size_t bytes, void *hip_st
 }
 
 // One batched step at offset k of its launch group (with the one-step
-// tiles when the three-step kernel was chosen); tick: steps to add to the
+// tiles when the multi-step kernel was chosen); tick: steps to add to the
 // lattices' step counters after it (stochastic rounding only).
 static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStream_t s) {
     hipError_t e = b->multi ? launch_batch(b->storage, b->tile_w1, b->d_lat, b->d_tiles1, b->ntiles1, parity,
@@ -1833,11 +1836,12 @@ static hipError_t batch_step(lb2d_batch *b, int parity, int k, int tick, hipStre
     return e;
 }
 
-// Three batched steps from a step of parity p as one three-step launch (p
-// -> p^1), at offset k of its launch group; tick as for batch_step.
-static hipError_t batch_triple(lb2d_batch *b, int p, int k, int tick, hipStream_t s) {
-    hipError_t e = launch_batch3(b->storage, b->d_lat, b->d_tiles, b->ntiles, p, b->grid, b->max_plane, b->nt,
-                                 b->sr, k, b->d_step, s);
+// multi_steps() batched steps from a step of parity p as one multi-step
+// launch (p -> p^1), at offset k of its launch group; tick as for
+// batch_step.
+static hipError_t batch_multi(lb2d_batch *b, int p, int k, int tick, hipStream_t s) {
+    hipError_t e = launch_batch_ms(b->storage, b->d_lat, b->d_tiles, b->ntiles, p, b->grid, b->max_plane, b->nt,
+                                   b->sr, k, b->d_step, s);
     if (e == hipSuccess && b->sr && tick) e = launch_tick_batch(b->d_lat, (int)b->lat.size(), tick, b->d_step, s);
     return e;
 }
@@ -1857,9 +1861,10 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         hipGraph_t gr = nullptr;
         HIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
+        const int ms = multi_steps();
         if (b->multi)
-            for (int k = 0; k < kGraphSteps && e == hipSuccess; k += 3)
-                e = batch_triple(b, (p0 + k) & 1, k, k == kGraphSteps - 3 ? kGraphSteps : 0, b->cap_stream);
+            for (int k = 0; k + ms <= kGraphSteps && e == hipSuccess; k += ms)
+                e = batch_multi(b, (p0 + k) & 1, k, k + ms == kGraphSteps ? kGraphSteps : 0, b->cap_stream);
         else
             for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
                 e = batch_step(b, (p0 + k) & 1, k, k == kGraphSteps - 1 ? kGraphSteps : 0, b->cap_stream);
@@ -1873,9 +1878,9 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         b->t += kGraphSteps;
         left -= kGraphSteps;
     }
-    for (; b->multi && left >= 3; left -= 3) {
-        HIPCHK(b, batch_triple(b, (int)(b->t & 1), 0, 3, b->stream));
-        b->t += 3;
+    for (; b->multi && left >= multi_steps(); left -= multi_steps()) {
+        HIPCHK(b, batch_multi(b, (int)(b->t & 1), 0, multi_steps(), b->stream));
+        b->t += multi_steps();
     }
     for (; left > 0; --left) {
         HIPCHK(b, batch_step(b, (int)(b->t & 1), 0, 1, b->stream));
@@ -1898,7 +1903,7 @@ int lb2d_batch_config(lb2d_batch *b, int *w, int *h, int *s, int *p) {
 int lb2d_batch_steps_per_launch(lb2d_batch *b, int *steps) {
     if (!b || !steps) return LB2D_E_INVAL;
     if (!b->final_) return b->fail(LB2D_E_STATE, "not finalized");
-    *steps = b->multi ? 3 : 1;
+    *steps = b->multi ? multi_steps() : 1;
     return LB2D_OK;
 }
 

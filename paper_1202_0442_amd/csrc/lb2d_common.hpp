@@ -45,6 +45,15 @@ struct PlainLattice {
     unsigned seed;        // key of the stochastic-rounding stream
 };
 
+// Steps per launch of the multi-step one-fluid kernel, and its tile (FP64:
+// kMultiTW / 2 x kMultiTH).  Measured on the porous 4096^2 lattice, FP32,
+// microseconds per step for 1 .. 6 steps per launch: 168, 112, 90.5, 77.9,
+// 71.9, 72.5.
+constexpr int kMultiSteps = 5;
+constexpr int kMultiTW = 64;
+constexpr int kMultiTH = 16;
+static_assert(kMultiSteps % 2 == 1, "an odd number of steps per launch keeps the buffer convention");
+
 // Tile of the batched step: lattice index and lower-left node.
 struct Tile {
     int lattice;

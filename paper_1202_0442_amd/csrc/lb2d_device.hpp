@@ -540,25 +540,25 @@ __global__ void __launch_bounds__(256) k_plain(PlainLattice L, int parity, int k
     plain_node<S, O, SR, NT>(plain_args<S>(L, parity), x, y, x < L.nx && y < L.ny, tkey);
 }
 
-// Three steps in one pass (temporal blocking).  A block of TW x TH threads
-// owns a tile of whole bricks; one LDS region holds the tile and two rings
-// of nodes around it, in the storage format (every value rounded exactly as
-// a store would round it):
-//  1. step one for the tile and both rings, pulled from the input buffer as
-//     in the one-step kernel, into LDS;
-//  2. step two for the tile and the inner ring, pulled from LDS into
-//     registers and, after a barrier, written back to the same slots;
-//  3. step three for the tile, pulled from LDS and written to the output
-//     buffer as whole bricks.
-// So the populations cross HBM once per three steps, and the results are
-// those of three one-step launches bit for bit.  A launch reads buffer p and
-// writes p^1, an odd number of steps ahead, so after every launch the state
-// lies in the buffer its step count names.  Ring nodes wrap periodically
-// with one conditional add or subtract, which needs nx >= TW + 2 and
-// ny >= TH + 2.  k: offset of the first of the three steps in its launch
-// group, as in k_plain.
-constexpr int kPlain3TW = 64;  // tile of the three-step kernel (FP64: 32 x 16)
-constexpr int kPlain3TH = 16;
+// NS steps in one pass (temporal blocking, NS = kMultiSteps).  A block of
+// TW x TH threads owns a tile of whole bricks; one LDS region holds the tile
+// and NS - 1 rings of nodes around it, in the storage format (every value
+// rounded exactly as a store would round it):
+//  * step 1 for the tile and all the rings, pulled from the input buffer as
+//    in the one-step kernel, into LDS;
+//  * step s = 2 .. NS-1 for the tile and rings 1 .. NS-s, pulled from LDS
+//    into registers and, after a barrier, written back to the same slots;
+//  * step NS for the tile, pulled from LDS and written to the output buffer
+//    as whole bricks.
+// So the populations cross HBM once per NS steps, and the results are those
+// of NS one-step launches bit for bit.  NS is odd: a launch reads buffer p
+// and writes p^1, so after every launch the state lies in the buffer its
+// step count names.  Ring nodes wrap periodically with one conditional add
+// or subtract; the host requires the lattice to hold the whole region
+// (nx >= TW + 2(NS-1), ny >= TH + 2(NS-1)).  Thread t below the total ring
+// size owns one ring node (inner rings first) for every step that needs it.
+// k: offset of the first of the NS steps in its launch group, as in k_plain.
+// (kMultiSteps, kMultiTW and kMultiTH are in lb2d_common.hpp.)
 
 // The first step of node (x, y) into LDS slot `slot` (planes of PL
 // elements); returns the node's link word.
@@ -579,21 +579,23 @@ __device__ __forceinline__ unsigned plain_stage(const PlainArgs<S> &L, unsigned 
     return lk;
 }
 
-// LDS region of the three-step kernel for a TW x TH tile: (TW + 4) x (TH + 4)
-// slots per plane, rows padded to 8 slots; the tile sits at offset (2, 2).
-template <int TW, int TH>
-struct Plain3Tile {
-    static constexpr int AW = TW + 4, AH = TH + 4, PITCH = (AW + 7) / 8 * 8, PL = AH * PITCH;
-    static constexpr int NR1 = 2 * (TW + 2) + 2 * TH;        // inner ring slots
-    static constexpr int NR2 = 2 * (TW + 4) + 2 * (TH + 2);  // outer ring slots
+// LDS region of the NS-step kernel for a TW x TH tile: (TW + 2(NS-1)) x
+// (TH + 2(NS-1)) slots per plane, rows padded to 8 slots; the tile sits at
+// offset (NS-1, NS-1).  Ring r (r = 1 .. NS-1) surrounds the tile at
+// distance r.
+template <int TW, int TH, int NS>
+struct MultiTile {
+    static constexpr int O = NS - 1, AW = TW + 2 * O, AH = TH + 2 * O, PITCH = (AW + 7) / 8 * 8, PL = AH * PITCH;
+    static constexpr int ring(int r) { return 2 * (TW + 2 * r) + 2 * (TH + 2 * r - 2); }
+    static constexpr int rings(int m) { return m <= 0 ? 0 : rings(m - 1) + ring(m); }
+    static constexpr int NR = rings(NS - 1);  // ring slots in all
 };
 
-// Slot s of the ring at distance r (1 or 2) around the tile, in region
-// coordinates: the ring's first row, its last row, then its first and last
-// columns without their corners.
-template <int TW, int TH>
+// Slot s of ring r in region coordinates: the ring's first row, its last
+// row, then its first and last columns without their corners.
+template <int TW, int TH, int NS>
 __device__ __forceinline__ void ring_slot(int s, int r, int &ax, int &ay) {
-    const int w = TW + 2 * r, h = TH + 2 * r, o = 2 - r;
+    const int w = TW + 2 * r, h = TH + 2 * r, o = NS - 1 - r;
     if (s < w) {
         ax = o + s;
         ay = o;
@@ -628,19 +630,18 @@ __device__ __forceinline__ void lds_pull_relax(const PlainArgs<S> &a, const S *s
     plain_relax(a, d, fluid);
 }
 
-// The three steps of the tile at (x0, y0) by a block of TW x TH threads;
-// key: stochastic-rounding keys of the three steps; sf: the block's LDS
-// region (9 planes).  No thread leaves before the last barrier, so a block
-// may run several tiles in a row (the caller separates them by a barrier).
-template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__device__ __forceinline__ void plain3_tile(const PlainArgs<S> &a, int x0, int y0, const unsigned (&key)[3],
-                                            S *sf) {
+// The NS steps of the tile at (x0, y0) by a block of TW x TH threads; key:
+// stochastic-rounding keys of the NS steps; sf: the block's LDS region (9
+// planes).  No thread leaves before the last barrier, so a block may run
+// several tiles in a row (the caller separates them by a barrier).
+template <typename S, typename O, bool SR, bool NT, int TW, int TH, int NS>
+__device__ __forceinline__ void multi_tile(const PlainArgs<S> &a, int x0, int y0, const unsigned (&key)[NS], S *sf) {
     using C = Codec<S>;
     using R = typename C::R;
-    using T = Plain3Tile<TW, TH>;
+    using T = MultiTile<TW, TH, NS>;
     constexpr int W = brick_w_for(sizeof(S)), H = brick_h_for(sizeof(S)), G = W * H;
-    constexpr int P = T::PITCH, PL = T::PL, NR1 = T::NR1, NR2 = T::NR2;
-    static_assert(TW % W == 0 && TH % H == 0 && NR1 + NR2 <= TW * TH, "tile of whole bricks");
+    constexpr int P = T::PITCH, PL = T::PL, OF = T::O;
+    static_assert(TW % W == 0 && TH % H == 0 && T::NR <= TW * TH, "tile of whole bricks");
     const int nx = (int)a.nx, ny = (int)a.ny;
     const int t = threadIdx.x;
     int lx, ly;
@@ -649,49 +650,55 @@ __device__ __forceinline__ void plain3_tile(const PlainArgs<S> &a, int x0, int y
     // such slots hold the nodes past the lattice's last row or column)
     const int gx = x0 + lx, gy = y0 + ly;
     const unsigned ux = (unsigned)(gx < nx ? gx : gx - nx), uy = (unsigned)(gy < ny ? gy : gy - ny);
-    const int c = (ly + 2) * P + lx + 2;
-    // 1. step one: the own node, and one ring slot for the first NR1 + NR2
-    // threads (inner ring first)
+    const int c = (ly + OF) * P + lx + OF;
+    // step 1: the own node, and the thread's ring node (ring rr, slot rc)
     const unsigned lk = plain_stage<S, O, SR, PL>(a, ux, uy, c, sf, key[0]);
-    int rc = -1;
+    int rc = -1, rr = NS;
     unsigned rlk = 1u, rx = 0u, ry = 0u;
-    if (t < NR1 + NR2) {
+    if (t < T::NR) {
+        int q = t, r = 1;
+        while (q >= T::ring(r)) {
+            q -= T::ring(r);
+            ++r;
+        }
         int ax, ay;
-        if (t < NR1) ring_slot<TW, TH>(t, 1, ax, ay);
-        else ring_slot<TW, TH>(t - NR1, 2, ax, ay);
-        int qx = x0 - 2 + ax, qy = y0 - 2 + ay;
+        ring_slot<TW, TH, NS>(q, r, ax, ay);
+        int qx = x0 - OF + ax, qy = y0 - OF + ay;
         qx = qx < 0 ? qx + nx : (qx >= nx ? qx - nx : qx);
         qy = qy < 0 ? qy + ny : (qy >= ny ? qy - ny : qy);
-        const unsigned l = plain_stage<S, O, SR, PL>(a, (unsigned)qx, (unsigned)qy, ay * P + ax, sf, key[0]);
-        if (t < NR1) {
-            rc = ay * P + ax;
-            rlk = l;
-            rx = (unsigned)qx;
-            ry = (unsigned)qy;
-        }
+        rlk = plain_stage<S, O, SR, PL>(a, (unsigned)qx, (unsigned)qy, ay * P + ax, sf, key[0]);
+        rc = ay * P + ax;
+        rr = r;
+        rx = (unsigned)qx;
+        ry = (unsigned)qy;
     }
     __syncthreads();
-    // 2. step two into registers: the own node, and the inner-ring node of
-    // the first NR1 threads; then, once every thread has read, back to LDS
-    const bool fl = (lk & 1u) == 0u, rfl = rc >= 0 && (rlk & 1u) == 0u;
+    // steps 2 .. NS-1: the own node and (while its ring is still needed)
+    // the ring node into registers; then, once every thread has read, back
+    // to their LDS slots
+    const bool fl = (lk & 1u) == 0u;
     R d[9], e[9];
-    if (fl) lds_pull_relax<S, P, PL>(a, sf, c, lk, true, d);
-    if (rfl) lds_pull_relax<S, P, PL>(a, sf, rc, rlk, true, e);
-    __syncthreads();
     unsigned w[5] = {0u, 0u, 0u, 0u, 0u};
-    if (fl) {
-        if constexpr (SR) sr_words(uy * a.nx + ux, key[1], w);
+#pragma unroll 1
+    for (int st = 1; st < NS - 1; ++st) {
+        const bool rfl = rr <= NS - 1 - st && (rlk & 1u) == 0u;
+        if (fl) lds_pull_relax<S, P, PL>(a, sf, c, lk, true, d);
+        if (rfl) lds_pull_relax<S, P, PL>(a, sf, rc, rlk, true, e);
+        __syncthreads();
+        if (fl) {
+            if constexpr (SR) sr_words(uy * a.nx + ux, key[st], w);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) sf[i * PL + c] = plain_enc<S, SR>(d[i], i, w);
-    }
-    if (rfl) {
-        if constexpr (SR) sr_words(ry * a.nx + rx, key[1], w);
+            for (int i = 0; i < 9; ++i) sf[i * PL + c] = plain_enc<S, SR>(d[i], i, w);
+        }
+        if (rfl) {
+            if constexpr (SR) sr_words(ry * a.nx + rx, key[st], w);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) sf[i * PL + rc] = plain_enc<S, SR>(e[i], i, w);
+            for (int i = 0; i < 9; ++i) sf[i * PL + rc] = plain_enc<S, SR>(e[i], i, w);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // 3. step three: the tile's nodes from LDS; a brick is written iff it
-    // holds a fluid node
+    // step NS: the tile's nodes from LDS; a brick is written iff it holds a
+    // fluid node
     const bool inside = gx < nx && gy < ny;
     const bool fluid = inside && fl;
     const unsigned long long bal = __ballot(fluid);
@@ -699,7 +706,7 @@ __device__ __forceinline__ void plain3_tile(const PlainArgs<S> &a, int x0, int y
     const unsigned long long gmask = (G >= 64) ? ~0ull : (((1ull << (G & 63)) - 1ull) << ((lane / G) * G));
     if (inside && (bal & gmask) != 0ull) {
         lds_pull_relax<S, P, PL>(a, sf, c, lk, fluid, d);
-        if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key[2], w);
+        if constexpr (SR) sr_words((unsigned)(gy * nx + gx), key[NS - 1], w);
         const O pl = (O)a.plane * (O)sizeof(S);
         LB2D_GLOBAL char *__restrict__ fout = (LB2D_GLOBAL char *)gbl(a.fout);
         const O s = brick_off<S, O>((unsigned)gx, (unsigned)gy, a.pnx);
@@ -712,42 +719,43 @@ __device__ __forceinline__ void plain3_tile(const PlainArgs<S> &a, int x0, int y
     }
 }
 
-// Keys of the stochastic rounding of steps st + 1, st + 2 and st + 3.
-__device__ __forceinline__ void sr_keys3(unsigned long long st, unsigned seed, unsigned (&key)[3]) {
+// Keys of the stochastic rounding of steps st + 1 .. st + NS.
+template <int NS>
+__device__ __forceinline__ void sr_keys(unsigned long long st, unsigned seed, unsigned (&key)[NS]) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) key[j] = lowbias32((unsigned)(st + 1ull + (unsigned long long)j) ^ seed);
+    for (int j = 0; j < NS; ++j) key[j] = lowbias32((unsigned)(st + 1ull + (unsigned long long)j) ^ seed);
 }
 
-template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_plain3(PlainLattice L, int parity, int k) {
-    __shared__ S sf[9 * Plain3Tile<TW, TH>::PL];
-    unsigned key[3] = {0u, 0u, 0u};
-    if constexpr (SR) sr_keys3(*L.step + (unsigned long long)k, L.seed, key);
-    plain3_tile<S, O, SR, NT, TW, TH>(plain_args<S>(L, parity), blockIdx.x * TW, blockIdx.y * TH, key, sf);
+template <typename S, typename O, bool SR, bool NT, int TW, int TH, int NS>
+__global__ void __launch_bounds__(TW *TH) k_plain_ms(PlainLattice L, int parity, int k) {
+    __shared__ S sf[9 * MultiTile<TW, TH, NS>::PL];
+    unsigned key[NS] = {};
+    if constexpr (SR) sr_keys<NS>(*L.step + (unsigned long long)k, L.seed, key);
+    multi_tile<S, O, SR, NT, TW, TH, NS>(plain_args<S>(L, parity), blockIdx.x * TW, blockIdx.y * TH, key, sf);
 }
 
-// Batched three-step kernel: blocks walk a table of TW x TH tiles of many
-// lattices, as k_batch does, each tile as in k_plain3 (every lattice of the
-// batch has at least the extent k_plain3 needs).
-template <typename S, typename O, bool SR, bool NT, int TW, int TH>
-__global__ void __launch_bounds__(TW *TH) k_batch3(const PlainLattice *__restrict__ lat,
-                                                  const Tile *__restrict__ tiles, int ntiles, int parity, int k,
-                                                  const unsigned long long *__restrict__ bstep) {
-    __shared__ S sf[9 * Plain3Tile<TW, TH>::PL];
+// Batched NS-step kernel: blocks walk a table of TW x TH tiles of many
+// lattices, as k_batch does, each tile as in k_plain_ms (every lattice of
+// the batch holds the whole region).
+template <typename S, typename O, bool SR, bool NT, int TW, int TH, int NS>
+__global__ void __launch_bounds__(TW *TH) k_batch_ms(const PlainLattice *__restrict__ lat,
+                                                    const Tile *__restrict__ tiles, int ntiles, int parity, int k,
+                                                    const unsigned long long *__restrict__ bstep) {
+    __shared__ S sf[9 * MultiTile<TW, TH, NS>::PL];
     unsigned long long step = 0ull;
     if constexpr (SR) step = *bstep + (unsigned long long)k;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int li = (int)ufl((unsigned)tiles[t].lattice);
         const int x0 = (int)ufl((unsigned)tiles[t].x0), y0 = (int)ufl((unsigned)tiles[t].y0);
         const PlainArgs<S> a = uniform_args(plain_args<S>(lat[li], parity));
-        unsigned key[3] = {0u, 0u, 0u};
+        unsigned key[NS] = {};
         if constexpr (SR) {
-            sr_keys3(step, lat[li].seed, key);
+            sr_keys<NS>(step, lat[li].seed, key);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) key[j] = ufl(key[j]);
+            for (int j = 0; j < NS; ++j) key[j] = ufl(key[j]);
         }
         if (t != (int)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
-        plain3_tile<S, O, SR, NT, TW, TH>(a, x0, y0, key, sf);
+        multi_tile<S, O, SR, NT, TW, TH, NS>(a, x0, y0, key, sf);
     }
 }
 

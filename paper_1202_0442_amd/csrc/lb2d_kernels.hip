@@ -41,42 +41,44 @@ hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool
     return hipGetLastError();
 }
 
-// Tile of the three-step kernel: 64 x 16 nodes (1024 threads), 32 x 16 for
-// 8-byte values (whose LDS region would otherwise take 115 KB).
-void plain3_tile(int st, int *tw, int *th) {
-    *tw = st == kF64 ? kPlain3TW / 2 : kPlain3TW;
-    *th = kPlain3TH;
+// Tile of the multi-step kernel: 64 x 16 nodes (1024 threads), 32 x 16 for
+// 8-byte values (whose LDS region then takes 69 KB).
+void multi_tile_shape(int st, int *tw, int *th) {
+    *tw = st == kF64 ? kMultiTW / 2 : kMultiTW;
+    *th = kMultiTH;
 }
 
-bool plain3_fits(int st, int nx, int ny) {
+int multi_steps() { return kMultiSteps; }
+
+bool multi_fits(int st, int nx, int ny) {
     int tw, th;
-    plain3_tile(st, &tw, &th);
-    return nx >= tw + 2 && ny >= th + 2;
+    multi_tile_shape(st, &tw, &th);
+    return nx >= tw + 2 * (kMultiSteps - 1) && ny >= th + 2 * (kMultiSteps - 1);
 }
 
 template <typename S, typename O, bool SR, bool NT>
-static void plain3_launch(const PlainLattice &L, int parity, int k, hipStream_t stream) {
-    constexpr int TW = sizeof(S) == 8 ? kPlain3TW / 2 : kPlain3TW, TH = kPlain3TH;
+static void multi_launch(const PlainLattice &L, int parity, int k, hipStream_t stream) {
+    constexpr int TW = sizeof(S) == 8 ? kMultiTW / 2 : kMultiTW, TH = kMultiTH;
     const dim3 blk(TW * TH), grd((L.nx + TW - 1) / TW, (L.ny + TH - 1) / TH);
-    hipLaunchKernelGGL((k_plain3<S, O, SR, NT, TW, TH>), grd, blk, 0, stream, L, parity, k);
+    hipLaunchKernelGGL((k_plain_ms<S, O, SR, NT, TW, TH, kMultiSteps>), grd, blk, 0, stream, L, parity, k);
 }
 
 template <bool NT>
-static void plain3_dispatch(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
+static void multi_dispatch(int st, const PlainLattice &L, int parity, bool sr, int k, hipStream_t stream) {
     if (sr && st == kF16)
-        plain3_launch<_Float16, uint32_t, true, NT>(L, parity, k, stream);
+        multi_launch<_Float16, uint32_t, true, NT>(L, parity, k, stream);
     else if (sr && st == kBF16)
-        plain3_launch<bf16s, uint32_t, true, NT>(L, parity, k, stream);
+        multi_launch<bf16s, uint32_t, true, NT>(L, parity, k, stream);
     else if (fits32(L.plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, (plain3_launch<S, uint32_t, false, NT>(L, parity, k, stream)));
+        LB2D_DISPATCH(st, (multi_launch<S, uint32_t, false, NT>(L, parity, k, stream)));
     else
-        LB2D_DISPATCH(st, (plain3_launch<S, size_t, false, NT>(L, parity, k, stream)));
+        LB2D_DISPATCH(st, (multi_launch<S, size_t, false, NT>(L, parity, k, stream)));
 }
 
-hipError_t launch_plain3(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t stream) {
-    if (!plain3_fits(st, L.nx, L.ny)) return hipErrorInvalidValue;
-    if (nt) plain3_dispatch<true>(st, L, parity, sr, k, stream);
-    else plain3_dispatch<false>(st, L, parity, sr, k, stream);
+hipError_t launch_plain_ms(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t stream) {
+    if (!multi_fits(st, L.nx, L.ny)) return hipErrorInvalidValue;
+    if (nt) multi_dispatch<true>(st, L, parity, sr, k, stream);
+    else multi_dispatch<false>(st, L, parity, sr, k, stream);
     return hipGetLastError();
 }
 
@@ -140,31 +142,32 @@ hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile 
 }
 
 template <typename S, typename O, bool SR, bool NT>
-static void batch3_launch(const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid, int k,
-                          const unsigned long long *bstep, hipStream_t stream) {
-    constexpr int TW = sizeof(S) == 8 ? kPlain3TW / 2 : kPlain3TW, TH = kPlain3TH;
-    hipLaunchKernelGGL((k_batch3<S, O, SR, NT, TW, TH>), dim3(grid), dim3(TW * TH), 0, stream, lat, tiles, ntiles,
-                       parity, k, bstep);
+static void batch_ms_launch(const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid, int k,
+                            const unsigned long long *bstep, hipStream_t stream) {
+    constexpr int TW = sizeof(S) == 8 ? kMultiTW / 2 : kMultiTW, TH = kMultiTH;
+    hipLaunchKernelGGL((k_batch_ms<S, O, SR, NT, TW, TH, kMultiSteps>), dim3(grid), dim3(TW * TH), 0, stream, lat,
+                       tiles, ntiles, parity, k, bstep);
 }
 
 template <bool NT>
-static void batch3_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                            size_t max_plane, bool sr, int k, const unsigned long long *bstep, hipStream_t stream) {
+static void batch_ms_dispatch(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                              size_t max_plane, bool sr, int k, const unsigned long long *bstep, hipStream_t stream) {
     if (sr && st == kF16)
-        batch3_launch<_Float16, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
+        batch_ms_launch<_Float16, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
     else if (sr && st == kBF16)
-        batch3_launch<bf16s, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
+        batch_ms_launch<bf16s, uint32_t, true, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream);
     else if (fits32(max_plane, storage_bytes(st)))
-        LB2D_DISPATCH(st, (batch3_launch<S, uint32_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
+        LB2D_DISPATCH(st,
+                      (batch_ms_launch<S, uint32_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
     else
-        LB2D_DISPATCH(st, (batch3_launch<S, size_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
+        LB2D_DISPATCH(st, (batch_ms_launch<S, size_t, false, NT>(lat, tiles, ntiles, parity, grid, k, bstep, stream)));
 }
 
-hipError_t launch_batch3(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
-                         size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
-                         hipStream_t stream) {
-    if (nt) batch3_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
-    else batch3_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+hipError_t launch_batch_ms(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+                           size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
+                           hipStream_t stream) {
+    if (nt) batch_ms_dispatch<true>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
+    else batch_ms_dispatch<false>(st, lat, tiles, ntiles, parity, grid, max_plane, sr, k, bstep, stream);
     return hipGetLastError();
 }
 

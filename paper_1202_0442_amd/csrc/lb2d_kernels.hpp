@@ -18,12 +18,14 @@ void plain_tile(int st, int *tw, int *th);
 // One-fluid step; sr: stochastic rounding (16-bit storage, 32-bit offsets),
 // nt: streaming stores, k: offset of the step in its launch group.
 hipError_t launch_plain(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
-// Three steps in one launch (buffer parity -> parity^1), for lattices of at
-// least one tile plus two nodes in each direction (plain3_fits).  Arguments
-// as for launch_plain (k: offset of the first of the three steps).
-void plain3_tile(int st, int *tw, int *th);
-bool plain3_fits(int st, int nx, int ny);
-hipError_t launch_plain3(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
+// multi_steps() (an odd number of) steps in one launch (buffer parity ->
+// parity^1), for lattices that hold the kernel's tile with multi_steps() - 1
+// rings of nodes around it (multi_fits).  Arguments as for launch_plain (k:
+// offset of the first of the steps).
+int multi_steps();
+void multi_tile_shape(int st, int *tw, int *th);
+bool multi_fits(int st, int nx, int ny);
+hipError_t launch_plain_ms(int st, const PlainLattice &L, int parity, bool sr, bool nt, int k, hipStream_t s);
 // Adds n to the device step counter.
 hipError_t launch_tick(unsigned long long *step, int n, hipStream_t s);
 // Tile shapes (width, height in nodes) of the batched step for a storage
@@ -36,10 +38,10 @@ int batch_shapes(int st, int *tw, int *th, int max);
 hipError_t launch_batch(int st, int tile_w, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity,
                         int grid, size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
                         hipStream_t s);
-// Batched three-step kernel over a table of plain3_tile-sized tiles of
-// lattices that each satisfy plain3_fits; arguments as for launch_batch (k:
-// offset of the first of the three steps).
-hipError_t launch_batch3(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
+// Batched multi-step kernel over a table of multi_tile_shape-sized tiles of
+// lattices that each satisfy multi_fits; arguments as for launch_batch (k:
+// offset of the first of the steps).
+hipError_t launch_batch_ms(int st, const PlainLattice *lat, const Tile *tiles, int ntiles, int parity, int grid,
                          size_t max_plane, bool nt, bool sr, int k, const unsigned long long *bstep,
                          hipStream_t s);
 // Adds n to the batch's step counter and to that of each of its nlat lattices.

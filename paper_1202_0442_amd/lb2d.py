@@ -279,7 +279,7 @@ class Lattice:
         self._chk(_lib.lb2d_prepare(self._h, int(nsteps)))
 
     def steps_per_launch(self):
-        """lb2d_steps_per_launch: 3 where the graphs run the three-step kernel."""
+        """lb2d_steps_per_launch: 5 where the graphs run the multi-step kernel."""
         v = _I(0)
         self._chk(_lib.lb2d_steps_per_launch(self._h, ctypes.byref(v)))
         return v.value
@@ -416,7 +416,7 @@ class Batch:
                     blocks_per_cu=v[3].value)
 
     def steps_per_launch(self):
-        """lb2d_batch_steps_per_launch: 3 when the three-step tile was chosen."""
+        """lb2d_batch_steps_per_launch: 5 when the multi-step tile was chosen."""
         v = _I(0)
         self._chk(_lib.lb2d_batch_steps_per_launch(self._h, ctypes.byref(v)))
         return v.value

@@ -51,7 +51,7 @@ def _batch(members, tune_cache=None):
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_ensemble_lattices_batched_match_oracle(storage):
-    """Eight generator lattices batched alone, 320 steps (six 48-step
+    """Eight generator lattices batched alone, 320 steps (five 60-step
     graphs), every member against its own oracle run."""
     cases = ensemble_cases()
     assert len(cases) == 8
@@ -93,12 +93,12 @@ def test_toy_batch_matches_oracle_and_single_lattices(storage):
 
 
 # Lattice sets of the tuned-shape test: "ragged" holds lattices narrower
-# or lower than the three-step kernel needs (its 64 x 16 tile, 32 x 16 for
-# FP64, plus two nodes each way), so the autotuner tries the three one-step
-# shapes only; "tiles" holds lattices of at least that extent (two of them
-# exactly), so it also tries the three-step kernel.
+# or lower than the multi-step kernel needs (its 64 x 16 tile, 32 x 16 for
+# FP64, plus four nodes each way), so the autotuner tries the three one-step
+# shapes only; "tiles" holds lattices of at least that extent (three of them
+# exactly in one direction), so it also tries the multi-step kernel.
 SETS = {"ragged": [(70, 41), (131, 77), (33, 200), (256, 9)],
-        "tiles": [(70, 41), (131, 77), (66, 200), (256, 18)]}
+        "tiles": [(72, 41), (131, 77), (72, 200), (256, 24)]}
 
 
 def _member(case, storage, rounding, seed):
@@ -115,7 +115,7 @@ def _member(case, storage, rounding, seed):
 def test_every_tuned_shape_equals_single_lattices(storage, rounding, lattices, tmp_path):
     """Every tile shape, schedule and grid the autotuner tries gives the
     lattices' own results bit for bit: each configuration is forced through
-    the tune cache and run for 75 steps (a 48-step graph, then three-step
+    the tune cache and run for 75 steps (a 60-step graph, then multi-step
     launches and single steps) against the lattices stepped alone."""
     import json
     cases = [porous_case(nx, ny, 30 + k, tau=0.6 + 0.15 * k) for k, (nx, ny) in enumerate(SETS[lattices])]

@@ -52,7 +52,7 @@ def test_porous_4096_sampled_patches(storage, tol_u):
         g.obstacle_circle(xc, yc, r)
     g.aveacceleration(1, w.accel_x)
     g.bind(storage, stream=stream)
-    k = 96                         # two graph launches of 48 steps (32 three-step launches)
+    k = 96                         # a 60-step graph and a 36-step one (multi-step launches)
     g.iteration(k)
     rho, ux, uy = g.moments(0)
     gm = g.mask()
@@ -177,8 +177,8 @@ def _sc_window_case(w, rho_a, rho_b, x0, y0, W):
 @pytest.mark.parametrize("storage,tol_r,tol_u", [("f64", 1e-11, 1e-10), ("f32", 1e-5, 1e-5)])
 def test_sc_solute_2048_sampled_patches(storage, tol_r, tol_u):
     """The two-component + solute + reaction workload at its full 2048^2
-    size, stepped by one 32-step graph launch (the library's graphs of up
-    to 48 steps, as the benchmark steps it),
+    size, stepped by one 32-step graph launch (the library's graphs hold up
+    to 60 steps; the benchmark steps it the same way),
     against the oracle on windows around sampled patches.  After k steps a
     node depends on the initial state within 2k nodes (the Shan-Chen
     stencil reads post-streaming densities of the neighbours), and discs

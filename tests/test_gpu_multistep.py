@@ -1,10 +1,10 @@
-"""The three-step kernel of the one-fluid lattice (temporal blocking: the
-first step of a tile and two rings of nodes around it, and the second step of
-the tile and the inner ring, kept in LDS; the third written to HBM) against
-the one-step kernel and the FP64 oracle.
+"""The multi-step kernel of the one-fluid lattice (temporal blocking, five
+steps per launch: the first step of a tile and four rings of nodes around it,
+then each further step on one ring fewer, kept in LDS; the fifth written to
+HBM) against the one-step kernel and the FP64 oracle.
 
-Launch graphs run the one-fluid step as three-step launches on lattices of
-at least 66 x 18 nodes (34 x 18 in FP64), then single steps; timing mode
+Launch graphs run the one-fluid step as five-step launches on lattices of
+at least 72 x 24 nodes (40 x 24 in FP64), then single steps; timing mode
 launches single steps.  So a lattice stepped through graphs and the same
 lattice stepped with timing on must agree bit for bit, in every storage
 format and with stochastic rounding, whose random words are keyed on each
@@ -20,7 +20,7 @@ from cases import build_gpu, build_oracle, porous_case
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(66, 18), (67, 19), (65, 18), (66, 17), (127, 31), (150, 90), (34, 18), (35, 47), (33, 47), (200, 20)]
+SHAPES = [(72, 24), (73, 25), (71, 24), (72, 23), (127, 31), (150, 90), (40, 24), (41, 47), (39, 47), (200, 26)]
 
 
 def _pair(case, storage, rounding):
@@ -39,10 +39,10 @@ def _pair(case, storage, rounding):
                                               ("bf16", "nearest"), ("f16", "stochastic"),
                                               ("bf16", "stochastic")])
 @pytest.mark.parametrize("nx,ny", SHAPES)
-def test_three_step_launches_equal_single_steps(nx, ny, storage, rounding):
-    """101 steps (one step, then from the odd step count two 48-step graphs
-    and a 4-step tail: a three-step launch and a single step) through graphs
-    equal 101 single launches, bit for bit."""
+def test_multi_step_launches_equal_single_steps(nx, ny, storage, rounding):
+    """101 steps (one step, then from the odd step count a 60-step graph and
+    a 40-step tail graph of eight five-step launches) through graphs equal
+    101 single launches, bit for bit."""
     case = porous_case(nx, ny, 40 + nx + ny, tau=0.7)
     a, b = _pair(case, storage, rounding)
     a.iteration(1)
@@ -56,17 +56,17 @@ def test_three_step_launches_equal_single_steps(nx, ny, storage, rounding):
 
 
 def test_steps_per_launch_follows_the_lattice_extent():
-    """The three-step kernel runs exactly where the lattice has the extent it
-    needs (its tile plus two nodes each way)."""
-    for (nx, ny, st, want) in [(66, 18, "f32", 3), (65, 18, "f32", 1), (66, 17, "f32", 1), (66, 18, "f16", 3),
-                               (34, 18, "f64", 3), (33, 18, "f64", 1), (4096, 4096, "f32", 3)]:
+    """The multi-step kernel runs exactly where the lattice has the extent it
+    needs (its tile plus four nodes each way)."""
+    for (nx, ny, st, want) in [(72, 24, "f32", 5), (71, 24, "f32", 1), (72, 23, "f32", 1), (72, 24, "f16", 5),
+                               (40, 24, "f64", 5), (39, 24, "f64", 1), (4096, 4096, "f32", 5)]:
         g = build_gpu(porous_case(nx, ny, 3) if nx * ny < 1e6 else dict(nx=nx, ny=ny, tau=0.8), st)
         assert g.steps_per_launch() == want, (nx, ny, st)
         g.close()
 
 
-@pytest.mark.parametrize("nx,ny", [(66, 18), (67, 19), (150, 90), (35, 47)])
-def test_three_step_launches_match_oracle(nx, ny):
+@pytest.mark.parametrize("nx,ny", [(72, 24), (73, 25), (150, 90), (41, 47)])
+def test_multi_step_launches_match_oracle(nx, ny):
     """Graph-stepped lattices against the oracle after 160 steps: FP64 within
     1e-12 of the largest velocity and density, FP32 within 1e-5."""
     case = porous_case(nx, ny, 70 + nx, tau=0.9)
@@ -86,7 +86,7 @@ def test_three_step_launches_match_oracle(nx, ny):
         assert eu <= tol and er <= tol
 
 
-def test_three_step_launches_conserve_mass_exactly_in_fp64():
+def test_multi_step_launches_conserve_mass_exactly_in_fp64():
     """Periodic box with bounce-back obstacles: the total mass after 400
     graph-launched steps equals the initial mass to rounding (FP64)."""
     case = porous_case(96, 48, 5, tau=0.8)

@@ -178,7 +178,7 @@ def test_runs_are_bitwise_deterministic():
 def test_graph_launch_equals_single_launches(kind):
     case = porous_case(150, 90, 16) if kind == "plain" else sc_solute_case(96, 64, 16)
     a = build_gpu(case, "f32")
-    a.iteration(70)  # a graph of 48 steps and a 22-step tail graph
+    a.iteration(70)  # a graph of 60 steps and a 10-step tail graph
     b = build_gpu(case, "f32")
     b.set_timing(True)
     b.iteration(70)
@@ -190,7 +190,7 @@ def test_graph_launch_equals_single_launches(kind):
 
 @pytest.mark.parametrize("kind,storage", [("plain", "f32"), ("plain", "f16sr"), ("full", "f32"), ("full", "f16sr")])
 def test_graphs_of_every_length_equal_single_launches(kind, storage):
-    """lb2d_iteration launches graphs of 48 steps and one graph of the
+    """lb2d_iteration launches graphs of 60 steps and one graph of the
     remaining steps, captured per starting parity (ahead by lb2d_prepare or
     on first use): calls of 1, 2, 5, 33, 63 and 7 steps (odd and even
     starts) equal the same steps launched one by one, also

@@ -81,7 +81,7 @@ def test_stochastic_stream_same_for_graph_and_single_steps():
 def test_batch_with_stochastic_rounding_equals_single_lattices(storage):
     """Each lattice of a batch draws the random words it draws alone (its
     own seed, step count and node numbering): batched runs of 75 steps (two
-    48-step graph and shorter launches) and of 1 + 74 steps (a first step at
+    60-step graph and shorter launches) and of 1 + 74 steps (a first step at
     odd parity) equal the lattices stepped one by one, bit for bit."""
     from paper_1202_0442_amd import lb2d
     cases = [porous_case(nx, ny, 20 + k, tau=0.6 + 0.1 * k) for k, (nx, ny) in
