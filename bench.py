@@ -641,7 +641,7 @@ def main():
     mlups = n * args.steps / (ms * 1e-3) / 1e6
     log(f"{mlups:.0f} MLUPS, {per * 1e3:.1f} us/step")
     # the dominant kernel advances `spl` steps per launch (the multi-step
-    # kernel: 2), launched back to back inside the graphs: launch time =
+    # kernel: 5), launched back to back inside the graphs: launch time =
     # spl x step time (HIP events on the stream the kernel runs on)
     spl = L.steps_per_launch()
     kernel = "k_plain_ms" if spl > 1 else "k_plain"

@@ -293,7 +293,7 @@ int lb2d_bind(lb2d_ctx *ctx, void *dev_ptr, size_t bytes, void *hip_stream);
  * launches captured HIP graphs: graphs of 60 steps, then one graph of the
  * remaining steps (a single launch for one step).  A graph is captured the
  * first time its length and starting parity (even or odd step count) are
- * needed and kept.  Inside the graphs, a one-fluid lattice (no solute, no
+ * needed, uploaded to the device on the context's stream and kept.  Inside the graphs, a one-fluid lattice (no solute, no
  * Shan-Chen, no openings or slip solids) of at least 72 x 24 nodes (40 x 24
  * in FP64) advances by a multi-step kernel, five steps per launch (the first
  * four of each five are kept in LDS and never reach memory), then single
@@ -302,9 +302,10 @@ int lb2d_iteration(lb2d_ctx *ctx, int64_t nsteps);
 /* Steps that one launch of the dominant step kernel advances inside the
  * graphs of lb2d_iteration: 5 for the multi-step kernel, else 1. */
 int lb2d_steps_per_launch(lb2d_ctx *ctx, int *steps);
-/* Captures, without running any step, the graphs that
+/* Captures and uploads, without running any step, the graphs that
  * lb2d_iteration(ctx, nsteps) will launch from the current step count, so
- * that the call itself launches without capture cost (for timed regions). */
+ * that the call itself launches without capture or upload cost (for timed
+ * regions). */
 int lb2d_prepare(lb2d_ctx *ctx, int64_t nsteps);
 
 /* ------------------------------------------------------------ output */

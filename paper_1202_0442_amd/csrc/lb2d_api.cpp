@@ -473,6 +473,9 @@ int build_graph(lb2d_ctx *c, int len, int p0, hipGraphExec_t *out) {
     if (e2 != hipSuccess) return c->fail(LB2D_E_HIP, "graph capture end: %s", hipGetErrorString(e2));
     HIPCHK(c, hipGraphInstantiate(&g, gr, nullptr, nullptr, 0));
     HIPCHK(c, hipGraphDestroy(gr));
+    // upload the executable graph now, so that its first launch costs what
+    // every later one does
+    HIPCHK(c, hipGraphUpload(g, c->stream));
     *out = g;
     return LB2D_OK;
 }
@@ -1872,6 +1875,7 @@ int lb2d_batch_iteration(lb2d_batch *b, int64_t nsteps) {
         if (e != hipSuccess || e2 != hipSuccess) return b->fail(LB2D_E_HIP, "batch graph capture failed");
         HIPCHK(b, hipGraphInstantiate(&b->graph[p0], gr, nullptr, nullptr, 0));
         HIPCHK(b, hipGraphDestroy(gr));
+        HIPCHK(b, hipGraphUpload(b->graph[p0], b->stream));
     }
     while (left >= kGraphSteps) {
         HIPCHK(b, hipGraphLaunch(b->graph[p0], b->stream));
