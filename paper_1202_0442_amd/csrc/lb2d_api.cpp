@@ -94,6 +94,7 @@ struct lb2d_ctx {
     double *totals = nullptr;
     long long *dstep = nullptr;
     unsigned *gflag = nullptr;
+    uint8_t *gseg = nullptr;  // two flag rows of growth_segments(nx, ny) bytes
     size_t staging_doubles = 0;
     double rho_ref[2] = {1.0, 1.0};
     int64_t t = 0;
@@ -193,7 +194,7 @@ bool is_nan(double v) { return std::isnan(v); }
 
 // Workspace layout of one lattice.
 struct Layout {
-    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, gflag, refl, total;
+    size_t f[2][2], g[2], mask, trig, links, b, staging, partial, gpartial, totals, dstep, gflag, gseg, refl, total;
     size_t staging_doubles;
 };
 
@@ -253,6 +254,8 @@ Layout make_layout(const lb2d_ctx *c, int storage) {
     off += align_up(8);
     L.gflag = off;
     off += align_up(8);
+    L.gseg = off;
+    off += align_up(2 * (size_t)growth_segments(c->nx, c->ny));
     // reflected shares of slip/mixed solids, per component
     L.refl = off;
     if (c->slip_any()) off += align_up((size_t)c->ncomp * n * 8);
@@ -285,6 +288,8 @@ FullParams full_params(const lb2d_ctx *c) {
     p.totals = c->totals;
     p.dstep = c->dstep;
     p.gflag = c->gflag;
+    p.gseg[0] = c->gseg;
+    p.gseg[1] = c->gseg + growth_segments(c->nx, c->ny);
     p.nx = c->nx;
     p.ny = c->ny;
     p.ncomp = c->ncomp;
@@ -1060,6 +1065,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     c->totals = (double *)(c->ws + L.totals);
     c->dstep = (long long *)(c->ws + L.dstep);
     c->gflag = (unsigned *)(c->ws + L.gflag);
+    c->gseg = (uint8_t *)(c->ws + L.gseg);
     c->refl_dev = c->slip_any() ? (double *)(c->ws + L.refl) : nullptr;
     const size_t n = c->n();
     hipStream_t s = c->stream;
@@ -1187,6 +1193,7 @@ int lb2d_bind(lb2d_ctx *c, void *dev_ptr, size_t bytes, void *hip_stream) {
     HIPCHK(c, launch_fill_f64(c->gpartial, 0.0, (size_t)growth_blocks(c->nx, c->ny) * 4, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->dstep, 0, 8, s));
     HIPCHK(c, launch_fill_u8((uint8_t *)c->gflag, 0, 8, s));
+    HIPCHK(c, launch_fill_u8(c->gseg, 0, 2 * (size_t)growth_segments(c->nx, c->ny), s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->t = 0;
     c->bound = true;

@@ -119,6 +119,9 @@ struct FullParams {
     double *totals;       // fixed-order sums of the tallies (LB2D_B_* indices)
     long long *dstep;     // completed steps (device copy)
     unsigned *gflag;      // [2]: a growth trigger fired in the step of that parity
+    uint8_t *gseg[2];     // [parity][y * ((nx + 255) / 256) + x / 256]: 1 = that
+                          // row segment of 256 nodes holds the target of a growth
+                          // trigger fired in the step of that parity
     unsigned pnx;         // padded nx of the brick layout
     size_t pplane;        // elements per population plane
     int nx, ny;

@@ -1643,6 +1643,9 @@ __global__ void __launch_bounds__(TX *TY) k_full(FullParams p, int parity) {
                 tal[2] += bn;
                 bn = 0.0;
                 p.gflag[parity] = 1u;
+                // the growth kernel visits only the row segments so marked
+                const int gx = wrapi(x + ex(code), nx), gy = wrapi(y + ey(code), ny);
+                p.gseg[parity][(size_t)gy * ((nx + 255) / 256) + gx / 256] = 1u;
             }
             p.trig[srow] = code;
         }
@@ -1708,21 +1711,30 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     __shared__ double sred[4 * 4];
     const int nx = p.nx, ny = p.ny;
     const size_t plane = p.pplane;
-    // steps without any trigger (the common case) only advance the counter
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!REACT || p.gflag[parity_new ^ 1] == 0u) {
+    if (!REACT) {
         if (first) {
             *p.dstep += 1;
             p.gflag[parity_new] = 0u;
         }
         return;
     }
+    // only the row segments that the step kernel marked can hold a node to
+    // grow (the targets of this step's triggers), so the others are skipped,
+    // all of them in a step without any trigger; the marks of the other
+    // parity (read by the previous step's launch) are cleared for the next
+    // step
+    const bool fired = p.gflag[parity_new ^ 1] != 0u;
+    const uint8_t *__restrict__ marked = p.gseg[parity_new ^ 1];
     double tal[4] = {0.0, 0.0, 0.0, 0.0};
     bool any = false;
     if constexpr (REACT) {
         const int segs_x = (nx + 255) / 256;
         const int nseg = segs_x * ny;
         for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+            const bool live = fired && marked[seg] != 0u;
+            if (threadIdx.x == 0) p.gseg[parity_new][seg] = 0u;
+            if (!live) continue;
             const int x = (seg % segs_x) * 256 + threadIdx.x;
             const int y = seg / segs_x;
             if (x >= nx) continue;

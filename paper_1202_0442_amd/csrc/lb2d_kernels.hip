@@ -186,8 +186,9 @@ hipError_t launch_tick_batch(const PlainLattice *lat, int nlat, int n, unsigned 
 
 int full_tiles(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
 int full_slots(int nx, int ny) { return full_tiles(nx, ny) * (kTX * kTY / 64); }
+int growth_segments(int nx, int ny) { return ((nx + 255) / 256) * ny; }
 int growth_blocks(int nx, int ny) {
-    const int segs = ((nx + 255) / 256) * ny;
+    const int segs = growth_segments(nx, ny);
     return segs < kGrowBlocks ? segs : kGrowBlocks;
 }
 

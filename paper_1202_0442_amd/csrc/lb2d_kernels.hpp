@@ -11,6 +11,9 @@ int full_tiles(int nx, int ny);
 // Running tally slots of the general step (one per wavefront) and blocks
 // (= tally slots) of the growth kernel.
 int full_slots(int nx, int ny);
+// Row segments of 256 nodes (((nx + 255) / 256) per row) that the growth
+// kernel walks, and its block count.
+int growth_segments(int nx, int ny);
 int growth_blocks(int nx, int ny);
 
 // Tile (in nodes) covered by one 256-thread block of the one-fluid step.
