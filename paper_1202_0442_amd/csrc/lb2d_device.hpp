@@ -1705,12 +1705,72 @@ __global__ void __launch_bounds__(256) k_open_gradient(FullParams p, int parity_
 // step's growth decisions).
 constexpr int kGrowBlocks = 1024;
 
-template <typename S, int NC, bool REACT>
-__global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
+// One row segment of the growth kernel: the thread's node (x = 256 * (seg %
+// segs_x) + threadIdx.x of row seg / segs_x) turns solid if a direct
+// neighbour's trigger points at it; its removed fluid and solute are added
+// to tal and any is set.
+template <typename S, int NC>
+__device__ __forceinline__ void grow_segment(const FullParams &p, int parity_new, int seg, int segs_x,
+                                             double (&tal)[4], bool &any) {
     using C = Codec<S>;
-    __shared__ double sred[4 * 4];
     const int nx = p.nx, ny = p.ny;
     const size_t plane = p.pplane;
+    const int x = (seg % segs_x) * 256 + threadIdx.x;
+    const int y = seg / segs_x;
+    if (x >= nx) return;
+    const size_t s = (size_t)y * nx + x;
+    if (p.mask[s]) return;
+    bool grow = false;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const int sx = x + ex(k), sy = y + ey(k);
+        if (across_closed(p, sx, sy)) continue;
+        const size_t sn = (size_t)wrapi(sy, ny) * nx + wrapi(sx, nx);
+        if (p.trig[sn] == (uint8_t)opp(k)) grow = true;
+    }
+    if (!grow) return;
+    any = true;
+    const size_t ps = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const S *__restrict__ f = (const S *)p.f[parity_new][c];
+        double r = 0.0;
+        for (int i = 0; i < 9; ++i)
+            r += wgt<double>(i) * p.cd.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
+        tal[c] += r;
+    }
+    const S *__restrict__ g = (const S *)p.g[parity_new];
+    double cc = 0.0;
+    for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], splane_dir(p.sq, k));
+    tal[2] += cc;
+    tal[3] += 1.0;
+    // the node's fluid and solute are removed: its stored values are
+    // cleared as the step clears every solid node (deviation 0 for the
+    // fluid, 0 for the solute)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        S *__restrict__ f = (S *)p.f[parity_new][c];
+        for (int i = 0; i < 9; ++i) f[(size_t)i * plane + ps] = C::enc(0.0, i);
+    }
+    for (int k = 0; k < p.sq; ++k) ((S *)p.g[parity_new])[(size_t)k * plane + ps] = C::enc(0.0, k);
+    if (p.slip)
+        for (int c = 0; c < NC; ++c) p.refl[c][s] = p.grow_R[c];
+    p.mask[s] = 1;
+    p.b[s] = p.b0;
+    // link words: own bit 0; neighbour s + e_j sees s at e_opp(j)
+    unsigned *lw = (unsigned *)p.links;
+    atomicOr(lw + (s >> 1), 1u << (16u * (unsigned)(s & 1)));
+#pragma unroll
+    for (int j = 1; j < 9; ++j) {
+        const size_t n = (size_t)wrapi(y + ey(j), ny) * nx + wrapi(x + ex(j), nx);
+        atomicOr(lw + (n >> 1), (1u << opp(j)) << (16u * (unsigned)(n & 1)));
+    }
+}
+
+template <typename S, int NC, bool REACT>
+__global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
+    __shared__ double sred[4 * 4];
+    const int nx = p.nx, ny = p.ny;
     const bool first = blockIdx.x == 0 && threadIdx.x == 0;
     if (!REACT) {
         if (first) {
@@ -1723,68 +1783,33 @@ __global__ void __launch_bounds__(256) k_growth(FullParams p, int parity_new) {
     // grow (the targets of this step's triggers), so the others are skipped,
     // all of them in a step without any trigger; the marks of the other
     // parity (read by the previous step's launch) are cleared for the next
-    // step
+    // step.  The block's segments are blockIdx.x + k * gridDim.x in
+    // increasing k; their marks are read 256 at a time, one per thread.
     const bool fired = p.gflag[parity_new ^ 1] != 0u;
     const uint8_t *__restrict__ marked = p.gseg[parity_new ^ 1];
+    __shared__ uint8_t slive[256];
     double tal[4] = {0.0, 0.0, 0.0, 0.0};
     bool any = false;
     if constexpr (REACT) {
         const int segs_x = (nx + 255) / 256;
         const int nseg = segs_x * ny;
-        for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-            const bool live = fired && marked[seg] != 0u;
-            if (threadIdx.x == 0) p.gseg[parity_new][seg] = 0u;
-            if (!live) continue;
-            const int x = (seg % segs_x) * 256 + threadIdx.x;
-            const int y = seg / segs_x;
-            if (x >= nx) continue;
-            const size_t s = (size_t)y * nx + x;
-            if (p.mask[s]) continue;
-            bool grow = false;
-#pragma unroll
-            for (int k = 1; k <= 4; ++k) {
-                const int sx = x + ex(k), sy = y + ey(k);
-                if (across_closed(p, sx, sy)) continue;
-                const size_t sn = (size_t)wrapi(sy, ny) * nx + wrapi(sx, nx);
-                if (p.trig[sn] == (uint8_t)opp(k)) grow = true;
+        const int stride = (int)gridDim.x;
+        for (int base = blockIdx.x; base < nseg; base += 256 * stride) {
+            const int mine = base + (int)threadIdx.x * stride;
+            bool lv = false;
+            if (mine < nseg) {
+                lv = fired && marked[mine] != 0u;
+                p.gseg[parity_new][mine] = 0u;
             }
-            if (!grow) continue;
-            any = true;
-            const size_t ps = brick_index<S>((unsigned)x, (unsigned)y, p.pnx);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const S *__restrict__ f = (const S *)p.f[parity_new][c];
-                double r = 0.0;
-                for (int i = 0; i < 9; ++i)
-                    r += wgt<double>(i) * p.cd.rho_ref[c] + (double)C::dec(f[(size_t)i * plane + ps], i);
-                tal[c] += r;
+            slive[threadIdx.x] = lv ? 1u : 0u;
+            if (__syncthreads_or(lv)) {
+                for (int k = 0; k < 256; ++k) {
+                    const int seg = base + k * stride;
+                    if (seg >= nseg) break;
+                    if (slive[k]) grow_segment<S, NC>(p, parity_new, seg, segs_x, tal, any);
+                }
             }
-            const S *__restrict__ g = (const S *)p.g[parity_new];
-            double cc = 0.0;
-            for (int k = 0; k < p.sq; ++k) cc += (double)C::dec(g[(size_t)k * plane + ps], splane_dir(p.sq, k));
-            tal[2] += cc;
-            tal[3] += 1.0;
-            // the node's fluid and solute are removed: its stored values are
-            // cleared as the step clears every solid node (deviation 0 for the
-            // fluid, 0 for the solute)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                S *__restrict__ f = (S *)p.f[parity_new][c];
-                for (int i = 0; i < 9; ++i) f[(size_t)i * plane + ps] = C::enc(0.0, i);
-            }
-            for (int k = 0; k < p.sq; ++k) ((S *)p.g[parity_new])[(size_t)k * plane + ps] = C::enc(0.0, k);
-            if (p.slip)
-                for (int c = 0; c < NC; ++c) p.refl[c][s] = p.grow_R[c];
-            p.mask[s] = 1;
-            p.b[s] = p.b0;
-            // link words: own bit 0; neighbour s + e_j sees s at e_opp(j)
-            unsigned *lw = (unsigned *)p.links;
-            atomicOr(lw + (s >> 1), 1u << (16u * (unsigned)(s & 1)));
-#pragma unroll
-            for (int j = 1; j < 9; ++j) {
-                const size_t n = (size_t)wrapi(y + ey(j), ny) * nx + wrapi(x + ex(j), nx);
-                atomicOr(lw + (n >> 1), (1u << opp(j)) << (16u * (unsigned)(n & 1)));
-            }
+            __syncthreads();
         }
     }
     if (__syncthreads_or(any)) {
