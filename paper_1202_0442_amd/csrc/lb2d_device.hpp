@@ -13,21 +13,26 @@
 // adhesiveforce, thermo and output.
 //
 // Design (bandwidth-bound stencil, no matrix cores):
-//  * populations are SoA planes [9][ny][nx] (x fastest) in two buffers; a
-//    step pulls f_i from x - e_i in buffer p and writes buffer p^1, so every
-//    load and store of a wavefront is a contiguous row segment;
+//  * populations are nine planes per buffer, each plane stored as bricks of
+//    4x4 (FP32), 4x8 (16-bit) or 8x4 (FP64) nodes, in two buffers; a step
+//    pulls f_i from x - e_i in buffer p and writes buffer p^1; the lanes of
+//    a wavefront cover whole bricks, and a brick is written only if it
+//    holds a fluid node;
 //  * half-way bounce-back is a per-lane address select: when x - e_i is
 //    solid the lane reads its own opposite population instead;
 //  * one fused pass per step does stream, moments, forces, equilibrium and
 //    BGK relaxation (and, in the general kernel, the solute step, reactive
-//    links and deposit gathering); solid nodes are skipped entirely;
+//    links and deposit gathering); solid nodes are skipped entirely; the
+//    one-fluid step runs five steps per launch, the first four kept in LDS
+//    for a tile and the rings around it;
 //  * Shan-Chen cohesion needs the post-stream densities of the 8
 //    neighbours: the general kernel computes a (TX+2) x (TY+2) density tile
 //    in LDS, pulling the halo nodes' populations again (they come from L2),
 //    and maps tiles to XCDs in contiguous bands so neighbouring tiles share
 //    an L2;
 //  * deposits are gathered by the solid node's own thread (no atomics);
-//    growth is decided there and applied by a separate gather kernel;
+//    growth is decided there and applied by a separate gather kernel over
+//    the row segments that hold a trigger's target;
 //  * every FP64 tally is a fixed-order block reduction followed by a
 //    fixed-order sum of the block partials, so results are bitwise
 //    reproducible.
@@ -411,7 +416,7 @@ __device__ __forceinline__ void plain_pull(const PlainArgs<S> &L, unsigned xx, u
 // forcing, Eq. (eq), BGK relaxation; d receives the post-collision
 // deviations (zero at solid nodes).  Every multiply-add is written out and
 // implicit contraction is off, so the rounding is the same in every kernel
-// this is inlined into (the one-step, batched and two-step kernels give the
+// this is inlined into (the one-step, multi-step and batched kernels give the
 // same bits).  The order of operations and the fused products are those the
 // compiler chose for the FP32 and FP64 one-step kernels with contraction
 // on: the diagonal projections e.u fuse the product of 1/rho with the x
