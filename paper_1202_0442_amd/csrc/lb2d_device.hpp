@@ -419,16 +419,17 @@ __device__ __forceinline__ void plain_pull(const PlainArgs<S> &L, unsigned xx, u
 // this is inlined into (the one-step, multi-step and batched kernels give the
 // same bits).  The order of operations and the fused products are those the
 // compiler chose for the FP32 and FP64 one-step kernels with contraction
-// on: the diagonal projections e.u fuse the product of 1/rho with the x
-// momentum, and the u.u term enters the bracket as one multiply-add.
+// on (the diagonal projections e.u fuse the product of 1/rho with the x
+// momentum, and the u.u term enters the bracket as one multiply-add),
+// except that the sums start from their first term rather than from zero.
 template <typename S, typename R>
 __device__ __forceinline__ void plain_relax(const PlainArgs<S> &L, R (&d)[9], bool fluid) {
 #pragma clang fp contract(off)
-    R drho = R(0);
+    R drho = d[0];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) drho = drho + d[i];
-    const R jx = ((((R(0) + d[1]) - d[3]) + d[5]) - d[6] - d[7]) + d[8];
-    const R jy = ((((R(0) + d[2]) - d[4]) + d[5]) + d[6] - d[7]) - d[8];
+    for (int i = 1; i < 9; ++i) drho = drho + d[i];
+    const R jx = (((d[1] - d[3]) + d[5]) - d[6] - d[7]) + d[8];
+    const R jy = (((d[2] - d[4]) + d[5]) + d[6] - d[7]) - d[8];
     const R rho = drho + L.rho_ref;
     const R tau = L.tau, omega = L.omega;
     const R Fx = fmar(rho, L.ax, L.Fx);
