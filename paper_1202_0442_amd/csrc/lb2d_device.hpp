@@ -640,8 +640,20 @@ __device__ __forceinline__ void lds_pull_relax(const PlainArgs<S> &a, const S *s
 // stochastic-rounding keys of the NS steps; sf: the block's LDS region (9
 // planes).  No thread leaves before the last barrier, so a block may run
 // several tiles in a row (the caller separates them by a barrier).
+// A value held in a vector register: a multiply-add may take one scalar
+// operand, so a uniform force term kept in a vector register spares the
+// copy into one that every collision would otherwise need.
+template <typename R>
+__device__ __forceinline__ R in_vgpr(R v) {
+    asm("" : "=v"(v) : "0"(v));
+    return v;
+}
+
 template <typename S, typename O, bool SR, bool NT, int TW, int TH, int NS>
-__device__ __forceinline__ void multi_tile(const PlainArgs<S> &a, int x0, int y0, const unsigned (&key)[NS], S *sf) {
+__device__ __forceinline__ void multi_tile(const PlainArgs<S> &a0, int x0, int y0, const unsigned (&key)[NS], S *sf) {
+    PlainArgs<S> a = a0;
+    a.Fx = in_vgpr(a0.Fx);
+    a.Fy = in_vgpr(a0.Fy);
     using C = Codec<S>;
     using R = typename C::R;
     using T = MultiTile<TW, TH, NS>;
